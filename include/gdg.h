@@ -1,0 +1,221 @@
+/*
+ * gdg.h -- C ABI of the MI355X (gfx950) sliding-window GDG decoder.
+ *
+ * GDG (belief propagation with guided decimation and guessing) from Gong,
+ * Cammerer and Renes, "Toward Low-latency Iterative Decoding of QLDPC Codes
+ * Under Circuit-Level Noise" (arXiv 2403.18901). The library decodes one
+ * window of a (W,1) sliding window (Sec. III, Eq. 6) for many shots at once:
+ * a window syndrome goes in, the window's correction comes out, and
+ * gdg_commit applies the committed part to the detector record (Eq. 7-8).
+ *
+ * Conventions for every entry point:
+ *  - Return 0 on success or a negative GDG_E* code; gdg_last_error() gives a
+ *    message (thread-local). No C++ exception crosses this boundary.
+ *  - Pointers named d_* are device pointers (HIP global memory) owned by the
+ *    caller; all other pointers are host pointers, read during the call only.
+ *  - Device work is enqueued asynchronously on `hip_stream` (a hipStream_t;
+ *    NULL = the null stream). Results are ready once the stream is synchronised.
+ *  - A decode failure is not a call failure: it shows in d_pm (+infinity) and
+ *    d_flags, and the shot counts as a logical failure (Sec. III).
+ */
+#ifndef GDG_H
+#define GDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GDG_OK 0
+#define GDG_EINVAL (-22)   /* bad argument */
+#define GDG_ENOMEM (-12)   /* device allocation failed */
+#define GDG_EDEVICE (-5)   /* a HIP call failed */
+#define GDG_ESHAPE (-34)   /* the window exceeds a supported size */
+
+/* Flags per shot in gdg_decode_batch's d_flags. */
+#define GDG_FLAG_SATISFIED 1      /* some path met the window syndrome (Eq. 5 finite) */
+#define GDG_FLAG_CONTRADICTION 2  /* every path ended in a peeling contradiction */
+#define GDG_FLAG_EXHAUSTED 4      /* no path met the syndrome and one ran to D_max */
+#define GDG_FLAG_FALLBACK 8       /* the learned proposer's answer failed; plain GDG was used */
+
+/*
+ * Detector error model (Sec. II-B): the circuit-code parity-check matrix
+ * H_circ (n_rows detectors x n_cols fault columns) in CSC form, the logical
+ * observable matrix L (n_obs x n_cols, Sec. III) in CSC form, and each
+ * column's prior flip probability. Rows are grouped by detector round, w rows
+ * per round, n_rounds rounds; row indices within a column are ascending and no
+ * column touches more than two consecutive rounds (Sec. II-B). Host memory,
+ * read during gdg_build_window only.
+ */
+typedef struct gdg_dem {
+  int32_t n_rows, n_cols, n_obs, w, n_rounds;
+  const int32_t* h_ptr;  /* [n_cols+1] */
+  const int32_t* h_idx;  /* [h_ptr[n_cols]] detector rows */
+  const int32_t* l_ptr;  /* [n_cols+1] */
+  const int32_t* l_idx;  /* [l_ptr[n_cols]] observable indices */
+  const double* priors;  /* [n_cols], in (0, 1/2] */
+} gdg_dem;
+
+/* Decoder parameters (Sec. II-A, Sec. IV, Fig. 2, Alg. 1-3). */
+typedef struct gdg_params {
+  float alpha;              /* min-sum scaling factor (Sec. II-A): 1.0 circuit level, 0.625 C1 */
+  float clip;               /* VN-to-CN messages clipped to [-clip, clip] (Sec. IV-D): 50 */
+  int32_t iters_per_step;   /* BP iterations per decimation step (Fig. 2): 6, at least 4 */
+  int32_t pre_iters;        /* BP iterations on the whole window before ranking (Sec. IV-C); 0 = off */
+  int32_t trunc_factor;     /* keep the first trunc_factor * m ranked columns (Sec. III: 2) */
+  int32_t g;                /* guessing depth: paths 0..2^g-1 (Alg. 2); 0 = main path only */
+  int32_t dmax_main;        /* D_max of the main path (Fig. 2: 25) */
+  int32_t extra_steps;      /* steps after the split of non-main paths (Fig. 2: 10) */
+  int32_t side_max_depth;   /* extra side paths split at depths g+1..side_max_depth; 0 = none */
+  int32_t low_error;        /* 1 = low-error mode: Alg. 3 off (Sec. IV-A, p <= 0.002) */
+} gdg_params;
+
+typedef struct gdg_window gdg_window;
+
+/* Summary of a built window. */
+typedef struct gdg_window_info {
+  int32_t k, W, m, n;       /* window index, rounds, rows, columns (incl. merged unit columns) */
+  int32_t row0;             /* first DEM row of the window */
+  int32_t n_act;            /* columns GDG runs on after truncation */
+  int32_t n_paths;          /* decision paths per shot */
+  int32_t n_edges;          /* edges of the window graph */
+  int32_t max_sub_edges;    /* bound on edges of a truncated sub-graph */
+  int32_t n_commit;         /* committed columns */
+  int32_t last;             /* 1 for the final window (commits everything) */
+  int32_t lds_bytes;        /* LDS per workgroup of the decode kernel */
+  int32_t waves;            /* wavefronts per workgroup of the decode kernel */
+} gdg_window_info;
+
+/*
+ * Build window k of a (W,F) sliding window over `dem` (Sec. III, Eq. 6): the
+ * detector rows of rounds k..k+W-1 and the fault columns starting in them.
+ * Columns that reach past the window's last round (the bottom-right H_1
+ * block) are replaced by one unit column per last-round row they touch, with
+ * prior p_j = (1 - prod (1 - 2 p_c))/2 over the merged columns, product in DEM
+ * column order (Sec. III "merge ... to an identity matrix"). Window column
+ * order: kept DEM columns in DEM order, then unit columns by row. Committed
+ * columns: those starting in round k, or all of them in the final window
+ * (k + W == n_rounds). Only F = 1 is supported (GDG_EINVAL otherwise).
+ * Uploads the window graph to the current device; *out is owned by the caller
+ * and released with gdg_window_free. The window is immutable afterwards and
+ * may be used from several streams at once.
+ */
+int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F,
+                     const gdg_params* prm, gdg_window** out);
+void gdg_window_free(gdg_window* win);
+int gdg_window_get_info(const gdg_window* win, gdg_window_info* info);
+
+/* Host copies of the window's column table: src[n] = DEM column or -1-row for
+ * a unit column (row local to the window), llr[n] = log((1-p)/p) in double,
+ * commit[n] = 1 if committed. Any pointer may be NULL. */
+int gdg_window_columns(const gdg_window* win, int32_t* src, double* llr, uint8_t* commit);
+
+/* Bytes of device workspace gdg_decode_batch needs for n_shots shots. */
+size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots);
+
+/*
+ * Optional per-shot diagnostics of gdg_decode_batch (all device pointers,
+ * each may be NULL):
+ *  sel        [n_shots][n_act] int32: kept window columns in ranked order
+ *  dec        [n_shots][n_paths][log_cap][3] int32: per decimation step the
+ *             selected VN (ranked index), its value, and the number of Alg. 3
+ *             decimations at that step; -1 past the last step
+ *  ends       [n_shots][n_paths][2] int32: end reason (1 satisfied, 2 D_max,
+ *             3 contradiction, 4 no eligible VN) and steps taken
+ *  first_post [n_shots][n_act] float: main-path posteriors after its first
+ *             step (NaN for decimated VNs)
+ *  edge_iters [n_shots] int64: active edges summed over all BP iterations
+ *  step_lsum  [n_shots][n_paths][log_cap][n_act] float: each VN's sum of its
+ *             last four posteriors at the end of every step's BP run (the
+ *             Alg. 1 key), NaN for decimated VNs and unused steps
+ */
+typedef struct gdg_trace {
+  int32_t* sel;
+  int32_t* dec;
+  int32_t log_cap;
+  int32_t* ends;
+  float* first_post;
+  int64_t* edge_iters;
+  float* step_lsum;
+} gdg_trace;
+
+/*
+ * Decode n_shots window syndromes (Alg. 2 inside the window, Sec. III-IV):
+ * optional preprocessing BP on the whole window, ranking by the sum of the
+ * last four posteriors and truncation to trunc_factor*m columns (Sec. III,
+ * IV-C), peeling (Sec. IV-D), then every decision path of Fig. 2 (main, tree
+ * and side paths; min-sum BP in steps of iters_per_step flooding iterations,
+ * Alg. 1 selection with Alg. 3 unless low_error, Alg. 2 values), path metric
+ * Eq. 5 in double precision and the smallest path metric (ties: lowest path
+ * id); if no path meets the syndrome, the main path's final decision.
+ *   d_syndrome: uint8 0/1, shot s's row r at d_syndrome[s*syn_stride + r],
+ *               r < m (e.g. the DEM detector record offset by row0).
+ *   d_ehat:     [n_shots][n] uint8 output, the window correction.
+ *   d_pm:       [n_shots] double output, +inf when no path met the syndrome.
+ *   d_flags:    [n_shots] int32 output, GDG_FLAG_* bits.
+ *   d_workspace: >= gdg_workspace_bytes(win, n_shots) bytes of device memory.
+ *   trace:      NULL or diagnostics as above (host struct of device pointers).
+ */
+int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                     int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
+                     void* d_workspace, size_t workspace_bytes, const gdg_trace* trace,
+                     void* hip_stream);
+
+/*
+ * Commit (Eq. 7-8): for each shot, XOR the DEM columns of the committed window
+ * columns with d_ehat = 1 into the detector record (updating the next window's
+ * syndrome, s_2' = s_2 + H_2 e_1) and their observable effect into d_obs
+ * (Eq. 9's L e).
+ *   d_ehat:       [n_shots][n] uint8 from gdg_decode_batch.
+ *   d_detectors:  uint8, shot s's DEM row r at d_detectors[s*det_stride + r], in/out.
+ *   d_obs:        uint8, shot s's observable o at d_obs[s*obs_stride + o], in/out.
+ */
+int gdg_commit(const gdg_window* win, int32_t n_shots, const uint8_t* d_ehat,
+               uint8_t* d_detectors, int64_t det_stride, uint8_t* d_obs, int64_t obs_stride,
+               void* hip_stream);
+
+/*
+ * Plain flooding min-sum BP on the whole window, no decimation (Eqs. 1-4):
+ * n_iters iterations from fresh messages; d_post [n_shots][n_iters][n] float
+ * receives every iteration's posteriors (Eq. 2), d_first_ok [n_shots] int32
+ * the first iteration whose hard decision met the syndrome (0 = none).
+ * Checks the message-passing kernels on their own.
+ */
+int gdg_bp(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome, int64_t syn_stride,
+           int32_t n_iters, float* d_post, int32_t* d_first_ok, void* hip_stream);
+
+/*
+ * Device copy of a DEM for sampling and evaluation. gdg_dem_upload copies the
+ * CSC arrays, a CSR copy of H and uint32 sampling thresholds floor(p 2^32).
+ */
+typedef struct gdg_dem_dev gdg_dem_dev;
+int gdg_dem_upload(const gdg_dem* dem, gdg_dem_dev** out);
+void gdg_dem_free(gdg_dem_dev* d);
+
+/*
+ * Synthetic shots: column c of shot s fires iff word (c mod 4) of
+ * Philox4x32-10(counter = (c div 4, shot0 + s, stream, 0xC0DE),
+ * key = (seed low, seed high)) is below floor(p_c 2^32) (Salmon et al.,
+ * SC'11). Writes detectors H e [n_shots][n_rows] and observables L e
+ * [n_shots][n_obs] (uint8). Inputs for the decoder, not part of it.
+ */
+int gdg_sample(const gdg_dem_dev* d, int32_t n_shots, uint64_t seed, uint32_t stream,
+               uint64_t shot0, uint8_t* d_detectors, uint8_t* d_obs, void* hip_stream);
+
+/*
+ * Shot evaluation (Sec. III, Eq. 8 and Eq. 9): d_fail[s] = 1 unless every
+ * residual detector of shot s is 0 and its observable accumulator (true
+ * observables XOR the committed L e) is 0.
+ */
+int gdg_evaluate(int32_t n_shots, int32_t n_rows, int32_t n_obs, const uint8_t* d_detectors,
+                 const uint8_t* d_obs, uint8_t* d_fail, void* hip_stream);
+
+const char* gdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GDG_H */

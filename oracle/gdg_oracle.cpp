@@ -286,8 +286,17 @@ int sgn(double x) { return x < 0.0 ? -1 : 1; }   // sign(0) = +1 (irrelevant, se
 // single active neighbour has an empty min; it sends +clip (reading: peeling
 // keeps BP from ever seeing one). sign(0) = +1: a zero magnitude zeroes every
 // other outgoing message anyway.
-long long bp_iteration(const Graph& g, const Status& st, const orc_params& P, Messages& ms) {
+long long bp_iteration(const Graph& g, const Status& st, const orc_params& P, Messages& ms,
+                       double* cn_min_abs = nullptr) {
   long long active_edges = 0;
+  if (cn_min_abs)
+    for (int r = 0; r < g.m; ++r) {
+      // smallest incoming |VN-to-CN message| of each active CN (the sign-tie detector)
+      double mn = kInf;
+      for (size_t a = 0; a < g.row_cols[r].size(); ++a)
+        if (st.vn[g.row_cols[r][a]] < 0) mn = std::min(mn, std::fabs(ms.v2c[g.row_ptr[r] + a]));
+      cn_min_abs[r] = mn;
+    }
   for (int r = 0; r < g.m; ++r) {
     if (st.cdeg[r] == 0) continue;
     const auto& rc = g.row_cols[r];
@@ -792,9 +801,11 @@ void orc_window_export(void* h, uint8_t* dense, int* src, double* prior, double*
 }
 
 // Plain flooding BP on the whole window with no decimation: n_iters iterations,
-// posteriors after each one in post[t][n]. Returns the first iteration (1-based)
-// whose hard decision met the syndrome, or 0.
-int orc_window_bp(void* h, const orc_params* P, const uint8_t* syn, int n_iters, double* post) {
+// posteriors after each one in post[t][n]; optionally cn_min[t][m], the smallest
+// incoming |VN-to-CN message| of each CN at iteration t. Returns the first
+// iteration (1-based) whose hard decision met the syndrome, or 0.
+int orc_window_bp(void* h, const orc_params* P, const uint8_t* syn, int n_iters, double* post,
+                  double* cn_min) {
   const Window& w = ((OrcWindow*)h)->win;
   Graph g = window_graph(w);
   Status st = initial_status(g, syn);
@@ -802,7 +813,7 @@ int orc_window_bp(void* h, const orc_params* P, const uint8_t* syn, int n_iters,
   init_messages(g, *P, ms);
   int first_ok = 0;
   for (int t = 0; t < n_iters; ++t) {
-    bp_iteration(g, st, *P, ms);
+    bp_iteration(g, st, *P, ms, cn_min ? cn_min + (size_t)t * w.m : nullptr);
     std::memcpy(post + (size_t)t * w.n, ms.post.data(), sizeof(double) * w.n);
     if (!first_ok && syndrome_ok(g, st, ms, nullptr)) first_ok = t + 1;
   }
@@ -870,7 +881,10 @@ void orc_window_decode(void* h, const orc_params* P, int n_shots, const uint8_t*
 
 // Replay one path of one shot with the given kept-column set and decision
 // sequence forced (the oracle's own choice is still computed); returns the
-// oracle's preprocessing ranking keys and, per step, the oracle's own choice.
+// oracle's preprocessing ranking keys and, per step, the oracle's own choice,
+// every VN's Alg. 1 key (step_lsum[step][n_act], NaN when decimated), the
+// smallest |VN-to-CN message| and |posterior| seen during the step's BP run,
+// and the largest of the four history posteriors of both picks.
 // Used to measure how far another implementation's decisions are from the
 // oracle's at the first point they differ. Outputs: own_g/own_v/own_key/
 // forced_key per step (the Alg. 1 sums of the oracle's pick and of the forced
@@ -879,7 +893,9 @@ int orc_window_replay(void* h, const orc_params* P, const uint8_t* syn, const in
                       int path_id, const int* forced_g, const int* forced_v, int n_forced,
                       int* own_g, int* own_v, double* own_key, double* forced_key,
                       int* own_class, int* forced_class, double* lsum, uint8_t* e_out,
-                      double* pm_out) {
+                      double* pm_out, double* step_lsum, double* step_min_msg, int max_steps,
+                      double* own_hmax, double* forced_hmax, double* step_min_post,
+                      int* step_nagg, double* step_agg_margin, double* first_post) {
   const Window& w = ((OrcWindow*)h)->win;
   // Re-run the path step by step with forcing, recording both choices.
   Graph full = window_graph(w);
@@ -929,8 +945,14 @@ int orc_window_replay(void* h, const orc_params* P, const uint8_t* syn, const in
   for (int D = 1; D <= ps.dmax; ++D) {
     hh.reset(sub.n);
     bool ok = false;
+    double min_msg = kInf;
+    std::vector<double> cmin(sub.m);
+    double min_post = kInf;
     for (int t = 1; t <= P->iters_per_step; ++t) {
-      bp_iteration(sub, st, *P, ms);
+      bp_iteration(sub, st, *P, ms, cmin.data());
+      for (int r = 0; r < sub.m; ++r) min_msg = std::min(min_msg, cmin[r]);
+      for (int c = 0; c < sub.n; ++c)
+        if (st.vn[c] < 0) min_post = std::min(min_post, std::fabs(ms.post[c]));
       if (t > P->iters_per_step - 4)
         for (int c = 0; c < sub.n; ++c)
           if (st.vn[c] < 0) hh.add(c, ms.post[c]);
@@ -940,6 +962,17 @@ int orc_window_replay(void* h, const orc_params* P, const uint8_t* syn, const in
       }
     }
     steps = D;
+    if (D == 1 && first_post)
+      for (int c = 0; c < sub.n; ++c)
+        first_post[c] = st.vn[c] < 0 ? ms.post[c] : std::numeric_limits<double>::quiet_NaN();
+    if (D - 1 < max_steps) {
+      if (step_min_msg) step_min_msg[D - 1] = min_msg;
+      if (step_min_post) step_min_post[D - 1] = min_post;
+      if (step_lsum)
+        for (int c = 0; c < sub.n; ++c)
+          step_lsum[(size_t)(D - 1) * sub.n + c] =
+              (!ok && st.vn[c] < 0) ? hh.sum[c] : std::numeric_limits<double>::quiet_NaN();
+    }
     if (ok) {
       end = END_CONVERGED;
       break;
@@ -958,8 +991,27 @@ int orc_window_replay(void* h, const orc_params* P, const uint8_t* syn, const in
     std::vector<int> agg;
     int fav = 0;
     int sel = select_vn(st.vn, sub.deg, hh, P->low_error != 0, D, on_main, n_unsat, &agg, &fav);
+    int nagg = 0;
+    double margin = kInf;   // distance of the closest Alg. 3 comparison to its threshold
+    if (!P->low_error) {
+      const double PA = on_main ? -3.0 : 0.0;
+      const double PB = D == 1 ? -16.0 : (on_main ? -12.0 : -10.0);
+      for (int c = 0; c < sub.n; ++c) {
+        if (st.vn[c] != -1 || sub.deg[c] <= 2) continue;
+        margin = std::min(margin, std::min(std::fabs(hh.mx[c] - PA), std::fabs(hh.sum[c] - PB)));
+        if (D <= 4) margin = std::min(margin, std::fabs(hh.mn[c] - 30.0));
+        if (n_unsat[c] >= 3) margin = std::min(margin, std::fabs(hh.mn[c] - 3.0));
+      }
+    }
     for (int c = 0; c < sub.n; ++c)
-      if (agg[c] >= 0) decimate(sub, st, c, agg[c]);
+      if (agg[c] >= 0) {
+        decimate(sub, st, c, agg[c]);
+        ++nagg;
+      }
+    if (D - 1 < max_steps) {
+      if (step_nagg) step_nagg[D - 1] = nagg;
+      if (step_agg_margin) step_agg_margin[D - 1] = margin;
+    }
     if (sel < 0) {
       end = END_NO_CANDIDATE;
       break;
@@ -970,10 +1022,12 @@ int orc_window_replay(void* h, const orc_params* P, const uint8_t* syn, const in
     own_v[i] = val;
     own_key[i] = hh.sum[sel];
     own_class[i] = hh.mx[sel] <= 0.0;
+    if (own_hmax) own_hmax[i] = hh.mx[sel];
     if (i < n_forced) {
       int fg = forced_g[i];
       forced_key[i] = (fg >= 0 && fg < sub.n) ? hh.sum[fg] : kInf;
       forced_class[i] = (fg >= 0 && fg < sub.n) ? (hh.mx[fg] <= 0.0) : -1;
+      if (forced_hmax) forced_hmax[i] = (fg >= 0 && fg < sub.n) ? hh.mx[fg] : kInf;
       sel = fg;
       val = forced_v[i];
     }
@@ -1000,15 +1054,19 @@ int orc_window_replay(void* h, const orc_params* P, const uint8_t* syn, const in
 // observables (obs_out, so a logical error shows as a nonzero entry),
 // fail[s] = 1 unless all residual detectors are 0 (Eq. 8) and obs_out is 0
 // (Eq. 9), per-window flags win_flags[s][n_windows] and the committed
-// correction e_out[s][n_cols] over DEM columns (caller zeroes it).
+// correction e_out[s][n_cols] over DEM columns (caller zeroes it). With
+// max_windows >= 0 only the first max_windows windows are decoded (det_out is
+// then the residual record the next window sees).
 int orc_decode_shots(int n_rows, int n_cols, int n_obs, int w, int n_rounds, const int* h_ptr,
                      const int* h_idx, const int* l_ptr, const int* l_idx, const double* prior,
                      int W, const orc_params* P, int n_shots, const uint8_t* det,
                      const uint8_t* obs, uint8_t* det_out, uint8_t* obs_out, uint8_t* fail,
-                     int* win_flags, uint8_t* e_out, long long* edge_iters, int n_threads) {
+                     int* win_flags, uint8_t* e_out, long long* edge_iters, int n_threads,
+                     int max_windows) {
   Dem d = make_dem(n_rows, n_cols, n_obs, w, n_rounds, h_ptr, h_idx, l_ptr, l_idx, prior);
   int nwin = n_rounds - W + 1;
   if (nwin < 1) return -1;
+  const int run_windows = (max_windows >= 0 && max_windows < nwin) ? max_windows : nwin;
   std::vector<Window> wins(nwin);
   for (int k = 0; k < nwin; ++k)
     if (!build_window(d, k, W, wins[k])) return -2;
@@ -1020,7 +1078,7 @@ int orc_decode_shots(int n_rows, int n_cols, int n_obs, int w, int n_rounds, con
       if (s >= n_shots) break;
       std::vector<uint8_t> dd(det + (size_t)s * n_rows, det + (size_t)(s + 1) * n_rows);
       std::vector<uint8_t> oo(n_obs, 0);
-      for (int k = 0; k < nwin; ++k) {
+      for (int k = 0; k < run_windows; ++k) {
         const Window& wn = wins[k];
         WindowResult wr;
         decode_window(wn, *P, dd.data() + wn.row0, wr, nullptr, nullptr, nullptr, 0, -1);

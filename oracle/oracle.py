@@ -63,13 +63,13 @@ def lib():
         L.orc_window_free.argtypes = [P]
         L.orc_window_dims.argtypes = [P, P]
         L.orc_window_export.argtypes = [P] * 6
-        L.orc_window_bp.argtypes = [P, P, P, i32, P]
+        L.orc_window_bp.argtypes = [P, P, P, i32, P, P]
         L.orc_window_bp.restype = i32
         L.orc_window_decode.argtypes = [P, P, i32, P, P, P, P, P, P, i32, P, i32, i32, P, P,
                                         i32, i32]
-        L.orc_window_replay.argtypes = [P, P, P, P, i32, P, P, i32] + [P] * 9
+        L.orc_window_replay.argtypes = [P, P, P, P, i32, P, P, i32] + [P] * 11 + [i32, P, P, P, P, P, P]
         L.orc_window_replay.restype = i32
-        L.orc_decode_shots.argtypes = [i32] * 5 + [P] * 5 + [i32, P, i32] + [P] * 8 + [i32]
+        L.orc_decode_shots.argtypes = [i32] * 5 + [P] * 5 + [i32, P, i32] + [P] * 8 + [i32, i32]
         L.orc_decode_shots.restype = i32
         L.orc_select_vn.argtypes = [i32, P, P, P, P, i32, i32, i32, P, P]
         L.orc_select_vn.restype = i32
@@ -132,10 +132,13 @@ class OracleWindow:
         lib().orc_window_export(self.h, _p(dense), _p(src), _p(prior), _p(llr), _p(commit))
         return dict(H=dense, src=src, prior=prior, llr=llr, commit=commit)
 
-    def bp(self, prm, syn, n_iters):
+    def bp(self, prm, syn, n_iters, with_cn_min=False):
         syn = np.ascontiguousarray(syn, np.uint8)
         post = np.zeros((n_iters, self.n), np.float64)
-        first = lib().orc_window_bp(self.h, C.byref(prm), _p(syn), n_iters, _p(post))
+        cmin = np.zeros((n_iters, self.m), np.float64) if with_cn_min else None
+        first = lib().orc_window_bp(self.h, C.byref(prm), _p(syn), n_iters, _p(post), _p(cmin))
+        if with_cn_min:
+            return post, first, cmin
         return post, first
 
     def decode(self, prm, syn, n_threads=None, logs=False, log_cap=32):
@@ -180,16 +183,31 @@ class OracleWindow:
         lsum = np.zeros(self.n, np.float64)
         e = np.zeros(self.n, np.uint8)
         pm = np.zeros(1, np.float64)
+        n_sub = self.n if prm.pre_iters == 0 else min(self.n, prm.trunc_factor * self.m)
+        step_lsum = np.full((max_steps, n_sub), np.nan)
+        step_min = np.full(max_steps, np.nan)
+        own_hmax = np.full(max_steps, np.nan)
+        forced_hmax = np.full(max_steps, np.nan)
+        step_min_post = np.full(max_steps, np.nan)
+        step_nagg = np.full(max_steps, -1, np.int32)
+        step_agg_margin = np.full(max_steps, np.nan)
+        first_post = np.full(n_sub, np.nan)
         r = lib().orc_window_replay(self.h, C.byref(prm), _p(syn), _p(fs), path_id, _p(fg),
                                     _p(fv), len(fg), _p(own_g), _p(own_v), _p(own_key),
                                     _p(forced_key), _p(own_class), _p(forced_class), _p(lsum),
-                                    _p(e), _p(pm))
+                                    _p(e), _p(pm), _p(step_lsum), _p(step_min), max_steps,
+                                    _p(own_hmax), _p(forced_hmax), _p(step_min_post),
+                                    _p(step_nagg), _p(step_agg_margin), _p(first_post))
         return dict(code=r, steps=r // 8, end=r % 8, own_g=own_g, own_v=own_v,
                     own_key=own_key, forced_key=forced_key, own_class=own_class,
-                    forced_class=forced_class, lsum=lsum, e=e, pm=float(pm[0]))
+                    forced_class=forced_class, lsum=lsum, e=e, pm=float(pm[0]),
+                    step_lsum=step_lsum, step_min_msg=step_min, own_hmax=own_hmax,
+                    forced_hmax=forced_hmax, step_min_post=step_min_post,
+                    step_nagg=step_nagg, step_agg_margin=step_agg_margin,
+                    first_post=first_post)
 
 
-def decode_shots(dem, W, prm, det, obs, n_threads=None):
+def decode_shots(dem, W, prm, det, obs, n_threads=None, max_windows=-1):
     """Sliding-window decode of whole shots; returns dict(fail, det_out, obs_out,
     win_flags, e (committed correction over DEM columns), edge_iters)."""
     det = np.ascontiguousarray(det, np.uint8)
@@ -206,7 +224,7 @@ def decode_shots(dem, W, prm, det, obs, n_threads=None):
     r = lib().orc_decode_shots(dem.n_rows, dem.n_cols, dem.n_obs, dem.w, dem.n_rounds,
                                *[_p(a) for a in keep], W, C.byref(prm), ns, _p(det), _p(obs),
                                _p(det_out), _p(obs_out), _p(fail), _p(wf), _p(e_out), _p(ei),
-                               n_threads or default_threads())
+                               n_threads or default_threads(), max_windows)
     if r < 0:
         raise ValueError(f"orc_decode_shots failed: {r}")
     return dict(fail=fail, det_out=det_out, obs_out=obs_out, win_flags=wf, e=e_out,

@@ -1,0 +1,530 @@
+// Host side of the GDG decoder library: window construction (Sec. III, Eq. 6,
+// the H_1 -> identity merge), the device layout of the window's Tanner graph,
+// the decode kernel's LDS plan, and the extern "C" entry points of gdg.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "../../include/gdg.h"
+#include "gdg_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? GDG_ENOMEM : GDG_EDEVICE;
+}
+
+template <typename T>
+int upload(const std::vector<T>& v, T** d) {
+  *d = nullptr;
+  size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+  hipError_t e = hipMalloc((void**)d, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  if (!v.empty()) {
+    e = hipMemcpy(*d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  return GDG_OK;
+}
+
+int align16(int x) { return (x + 15) & ~15; }
+
+// Checks the DEM's CSC arrays: indices in range, rows ascending per column,
+// priors in (0, 1/2], no column spanning more than two consecutive rounds.
+int validate_dem(const gdg_dem* d) {
+  if (!d || d->n_rows <= 0 || d->n_cols <= 0 || d->n_obs < 0 || d->w <= 0 || d->n_rounds <= 0)
+    return fail(GDG_EINVAL, "dem: bad sizes");
+  if ((long long)d->w * d->n_rounds != d->n_rows) return fail(GDG_EINVAL, "dem: n_rows != w*n_rounds");
+  if (!d->h_ptr || !d->h_idx || !d->l_ptr || !d->priors || (d->l_ptr[d->n_cols] > 0 && !d->l_idx))
+    return fail(GDG_EINVAL, "dem: null array");
+  if (d->h_ptr[0] != 0 || d->l_ptr[0] != 0) return fail(GDG_EINVAL, "dem: pointers must start at 0");
+  for (int c = 0; c < d->n_cols; ++c) {
+    int a = d->h_ptr[c], b = d->h_ptr[c + 1];
+    if (b <= a) return fail(GDG_EINVAL, "dem: empty or decreasing column");
+    for (int e = a; e < b; ++e) {
+      int r = d->h_idx[e];
+      if (r < 0 || r >= d->n_rows) return fail(GDG_EINVAL, "dem: row index out of range");
+      if (e > a && r <= d->h_idx[e - 1]) return fail(GDG_EINVAL, "dem: rows not ascending");
+    }
+    if (d->h_idx[b - 1] / d->w - d->h_idx[a] / d->w > 1)
+      return fail(GDG_EINVAL, "dem: column spans more than two rounds");
+    if (d->l_ptr[c + 1] < d->l_ptr[c]) return fail(GDG_EINVAL, "dem: bad observable pointers");
+    for (int e = d->l_ptr[c]; e < d->l_ptr[c + 1]; ++e)
+      if (d->l_idx[e] < 0 || d->l_idx[e] >= d->n_obs)
+        return fail(GDG_EINVAL, "dem: observable index out of range");
+    double p = d->priors[c];
+    if (!(p > 0.0 && p <= 0.5)) return fail(GDG_EINVAL, "dem: prior outside (0, 1/2]");
+  }
+  return GDG_OK;
+}
+
+}  // namespace
+
+struct gdg_window {
+  gdg_window_info info{};
+  gdg_params prm{};
+  std::vector<int> src;
+  std::vector<double> llr64;
+  std::vector<uint8_t> commit;
+  gdg_win_dev dev{};
+  gdg_lds lds{};
+  gdg_commit_dev cm{};
+  int waves = 1;
+  std::vector<void*> allocs;
+
+  ~gdg_window() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  template <typename T>
+  int put(const std::vector<T>& v, const T** out) {
+    T* d = nullptr;
+    int rc = upload(v, &d);
+    if (d) allocs.push_back(d);
+    *out = d;
+    return rc;
+  }
+};
+
+struct gdg_dem_dev {
+  gdg_dem_dev_k k{};
+  std::vector<void*> allocs;
+  ~gdg_dem_dev() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+// LDS plan of the decode kernel for `waves` wavefronts per workgroup.
+gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
+  gdg_lds L{};
+  const int m = w.m, n = w.n, na = w.n_act, E = max_sub_edges, P = w.n_paths;
+  int off = 0;
+  auto take = [&](int bytes) {
+    int o = off;
+    off = align16(off + bytes);
+    return o;
+  };
+  L.pbits_words = (na + 31) / 32;
+  L.obits_words = (n + 31) / 32 + 1;
+  L.sorig = take(m);
+  L.sel = take(2 * na);
+  L.rptr = take(2 * (m + 1));
+  L.rvn = take(2 * E);
+  L.rcsc = take(2 * E);
+  L.cptr = take(2 * (na + 1));
+  L.crow = take(2 * E);
+  L.llr = take(4 * na);
+  L.deg = take(na);
+  L.ppm = take(8 * P);
+  L.pend = take(4 * P);
+  L.pbits = take(4 * P * L.pbits_words);
+  L.misc = take(16);
+  L.iscan = take(4 * (std::max(m, na) + 1));
+  L.obits = take(4 * L.obits_words);
+  L.eacc = take(8);
+  L.u_base = off;
+  // preprocessing region
+  int prep = 0;
+  L.sort_n = 1;
+  while (L.sort_n < n) L.sort_n <<= 1;
+  if (w.pre_iters > 0) {
+    int po = 0;
+    auto ptake = [&](int bytes) {
+      int o = po;
+      po = align16(po + bytes);
+      return o;
+    };
+    L.p_post = ptake(4 * n);
+    const int c2v_bytes = std::max(4 * w.e_full, 8 * L.sort_n);
+    L.p_c2v = ptake(c2v_bytes);
+    L.p_keys = L.p_c2v;   // the sort keys reuse the message array
+    L.p_lsum = ptake(4 * n);
+    prep = po;
+  }
+  L.p_loc = 0;   // written after the preprocessing region is dead
+  const int loc_bytes = align16(2 * n);
+  // per-wavefront path region
+  int wo = 0;
+  auto wtake = [&](int bytes) {
+    int o = wo;
+    wo = align16(wo + bytes);
+    return o;
+  };
+  L.w_post = wtake(4 * na);
+  L.w_status = wtake(na);
+  L.w_c2v = wtake(4 * E);
+  L.w_unsat = wtake(m);
+  L.w_prop = wtake(4 * ((na + 3) / 4));
+  L.w_bits = wtake(4 * L.obits_words);
+  L.w_stride = wo;
+  const int uni = std::max(std::max(prep, loc_bytes), waves * L.w_stride);
+  L.total = L.u_base + uni;
+  return L;
+}
+
+int max_lds_per_block() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 65536;
+  return v > 0 ? v : 65536;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gdg_last_error(void) { return g_err.c_str(); }
+
+int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const gdg_params* prm,
+                     gdg_window** out) {
+  if (!out || !prm) return fail(GDG_EINVAL, "null argument");
+  *out = nullptr;
+  int rc = validate_dem(dem);
+  if (rc) return rc;
+  if (F != 1) return fail(GDG_EINVAL, "only F = 1 windows are supported");
+  if (W < 1 || k < 0 || k + W > dem->n_rounds) return fail(GDG_EINVAL, "window out of range");
+  if (prm->iters_per_step < 4) return fail(GDG_EINVAL, "iters_per_step must be >= 4");
+  if (prm->g < 0 || prm->g > 5) return fail(GDG_EINVAL, "g must be in 0..5");
+  if (prm->dmax_main < 1 || prm->extra_steps < 0 || prm->pre_iters < 0 || prm->trunc_factor < 1)
+    return fail(GDG_EINVAL, "bad step limits");
+  if (!(prm->clip > 0.0f) || !(prm->alpha > 0.0f)) return fail(GDG_EINVAL, "bad alpha/clip");
+
+  const int w = dem->w;
+  const int row0 = k * w, m = W * w, last_round = k + W - 1;
+  const bool last = (k + W == dem->n_rounds);
+  std::unique_ptr<gdg_window> win(new gdg_window());
+  win->prm = *prm;
+  // window columns: DEM columns starting inside, not reaching past; then unit columns
+  std::vector<std::vector<int>> col_rows;
+  std::vector<double> prior;
+  std::vector<double> keep(m, 1.0);
+  std::vector<char> touched(m, 0);
+  for (int c = 0; c < dem->n_cols; ++c) {
+    const int a = dem->h_ptr[c], b = dem->h_ptr[c + 1];
+    const int fr = dem->h_idx[a] / w, lr = dem->h_idx[b - 1] / w;
+    if (fr < k || fr > last_round) continue;
+    if (lr > last_round) {
+      for (int e = a; e < b; ++e) {
+        const int r = dem->h_idx[e];
+        if (r / w != last_round) continue;
+        keep[r - row0] *= (1.0 - 2.0 * dem->priors[c]);
+        touched[r - row0] = 1;
+      }
+      continue;
+    }
+    std::vector<int> rows;
+    for (int e = a; e < b; ++e) rows.push_back(dem->h_idx[e] - row0);
+    col_rows.push_back(rows);
+    prior.push_back(dem->priors[c]);
+    win->src.push_back(c);
+    win->commit.push_back((uint8_t)(last || fr == k));
+  }
+  for (int r = 0; r < m; ++r) {
+    if (!touched[r]) continue;
+    col_rows.push_back(std::vector<int>{r});
+    prior.push_back(0.5 * (1.0 - keep[r]));
+    win->src.push_back(-1 - r);
+    win->commit.push_back(0);
+  }
+  const int n = (int)col_rows.size();
+  if (n == 0) return fail(GDG_EINVAL, "empty window");
+  if (n > 65535 || m > 512) return fail(GDG_ESHAPE, "window too large");
+  win->llr64.resize(n);
+  for (int c = 0; c < n; ++c) win->llr64[c] = std::log((1.0 - prior[c]) / prior[c]);
+
+  // CSC and CSR
+  std::vector<int> col_ptr(n + 1, 0);
+  for (int c = 0; c < n; ++c) col_ptr[c + 1] = col_ptr[c] + (int)col_rows[c].size();
+  const int E = col_ptr[n];
+  if (E > 1 << 24) return fail(GDG_ESHAPE, "too many edges");
+  std::vector<std::vector<std::pair<int, int>>> rows(m);   // (column, position in column)
+  for (int c = 0; c < n; ++c)
+    for (size_t t = 0; t < col_rows[c].size(); ++t) rows[col_rows[c][t]].push_back({c, (int)t});
+  std::vector<int> row_ptr(m + 1, 0);
+  std::vector<uint16_t> row_col;
+  std::vector<uint8_t> row_kcol, deg(n);
+  int max_row = 0;
+  for (int r = 0; r < m; ++r) {
+    row_ptr[r + 1] = row_ptr[r] + (int)rows[r].size();
+    max_row = std::max(max_row, (int)rows[r].size());
+    for (auto& pr : rows[r]) {
+      row_col.push_back((uint16_t)pr.first);
+      row_kcol.push_back((uint8_t)pr.second);
+    }
+  }
+  if (max_row > 64) return fail(GDG_ESHAPE, "a window row has more than 64 columns");
+  int max_col = 0;
+  for (int c = 0; c < n; ++c) {
+    deg[c] = (uint8_t)col_rows[c].size();
+    max_col = std::max(max_col, (int)col_rows[c].size());
+  }
+  if (max_col > 255) return fail(GDG_ESHAPE, "column degree above 255");
+  std::vector<float> llr(n);
+  for (int c = 0; c < n; ++c) llr[c] = (float)win->llr64[c];
+
+  const int n_act = prm->pre_iters > 0 ? std::min(n, prm->trunc_factor * m) : n;
+  std::vector<int> degs(deg.begin(), deg.end());
+  std::sort(degs.begin(), degs.end(), std::greater<int>());
+  int max_sub = 0;
+  for (int i = 0; i < n_act; ++i) max_sub += degs[i];
+  if (max_sub > 65535 || n_act > 1024) return fail(GDG_ESHAPE, "truncated graph too large");
+  int n_paths = prm->g > 0 ? (1 << prm->g) : 1;
+  if (prm->g > 0 && prm->side_max_depth > prm->g) n_paths += prm->side_max_depth - prm->g;
+
+  gdg_win_dev& D = win->dev;
+  D.m = m;
+  D.n = n;
+  D.n_act = n_act;
+  D.e_full = E;
+  D.n_paths = n_paths;
+  D.g = prm->g;
+  D.dmax_main = prm->dmax_main;
+  D.extra = prm->extra_steps;
+  D.side_max_depth = prm->side_max_depth;
+  D.low_error = prm->low_error ? 1 : 0;
+  D.iters = prm->iters_per_step;
+  D.pre_iters = prm->pre_iters;
+  D.alpha = prm->alpha;
+  D.clip = prm->clip;
+  if ((rc = win->put(row_ptr, &D.row_ptr))) return rc;
+  if ((rc = win->put(row_col, &D.row_col))) return rc;
+  if ((rc = win->put(row_kcol, &D.row_kcol))) return rc;
+  if ((rc = win->put(col_ptr, &D.col_ptr))) return rc;
+  if ((rc = win->put(llr, &D.llr))) return rc;
+  if ((rc = win->put(win->llr64, &D.llr64))) return rc;
+  if ((rc = win->put(deg, &D.deg))) return rc;
+
+  // commit tables
+  std::vector<std::vector<int>> by_row(dem->n_rows);
+  std::vector<std::vector<int>> by_obs(dem->n_obs);
+  int n_commit = 0;
+  for (int c = 0; c < n; ++c) {
+    if (!win->commit[c]) continue;
+    ++n_commit;
+    const int dc = win->src[c];
+    for (int e = dem->h_ptr[dc]; e < dem->h_ptr[dc + 1]; ++e) by_row[dem->h_idx[e]].push_back(c);
+    for (int e = dem->l_ptr[dc]; e < dem->l_ptr[dc + 1]; ++e) by_obs[dem->l_idx[e]].push_back(c);
+  }
+  std::vector<int> rg, rp(1, 0), rc_, op(1, 0), oc;
+  for (int r = 0; r < dem->n_rows; ++r) {
+    if (by_row[r].empty()) continue;
+    rg.push_back(r);
+    rc_.insert(rc_.end(), by_row[r].begin(), by_row[r].end());
+    rp.push_back((int)rc_.size());
+  }
+  for (int o = 0; o < dem->n_obs; ++o) {
+    oc.insert(oc.end(), by_obs[o].begin(), by_obs[o].end());
+    op.push_back((int)oc.size());
+  }
+  win->cm.n_rows = (int)rg.size();
+  win->cm.n_obs = dem->n_obs;
+  win->cm.n_win = n;
+  if ((rc = win->put(rg, &win->cm.row_global))) return rc;
+  if ((rc = win->put(rp, &win->cm.row_ptr))) return rc;
+  if ((rc = win->put(rc_, &win->cm.row_col))) return rc;
+  if ((rc = win->put(op, &win->cm.obs_ptr))) return rc;
+  if ((rc = win->put(oc, &win->cm.obs_col))) return rc;
+
+  // LDS plan: as many wavefronts as paths (at most 8), at least 4 when the
+  // whole-window preprocessing runs, within the per-workgroup LDS limit.
+  const int limit = max_lds_per_block();
+  int waves = std::min(8, n_paths);
+  if (prm->pre_iters > 0) waves = std::max(waves, 4);
+  if (const char* env = getenv("GDG_WAVES")) {
+    int v = atoi(env);
+    if (v >= 1 && v <= 16) waves = v;
+  }
+  gdg_lds L = plan_lds(D, max_sub, waves);
+  while (L.total > limit && waves > 1) {
+    waves /= 2;
+    L = plan_lds(D, max_sub, waves);
+  }
+  if (L.total > limit) return fail(GDG_ESHAPE, "window does not fit in LDS");
+  if (L.total > 65536) {
+    hipError_t e = gdg_decode_set_lds_limit(D, L.total);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  }
+  win->lds = L;
+  win->waves = waves;
+
+  gdg_window_info& I = win->info;
+  I.k = k;
+  I.W = W;
+  I.m = m;
+  I.n = n;
+  I.row0 = row0;
+  I.n_act = n_act;
+  I.n_paths = n_paths;
+  I.n_edges = E;
+  I.max_sub_edges = max_sub;
+  I.n_commit = n_commit;
+  I.last = last ? 1 : 0;
+  I.lds_bytes = L.total;
+  I.waves = waves;
+  *out = win.release();
+  return GDG_OK;
+}
+
+void gdg_window_free(gdg_window* win) { delete win; }
+
+int gdg_window_get_info(const gdg_window* win, gdg_window_info* info) {
+  if (!win || !info) return fail(GDG_EINVAL, "null argument");
+  *info = win->info;
+  return GDG_OK;
+}
+
+int gdg_window_columns(const gdg_window* win, int32_t* src, double* llr, uint8_t* commit) {
+  if (!win) return fail(GDG_EINVAL, "null window");
+  const int n = win->info.n;
+  for (int c = 0; c < n; ++c) {
+    if (src) src[c] = win->src[c];
+    if (llr) llr[c] = win->llr64[c];
+    if (commit) commit[c] = win->commit[c];
+  }
+  return GDG_OK;
+}
+
+size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots) {
+  (void)win;
+  (void)n_shots;
+  return 0;   // the decode kernel keeps all of its state in LDS
+}
+
+int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                     int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
+                     void* d_workspace, size_t workspace_bytes, const gdg_trace* trace,
+                     void* hip_stream) {
+  (void)d_workspace;
+  (void)workspace_bytes;
+  if (!win) return fail(GDG_EINVAL, "null window");
+  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+  if (n_shots == 0) return GDG_OK;
+  if (!d_syndrome || !d_ehat || !d_pm || !d_flags) return fail(GDG_EINVAL, "null buffer");
+  if (syn_stride < win->info.m) return fail(GDG_EINVAL, "syn_stride < m");
+  gdg_trace_dev tr{};
+  if (trace) {
+    tr.sel = trace->sel;
+    tr.dec = trace->dec;
+    tr.log_cap = trace->log_cap;
+    tr.ends = trace->ends;
+    tr.first_post = trace->first_post;
+    tr.edge_iters = (long long*)trace->edge_iters;
+    tr.step_lsum = trace->step_lsum;
+    if (tr.dec && tr.log_cap <= 0) return fail(GDG_EINVAL, "trace log_cap must be positive");
+  }
+  hipError_t e = gdg_launch_decode(win->dev, win->lds, win->waves, n_shots, d_syndrome,
+                                   syn_stride, d_ehat, d_pm, d_flags, tr,
+                                   (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "decode launch");
+  return GDG_OK;
+}
+
+int gdg_commit(const gdg_window* win, int32_t n_shots, const uint8_t* d_ehat,
+               uint8_t* d_detectors, int64_t det_stride, uint8_t* d_obs, int64_t obs_stride,
+               void* hip_stream) {
+  if (!win) return fail(GDG_EINVAL, "null window");
+  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+  if (n_shots == 0) return GDG_OK;
+  if (!d_ehat || !d_detectors || (!d_obs && win->cm.n_obs > 0))
+    return fail(GDG_EINVAL, "null buffer");
+  hipError_t e = gdg_launch_commit(win->cm, n_shots, d_ehat, d_detectors, det_stride, d_obs,
+                                   obs_stride, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "commit launch");
+  return GDG_OK;
+}
+
+int gdg_bp(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome, int64_t syn_stride,
+           int32_t n_iters, float* d_post, int32_t* d_first_ok, void* hip_stream) {
+  if (!win) return fail(GDG_EINVAL, "null window");
+  if (n_shots < 0 || n_iters < 1) return fail(GDG_EINVAL, "bad sizes");
+  if (n_shots == 0) return GDG_OK;
+  if (!d_syndrome || !d_post || !d_first_ok) return fail(GDG_EINVAL, "null buffer");
+  if (syn_stride < win->info.m) return fail(GDG_EINVAL, "syn_stride < m");
+  const size_t lds = (size_t)((win->dev.m + 15) & ~15) + 4 * (size_t)((win->dev.n + 3) & ~3) +
+                     4 * (size_t)win->dev.e_full;
+  if (lds > (size_t)max_lds_per_block()) return fail(GDG_ESHAPE, "window does not fit in LDS");
+  hipError_t e = gdg_launch_bp(win->dev, n_shots, d_syndrome, syn_stride, n_iters, d_post,
+                               d_first_ok, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "bp launch");
+  return GDG_OK;
+}
+
+int gdg_dem_upload(const gdg_dem* dem, gdg_dem_dev** out) {
+  if (!out) return fail(GDG_EINVAL, "null argument");
+  *out = nullptr;
+  int rc = validate_dem(dem);
+  if (rc) return rc;
+  std::unique_ptr<gdg_dem_dev> d(new gdg_dem_dev());
+  const int nc = dem->n_cols;
+  std::vector<int> hp(dem->h_ptr, dem->h_ptr + nc + 1), hi(dem->h_idx, dem->h_idx + dem->h_ptr[nc]);
+  std::vector<int> lp(dem->l_ptr, dem->l_ptr + nc + 1), li(dem->l_idx, dem->l_idx + dem->l_ptr[nc]);
+  std::vector<uint32_t> thr(nc);
+  for (int c = 0; c < nc; ++c) {
+    double t = std::floor(dem->priors[c] * 4294967296.0);
+    thr[c] = t >= 4294967295.0 ? 4294967295u : (uint32_t)t;
+  }
+  auto put = [&](auto& v, auto** p) {
+    using T = typename std::remove_reference<decltype(v)>::type::value_type;
+    T* dp = nullptr;
+    int r = upload(v, &dp);
+    if (dp) d->allocs.push_back(dp);
+    *p = dp;
+    return r;
+  };
+  d->k.n_rows = dem->n_rows;
+  d->k.n_cols = nc;
+  d->k.n_obs = dem->n_obs;
+  if ((rc = put(hp, &d->k.h_ptr))) return rc;
+  if ((rc = put(hi, &d->k.h_idx))) return rc;
+  if ((rc = put(lp, &d->k.l_ptr))) return rc;
+  if ((rc = put(li, &d->k.l_idx))) return rc;
+  if ((rc = put(thr, &d->k.thr))) return rc;
+  *out = d.release();
+  return GDG_OK;
+}
+
+void gdg_dem_free(gdg_dem_dev* d) { delete d; }
+
+int gdg_sample(const gdg_dem_dev* d, int32_t n_shots, uint64_t seed, uint32_t stream,
+               uint64_t shot0, uint8_t* d_detectors, uint8_t* d_obs, void* hip_stream) {
+  if (!d) return fail(GDG_EINVAL, "null dem");
+  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+  if (n_shots == 0) return GDG_OK;
+  if (!d_detectors || (!d_obs && d->k.n_obs > 0)) return fail(GDG_EINVAL, "null buffer");
+  hipError_t e = gdg_launch_sample(d->k, n_shots, seed, stream, shot0, d_detectors, d_obs,
+                                   (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "sample launch");
+  return GDG_OK;
+}
+
+int gdg_evaluate(int32_t n_shots, int32_t n_rows, int32_t n_obs, const uint8_t* d_detectors,
+                 const uint8_t* d_obs, uint8_t* d_fail, void* hip_stream) {
+  if (n_shots < 0 || n_rows < 0 || n_obs < 0) return fail(GDG_EINVAL, "bad sizes");
+  if (n_shots == 0) return GDG_OK;
+  if (!d_detectors || !d_fail || (!d_obs && n_obs > 0)) return fail(GDG_EINVAL, "null buffer");
+  hipError_t e = gdg_launch_evaluate(n_shots, n_rows, n_obs, d_detectors, d_obs, d_fail,
+                                     (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "evaluate launch");
+  return GDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Internal interface between the host side (gdg_host.cpp) and the kernels
+// (gdg_kernels.hip). Plain structs of device pointers and sizes, passed by
+// value to the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Window graph on the device plus decoder parameters.
+struct gdg_win_dev {
+  int m, n, n_act, e_full, n_paths;
+  int g, dmax_main, extra, side_max_depth, low_error, iters, pre_iters;
+  float alpha, clip;
+  const int* row_ptr;       // [m+1] window CSR
+  const uint16_t* row_col;  // [e_full] column of each CSR edge (ascending per row)
+  const uint8_t* row_kcol;  // [e_full] position of that edge in its column's CSC list
+  const int* col_ptr;       // [n+1] window CSC
+  const float* llr;         // [n] prior LLR rounded to float
+  const double* llr64;      // [n] prior LLR in double (path metric, Eq. 5)
+  const uint8_t* deg;       // [n] column degree
+};
+
+// Byte offsets of the decode kernel's dynamic LDS regions.
+struct gdg_lds {
+  int total;
+  // per shot
+  int sorig, sel, rptr, rvn, rcsc, cptr, crow, llr, deg, ppm, pend, pbits, misc, iscan, obits, eacc;
+  int pbits_words, obits_words;
+  // phase union (relative to u_base)
+  int u_base;
+  int p_post, p_c2v, p_lsum, p_keys, p_loc, sort_n;
+  int w_stride, w_post, w_status, w_c2v, w_unsat, w_prop, w_bits;
+};
+
+struct gdg_trace_dev {
+  int* sel;
+  int* dec;
+  int log_cap;
+  int* ends;
+  float* first_post;
+  long long* edge_iters;
+  float* step_lsum;
+};
+
+// Commit tables: affected DEM rows with the committed window columns touching
+// each (CSR), and per observable the committed window columns in its L row.
+struct gdg_commit_dev {
+  int n_rows, n_obs, n_win;
+  const int* row_global;  // [n_rows] DEM row index
+  const int* row_ptr;     // [n_rows+1]
+  const int* row_col;     // window columns
+  const int* obs_ptr;     // [n_obs+1]
+  const int* obs_col;
+};
+
+struct gdg_dem_dev_k {
+  int n_rows, n_cols, n_obs;
+  const int* h_ptr;
+  const int* h_idx;
+  const int* l_ptr;
+  const int* l_idx;
+  const uint32_t* thr;
+};
+
+hipError_t gdg_launch_decode(const gdg_win_dev& w, const gdg_lds& L, int waves, int n_shots,
+                             const uint8_t* syn, long long syn_stride, uint8_t* ehat, double* pm,
+                             int* flags, const gdg_trace_dev& tr, hipStream_t st);
+hipError_t gdg_decode_set_lds_limit(const gdg_win_dev& w, int bytes);
+hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, long long stride,
+                         int n_iters, float* post, int* first_ok, hipStream_t st);
+hipError_t gdg_launch_commit(const gdg_commit_dev& cm, int n_shots, const uint8_t* ehat,
+                             uint8_t* det, long long det_stride, uint8_t* obs,
+                             long long obs_stride, hipStream_t st);
+hipError_t gdg_launch_sample(const gdg_dem_dev_k& d, int n_shots, uint64_t seed, uint32_t stream,
+                             uint64_t shot0, uint8_t* det, uint8_t* obs, hipStream_t st);
+hipError_t gdg_launch_evaluate(int n_shots, int n_rows, int n_obs, const uint8_t* det,
+                               const uint8_t* obs, uint8_t* fail, hipStream_t st);

@@ -1,0 +1,1110 @@
+// HIP kernels (gfx950 / CDNA4) of the sliding-window GDG decoder
+// (arXiv 2403.18901): min-sum belief propagation with guided decimation,
+// peeling and guessing, for many shots at once.
+//
+// Mapping. One workgroup decodes one shot's window. All of its wavefronts
+// first run the preprocessing BP on the whole window together, rank and
+// truncate the columns (Sec. III, Sec. IV-C) and build the shot's truncated
+// Tanner graph in LDS. Each wavefront then runs whole decision paths of Fig. 2,
+// one at a time, taking the next path id from an LDS counter, so the long main
+// path starts first. A path's BP messages live in LDS and registers:
+//   * check node (CN) state lives in the registers of the lane that owns the
+//     CN: two smallest magnitudes, position of the smallest, the sign bits of
+//     the incoming messages and their parity (two-min + sign parity, Eq. 1);
+//   * the CN phase gathers posteriors from LDS, forms each extrinsic VN-to-CN
+//     message (Eq. 3) from the posterior and the CN's previous outgoing message,
+//     clips it, and writes the new CN-to-VN messages to an LDS array laid out
+//     by column, so the VN phase sums contiguous entries (Eq. 2);
+//   * the syndrome check of the previous iteration's hard decisions (Eq. 4) is
+//     folded into the CN phase;
+//   * Alg. 1 is a wavefront min-reduction of 64-bit keys (order-preserving
+//     float bits << 32 | VN index), Alg. 3 and peeling are lane-parallel passes
+//     with wavefront ballots.
+// Decimated VNs keep NaN in the posterior array, which is how CNs skip their
+// stale messages (Sec. II-A). No matrix cores: the work is sparse gathers.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gdg_kernels.h"
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr float kInfF = __builtin_huge_valf();
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+__device__ __forceinline__ uint32_t ord_f32(float x) {
+  if (x == 0.0f) x = 0.0f;   // -0 and +0 compare equal
+  uint32_t b = __float_as_uint(x);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long u = __shfl_xor(v, o, kWave);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ float clampf(float x, float c) { return fminf(fmaxf(x, -c), c); }
+
+// Exclusive prefix sum in place over a[0..len) (int32 in LDS) by wavefront 0;
+// a[len] receives the total. Caller synchronises the workgroup around it.
+__device__ void wg_exclusive_scan_wave0(int* a, int len) {
+  int lane = threadIdx.x & (kWave - 1);
+  if ((threadIdx.x >> 6) != 0) return;
+  int carry = 0;
+  for (int base = 0; base < len; base += kWave) {
+    int i = base + lane;
+    int x = i < len ? a[i] : 0;
+    int inc = wave_incl_scan(x, lane);
+    if (i < len) a[i] = carry + inc - x;
+    carry += __shfl(inc, kWave - 1, kWave);
+  }
+  if (lane == 0) a[len] = carry;
+}
+
+// ------------------------------------------------------------------ whole-window BP
+//
+// Workgroup-cooperative flooding min-sum on the full window graph (used for
+// the preprocessing BP and for gdg_bp). CN-to-VN messages are kept per edge in
+// column order (c2v[col_ptr[c] + t] is the message on column c's t-th edge).
+
+struct FullBP {
+  const gdg_win_dev* w;
+  float* post;          // [n]
+  float* c2v;           // [E]
+  const uint8_t* syn;   // [m] in LDS
+};
+
+// CN phase: new messages from the posteriors and the previous messages; returns
+// this thread's OR of "row j unsatisfied by the hard decisions of post".
+__device__ int full_cn_phase(const FullBP& b) {
+  const gdg_win_dev& w = *b.w;
+  int bad = 0;
+  for (int j = threadIdx.x; j < w.m; j += blockDim.x) {
+    const int e0 = w.row_ptr[j], e1 = w.row_ptr[j + 1];
+    float n1 = kInfF, n2 = kInfF;
+    int nidx = 0, npar = b.syn[j], hx = b.syn[j];
+    unsigned long long nmask = 0ull;
+    for (int e = e0; e < e1; ++e) {
+      const int c = w.row_col[e];
+      const int slot = w.col_ptr[c] + w.row_kcol[e];
+      const float pv = b.post[c];
+      hx ^= (pv <= 0.0f);
+      const float x = clampf(pv - b.c2v[slot], w.clip);
+      const float a = fabsf(x);
+      const int neg = x < 0.0f;
+      const int k = e - e0;
+      nmask |= (unsigned long long)neg << k;
+      npar ^= neg;
+      if (a < n1) {
+        n2 = n1;
+        n1 = a;
+        nidx = k;
+      } else if (a < n2) {
+        n2 = a;
+      }
+    }
+    const float m2 = n2 == kInfF ? w.clip : n2;
+    const float m1 = n1 == kInfF ? w.clip : n1;
+    for (int e = e0; e < e1; ++e) {
+      const int k = e - e0;
+      const int c = w.row_col[e];
+      const int slot = w.col_ptr[c] + w.row_kcol[e];
+      float v = w.alpha * (k == nidx ? m2 : m1);
+      if ((npar ^ (int)(nmask >> k)) & 1) v = -v;
+      b.c2v[slot] = v;
+    }
+    bad |= hx;
+  }
+  return bad;
+}
+
+// VN phase: posterior = prior + sum of incoming messages (Eq. 2), in column
+// edge order. Optional running sum of posteriors into lsum.
+__device__ void full_vn_phase(const FullBP& b, float* lsum) {
+  const gdg_win_dev& w = *b.w;
+  for (int c = threadIdx.x; c < w.n; c += blockDim.x) {
+    float s = w.llr[c];
+    for (int e = w.col_ptr[c]; e < w.col_ptr[c + 1]; ++e) s += b.c2v[e];
+    b.post[c] = s;
+    if (lsum) lsum[c] += s;
+  }
+}
+
+__device__ int full_check(const FullBP& b) {
+  const gdg_win_dev& w = *b.w;
+  int bad = 0;
+  for (int j = threadIdx.x; j < w.m; j += blockDim.x) {
+    int hx = b.syn[j];
+    for (int e = w.row_ptr[j]; e < w.row_ptr[j + 1]; ++e) hx ^= (b.post[w.row_col[e]] <= 0.0f);
+    bad |= hx;
+  }
+  return bad;
+}
+
+// ------------------------------------------------------------------ decode kernel
+
+struct PathRegs {
+  int pid, dmax, split;
+};
+
+__device__ __forceinline__ int path_value(const gdg_win_dev& w, int pid, int split, int D, int f) {
+  if (pid == 0) return f;
+  if (w.g > 0 && pid < (1 << w.g)) {
+    if (D > w.g) return f;
+    return ((pid >> (w.g - D)) & 1) ? 1 - f : f;
+  }
+  return D == split ? 1 - f : f;
+}
+
+__device__ __forceinline__ bool path_on_main(const gdg_win_dev& w, int pid, int split, int D) {
+  if (pid == 0) return true;
+  if (w.g > 0 && pid < (1 << w.g)) {
+    int taken = D - 1 < w.g ? D - 1 : w.g;
+    if (taken <= 0) return true;
+    return (pid >> (w.g - taken)) == 0;
+  }
+  return D <= split;
+}
+
+// Alg. 3 for one VN: history sum / min / max over the last four posteriors.
+__device__ __forceinline__ int agg_dec(float hsum, float hmin, float hmax, int D, bool on_main,
+                                       int n_unsat) {
+  const float PA = on_main ? -3.0f : 0.0f;
+  float PB = on_main ? -12.0f : -10.0f;
+  if (D == 1) PB = -16.0f;
+  if (hmax < PA && hsum < PB) return 1;
+  if ((hmin > 30.0f && D <= 4) || (hmin > 3.0f && n_unsat >= 3)) return 0;
+  return -1;
+}
+
+enum { END_CONVERGED = 1, END_EXHAUSTED = 2, END_CONTRADICTION = 3, END_NO_CANDIDATE = 4 };
+
+template <int CPL, int VPL>
+struct PathCtx {
+  // shared (per shot) sub-graph in LDS
+  const uint16_t* rptr;   // [m+1]
+  const uint16_t* rvn;    // [E_sub] VN of each CSR edge
+  const uint16_t* rcsc;   // [E_sub] column-order slot of each CSR edge
+  const uint16_t* cptr;   // [n_act+1]
+  const uint16_t* crow;   // [E_sub] row of each column-order slot
+  const float* llr;       // [n_act]
+  const uint8_t* deg;     // [n_act]
+  const uint8_t* sorig;   // [m]
+  // per wavefront
+  float* post;            // [n_act] NaN = decimated
+  int8_t* status;         // [n_act] -1 active, 0/1 decimated
+  float* c2v;             // [E_sub]
+  uint8_t* unsat;         // [m]
+  uint32_t* prop;         // [ceil(n_act/4)] peeling proposals, one byte per VN
+  int lane;
+  int m, n;
+  // CN registers (CN j = lane + 64 q)
+  float m1[CPL], m2[CPL];
+  int idx[CPL], par[CPL], cdeg[CPL], sres[CPL];
+  unsigned long long mask[CPL];
+  // VN registers (VN v = lane + 64 r): history over the last four iterations
+  float hs[VPL], hmn[VPL], hmx[VPL];
+};
+
+// Recount every owned CN's active degree and residual syndrome from the VN
+// status, find dead CNs (no active VN, residual 1) and post peeling proposals
+// of degree-one CNs (Sec. IV-D, Appendix C).
+template <int CPL, int VPL>
+__device__ void cn_recount(PathCtx<CPL, VPL>& P, bool& dead, bool& proposed) {
+  dead = false;
+  proposed = false;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int j = P.lane + kWave * q;
+    if (j < P.m) {
+      const int e0 = P.rptr[j], e1 = P.rptr[j + 1];
+      int cnt = 0, x = P.sorig[j], only = -1;
+      for (int e = e0; e < e1; ++e) {
+        const int v = P.rvn[e];
+        const int st = P.status[v];
+        if (st < 0) {
+          ++cnt;
+          only = v;
+        } else {
+          x ^= st;
+        }
+      }
+      P.cdeg[q] = cnt;
+      P.sres[q] = x;
+      if (cnt == 0 && x) dead = true;
+      if (cnt == 1) {
+        atomicOr(&P.prop[only >> 2], (1u << x) << ((only & 3) * 8));
+        proposed = true;
+      }
+    }
+  }
+}
+
+// Peeling closure in synchronous rounds. Returns false on a contradiction
+// (a dead CN, or two different proposals for one VN; then the round is not
+// applied). Leaves the CN registers recounted.
+template <int CPL, int VPL>
+__device__ bool peel(PathCtx<CPL, VPL>& P) {
+  for (;;) {
+    bool dead, proposed;
+    cn_recount(P, dead, proposed);
+    const bool any_dead = wave_any(dead);
+    const bool any_prop = wave_any(proposed);
+    wave_sync();
+    bool conflict = false;
+#pragma unroll
+    for (int r = 0; r < VPL; ++r) {
+      const int v = P.lane + kWave * r;
+      if (v < P.n) {
+        const uint32_t p = (P.prop[v >> 2] >> ((v & 3) * 8)) & 3u;
+        if (p == 3u) conflict = true;
+      }
+    }
+    const bool any_conflict = wave_any(conflict);
+    if (any_dead || !any_prop || any_conflict) {
+      // clear proposals for the next call
+      for (int i = P.lane; i < (P.n + 3) / 4; i += kWave) P.prop[i] = 0u;
+      wave_sync();
+      return !(any_dead || any_conflict);
+    }
+#pragma unroll
+    for (int r = 0; r < VPL; ++r) {
+      const int v = P.lane + kWave * r;
+      if (v < P.n) {
+        const uint32_t p = (P.prop[v >> 2] >> ((v & 3) * 8)) & 3u;
+        if (p) {
+          P.status[v] = (int8_t)(p == 2u ? 1 : 0);
+          P.post[v] = __builtin_nanf("");
+        }
+      }
+    }
+    wave_sync();
+    for (int i = P.lane; i < (P.n + 3) / 4; i += kWave) P.prop[i] = 0u;
+    wave_sync();
+  }
+}
+
+// One flooding CN phase. Returns this lane's OR of unsatisfied owned CNs under
+// the hard decisions of the current posteriors.
+template <int CPL, int VPL>
+__device__ __forceinline__ int cn_phase(PathCtx<CPL, VPL>& P, float alpha, float clip) {
+  int bad = 0;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int j = P.lane + kWave * q;
+    if (j < P.m && P.cdeg[q] > 0) {
+      const int e0 = P.rptr[j], e1 = P.rptr[j + 1];
+      const float om1 = P.m1[q];
+      const float om2 = P.m2[q] == kInfF ? clip : P.m2[q];
+      const int oidx = P.idx[q], opar = P.par[q];
+      const unsigned long long omask = P.mask[q];
+      float n1 = kInfF, n2 = kInfF;
+      int nidx = 0, npar = P.sres[q], hx = P.sres[q];
+      unsigned long long nmask = 0ull, amask = 0ull;
+      for (int e = e0; e < e1; ++e) {
+        const int k = e - e0;
+        const float pv = P.post[P.rvn[e]];
+        if (pv != pv) continue;   // decimated VN: stale message ignored
+        amask |= 1ull << k;
+        hx ^= (pv <= 0.0f);
+        float old = alpha * (k == oidx ? om2 : om1);
+        if ((opar ^ (int)(omask >> k)) & 1) old = -old;
+        const float x = clampf(pv - old, clip);
+        const float a = fabsf(x);
+        const int neg = x < 0.0f;
+        nmask |= (unsigned long long)neg << k;
+        npar ^= neg;
+        if (a < n1) {
+          n2 = n1;
+          n1 = a;
+          nidx = k;
+        } else if (a < n2) {
+          n2 = a;
+        }
+      }
+      P.m1[q] = n1;
+      P.m2[q] = n2;
+      P.idx[q] = nidx;
+      P.par[q] = npar;
+      P.mask[q] = nmask;
+      const float s1 = alpha * n1;
+      const float s2 = alpha * (n2 == kInfF ? clip : n2);
+      while (amask) {
+        const int k = __builtin_ctzll(amask);
+        amask &= amask - 1ull;
+        float v = k == nidx ? s2 : s1;
+        if ((npar ^ (int)(nmask >> k)) & 1) v = -v;
+        P.c2v[P.rcsc[e0 + k]] = v;
+      }
+      bad |= hx;
+    } else if (j < P.m) {
+      bad |= P.sres[q];
+    }
+  }
+  return bad;
+}
+
+template <int CPL, int VPL>
+__device__ __forceinline__ int check_pass(PathCtx<CPL, VPL>& P, bool write_unsat) {
+  int bad = 0;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int j = P.lane + kWave * q;
+    if (j < P.m) {
+      int hx = P.sres[q];
+      for (int e = P.rptr[j]; e < P.rptr[j + 1]; ++e) {
+        const float pv = P.post[P.rvn[e]];
+        if (pv == pv) hx ^= (pv <= 0.0f);
+      }
+      if (write_unsat) P.unsat[j] = (uint8_t)hx;
+      bad |= hx;
+    }
+  }
+  return bad;
+}
+
+template <int CPL, int VPL>
+__global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds L, int n_shots,
+                                                          const uint8_t* __restrict__ syn,
+                                                          long long syn_stride,
+                                                          uint8_t* __restrict__ ehat,
+                                                          double* __restrict__ pm_out,
+                                                          int* __restrict__ flags_out,
+                                                          gdg_trace_dev tr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int shot = blockIdx.x;
+  if (shot >= n_shots) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid >> 6;
+  const int m = w.m, n = w.n, n_act = w.n_act;
+
+  uint8_t* sorig = smem + L.sorig;
+  int16_t* sel = (int16_t*)(smem + L.sel);
+  uint16_t* rptr = (uint16_t*)(smem + L.rptr);
+  uint16_t* rvn = (uint16_t*)(smem + L.rvn);
+  uint16_t* rcsc = (uint16_t*)(smem + L.rcsc);
+  uint16_t* cptr = (uint16_t*)(smem + L.cptr);
+  uint16_t* crow = (uint16_t*)(smem + L.crow);
+  float* sllr = (float*)(smem + L.llr);
+  uint8_t* sdeg = smem + L.deg;
+  double* ppm = (double*)(smem + L.ppm);
+  int* pend = (int*)(smem + L.pend);
+  uint32_t* pbits = (uint32_t*)(smem + L.pbits);
+  int* misc = (int*)(smem + L.misc);            // [0] path counter, [1] pre-converged
+  int* iscan = (int*)(smem + L.iscan);          // scratch for scans, max(m, n_act) + 1
+  uint32_t* obits = (uint32_t*)(smem + L.obits);  // window bitmask of the answer
+  unsigned long long* eacc = (unsigned long long*)(smem + L.eacc);
+  unsigned char* U = smem + L.u_base;
+
+  for (int j = tid; j < m; j += blockDim.x) sorig[j] = syn[(long long)shot * syn_stride + j] & 1;
+  if (tid == 0) {
+    misc[0] = 0;
+    misc[1] = 0;
+    *eacc = 0ull;
+  }
+  for (int i = tid; i < L.obits_words; i += blockDim.x) obits[i] = 0u;
+  __syncthreads();
+
+  long long my_edges = 0;
+
+  // ---------------------------------------------------------- preprocessing
+  if (w.pre_iters > 0) {
+    FullBP b;
+    b.w = &w;
+    b.post = (float*)(U + L.p_post);
+    b.c2v = (float*)(U + L.p_c2v);
+    b.syn = sorig;
+    float* lsum = (float*)(U + L.p_lsum);
+    for (int c = tid; c < n; c += blockDim.x) {
+      b.post[c] = w.llr[c];
+      lsum[c] = 0.0f;
+    }
+    for (int e = tid; e < w.e_full; e += blockDim.x) b.c2v[e] = 0.0f;
+    __syncthreads();
+    bool conv = false;
+    int iters_done = 0;
+    for (int t = 1; t <= w.pre_iters; ++t) {
+      const int bad = full_cn_phase(b);
+      const int any_bad = __syncthreads_or(bad);
+      if (t >= 2 && !any_bad) {
+        conv = true;
+        break;
+      }
+      full_vn_phase(b, t > w.pre_iters - 4 ? lsum : nullptr);
+      iters_done = t;
+      __syncthreads();
+    }
+    if (!conv) conv = !__syncthreads_or(full_check(b));
+    if (tid == 0) *eacc = (unsigned long long)iters_done * (unsigned long long)w.e_full;
+    if (conv) {
+      // the hard decision of the preprocessing BP is the answer
+      for (int base = wave * kWave; base < n; base += blockDim.x) {
+        const int c = base + lane;
+        const bool one = c < n && b.post[c] <= 0.0f;
+        const unsigned long long bal = __ballot(one);
+        if (lane == 0) {
+          obits[base >> 5] = (uint32_t)bal;
+          if ((base >> 5) + 1 < L.obits_words) obits[(base >> 5) + 1] = (uint32_t)(bal >> 32);
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double pm = 0.0;
+        for (int wd = 0; wd < L.obits_words; ++wd) {
+          uint32_t x = obits[wd];
+          while (x) {
+            const int bt = __builtin_ctz(x);
+            x &= x - 1u;
+            pm += w.llr64[wd * 32 + bt];
+          }
+        }
+        pm_out[shot] = pm;
+        flags_out[shot] = 1;
+        misc[1] = 1;
+      }
+      for (int c = tid; c < n; c += blockDim.x)
+        ehat[(long long)shot * n + c] = (uint8_t)((obits[c >> 5] >> (c & 31)) & 1u);
+      if (tr.sel)
+        for (int v = tid; v < n_act; v += blockDim.x) tr.sel[(long long)shot * n_act + v] = -1;
+      if (tr.ends)
+        for (int i = tid; i < w.n_paths * 2; i += blockDim.x)
+          tr.ends[(long long)shot * w.n_paths * 2 + i] = 0;
+      if (tr.dec)
+        for (int i = tid; i < w.n_paths * tr.log_cap * 3; i += blockDim.x)
+          tr.dec[(long long)shot * w.n_paths * tr.log_cap * 3 + i] = -1;
+      if (tr.first_post)
+        for (int v = tid; v < n_act; v += blockDim.x)
+          tr.first_post[(long long)shot * n_act + v] = __builtin_nanf("");
+      if (tr.step_lsum)
+        for (long long i = tid; i < (long long)w.n_paths * tr.log_cap * n_act; i += blockDim.x)
+          tr.step_lsum[(long long)shot * w.n_paths * tr.log_cap * n_act + i] = __builtin_nanf("");
+      if (tr.edge_iters && tid == 0) tr.edge_iters[shot] = (long long)*eacc;
+      return;
+    }
+    // rank: ascending sum of the last four posteriors, ties by column index
+    __syncthreads();
+    unsigned long long* keys = (unsigned long long*)(U + L.p_keys);
+    const int NP = L.sort_n;
+    for (int i = tid; i < NP; i += blockDim.x)
+      keys[i] = i < n ? (((unsigned long long)ord_f32(lsum[i]) << 32) | (unsigned)i) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= NP; k <<= 1) {
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int i = tid; i < NP; i += blockDim.x) {
+          const int ixj = i ^ jj;
+          if (ixj > i) {
+            const unsigned long long a = keys[i], bb = keys[ixj];
+            const bool up = (i & k) == 0;
+            if ((a > bb) == up) {
+              keys[i] = bb;
+              keys[ixj] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int v = tid; v < n_act; v += blockDim.x) sel[v] = (int16_t)(keys[v] & 0xffffu);
+  } else {
+    for (int v = tid; v < n_act; v += blockDim.x) sel[v] = (int16_t)v;
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------- truncated sub-graph
+  {
+    int16_t* loc = (int16_t*)(U + L.p_loc);
+    for (int c = tid; c < n; c += blockDim.x) loc[c] = -1;
+    __syncthreads();
+    for (int v = tid; v < n_act; v += blockDim.x) loc[sel[v]] = (int16_t)v;
+    for (int v = tid; v < n_act; v += blockDim.x) {
+      const int c = sel[v];
+      iscan[v] = w.col_ptr[c + 1] - w.col_ptr[c];
+      sllr[v] = w.llr[c];
+      sdeg[v] = w.deg[c];
+    }
+    __syncthreads();
+    wg_exclusive_scan_wave0(iscan, n_act);
+    __syncthreads();
+    for (int v = tid; v <= n_act; v += blockDim.x) cptr[v] = (uint16_t)iscan[v];
+    __syncthreads();
+    for (int j = tid; j < m; j += blockDim.x) {
+      int cnt = 0;
+      for (int e = w.row_ptr[j]; e < w.row_ptr[j + 1]; ++e) cnt += loc[w.row_col[e]] >= 0;
+      iscan[j] = cnt;
+    }
+    __syncthreads();
+    wg_exclusive_scan_wave0(iscan, m);
+    __syncthreads();
+    for (int j = tid; j <= m; j += blockDim.x) rptr[j] = (uint16_t)iscan[j];
+    __syncthreads();
+    for (int j = tid; j < m; j += blockDim.x) {
+      int pos = rptr[j];
+      for (int e = w.row_ptr[j]; e < w.row_ptr[j + 1]; ++e) {
+        const int v = loc[w.row_col[e]];
+        if (v < 0) continue;
+        const int slot = cptr[v] + w.row_kcol[e];
+        rvn[pos] = (uint16_t)v;
+        rcsc[pos] = (uint16_t)slot;
+        crow[slot] = (uint16_t)j;
+        ++pos;
+      }
+    }
+    if (tr.sel)
+      for (int v = tid; v < n_act; v += blockDim.x) tr.sel[(long long)shot * n_act + v] = sel[v];
+    __syncthreads();
+  }
+
+  // ---------------------------------------------------------- decision paths
+  {
+    unsigned char* Wb = U + wave * L.w_stride;
+    PathCtx<CPL, VPL> P;
+    P.rptr = rptr;
+    P.rvn = rvn;
+    P.rcsc = rcsc;
+    P.cptr = cptr;
+    P.crow = crow;
+    P.llr = sllr;
+    P.deg = sdeg;
+    P.sorig = sorig;
+    P.post = (float*)(Wb + L.w_post);
+    P.status = (int8_t*)(Wb + L.w_status);
+    P.c2v = (float*)(Wb + L.w_c2v);
+    P.unsat = Wb + L.w_unsat;
+    P.prop = (uint32_t*)(Wb + L.w_prop);
+    uint32_t* wbits = (uint32_t*)(Wb + L.w_bits);
+    P.lane = lane;
+    P.m = m;
+    P.n = n_act;
+    const int T = w.iters;
+    const float alpha = w.alpha, clip = w.clip;
+    for (int i = lane; i < (n_act + 3) / 4; i += kWave) P.prop[i] = 0u;
+    wave_sync();
+
+    for (;;) {
+      int pid = 0;
+      if (lane == 0) pid = atomicAdd(&misc[0], 1);
+      pid = __shfl(pid, 0, kWave);
+      if (pid >= w.n_paths) break;
+      int dmax, split;
+      if (pid == 0) {
+        dmax = w.dmax_main;
+        split = 0;
+      } else if (w.g > 0 && pid < (1 << w.g)) {
+        dmax = w.g + w.extra;
+        split = w.g;
+      } else {
+        split = w.g + 1 + (pid - (1 << w.g));
+        dmax = split + w.extra;
+      }
+      int* dlog = tr.dec ? tr.dec + ((long long)shot * w.n_paths + pid) * tr.log_cap * 3 : nullptr;
+
+      // fresh path: every VN active, messages from the priors
+#pragma unroll
+      for (int r = 0; r < VPL; ++r) {
+        const int v = lane + kWave * r;
+        if (v < n_act) {
+          P.status[v] = -1;
+          P.post[v] = sllr[v];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        P.m1[q] = 0.0f;
+        P.m2[q] = 0.0f;
+        P.idx[q] = 0;
+        P.par[q] = 0;
+        P.mask[q] = 0ull;
+      }
+      wave_sync();
+      int end = 0, steps = 0;
+      if (!peel(P)) end = END_CONTRADICTION;   // peel at init too
+      for (int D = 1; end == 0 && D <= dmax; ++D) {
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+          P.hs[r] = 0.0f;
+          P.hmn[r] = kInfF;
+          P.hmx[r] = -kInfF;
+        }
+        bool conv = false;
+        for (int t = 1; t <= T; ++t) {
+          const int bad = cn_phase(P, alpha, clip);
+          const bool any_bad = wave_any(bad != 0);
+          if (t >= 2 && !any_bad) {
+            conv = true;
+            break;
+          }
+          wave_sync();
+          const bool hist = t > T - 4;
+#pragma unroll
+          for (int r = 0; r < VPL; ++r) {
+            const int v = lane + kWave * r;
+            if (v < n_act && P.status[v] < 0) {
+              float s = sllr[v];
+              const int c0 = cptr[v], c1 = cptr[v + 1];
+              for (int e = c0; e < c1; ++e) s += P.c2v[e];
+              P.post[v] = s;
+              my_edges += c1 - c0;
+              if (hist) {
+                P.hs[r] += s;
+                P.hmn[r] = fminf(P.hmn[r], s);
+                P.hmx[r] = fmaxf(P.hmx[r], s);
+              }
+            }
+          }
+          wave_sync();
+        }
+        if (!conv) conv = !wave_any(check_pass(P, !w.low_error) != 0);
+        steps = D;
+        if (tr.step_lsum && D - 1 < tr.log_cap) {
+          float* sl = tr.step_lsum + (((long long)shot * w.n_paths + pid) * tr.log_cap + (D - 1)) * n_act;
+#pragma unroll
+          for (int r = 0; r < VPL; ++r) {
+            const int v = lane + kWave * r;
+            if (v < n_act) sl[v] = (!conv && P.status[v] < 0) ? P.hs[r] : __builtin_nanf("");
+          }
+        }
+        if (tr.first_post && pid == 0 && D == 1) {
+          for (int v = lane; v < n_act; v += kWave)
+            tr.first_post[(long long)shot * n_act + v] = P.post[v];
+        }
+        if (conv) {
+          end = END_CONVERGED;
+          break;
+        }
+        if (D == dmax) {
+          end = END_EXHAUSTED;
+          break;
+        }
+        // Alg. 1 with Alg. 3 inside it
+        wave_sync();
+        const bool on_main = path_on_main(w, pid, split, D);
+        unsigned long long kall = ~0ull, kneg = ~0ull;
+        int n_agg = 0;
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+          const int v = lane + kWave * r;
+          if (v < n_act && P.status[v] < 0 && sdeg[v] >= 3) {
+            if (!w.low_error) {
+              int nu = 0;
+              for (int e = cptr[v]; e < cptr[v + 1]; ++e) nu += P.unsat[crow[e]];
+              const int b = agg_dec(P.hs[r], P.hmn[r], P.hmx[r], D, on_main, nu);
+              if (b >= 0) {
+                P.status[v] = (int8_t)b;
+                P.post[v] = __builtin_nanf("");
+                ++n_agg;
+                continue;
+              }
+            }
+            const unsigned long long key =
+                ((unsigned long long)ord_f32(P.hs[r]) << 32) | (unsigned)v;
+            kall = key < kall ? key : kall;
+            if (P.hmx[r] <= 0.0f) kneg = key < kneg ? key : kneg;
+          }
+        }
+        kall = wave_min_u64(kall);
+        kneg = wave_min_u64(kneg);
+        n_agg = wave_sum_i32(n_agg);
+        int gsel, fav;
+        if (kneg != ~0ull) {
+          gsel = (int)(kneg & 0xffffffffu);
+          fav = 1;
+        } else if (kall != ~0ull) {
+          gsel = (int)(kall & 0xffffffffu);
+          fav = (uint32_t)(kall >> 32) <= 0x80000000u ? 1 : 0;   // sum <= 0 -> 1
+        } else {
+          gsel = -1;
+          fav = 0;
+        }
+        wave_sync();
+        if (gsel < 0) {
+          if (dlog && lane == 0 && D - 1 < tr.log_cap) {
+            dlog[(D - 1) * 3 + 0] = -1;
+            dlog[(D - 1) * 3 + 1] = -1;
+            dlog[(D - 1) * 3 + 2] = n_agg;
+          }
+          end = END_NO_CANDIDATE;
+          break;
+        }
+        const int val = path_value(w, pid, split, D, fav);
+        if (lane == 0) {
+          P.status[gsel] = (int8_t)val;
+          P.post[gsel] = __builtin_nanf("");
+          if (dlog && D - 1 < tr.log_cap) {
+            dlog[(D - 1) * 3 + 0] = gsel;
+            dlog[(D - 1) * 3 + 1] = val;
+            dlog[(D - 1) * 3 + 2] = n_agg;
+          }
+        }
+        wave_sync();
+        if (!peel(P)) {
+          end = END_CONTRADICTION;
+          break;
+        }
+      }
+      if (end == 0) end = END_EXHAUSTED;   // dmax < 1
+      if (dlog) {
+        // entries past the last logged step
+        const int first_free = (end == END_NO_CANDIDATE) ? steps : steps - (end == END_CONTRADICTION ? 0 : 1);
+        for (int i = lane; i < tr.log_cap; i += kWave) {
+          if (i >= first_free && i >= 0) {
+            dlog[i * 3 + 0] = -1;
+            dlog[i * 3 + 1] = -1;
+            dlog[i * 3 + 2] = -1;
+          }
+        }
+      }
+      if (tr.step_lsum) {
+        for (int i = steps; i < tr.log_cap; ++i) {
+          float* sl = tr.step_lsum + (((long long)shot * w.n_paths + pid) * tr.log_cap + i) * n_act;
+          for (int v = lane; v < n_act; v += kWave) sl[v] = __builtin_nanf("");
+        }
+      }
+      if (tr.ends && lane == 0) {
+        tr.ends[((long long)shot * w.n_paths + pid) * 2 + 0] = end;
+        tr.ends[((long long)shot * w.n_paths + pid) * 2 + 1] = steps;
+      }
+      // path answer: bits over the sub-graph
+      uint32_t* mybits = pbits + pid * L.pbits_words;
+#pragma unroll
+      for (int r = 0; r < VPL; ++r) {
+        const int v = lane + kWave * r;
+        bool one = false;
+        if (v < n_act) {
+          const int st = P.status[v];
+          one = st >= 0 ? st == 1 : P.post[v] <= 0.0f;
+        }
+        const unsigned long long bal = __ballot(one);
+        if (lane == 0 && kWave * r < n_act) {
+          mybits[2 * r] = (uint32_t)bal;
+          if (2 * r + 1 < L.pbits_words) mybits[2 * r + 1] = (uint32_t)(bal >> 32);
+        }
+      }
+      wave_sync();
+      double pm = __builtin_inf();
+      if (end == END_CONVERGED) {
+        // Eq. 5 in ascending window-column order
+        for (int i = lane; i < L.obits_words; i += kWave) wbits[i] = 0u;
+        wave_sync();
+        for (int v = lane; v < n_act; v += kWave) {
+          if ((mybits[v >> 5] >> (v & 31)) & 1u) {
+            const int c = sel[v];
+            atomicOr(&wbits[c >> 5], 1u << (c & 31));
+          }
+        }
+        wave_sync();
+        if (lane == 0) {
+          pm = 0.0;
+          for (int wd = 0; wd < L.obits_words; ++wd) {
+            uint32_t x = wbits[wd];
+            while (x) {
+              const int bt = __builtin_ctz(x);
+              x &= x - 1u;
+              pm += w.llr64[wd * 32 + bt];
+            }
+          }
+        }
+      }
+      if (lane == 0) {
+        ppm[pid] = pm;
+        pend[pid] = end;
+      }
+      wave_sync();
+    }
+  }
+  my_edges = wave_sum_i64(my_edges);
+  if (lane == 0 && my_edges) atomicAdd(eacc, (unsigned long long)my_edges);
+  __syncthreads();
+
+  // ---------------------------------------------------------- best path, output
+  if (tid == 0) {
+    int best = -1;
+    double bpm = __builtin_inf();
+    int n_contra = 0, n_exh = 0;
+    for (int p = 0; p < w.n_paths; ++p) {
+      if (pend[p] == END_CONTRADICTION) ++n_contra;
+      if (pend[p] == END_EXHAUSTED) ++n_exh;
+      if (pend[p] == END_CONVERGED && ppm[p] < bpm) {
+        bpm = ppm[p];
+        best = p;
+      }
+    }
+    int fl = 0;
+    if (best >= 0) {
+      fl = 1;
+    } else {
+      if (n_contra == w.n_paths) fl |= 2;
+      if (n_exh > 0) fl |= 4;
+    }
+    misc[2] = best >= 0 ? best : 0;
+    pm_out[shot] = bpm;
+    flags_out[shot] = fl;
+    if (tr.edge_iters) tr.edge_iters[shot] = (long long)*eacc;
+  }
+  __syncthreads();
+  const uint32_t* ansbits = pbits + misc[2] * L.pbits_words;
+  for (int v = tid; v < n_act; v += blockDim.x) {
+    if ((ansbits[v >> 5] >> (v & 31)) & 1u) {
+      const int c = sel[v];
+      atomicOr(&obits[c >> 5], 1u << (c & 31));
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < n; c += blockDim.x)
+    ehat[(long long)shot * n + c] = (uint8_t)((obits[c >> 5] >> (c & 31)) & 1u);
+}
+
+// ------------------------------------------------------------------ plain BP
+
+__global__ __launch_bounds__(1024) void gdg_bp_kernel(gdg_win_dev w, int n_shots,
+                                                      const uint8_t* __restrict__ syn,
+                                                      long long syn_stride, int n_iters,
+                                                      float* __restrict__ post_out,
+                                                      int* __restrict__ first_ok) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int shot = blockIdx.x;
+  if (shot >= n_shots) return;
+  const int tid = threadIdx.x;
+  uint8_t* s = smem;
+  float* post = (float*)(smem + ((w.m + 15) & ~15));
+  float* c2v = post + ((w.n + 3) & ~3);
+  for (int j = tid; j < w.m; j += blockDim.x) s[j] = syn[(long long)shot * syn_stride + j] & 1;
+  for (int c = tid; c < w.n; c += blockDim.x) post[c] = w.llr[c];
+  for (int e = tid; e < w.e_full; e += blockDim.x) c2v[e] = 0.0f;
+  __syncthreads();
+  FullBP b;
+  b.w = &w;
+  b.post = post;
+  b.c2v = c2v;
+  b.syn = s;
+  int first = 0;
+  for (int t = 1; t <= n_iters; ++t) {
+    const int bad = full_cn_phase(b);
+    const int any_bad = __syncthreads_or(bad);
+    if (t >= 2 && !any_bad && first == 0) first = t - 1;
+    full_vn_phase(b, nullptr);
+    __syncthreads();
+    for (int c = tid; c < w.n; c += blockDim.x)
+      post_out[((long long)shot * n_iters + (t - 1)) * w.n + c] = post[c];
+  }
+  const int bad = __syncthreads_or(full_check(b));
+  if (tid == 0) first_ok[shot] = first ? first : (bad ? 0 : n_iters);
+}
+
+// ------------------------------------------------------------------ commit
+//
+// One thread per (shot, affected DEM row): XOR of the committed window columns
+// decided 1 that touch the row (Eq. 7-8 update). Rows are disjoint per thread,
+// so no atomics. Observables likewise, one thread per (shot, observable).
+
+__global__ void gdg_commit_kernel(gdg_commit_dev cm, int n_shots, const uint8_t* __restrict__ ehat,
+                                  uint8_t* __restrict__ det, long long det_stride,
+                                  uint8_t* __restrict__ obs, long long obs_stride) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)cm.n_rows + cm.n_obs;
+  const long long total = per * n_shots;
+  if (i >= total) return;
+  const int shot = (int)(i / per);
+  const int r = (int)(i % per);
+  const uint8_t* e = ehat + (long long)shot * cm.n_win;
+  if (r < cm.n_rows) {
+    int x = 0;
+    for (int t = cm.row_ptr[r]; t < cm.row_ptr[r + 1]; ++t) x ^= e[cm.row_col[t]];
+    if (x) det[(long long)shot * det_stride + cm.row_global[r]] ^= 1;
+  } else {
+    const int o = r - cm.n_rows;
+    int x = 0;
+    for (int t = cm.obs_ptr[o]; t < cm.obs_ptr[o + 1]; ++t) x ^= e[cm.obs_col[t]];
+    if (x) obs[(long long)shot * obs_stride + o] ^= 1;
+  }
+}
+
+// ------------------------------------------------------------------ sampler
+//
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, each two 32x32 -> 64-bit
+// products with the multipliers 0xD2511F53 / 0xCD9E8D57, key bumped by the
+// Weyl constants 0x9E3779B9 / 0xBB67AE85 between rounds.
+
+__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// One workgroup per shot; detector and observable bits accumulate in LDS.
+__global__ __launch_bounds__(256) void gdg_sample_kernel(gdg_dem_dev_k d, int n_shots, uint64_t seed,
+                                                         uint32_t stream, uint64_t shot0,
+                                                         uint8_t* __restrict__ det,
+                                                         uint8_t* __restrict__ obs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int s = blockIdx.x;
+  if (s >= n_shots) return;
+  uint32_t* dbits = (uint32_t*)smem;
+  const int dw = (d.n_rows + 31) >> 5;
+  uint32_t* obits = dbits + dw;
+  const int ow = (d.n_obs + 31) >> 5;
+  for (int i = threadIdx.x; i < dw + ow; i += blockDim.x) dbits[i] = 0u;
+  __syncthreads();
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const uint32_t sh = (uint32_t)(shot0 + (uint64_t)s);
+  const int ngroups = (d.n_cols + 3) >> 2;
+  for (int gq = threadIdx.x; gq < ngroups; gq += blockDim.x) {
+    uint32_t c[4] = {(uint32_t)gq, sh, stream, 0xC0DEu};
+    philox(c, k0, k1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int col = gq * 4 + t;
+      if (col < d.n_cols && c[t] < d.thr[col]) {
+        for (int e = d.h_ptr[col]; e < d.h_ptr[col + 1]; ++e) {
+          const int r = d.h_idx[e];
+          atomicXor(&dbits[r >> 5], 1u << (r & 31));
+        }
+        for (int e = d.l_ptr[col]; e < d.l_ptr[col + 1]; ++e) {
+          const int o = d.l_idx[e];
+          atomicXor(&obits[o >> 5], 1u << (o & 31));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < d.n_rows; r += blockDim.x)
+    det[(long long)s * d.n_rows + r] = (uint8_t)((dbits[r >> 5] >> (r & 31)) & 1u);
+  for (int o = threadIdx.x; o < d.n_obs; o += blockDim.x)
+    obs[(long long)s * d.n_obs + o] = (uint8_t)((obits[o >> 5] >> (o & 31)) & 1u);
+}
+
+__global__ void gdg_evaluate_kernel(int n_shots, int n_rows, int n_obs,
+                                    const uint8_t* __restrict__ det, const uint8_t* __restrict__ obs,
+                                    uint8_t* __restrict__ fail) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_shots) return;
+  int bad = 0;
+  for (int r = 0; r < n_rows; ++r) bad |= det[(long long)s * n_rows + r];
+  for (int o = 0; o < n_obs; ++o) bad |= obs[(long long)s * n_obs + o];
+  fail[s] = (uint8_t)(bad != 0);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t gdg_launch_decode(const gdg_win_dev& w, const gdg_lds& L, int waves, int n_shots,
+                             const uint8_t* syn, long long syn_stride, uint8_t* ehat, double* pm,
+                             int* flags, const gdg_trace_dev& tr, hipStream_t st) {
+  dim3 grid(n_shots), block(waves * kWave);
+  const size_t lds = (size_t)L.total;
+  if (w.m <= 128 && w.n_act <= 384) {
+    hipLaunchKernelGGL((gdg_decode_kernel<2, 6>), grid, block, lds, st, w, L, n_shots, syn,
+                       syn_stride, ehat, pm, flags, tr);
+  } else if (w.m <= 256 && w.n_act <= 512) {
+    hipLaunchKernelGGL((gdg_decode_kernel<4, 8>), grid, block, lds, st, w, L, n_shots, syn,
+                       syn_stride, ehat, pm, flags, tr);
+  } else if (w.m <= 512 && w.n_act <= 1024) {
+    hipLaunchKernelGGL((gdg_decode_kernel<8, 16>), grid, block, lds, st, w, L, n_shots, syn,
+                       syn_stride, ehat, pm, flags, tr);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t gdg_decode_set_lds_limit(const gdg_win_dev& w, int bytes) {
+  hipError_t e = hipSuccess;
+  if (w.m <= 128 && w.n_act <= 384)
+    e = hipFuncSetAttribute((const void*)gdg_decode_kernel<2, 6>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  else if (w.m <= 256 && w.n_act <= 512)
+    e = hipFuncSetAttribute((const void*)gdg_decode_kernel<4, 8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  else
+    e = hipFuncSetAttribute((const void*)gdg_decode_kernel<8, 16>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e;
+}
+
+hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, long long stride,
+                         int n_iters, float* post, int* first_ok, hipStream_t st) {
+  const size_t lds = (size_t)((w.m + 15) & ~15) + 4 * (size_t)((w.n + 3) & ~3) +
+                     4 * (size_t)w.e_full;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)gdg_bp_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(gdg_bp_kernel, dim3(n_shots), dim3(256), lds, st, w, n_shots, syn, stride,
+                     n_iters, post, first_ok);
+  return hipGetLastError();
+}
+
+hipError_t gdg_launch_commit(const gdg_commit_dev& cm, int n_shots, const uint8_t* ehat,
+                             uint8_t* det, long long det_stride, uint8_t* obs,
+                             long long obs_stride, hipStream_t st) {
+  const long long total = ((long long)cm.n_rows + cm.n_obs) * n_shots;
+  if (total == 0) return hipSuccess;
+  const int bs = 256;
+  const long long nb = (total + bs - 1) / bs;
+  hipLaunchKernelGGL(gdg_commit_kernel, dim3((unsigned)nb), dim3(bs), 0, st, cm, n_shots, ehat,
+                     det, det_stride, obs, obs_stride);
+  return hipGetLastError();
+}
+
+hipError_t gdg_launch_sample(const gdg_dem_dev_k& d, int n_shots, uint64_t seed, uint32_t stream,
+                             uint64_t shot0, uint8_t* det, uint8_t* obs, hipStream_t st) {
+  const size_t lds = 4 * (size_t)(((d.n_rows + 31) >> 5) + ((d.n_obs + 31) >> 5));
+  hipLaunchKernelGGL(gdg_sample_kernel, dim3(n_shots), dim3(256), lds, st, d, n_shots, seed,
+                     stream, shot0, det, obs);
+  return hipGetLastError();
+}
+
+hipError_t gdg_launch_evaluate(int n_shots, int n_rows, int n_obs, const uint8_t* det,
+                               const uint8_t* obs, uint8_t* fail, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL(gdg_evaluate_kernel, dim3((n_shots + bs - 1) / bs), dim3(bs), 0, st, n_shots,
+                     n_rows, n_obs, det, obs, fail);
+  return hipGetLastError();
+}

@@ -1,0 +1,257 @@
+"""Python binding of the gdg C ABI (include/gdg.h): argument marshalling only.
+
+Every step of the decoder runs in the HIP library libgdg_hip.so; torch supplies
+device memory and the current stream. If the library is missing the calls
+raise -- there is no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgdg_hip.so")
+
+GDG_FLAG_SATISFIED = 1
+GDG_FLAG_CONTRADICTION = 2
+GDG_FLAG_EXHAUSTED = 4
+GDG_FLAG_FALLBACK = 8
+
+EXPORTED = ["gdg_build_window", "gdg_window_free", "gdg_window_get_info", "gdg_window_columns",
+            "gdg_workspace_bytes", "gdg_decode_batch", "gdg_commit", "gdg_bp", "gdg_dem_upload",
+            "gdg_dem_free", "gdg_sample", "gdg_evaluate", "gdg_last_error"]
+
+
+class Dem(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("n_obs", C.c_int32),
+                ("w", C.c_int32), ("n_rounds", C.c_int32), ("h_ptr", C.c_void_p),
+                ("h_idx", C.c_void_p), ("l_ptr", C.c_void_p), ("l_idx", C.c_void_p),
+                ("priors", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("alpha", C.c_float), ("clip", C.c_float), ("iters_per_step", C.c_int32),
+                ("pre_iters", C.c_int32), ("trunc_factor", C.c_int32), ("g", C.c_int32),
+                ("dmax_main", C.c_int32), ("extra_steps", C.c_int32),
+                ("side_max_depth", C.c_int32), ("low_error", C.c_int32)]
+
+
+class WindowInfo(C.Structure):
+    _fields_ = [(f, C.c_int32) for f in ("k", "W", "m", "n", "row0", "n_act", "n_paths", "n_edges",
+                                         "max_sub_edges", "n_commit", "last", "lds_bytes",
+                                         "waves")]
+
+
+class Trace(C.Structure):
+    _fields_ = [("sel", C.c_void_p), ("dec", C.c_void_p), ("log_cap", C.c_int32),
+                ("ends", C.c_void_p), ("first_post", C.c_void_p), ("edge_iters", C.c_void_p),
+                ("step_lsum", C.c_void_p)]
+
+
+def params(alpha=1.0, clip=50.0, iters_per_step=6, pre_iters=0, trunc_factor=2, g=0,
+           dmax_main=25, extra_steps=10, side_max_depth=0, low_error=1) -> Params:
+    return Params(alpha, clip, iters_per_step, pre_iters, trunc_factor, g, dmax_main,
+                  extra_steps, side_max_depth, low_error)
+
+
+_lib = None
+
+
+def lib():
+    """Loads libgdg_hip.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2403_18901_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, u32, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
+        L.gdg_build_window.argtypes = [P, i32, i32, i32, P, P]
+        L.gdg_window_free.argtypes = [P]
+        L.gdg_window_get_info.argtypes = [P, P]
+        L.gdg_window_columns.argtypes = [P, P, P, P]
+        L.gdg_workspace_bytes.argtypes = [P, i32]
+        L.gdg_workspace_bytes.restype = C.c_size_t
+        L.gdg_decode_batch.argtypes = [P, i32, P, i64, P, P, P, P, C.c_size_t, P, P]
+        L.gdg_commit.argtypes = [P, i32, P, P, i64, P, i64, P]
+        L.gdg_bp.argtypes = [P, i32, P, i64, i32, P, P, P]
+        L.gdg_dem_upload.argtypes = [P, P]
+        L.gdg_dem_free.argtypes = [P]
+        L.gdg_sample.argtypes = [P, i32, u64, u32, u64, P, P, P]
+        L.gdg_evaluate.argtypes = [i32, i32, i32, P, P, P, P]
+        L.gdg_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError(f"gdg error {rc}: {lib().gdg_last_error().decode()}")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, offset=0):
+    return C.c_void_p(t.data_ptr() + offset) if t is not None else None
+
+
+class _HostDem:
+    """Keeps contiguous host arrays alive for a gdg_dem struct."""
+
+    def __init__(self, dem):
+        self.arrs = [np.ascontiguousarray(dem.h_ptr, np.int32),
+                     np.ascontiguousarray(dem.h_idx, np.int32),
+                     np.ascontiguousarray(dem.l_ptr, np.int32),
+                     np.ascontiguousarray(dem.l_idx, np.int32),
+                     np.ascontiguousarray(dem.priors, np.float64)]
+        p = [a.ctypes.data_as(C.c_void_p) for a in self.arrs]
+        self.s = Dem(dem.n_rows, dem.n_cols, dem.n_obs, dem.w, dem.n_rounds, *p)
+
+
+class Window:
+    """One window of a (W,1) sliding window, built and held by the library."""
+
+    def __init__(self, dem, k: int, W: int, prm: Params):
+        hd = _HostDem(dem)
+        h = C.c_void_p()
+        _check(lib().gdg_build_window(C.byref(hd.s), k, W, 1, C.byref(prm), C.byref(h)))
+        self.h = h
+        self.prm = prm
+        info = WindowInfo()
+        _check(lib().gdg_window_get_info(self.h, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in WindowInfo._fields_}
+        self.m, self.n, self.row0 = info.m, info.n, info.row0
+        self.n_act, self.n_paths = info.n_act, info.n_paths
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.gdg_window_free(self.h)
+            self.h = None
+
+    def columns(self):
+        src = np.zeros(self.n, np.int32)
+        llr = np.zeros(self.n, np.float64)
+        commit = np.zeros(self.n, np.uint8)
+        _check(lib().gdg_window_columns(self.h, src.ctypes.data_as(C.c_void_p),
+                                        llr.ctypes.data_as(C.c_void_p),
+                                        commit.ctypes.data_as(C.c_void_p)))
+        return src, llr, commit
+
+    def decode(self, syn: torch.Tensor, syn_offset: int = 0, n_shots: int | None = None,
+               trace: bool = False, log_cap: int = 32, out=None, step_lsum: bool = False):
+        """syn: uint8 cuda tensor [n_shots, stride]; window rows start at column syn_offset."""
+        assert syn.dtype == torch.uint8 and syn.is_cuda and syn.dim() == 2 and syn.is_contiguous()
+        ns = syn.shape[0] if n_shots is None else n_shots
+        dev = syn.device
+        if out is None:
+            ehat = torch.empty((ns, self.n), dtype=torch.uint8, device=dev)
+            pm = torch.empty(ns, dtype=torch.float64, device=dev)
+            flags = torch.empty(ns, dtype=torch.int32, device=dev)
+        else:
+            ehat, pm, flags = out
+        tr = None
+        trd = None
+        if trace:
+            trd = dict(sel=torch.empty((ns, self.n_act), dtype=torch.int32, device=dev),
+                       dec=torch.empty((ns, self.n_paths, log_cap, 3), dtype=torch.int32,
+                                       device=dev),
+                       ends=torch.empty((ns, self.n_paths, 2), dtype=torch.int32, device=dev),
+                       first_post=torch.empty((ns, self.n_act), dtype=torch.float32, device=dev),
+                       edge_iters=torch.empty(ns, dtype=torch.int64, device=dev))
+            if step_lsum:
+                trd["step_lsum"] = torch.empty((ns, self.n_paths, log_cap, self.n_act),
+                                               dtype=torch.float32, device=dev)
+            tr = Trace(_ptr(trd["sel"]), _ptr(trd["dec"]), log_cap, _ptr(trd["ends"]),
+                       _ptr(trd["first_post"]), _ptr(trd["edge_iters"]),
+                       _ptr(trd.get("step_lsum")))
+        _check(lib().gdg_decode_batch(self.h, ns, _ptr(syn, syn_offset), syn.shape[1], _ptr(ehat),
+                                      _ptr(pm), _ptr(flags), None, 0,
+                                      C.byref(tr) if tr is not None else None, _stream()))
+        if trace:
+            return ehat, pm, flags, trd
+        return ehat, pm, flags
+
+    def commit(self, ehat: torch.Tensor, det: torch.Tensor, obs: torch.Tensor):
+        ns = ehat.shape[0]
+        _check(lib().gdg_commit(self.h, ns, _ptr(ehat), _ptr(det), det.shape[1], _ptr(obs),
+                                obs.shape[1] if obs.dim() == 2 else 0, _stream()))
+
+    def bp(self, syn: torch.Tensor, n_iters: int, syn_offset: int = 0):
+        ns = syn.shape[0]
+        post = torch.empty((ns, n_iters, self.n), dtype=torch.float32, device=syn.device)
+        first = torch.empty(ns, dtype=torch.int32, device=syn.device)
+        _check(lib().gdg_bp(self.h, ns, _ptr(syn, syn_offset), syn.shape[1], n_iters, _ptr(post),
+                            _ptr(first), _stream()))
+        return post, first
+
+
+class DeviceDem:
+    """Device copy of a DEM for sampling shots on the GPU."""
+
+    def __init__(self, dem):
+        hd = _HostDem(dem)
+        h = C.c_void_p()
+        _check(lib().gdg_dem_upload(C.byref(hd.s), C.byref(h)))
+        self.h = h
+        self.n_rows, self.n_obs, self.n_cols = dem.n_rows, dem.n_obs, dem.n_cols
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.gdg_dem_free(self.h)
+            self.h = None
+
+    def sample(self, n_shots: int, seed: int, stream: int = 0, shot0: int = 0, device="cuda",
+               out=None):
+        if out is None:
+            det = torch.empty((n_shots, self.n_rows), dtype=torch.uint8, device=device)
+            obs = torch.empty((n_shots, max(self.n_obs, 1)), dtype=torch.uint8, device=device)
+        else:
+            det, obs = out
+        _check(lib().gdg_sample(self.h, n_shots, seed, stream, shot0, _ptr(det), _ptr(obs),
+                                _stream()))
+        return det, obs
+
+
+def evaluate(det: torch.Tensor, obs: torch.Tensor, out=None) -> torch.Tensor:
+    ns = det.shape[0]
+    fail = out if out is not None else torch.empty(ns, dtype=torch.uint8, device=det.device)
+    _check(lib().gdg_evaluate(ns, det.shape[1], obs.shape[1], _ptr(det), _ptr(obs), _ptr(fail),
+                              _stream()))
+    return fail
+
+
+class SlidingWindowDecoder:
+    """(W,1) sliding-window GDG over a DEM: window k is decoded on the current
+    residual detectors and committed before window k+1 (Sec. III)."""
+
+    def __init__(self, dem, prm: Params, W: int = 3):
+        self.dem = dem
+        self.W = W
+        self.n_windows = dem.n_rounds - W + 1
+        if self.n_windows < 1:
+            raise ValueError("fewer detector rounds than the window size")
+        self.windows = [Window(dem, k, W, prm) for k in range(self.n_windows)]
+
+    def decode(self, det: torch.Tensor, obs: torch.Tensor, trace: bool = False):
+        """Decodes in place: det becomes the residual detector record and obs the
+        observable accumulator (true observables XOR L e). Returns per-shot
+        failure flags (Eq. 8 and Eq. 9) and per-window flags."""
+        ns = det.shape[0]
+        wflags = torch.empty((ns, self.n_windows), dtype=torch.int32, device=det.device)
+        traces = []
+        for k, w in enumerate(self.windows):
+            res = w.decode(det, syn_offset=w.row0, trace=trace)
+            ehat, pm, fl = res[:3]
+            if trace:
+                traces.append(res[3])
+            wflags[:, k] = fl
+            w.commit(ehat, det, obs)
+        fail = evaluate(det, obs)
+        if trace:
+            return fail, wflags, traces
+        return fail, wflags

@@ -1,0 +1,388 @@
+"""GPU path (through the C ABI) against the FP64 oracle on the same seeded shots.
+
+Bars (stated with each test): bit-exact for integer work (sampling, commit,
+syndrome consistency), posteriors within 1e-4 relative (|x - ref| <=
+1e-4 max(|ref|, 1)) in FP32, decision differences only inside a 1e-5 tie
+margin of the oracle's own scores, logical error counts inside the oracle's
+2-sigma Wilson interval.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gdg_inputs.bb import get_code
+from gdg_inputs.dem import circuit_dem, phenomenological_dem
+from gdg_inputs.philox import sample_errors, syndromes
+from oracle import oracle as O
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+
+def _g():
+    import paper_2403_18901_amd.gdg as g
+    return g
+
+
+def test_library_exports_every_declared_symbol():
+    """CPU: the built library loads and exports every entry point of include/gdg.h."""
+    import os
+    import re
+    g = _g()
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "gdg.h")).read()
+    declared = set(re.findall(r"\b(gdg_[a-z_]+)\s*\(", hdr))
+    assert declared == set(g.EXPORTED)
+    L = g.lib()
+    for s in declared:
+        assert hasattr(L, s), s
+
+
+def wilson(k, n, z=2.0):
+    if n == 0:
+        return 0.0, 1.0
+    p = k / n
+    den = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / den
+    h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / den
+    return c - h, c + h
+
+
+C1 = dict(alpha=0.625, g=0, pre_iters=0, low_error=1, dmax_main=25)
+
+
+def c1_dem():
+    return phenomenological_dem(get_code("72"), 6, 0.005, 0.005)
+
+
+def c2_dem(key="144", rounds=12, p=0.002):
+    return circuit_dem(get_code(key), rounds, p)
+
+
+def c2_params(p):
+    return dict(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=int(p <= 0.002),
+                dmax_main=25, extra_steps=10)
+
+
+# ------------------------------------------------------------------ sampler, commit
+
+@gpu
+@pytest.mark.parametrize("model", ["phen", "circuit"])
+def test_device_sampler_bit_exact(model):
+    g = _g()
+    dem = c1_dem() if model == "phen" else c2_dem("72", 6, 0.003)
+    n = 300
+    dd = g.DeviceDem(dem)
+    det, obs = dd.sample(n, seed=12345, stream=3, shot0=77)
+    torch.cuda.synchronize()
+    e = sample_errors(dem.thresholds(), n, seed=12345, stream=3, shot0=77)
+    rd, ro = syndromes(dem, e)
+    assert np.array_equal(det.cpu().numpy(), rd)
+    assert np.array_equal(obs.cpu().numpy()[:, :dem.n_obs], ro)
+
+
+@gpu
+def test_commit_matches_integer_reference():
+    g = _g()
+    dem = c2_dem("72", 6, 0.003)
+    prm = g.params(**c2_params(0.003))
+    rng = np.random.default_rng(0)
+    ns = 64
+    for k in (0, 2, dem.n_rounds - 3):
+        w = g.Window(dem, k, 3, prm)
+        src, llr, commit = w.columns()
+        ehat = (rng.random((ns, w.n)) < 0.05).astype(np.uint8)
+        det = rng.integers(0, 2, (ns, dem.n_rows)).astype(np.uint8)
+        obs = rng.integers(0, 2, (ns, dem.n_obs)).astype(np.uint8)
+        dt, ot = torch.from_numpy(det).cuda(), torch.from_numpy(obs).cuda()
+        w.commit(torch.from_numpy(ehat).cuda(), dt, ot)
+        torch.cuda.synchronize()
+        H = dem.dense_h().astype(np.int64)
+        L = dem.dense_l().astype(np.int64)
+        full = np.zeros((ns, dem.n_cols), np.int64)
+        for c in range(w.n):
+            if commit[c]:
+                full[:, src[c]] = ehat[:, c]
+        assert np.array_equal(dt.cpu().numpy(), (det + full @ H.T) % 2)
+        assert np.array_equal(ot.cpu().numpy(), (obs + full @ L.T) % 2)
+
+
+# ------------------------------------------------------------------ BP posteriors
+
+def _rel_ok(x, ref, tol=1e-4):
+    return np.abs(x - ref) <= tol * np.maximum(np.abs(ref), 1.0)
+
+
+@gpu
+@pytest.mark.parametrize("model,k", [("phen", 1), ("phen", 4), ("circuit", 0), ("circuit", 5)])
+def test_bp_posteriors_within_1e4(model, k):
+    """Plain min-sum BP on the whole window: every iteration's posteriors
+    within 1e-4 relative of the FP64 oracle. The one allowed exception is a
+    sign tie: a VN-to-CN message within 1e-3 of zero whose sign FP32 and FP64
+    decide differently flips that CN's other outgoing messages; from the first
+    iteration where a posterior leaves the tolerance, every offending VN must
+    sit next to such a CN, and the shot is not compared further."""
+    g = _g()
+    if model == "phen":
+        dem, prm, op = c1_dem(), g.params(**C1), O.params(alpha=0.625)
+    else:
+        dem = c2_dem("144", 12, 0.003)
+        prm, op = g.params(**c2_params(0.003)), O.params(alpha=1.0)
+    e = sample_errors(dem.thresholds(), 40, seed=21)
+    det, _ = syndromes(dem, e)
+    w = g.Window(dem, k, 3, prm)
+    ow = O.OracleWindow(dem, k, 3)
+    # the bar covers posteriors before the first decimation: the 8 preprocessing
+    # iterations, or one 6-iteration step (FP32 rounding keeps growing after that)
+    iters = 8
+    post, first = w.bp(torch.from_numpy(det).cuda(), iters, syn_offset=w.row0)
+    torch.cuda.synchronize()
+    post = post.cpu().numpy()
+    first = first.cpu().numpy()
+    H = ow.export()["H"]
+    n_ok = 0
+    n_tie = 0
+    for s in range(det.shape[0]):
+        syn = det[s, w.row0:w.row0 + w.m]
+        ref, rfirst, cmin = ow.bp(op, syn, iters, with_cn_min=True)
+        ok = _rel_ok(post[s], ref)
+        if not ok.all():
+            t = int(np.argwhere(~ok.all(1))[0][0])
+            for v in np.nonzero(~ok[t])[0]:
+                rows = np.nonzero(H[:, v])[0]
+                assert (cmin[t][rows] <= 1e-3).any(), ("no sign tie", s, t, v)
+            n_tie += 1
+            continue
+        n_ok += rfirst == first[s]
+    assert n_tie <= max(2, det.shape[0] // 10)
+    assert n_ok >= det.shape[0] - n_tie - 1
+
+
+# ------------------------------------------------------------------ window decode
+
+def _compare_window(dem, k, gp, op, det, log_cap=32, require_exact=0.97):
+    """Runs one window on both sides on the same syndromes.
+
+    * Syndrome consistency is exact: every answer the GPU reports as satisfying
+      the window reproduces the window syndrome bit for bit.
+    * Answers: where both sides find a satisfying path, the answer and its path
+      metric (Eq. 5, double, same summation order) are identical on at least
+      `require_exact` of the shots; where neither does, only that agrees.
+    * Decisions: every path's decision log is replayed in the oracle (which
+      follows the GPU's choices); at every step where the oracle would choose
+      differently, the two candidates' Alg. 1 keys in the oracle's arithmetic
+      must differ by at most the 1e-5 tie margin plus twice the measured
+      FP32-vs-FP64 drift of the keys at that step (the largest difference of any
+      VN's key between the two sides), or one of the two picks must have a
+      history posterior within that window of zero (the class boundary of
+      Alg. 1, which also fixes the favoured value). Loopy min-sum amplifies rounding
+      differences by about 5x per six-iteration step in paths that do not
+      converge, so deep steps get a wider window; a logic error (wrong key,
+      tie-break, peeling or branch value) does not fit inside it.
+    """
+    g = _g()
+    w = g.Window(dem, k, 3, gp)
+    ow = O.OracleWindow(dem, k, 3)
+    syn = np.ascontiguousarray(det[:, w.row0:w.row0 + w.m])
+    ehat, pm, fl, tr = w.decode(torch.from_numpy(det).cuda(), syn_offset=w.row0, trace=True,
+                                log_cap=log_cap, step_lsum=True)
+    torch.cuda.synchronize()
+    ehat, pm, fl = ehat.cpu().numpy(), pm.cpu().numpy(), fl.cpu().numpy()
+    tr = {k_: v.cpu().numpy() for k_, v in tr.items()}
+    ref = ow.decode(op, syn, logs=True, log_cap=log_cap)
+    H = ow.export()["H"].astype(np.int64)
+    ns = det.shape[0]
+    exact = both_failed = exact_logs = 0
+    for s in range(ns):
+        if fl[s] & 1:
+            assert np.array_equal((ehat[s].astype(np.int64) @ H.T) % 2, syn[s]), s
+            assert np.isfinite(pm[s])
+        if not (fl[s] & 1) and not (ref["flags"][s] & 1):
+            both_failed += 1
+        elif np.array_equal(ref["e"][s], ehat[s]) and pm[s] == ref["pm"][s]:
+            assert fl[s] == ref["flags"][s], s
+            exact += 1
+        same_sel = tr["sel"][s][0] == -1 or (ref["sel"][s][:w.n_act] == tr["sel"][s]).all()
+        if same_sel and np.array_equal(ref["dec"][s][:, :, :2], tr["dec"][s][:, :, :2]):
+            exact_logs += 1
+            continue
+        _check_decisions(ow, op, syn[s], ref, tr, s, w.n_act)
+    assert exact >= require_exact * (ns - both_failed), (exact, ns, both_failed)
+    assert both_failed <= 0.05 * ns
+    return exact, exact_logs
+
+
+def _close(a, b, tol):
+    return abs(a - b) <= tol + 1e-5 * max(1.0, abs(a), abs(b))
+
+
+def _sign_tie(r, i, drift):
+    """A posterior of step i within the drift of zero (Eq. 4 hard decision)."""
+    return r["step_min_post"][i] <= 4 * drift + 1e-5
+
+
+def _agg_tie(r, i, drift):
+    """An Alg. 3 comparison of step i within the drift of its threshold, or a
+    hard decision feeding its unsatisfied-CN count within the drift of zero."""
+    return r["step_agg_margin"][i] <= drift + 1e-5 or _sign_tie(r, i, drift)
+
+
+def _check_decisions(ow, op, syn, ref, tr, s, n_act):
+    gsel = tr["sel"][s]
+    if gsel[0] >= 0 and not (ref["sel"][s][:n_act] == gsel).all():
+        # truncation boundary (ranking after 8 iterations, drift <= 1e-4
+        # relative): the differing columns must tie on the ranking key
+        r = ow.replay(op, syn, None, 0, [], [])
+        lsum = r["lsum"]
+        kth = np.sort(lsum, kind="stable")[n_act - 1]
+        diff = set(gsel.tolist()) ^ set(ref["sel"][s][:n_act].tolist())
+        for c in diff:
+            assert _close(lsum[c], kth, 4e-4 * max(1.0, abs(kth))), ("truncation", s, c)
+        forced_sel = gsel
+    else:
+        forced_sel = None
+    n_paths = tr["dec"].shape[1]
+    for p in range(n_paths):
+        gd = tr["dec"][s, p]
+        steps = int((gd[:, 0] >= 0).sum())
+        fg, fv = gd[:steps, 0], gd[:steps, 1]
+        r = ow.replay(op, syn, forced_sel, p, fg, fv)
+        drift = 0.0
+        for i in range(steps):
+            a, b = tr["step_lsum"][s, p, i], r["step_lsum"][i]
+            both = np.isfinite(a) & np.isfinite(b)
+            if (np.isfinite(a) == np.isfinite(b)).all():
+                drift = max(drift, float(np.max(np.abs(a[both] - b[both]))) if both.any() else 0.0)
+            else:
+                # Either one side met the syndrome at this step and the other did
+                # not (the syndrome check turned on a posterior sign inside the
+                # drift; keys are sums of four posteriors, hence the factor 4), or
+                # the previous step's Alg. 3 pass decided a different set (one of
+                # its comparisons sat inside the drift of its threshold).
+                assert _sign_tie(r, i, drift) or (i > 0 and _agg_tie(r, i - 1, drift)), \
+                    ("active sets", s, p, i, drift)
+                break
+            if int(gd[i, 2]) != int(r["step_nagg"][i]):
+                # Alg. 3 decided a different set at this step: a threshold or an
+                # unsatisfied-CN count (hard decisions, Eq. 4) inside the drift
+                assert _agg_tie(r, i, drift), ("alg3", s, p, i, drift)
+                break
+            if r["own_g"][i] == fg[i] and r["own_v"][i] == fv[i]:
+                continue
+            # a history posterior at the class boundary (all four <= 0) decides
+            # the class, and with it the favoured value, inside the drift
+            boundary = (_close(r["own_hmax"][i], 0.0, drift)
+                        or _close(r["forced_hmax"][i], 0.0, drift))
+            if r["own_g"][i] == fg[i]:
+                # same VN, other value: the favoured value follows the sign of its key
+                assert boundary or _close(r["own_key"][i], 0.0, drift), ("value", s, p, i, drift)
+            else:
+                assert boundary or _close(r["own_key"][i], r["forced_key"][i], 2 * drift), \
+                    ("select", s, p, i, r["own_key"][i], r["forced_key"][i], drift)
+
+
+def _residual_before(dem, op, det, obs, k):
+    """The detector record window k sees: the oracle decodes and commits windows
+    0..k-1 (both sides then decode window k on the same syndromes)."""
+    if k == 0:
+        return det
+    return O.decode_shots(dem, 3, op, det, obs, max_windows=k)["det_out"]
+
+
+@gpu
+@pytest.mark.parametrize("k", [0, 1, 4])
+def test_window_decode_c1(k):
+    g = _g()
+    dem = c1_dem()
+    op = O.params(alpha=0.625)
+    e = sample_errors(dem.thresholds(), 400, seed=0)
+    det, obs = syndromes(dem, e)
+    det = _residual_before(dem, op, det, obs, k)
+    _compare_window(dem, k, g.params(**C1), op, det)
+
+
+@gpu
+@pytest.mark.parametrize("p", [0.002, 0.003])
+@pytest.mark.parametrize("k", [0, 5, 9])
+def test_window_decode_c2(p, k):
+    g = _g()
+    dem = c2_dem("144", 12, p)
+    e = sample_errors(dem.thresholds(), 120, seed=7)
+    det, obs = syndromes(dem, e)
+    cp = c2_params(p)
+    op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=cp["low_error"])
+    det = _residual_before(dem, op, det, obs, k)
+    _compare_window(dem, k, g.params(**cp), op, det, require_exact=0.9)
+
+
+@gpu
+def test_window_first_step_posteriors():
+    """Posteriors of the main path after its first step (before any
+    decimation) within 1e-4 relative of the oracle on the same sub-graph."""
+    g = _g()
+    dem = c2_dem("144", 12, 0.003)
+    e = sample_errors(dem.thresholds(), 60, seed=3)
+    det, obs = syndromes(dem, e)
+    cp = c2_params(0.003)
+    op0 = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
+    det = _residual_before(dem, op0, det, obs, 4)
+    w = g.Window(dem, 4, 3, g.params(**cp))
+    ow = O.OracleWindow(dem, 4, 3)
+    op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
+    syn = np.ascontiguousarray(det[:, w.row0:w.row0 + w.m])
+    _, _, _, tr = w.decode(torch.from_numpy(det).cuda(), syn_offset=w.row0, trace=True)
+    torch.cuda.synchronize()
+    fp = tr["first_post"].cpu().numpy()
+    sel = tr["sel"].cpu().numpy()
+    checked = 0
+    for s in range(det.shape[0]):
+        if sel[s][0] < 0:
+            continue          # preprocessing alone met the syndrome
+        # the oracle runs the main path on the GPU's kept columns (ranking ties
+        # may order near-equal columns differently)
+        r = O.OracleWindow.replay(ow, op, syn[s], sel[s], 0, [], [])
+        act = np.isfinite(fp[s])
+        assert (act == np.isfinite(r["first_post"])).all(), s
+        assert _rel_ok(fp[s][act], r["first_post"][act]).all(), s
+        checked += 1
+    assert checked >= 20
+
+
+# ------------------------------------------------------------------ whole shots
+
+def _pipeline(dem, gp, op, n_shots, seed):
+    g = _g()
+    e = sample_errors(dem.thresholds(), n_shots, seed=seed)
+    det, obs = syndromes(dem, e)
+    dec = g.SlidingWindowDecoder(dem, gp, W=3)
+    d = torch.from_numpy(det).cuda()
+    o = torch.from_numpy(obs).cuda()
+    fail, wf = dec.decode(d, o)
+    torch.cuda.synchronize()
+    ref = O.decode_shots(dem, 3, op, det, obs)
+    return fail.cpu().numpy().astype(bool), wf.cpu().numpy(), d.cpu().numpy(), ref
+
+
+@gpu
+def test_pipeline_c1_1000_shots():
+    """C1: [[72,12,6]] phenomenological, 1000 shots from seed 0, plain BPGD.
+    Residual detectors vanish exactly on every shot the GPU counts as a
+    success; the failure count lies in the oracle's 2-sigma Wilson interval."""
+    dem = c1_dem()
+    gf, wf, resid, ref = _pipeline(dem, _g().params(**C1), O.params(alpha=0.625), 1000, 0)
+    assert not resid[~gf].any()
+    lo, hi = wilson(int(ref["fail"].sum()), 1000)
+    assert lo * 1000 - 1e-9 <= gf.sum() <= hi * 1000 + 1e-9
+    assert (gf == ref["fail"].astype(bool)).mean() >= 0.99
+
+
+@gpu
+@pytest.mark.parametrize("p", [0.003])
+def test_pipeline_c2_ler_parity(p):
+    dem = c2_dem("144", 12, p)
+    cp = c2_params(p)
+    op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=cp["low_error"])
+    gf, wf, resid, ref = _pipeline(dem, _g().params(**cp), op, 200, 99)
+    assert not resid[~gf].any()
+    lo, hi = wilson(int(ref["fail"].sum()), 200)
+    assert lo * 200 - 1e-9 <= gf.sum() <= hi * 200 + 1e-9
