@@ -1,0 +1,260 @@
+"""Benchmark: decoded windows/s and window latency of sliding-window GDG on
+[[144,12,12]] under circuit-level noise, one MI355X.
+
+A step is one pass of the whole decoder over one batch of synthetic shots:
+for every (3,1) window in turn, decode (preprocessing BP, ranking and
+truncation, peeling, 16 decision paths, path metric) and commit, then the
+Eq. 8 / Eq. 9 evaluation. Shots are sampled on the GPU from the circuit-level
+DEM before the timed region; every step decodes a fresh batch.
+
+Prints one JSON line (see the design doc for the field definitions).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+
+LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+BYTES_PER_EDGE_ITER = 16         # one FP32 message written and read each way
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots", type=int, default=100000, help="shots per step")
+    ap.add_argument("--p", type=float, default=0.002)
+    ap.add_argument("--code", default="144")
+    ap.add_argument("--rounds", type=int, default=12)
+    ap.add_argument("--g", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget for the oracle CPU baseline (0 = skip)")
+    ap.add_argument("--latency-windows", type=int, default=110,
+                    help="single-shot windows timed for the latency figures")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the decoder shards "
+              "shots across GPUs with no communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from gdg_inputs.bb import get_code
+    from gdg_inputs.dem import circuit_dem
+    import paper_2403_18901_amd.gdg as G
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    code = get_code(args.code)
+    dem = circuit_dem(code, args.rounds, args.p)
+    low_error = 1 if args.p <= 0.002 else 0
+    prm = G.params(alpha=1.0, g=args.g, pre_iters=8, trunc_factor=2, low_error=low_error,
+                   dmax_main=25, extra_steps=10)
+    dec = G.SlidingWindowDecoder(dem, prm, W=3)
+    ddem = G.DeviceDem(dem)
+    B = args.shots
+    nwin = dec.n_windows
+    n_batches = args.warmup + args.steps
+    batches = []
+    for i in range(n_batches):
+        det, obs = ddem.sample(B, seed=args.seed, stream=0, shot0=i * B, device=dev)
+        batches.append((det, obs))
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ehat_bufs = [torch.empty((B, w.n), dtype=torch.uint8, device=dev) for w in dec.windows]
+    pm_buf = torch.empty(B, dtype=torch.float64, device=dev)
+    fl_buf = torch.empty(B, dtype=torch.int32, device=dev)
+    fail_buf = torch.empty(B, dtype=torch.uint8, device=dev)
+    edge_buf = torch.empty(B, dtype=torch.int64, device=dev)
+
+    def run_step(det, obs, events=None, edge_sum=None):
+        for k, w in enumerate(dec.windows):
+            if events is not None:
+                events[k][0].record(stream)
+            trace = G.Trace(None, None, 0, None, None, G._ptr(edge_buf), None)
+            G._check(G.lib().gdg_decode_batch(w.h, B, G._ptr(det, w.row0), det.shape[1],
+                                               G._ptr(ehat_bufs[k]), G._ptr(pm_buf),
+                                               G._ptr(fl_buf), None, 0, G.C.byref(trace),
+                                               G._stream()))
+            if events is not None:
+                events[k][1].record(stream)
+            if edge_sum is not None:
+                edge_sum.append(edge_buf.sum())
+            w.commit(ehat_bufs[k], det, obs)
+            if events is not None:
+                events[k][2].record(stream)
+        G.evaluate(det, obs, out=fail_buf)
+        return fail_buf.sum()
+
+    for i in range(args.warmup):
+        run_step(*batches[i])
+    torch.cuda.synchronize()
+
+    all_events = []
+    edge_sums = []
+    fails = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, n_batches):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nwin)]
+        all_events.append(ev)
+        fails.append(run_step(*batches[i], events=ev, edge_sum=edge_sums))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    windows = args.steps * B * nwin
+    value = windows / elapsed
+    dec_ms = [ev[k][0].elapsed_time(ev[k][1]) for ev in all_events for k in range(nwin)]
+    win_ms = [ev[k][0].elapsed_time(ev[k][2]) for ev in all_events for k in range(nwin)]
+    edge_iters = int(sum(int(x.item()) for x in edge_sums))
+    n_fail = int(sum(int(f.item()) for f in fails))
+    shots = args.steps * B
+    P_L = n_fail / shots
+    ler_round = 1.0 - (1.0 - P_L) ** (1.0 / args.rounds) if P_L < 1 else 1.0
+
+    # roofline of the decode kernel: algorithmic LDS bytes per launch / mean launch time
+    mean_dec_s = float(np.mean(dec_ms)) / 1e3
+    launches = len(dec_ms)
+    bytes_per_launch = BYTES_PER_EDGE_ITER * edge_iters / launches
+    achieved_gbs = bytes_per_launch / mean_dec_s / 1e9
+
+    # single-shot window latency (one window of one shot, decode + commit)
+    lat = []
+    if args.latency_windows > 0:
+        det1, obs1 = ddem.sample(max(1, args.latency_windows // nwin + 1), seed=args.seed + 1,
+                                 stream=1, device=dev)
+        torch.cuda.synchronize()
+        for s in range(det1.shape[0]):
+            d = det1[s:s + 1].contiguous()
+            o = obs1[s:s + 1].contiguous()
+            for k, w in enumerate(dec.windows):
+                if len(lat) >= args.latency_windows:
+                    break
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                eh, _, _ = w.decode(d, syn_offset=w.row0)
+                w.commit(eh, d, o)
+                e1.record(stream)
+                e1.synchronize()
+                lat.append(e0.elapsed_time(e1))
+
+    if args.copy_probe:
+        # plain copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters
+        src = torch.empty(256 * 1024 * 1024, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(dem, args, nwin)
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "decode_traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            t = json.load(f)
+        if t.get("kernel_hash") == kernel_hash():
+            traffic = t.get("bytes_per_launch")
+
+    out = {
+        "metric": "decoded windows/s and p99 window latency, [[144,12,12]] GDG at matched LER",
+        "value": value,
+        "unit": "windows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"GDG g={args.g} ({1 << args.g} paths), [[{code.n},12,12]] "
+                        f"circuit-level p={args.p}, {args.rounds} rounds, (3,1) windows "
+                        f"x {nwin} per shot, {B} shots per step, FP32 messages",
+            "code": code.name, "p": args.p, "rounds": args.rounds, "W": 3, "F": 1,
+            "shots_per_step": B, "windows_per_shot": nwin,
+            "low_error_mode": bool(low_error), "pre_iters": 8, "n_act": dec.windows[1].n_act,
+            "waves_per_workgroup": dec.windows[1].info["waves"],
+            "lds_bytes": dec.windows[1].info["lds_bytes"],
+        },
+        "latency_ms": {
+            "batch_window_p50": float(np.percentile(win_ms, 50)),
+            "batch_window_p99": float(np.percentile(win_ms, 99)),
+            "single_window_p50": float(np.percentile(lat, 50)) if lat else None,
+            "single_window_p99": float(np.percentile(lat, 99)) if lat else None,
+            "single_window_max": float(np.max(lat)) if lat else None,
+            "paper_context_worst_case_cpu": 3.0,
+        },
+        "ler": {"shots": shots, "failures": n_fail, "P_L": P_L, "per_round": ler_round},
+        "edge_iters_per_s": edge_iters / (float(np.sum(dec_ms)) / 1e3),
+        "roofline": {
+            "bound": "lds",
+            "achieved": achieved_gbs,
+            "peak": LDS_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / LDS_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "gdg_decode_kernel",
+            "mean_launch_ms": mean_dec_s * 1e3,
+            "edge_iters_per_launch": edge_iters / launches,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2403_18901_amd", "csrc", "gdg_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(dem, args, nwin):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
+    from gdg_inputs.philox import sample_errors, syndromes
+    from oracle import oracle as O
+    threads = len(os.sched_getaffinity(0))
+    op = O.params(alpha=1.0, g=args.g, pre_iters=8, trunc_factor=2,
+                  low_error=1 if args.p <= 0.002 else 0)
+    # calibrate on a small sample, then size the sample to the time budget
+    n0 = max(threads, 16)
+    e = sample_errors(dem.thresholds(), n0, seed=args.seed)
+    det, obs = syndromes(dem, e)
+    t = time.perf_counter()
+    O.decode_shots(dem, 3, op, det, obs, n_threads=threads)
+    dt = time.perf_counter() - t
+    n = int(max(n0, min(20000, n0 * args.cpu_seconds / max(dt, 1e-3))))
+    e = sample_errors(dem.thresholds(), n, seed=args.seed)
+    det, obs = syndromes(dem, e)
+    t = time.perf_counter()
+    r = O.decode_shots(dem, 3, op, det, obs, n_threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": n * nwin / dt, "unit": "windows/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} shots x {nwin} windows of the same workload (first {n} shots of "
+                      f"seed {args.seed}), {dt:.1f} s, {int(r['fail'].sum())} failures"}
+
+
+if __name__ == "__main__":
+    main()

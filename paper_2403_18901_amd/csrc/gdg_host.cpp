@@ -125,6 +125,8 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
   L.pbits_words = (na + 31) / 32;
   L.obits_words = (n + 31) / 32 + 1;
   L.sorig = take(m);
+  L.psyn = take(m);
+  L.rhist = take(4 * 65);
   L.sel = take(2 * na);
   L.rptr = take(2 * (m + 1));
   L.rvn = take(2 * E);
@@ -137,7 +139,7 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
   L.pend = take(4 * P);
   L.pbits = take(4 * P * L.pbits_words);
   L.misc = take(16);
-  L.iscan = take(4 * (std::max(m, na) + 1));
+  L.iscan = take(4 * (std::max(2 * m + 1, na + 1)));
   L.obits = take(4 * L.obits_words);
   L.eacc = take(8);
   L.u_base = off;
@@ -152,6 +154,7 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
       po = align16(po + bytes);
       return o;
     };
+    L.p_cs = ptake(4 * w.e_full);
     L.p_post = ptake(4 * n);
     const int c2v_bytes = std::max(4 * w.e_full, 8 * L.sort_n);
     L.p_c2v = ptake(c2v_bytes);
@@ -160,7 +163,7 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
     prep = po;
   }
   L.p_loc = 0;   // written after the preprocessing region is dead
-  const int loc_bytes = align16(2 * n);
+  const int loc_bytes = align16(2 * n + 2 * m);   // column map and row order
   // per-wavefront path region
   int wo = 0;
   auto wtake = [&](int bytes) {
@@ -272,6 +275,9 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
     }
   }
   if (max_row > 64) return fail(GDG_ESHAPE, "a window row has more than 64 columns");
+  if (E > 65535) return fail(GDG_ESHAPE, "window has more than 65535 edges");
+  std::vector<uint32_t> row_cs(E);
+  for (int e = 0; e < E; ++e) row_cs[e] = (uint32_t)row_col[e] | ((uint32_t)(col_ptr[row_col[e]] + row_kcol[e]) << 16);
   int max_col = 0;
   for (int c = 0; c < n; ++c) {
     deg[c] = (uint8_t)col_rows[c].size();
@@ -308,6 +314,7 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   if ((rc = win->put(row_ptr, &D.row_ptr))) return rc;
   if ((rc = win->put(row_col, &D.row_col))) return rc;
   if ((rc = win->put(row_kcol, &D.row_kcol))) return rc;
+  if ((rc = win->put(row_cs, &D.row_cs))) return rc;
   if ((rc = win->put(col_ptr, &D.col_ptr))) return rc;
   if ((rc = win->put(llr, &D.llr))) return rc;
   if ((rc = win->put(win->llr64, &D.llr64))) return rc;
@@ -344,14 +351,15 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   if ((rc = win->put(op, &win->cm.obs_ptr))) return rc;
   if ((rc = win->put(oc, &win->cm.obs_col))) return rc;
 
-  // LDS plan: as many wavefronts as paths (at most 8), at least 4 when the
-  // whole-window preprocessing runs, within the per-workgroup LDS limit.
+  // LDS plan: four wavefronts (as many as paths if fewer and no whole-window
+  // preprocessing), within the per-workgroup LDS limit. Measured on MI355X for
+  // [[144,12,12]] windows: two 4-wave workgroups per CU beat one 8-wave one.
   const int limit = max_lds_per_block();
-  int waves = std::min(8, n_paths);
-  if (prm->pre_iters > 0) waves = std::max(waves, 4);
+  int waves = std::min(4, n_paths);
+  if (prm->pre_iters > 0) waves = 4;
   if (const char* env = getenv("GDG_WAVES")) {
     int v = atoi(env);
-    if (v >= 1 && v <= 16) waves = v;
+    if (v >= 1 && v <= 8) waves = v;
   }
   gdg_lds L = plan_lds(D, max_sub, waves);
   while (L.total > limit && waves > 1) {
@@ -460,7 +468,7 @@ int gdg_bp(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome, in
   if (!d_syndrome || !d_post || !d_first_ok) return fail(GDG_EINVAL, "null buffer");
   if (syn_stride < win->info.m) return fail(GDG_EINVAL, "syn_stride < m");
   const size_t lds = (size_t)((win->dev.m + 15) & ~15) + 4 * (size_t)((win->dev.n + 3) & ~3) +
-                     4 * (size_t)win->dev.e_full;
+                     8 * (size_t)win->dev.e_full;
   if (lds > (size_t)max_lds_per_block()) return fail(GDG_ESHAPE, "window does not fit in LDS");
   hipError_t e = gdg_launch_bp(win->dev, n_shots, d_syndrome, syn_stride, n_iters, d_post,
                                d_first_ok, (hipStream_t)hip_stream);

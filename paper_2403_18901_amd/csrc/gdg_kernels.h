@@ -14,6 +14,7 @@ struct gdg_win_dev {
   const int* row_ptr;       // [m+1] window CSR
   const uint16_t* row_col;  // [e_full] column of each CSR edge (ascending per row)
   const uint8_t* row_kcol;  // [e_full] position of that edge in its column's CSC list
+  const uint32_t* row_cs;   // [e_full] column | (column-order slot << 16) of each CSR edge
   const int* col_ptr;       // [n+1] window CSC
   const float* llr;         // [n] prior LLR rounded to float
   const double* llr64;      // [n] prior LLR in double (path metric, Eq. 5)
@@ -24,11 +25,11 @@ struct gdg_win_dev {
 struct gdg_lds {
   int total;
   // per shot
-  int sorig, sel, rptr, rvn, rcsc, cptr, crow, llr, deg, ppm, pend, pbits, misc, iscan, obits, eacc;
+  int sorig, psyn, rhist, sel, rptr, rvn, rcsc, cptr, crow, llr, deg, ppm, pend, pbits, misc, iscan, obits, eacc;
   int pbits_words, obits_words;
   // phase union (relative to u_base)
   int u_base;
-  int p_post, p_c2v, p_lsum, p_keys, p_loc, sort_n;
+  int p_cs, p_post, p_c2v, p_lsum, p_keys, p_loc, sort_n;
   int w_stride, w_post, w_status, w_c2v, w_unsat, w_prop, w_bits;
 };
 

@@ -98,14 +98,28 @@ __device__ void wg_exclusive_scan_wave0(int* a, int len) {
 // ------------------------------------------------------------------ whole-window BP
 //
 // Workgroup-cooperative flooding min-sum on the full window graph (used for
-// the preprocessing BP and for gdg_bp). CN-to-VN messages are kept per edge in
-// column order (c2v[col_ptr[c] + t] is the message on column c's t-th edge).
+// the preprocessing BP and for gdg_bp). The window's CSR edges are staged in
+// LDS as (column | column-order slot << 16); CN-to-VN messages are kept per
+// edge in column order (c2v[col_ptr[c] + t] is the message on column c's t-th
+// edge), so the VN phase sums contiguous entries. Loads are issued in batches
+// of kBatch edges so that their latencies overlap.
+
+constexpr int kBatch = 8;
+
+// Running two smallest magnitudes and the position of the smallest (first
+// position on ties), without branches.
+__device__ __forceinline__ void two_min(float a, int k, float& n1, float& n2, int& nidx) {
+  n2 = fminf(n2, fmaxf(n1, a));
+  nidx = a < n1 ? k : nidx;
+  n1 = fminf(n1, a);
+}
 
 struct FullBP {
   const gdg_win_dev* w;
+  const uint32_t* cs;   // [E] staged CSR edges
   float* post;          // [n]
   float* c2v;           // [E]
-  const uint8_t* syn;   // [m] in LDS
+  const uint8_t* syn;   // [m]
 };
 
 // CN phase: new messages from the posteriors and the previous messages; returns
@@ -114,38 +128,49 @@ __device__ int full_cn_phase(const FullBP& b) {
   const gdg_win_dev& w = *b.w;
   int bad = 0;
   for (int j = threadIdx.x; j < w.m; j += blockDim.x) {
-    const int e0 = w.row_ptr[j], e1 = w.row_ptr[j + 1];
+    const int e0 = w.row_ptr[j], dg = w.row_ptr[j + 1] - e0;
     float n1 = kInfF, n2 = kInfF;
     int nidx = 0, npar = b.syn[j], hx = b.syn[j];
     unsigned long long nmask = 0ull;
-    for (int e = e0; e < e1; ++e) {
-      const int c = w.row_col[e];
-      const int slot = w.col_ptr[c] + w.row_kcol[e];
-      const float pv = b.post[c];
-      hx ^= (pv <= 0.0f);
-      const float x = clampf(pv - b.c2v[slot], w.clip);
-      const float a = fabsf(x);
-      const int neg = x < 0.0f;
-      const int k = e - e0;
-      nmask |= (unsigned long long)neg << k;
-      npar ^= neg;
-      if (a < n1) {
-        n2 = n1;
-        n1 = a;
-        nidx = k;
-      } else if (a < n2) {
-        n2 = a;
+    for (int k0 = 0; k0 < dg; k0 += kBatch) {
+      uint32_t cs[kBatch];
+      float pv[kBatch], old[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) cs[i] = b.cs[e0 + min(k0 + i, dg - 1)];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        pv[i] = b.post[cs[i] & 0xffffu];
+        old[i] = b.c2v[cs[i] >> 16];
+      }
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int k = k0 + i;
+        if (k < dg) {
+          hx ^= (pv[i] <= 0.0f);
+          const float x = clampf(pv[i] - old[i], w.clip);
+          const float a = fabsf(x);
+          const int neg = x < 0.0f;
+          nmask |= (unsigned long long)neg << k;
+          npar ^= neg;
+          two_min(a, k, n1, n2, nidx);
+        }
       }
     }
-    const float m2 = n2 == kInfF ? w.clip : n2;
-    const float m1 = n1 == kInfF ? w.clip : n1;
-    for (int e = e0; e < e1; ++e) {
-      const int k = e - e0;
-      const int c = w.row_col[e];
-      const int slot = w.col_ptr[c] + w.row_kcol[e];
-      float v = w.alpha * (k == nidx ? m2 : m1);
-      if ((npar ^ (int)(nmask >> k)) & 1) v = -v;
-      b.c2v[slot] = v;
+    const float s2 = w.alpha * (n2 == kInfF ? w.clip : n2);
+    const float s1 = w.alpha * (n1 == kInfF ? w.clip : n1);
+    for (int k0 = 0; k0 < dg; k0 += kBatch) {
+      uint32_t cs[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) cs[i] = b.cs[e0 + min(k0 + i, dg - 1)];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int k = k0 + i;
+        if (k < dg) {
+          float v = k == nidx ? s2 : s1;
+          if ((npar ^ (int)(nmask >> k)) & 1) v = -v;
+          b.c2v[cs[i] >> 16] = v;
+        }
+      }
     }
     bad |= hx;
   }
@@ -157,8 +182,16 @@ __device__ int full_cn_phase(const FullBP& b) {
 __device__ void full_vn_phase(const FullBP& b, float* lsum) {
   const gdg_win_dev& w = *b.w;
   for (int c = threadIdx.x; c < w.n; c += blockDim.x) {
+    const int c0 = w.col_ptr[c], dg = w.col_ptr[c + 1] - c0;
     float s = w.llr[c];
-    for (int e = w.col_ptr[c]; e < w.col_ptr[c + 1]; ++e) s += b.c2v[e];
+    for (int k0 = 0; k0 < dg; k0 += kBatch) {
+      float x[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) x[i] = b.c2v[c0 + min(k0 + i, dg - 1)];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i)
+        if (k0 + i < dg) s += x[i];
+    }
     b.post[c] = s;
     if (lsum) lsum[c] += s;
   }
@@ -168,18 +201,26 @@ __device__ int full_check(const FullBP& b) {
   const gdg_win_dev& w = *b.w;
   int bad = 0;
   for (int j = threadIdx.x; j < w.m; j += blockDim.x) {
+    const int e0 = w.row_ptr[j], dg = w.row_ptr[j + 1] - e0;
     int hx = b.syn[j];
-    for (int e = w.row_ptr[j]; e < w.row_ptr[j + 1]; ++e) hx ^= (b.post[w.row_col[e]] <= 0.0f);
+    for (int k0 = 0; k0 < dg; k0 += kBatch) {
+      float pv[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) pv[i] = b.post[b.cs[e0 + min(k0 + i, dg - 1)] & 0xffffu];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i)
+        if (k0 + i < dg) hx ^= (pv[i] <= 0.0f);
+    }
     bad |= hx;
   }
   return bad;
 }
 
-// ------------------------------------------------------------------ decode kernel
+__device__ void stage_edges(const gdg_win_dev& w, uint32_t* cs) {
+  for (int e = threadIdx.x; e < w.e_full; e += blockDim.x) cs[e] = w.row_cs[e];
+}
 
-struct PathRegs {
-  int pid, dmax, split;
-};
+// ------------------------------------------------------------------ decode kernel
 
 __device__ __forceinline__ int path_value(const gdg_win_dev& w, int pid, int split, int D, int f) {
   if (pid == 0) return f;
@@ -213,54 +254,62 @@ __device__ __forceinline__ int agg_dec(float hsum, float hmin, float hmax, int D
 
 enum { END_CONVERGED = 1, END_EXHAUSTED = 2, END_CONTRADICTION = 3, END_NO_CANDIDATE = 4 };
 
+// State of one decision path, held by one wavefront. CN j = lane + 64 q and
+// VN v = lane + 64 r belong to this lane; their static data and message state
+// sit in registers, what other lanes read sits in LDS.
 template <int CPL, int VPL>
 struct PathCtx {
   // shared (per shot) sub-graph in LDS
-  const uint16_t* rptr;   // [m+1]
   const uint16_t* rvn;    // [E_sub] VN of each CSR edge
   const uint16_t* rcsc;   // [E_sub] column-order slot of each CSR edge
-  const uint16_t* cptr;   // [n_act+1]
   const uint16_t* crow;   // [E_sub] row of each column-order slot
-  const float* llr;       // [n_act]
-  const uint8_t* deg;     // [n_act]
-  const uint8_t* sorig;   // [m]
-  // per wavefront
-  float* post;            // [n_act] NaN = decimated
+  // per wavefront, LDS
+  float* post;            // [n_act]; +infinity once decimated
   int8_t* status;         // [n_act] -1 active, 0/1 decimated
-  float* c2v;             // [E_sub]
+  float* c2v;             // [E_sub] CN-to-VN messages in column order
   uint8_t* unsat;         // [m]
   uint32_t* prop;         // [ceil(n_act/4)] peeling proposals, one byte per VN
-  int lane;
-  int m, n;
-  // CN registers (CN j = lane + 64 q)
+  int lane, m, n;
+  // CN registers
+  int ce0[CPL], cdg[CPL], so[CPL];            // CSR start, degree, window syndrome bit
   float m1[CPL], m2[CPL];
   int idx[CPL], par[CPL], cdeg[CPL], sres[CPL];
   unsigned long long mask[CPL];
-  // VN registers (VN v = lane + 64 r): history over the last four iterations
-  float hs[VPL], hmn[VPL], hmx[VPL];
+  // VN registers
+  int vc0[VPL], vdg[VPL], st[VPL];             // CSC start, degree (sub-graph = window), status
+  float llr[VPL];
+  float hs[VPL], hmn[VPL], hmx[VPL];           // history over the last four iterations
 };
 
 // Recount every owned CN's active degree and residual syndrome from the VN
 // status, find dead CNs (no active VN, residual 1) and post peeling proposals
 // of degree-one CNs (Sec. IV-D, Appendix C).
 template <int CPL, int VPL>
-__device__ void cn_recount(PathCtx<CPL, VPL>& P, bool& dead, bool& proposed) {
+__device__ __forceinline__ void cn_recount(PathCtx<CPL, VPL>& P, bool& dead, bool& proposed) {
   dead = false;
   proposed = false;
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     const int j = P.lane + kWave * q;
     if (j < P.m) {
-      const int e0 = P.rptr[j], e1 = P.rptr[j + 1];
-      int cnt = 0, x = P.sorig[j], only = -1;
-      for (int e = e0; e < e1; ++e) {
-        const int v = P.rvn[e];
-        const int st = P.status[v];
-        if (st < 0) {
-          ++cnt;
-          only = v;
-        } else {
-          x ^= st;
+      const int e0 = P.ce0[q], dg = P.cdg[q];
+      int cnt = 0, x = P.so[q], only = 0;
+      for (int k0 = 0; k0 < dg; k0 += kBatch) {
+        int vv[kBatch], sv[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) vv[i] = P.rvn[e0 + min(k0 + i, dg - 1)];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) sv[i] = P.status[vv[i]];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+          if (k0 + i < dg) {
+            if (sv[i] < 0) {
+              ++cnt;
+              only = vv[i];
+            } else {
+              x ^= sv[i];
+            }
+          }
         }
       }
       P.cdeg[q] = cnt;
@@ -274,6 +323,19 @@ __device__ void cn_recount(PathCtx<CPL, VPL>& P, bool& dead, bool& proposed) {
   }
 }
 
+// Decimate owned VN v (register slot r). Its posterior becomes +infinity: every
+// VN-to-CN message it would send then clips to +clip with a + sign and a 0 hard
+// decision, so a CN's two-min, sign parity and syndrome check see exactly its
+// active neighbours plus entries at +clip -- which reproduces the rule that a
+// CN with a single active neighbour sends clip -- and its outgoing message to
+// the decimated VN is never read.
+template <int CPL, int VPL>
+__device__ __forceinline__ void set_status(PathCtx<CPL, VPL>& P, int r, int v, int value) {
+  P.st[r] = value;
+  P.status[v] = (int8_t)value;
+  P.post[v] = kInfF;
+}
+
 // Peeling closure in synchronous rounds. Returns false on a contradiction
 // (a dead CN, or two different proposals for one VN; then the round is not
 // applied). Leaves the CN registers recounted.
@@ -285,95 +347,98 @@ __device__ bool peel(PathCtx<CPL, VPL>& P) {
     const bool any_dead = wave_any(dead);
     const bool any_prop = wave_any(proposed);
     wave_sync();
+    if (any_dead || !any_prop) {
+      if (any_prop) {
+        for (int i = P.lane; i < (P.n + 3) / 4; i += kWave) P.prop[i] = 0u;
+        wave_sync();
+      }
+      return !any_dead;
+    }
+    uint32_t pr[VPL];
     bool conflict = false;
 #pragma unroll
     for (int r = 0; r < VPL; ++r) {
       const int v = P.lane + kWave * r;
-      if (v < P.n) {
-        const uint32_t p = (P.prop[v >> 2] >> ((v & 3) * 8)) & 3u;
-        if (p == 3u) conflict = true;
-      }
+      pr[r] = v < P.n ? (P.prop[v >> 2] >> ((v & 3) * 8)) & 3u : 0u;
+      if (pr[r] == 3u) conflict = true;
     }
     const bool any_conflict = wave_any(conflict);
-    if (any_dead || !any_prop || any_conflict) {
-      // clear proposals for the next call
-      for (int i = P.lane; i < (P.n + 3) / 4; i += kWave) P.prop[i] = 0u;
-      wave_sync();
-      return !(any_dead || any_conflict);
-    }
-#pragma unroll
-    for (int r = 0; r < VPL; ++r) {
-      const int v = P.lane + kWave * r;
-      if (v < P.n) {
-        const uint32_t p = (P.prop[v >> 2] >> ((v & 3) * 8)) & 3u;
-        if (p) {
-          P.status[v] = (int8_t)(p == 2u ? 1 : 0);
-          P.post[v] = __builtin_nanf("");
-        }
-      }
-    }
     wave_sync();
     for (int i = P.lane; i < (P.n + 3) / 4; i += kWave) P.prop[i] = 0u;
+    if (any_conflict) {
+      wave_sync();
+      return false;
+    }
+#pragma unroll
+    for (int r = 0; r < VPL; ++r)
+      if (pr[r]) set_status(P, r, P.lane + kWave * r, pr[r] == 2u ? 1 : 0);
     wave_sync();
   }
 }
 
-// One flooding CN phase. Returns this lane's OR of unsatisfied owned CNs under
-// the hard decisions of the current posteriors.
+// One flooding CN phase: new CN-to-VN messages (Eq. 1) from the extrinsic
+// VN-to-CN messages (Eq. 3, clipped) formed from the posteriors and each CN's
+// previous outgoing message. Returns this lane's OR of unsatisfied owned CNs
+// under the hard decisions (Eq. 4) of the posteriors it read. Decimated VNs
+// hold +infinity (see set_status), so no edge needs a branch.
 template <int CPL, int VPL>
 __device__ __forceinline__ int cn_phase(PathCtx<CPL, VPL>& P, float alpha, float clip) {
   int bad = 0;
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
-    const int j = P.lane + kWave * q;
-    if (j < P.m && P.cdeg[q] > 0) {
-      const int e0 = P.rptr[j], e1 = P.rptr[j + 1];
-      const float om1 = P.m1[q];
-      const float om2 = P.m2[q] == kInfF ? clip : P.m2[q];
-      const int oidx = P.idx[q], opar = P.par[q];
-      const unsigned long long omask = P.mask[q];
-      float n1 = kInfF, n2 = kInfF;
-      int nidx = 0, npar = P.sres[q], hx = P.sres[q];
-      unsigned long long nmask = 0ull, amask = 0ull;
-      for (int e = e0; e < e1; ++e) {
-        const int k = e - e0;
-        const float pv = P.post[P.rvn[e]];
-        if (pv != pv) continue;   // decimated VN: stale message ignored
-        amask |= 1ull << k;
-        hx ^= (pv <= 0.0f);
-        float old = alpha * (k == oidx ? om2 : om1);
-        if ((opar ^ (int)(omask >> k)) & 1) old = -old;
-        const float x = clampf(pv - old, clip);
-        const float a = fabsf(x);
-        const int neg = x < 0.0f;
-        nmask |= (unsigned long long)neg << k;
-        npar ^= neg;
-        if (a < n1) {
-          n2 = n1;
-          n1 = a;
-          nidx = k;
-        } else if (a < n2) {
-          n2 = a;
+    const int e0 = P.ce0[q], dg = P.cdg[q];
+    const float om1 = alpha * P.m1[q];
+    const float om2 = alpha * (P.m2[q] == kInfF ? clip : P.m2[q]);
+    const int oidx = P.idx[q];
+    const unsigned long long oneg = P.par[q] ? ~P.mask[q] : P.mask[q];   // sign of each old message
+    float n1 = kInfF, n2 = kInfF;
+    int nidx = 0, npar = P.sres[q], hx = P.sres[q];
+    unsigned long long nmask = 0ull;
+    for (int k0 = 0; k0 < dg; k0 += kBatch) {
+      int vv[kBatch];
+      float pv[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) vv[i] = P.rvn[e0 + min(k0 + i, dg - 1)];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) pv[i] = P.post[vv[i]];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int k = k0 + i;
+        if (k < dg) {
+          hx ^= (pv[i] <= 0.0f);
+          float old = k == oidx ? om2 : om1;
+          if ((oneg >> k) & 1ull) old = -old;
+          const float x = clampf(pv[i] - old, clip);
+          const int neg = x < 0.0f;
+          nmask |= (unsigned long long)neg << k;
+          npar ^= neg;
+          two_min(fabsf(x), k, n1, n2, nidx);
         }
       }
-      P.m1[q] = n1;
-      P.m2[q] = n2;
-      P.idx[q] = nidx;
-      P.par[q] = npar;
-      P.mask[q] = nmask;
-      const float s1 = alpha * n1;
-      const float s2 = alpha * (n2 == kInfF ? clip : n2);
-      while (amask) {
-        const int k = __builtin_ctzll(amask);
-        amask &= amask - 1ull;
-        float v = k == nidx ? s2 : s1;
-        if ((npar ^ (int)(nmask >> k)) & 1) v = -v;
-        P.c2v[P.rcsc[e0 + k]] = v;
-      }
-      bad |= hx;
-    } else if (j < P.m) {
-      bad |= P.sres[q];
     }
+    P.m1[q] = n1;
+    P.m2[q] = n2;
+    P.idx[q] = nidx;
+    P.par[q] = npar;
+    P.mask[q] = nmask;
+    const float s1 = alpha * n1;
+    const float s2 = alpha * (n2 == kInfF ? clip : n2);
+    const unsigned long long nneg = npar ? ~nmask : nmask;   // sign of each new message
+    for (int k0 = 0; k0 < dg; k0 += kBatch) {
+      int sl[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) sl[i] = P.rcsc[e0 + min(k0 + i, dg - 1)];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int k = k0 + i;
+        if (k < dg) {
+          float v = k == nidx ? s2 : s1;
+          if ((nneg >> k) & 1ull) v = -v;
+          P.c2v[sl[i]] = v;
+        }
+      }
+    }
+    bad |= hx;
   }
   return bad;
 }
@@ -385,10 +450,15 @@ __device__ __forceinline__ int check_pass(PathCtx<CPL, VPL>& P, bool write_unsat
   for (int q = 0; q < CPL; ++q) {
     const int j = P.lane + kWave * q;
     if (j < P.m) {
+      const int e0 = P.ce0[q], dg = P.cdg[q];
       int hx = P.sres[q];
-      for (int e = P.rptr[j]; e < P.rptr[j + 1]; ++e) {
-        const float pv = P.post[P.rvn[e]];
-        if (pv == pv) hx ^= (pv <= 0.0f);
+      for (int k0 = 0; k0 < dg; k0 += kBatch) {
+        float pv[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) pv[i] = P.post[P.rvn[e0 + min(k0 + i, dg - 1)]];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+          if (k0 + i < dg) hx ^= (pv[i] <= 0.0f);
       }
       if (write_unsat) P.unsat[j] = (uint8_t)hx;
       bad |= hx;
@@ -397,14 +467,45 @@ __device__ __forceinline__ int check_pass(PathCtx<CPL, VPL>& P, bool write_unsat
   return bad;
 }
 
+// VN phase: posteriors of the owned active VNs (Eq. 2), and the history of the
+// last four iterations of the step.
 template <int CPL, int VPL>
-__global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds L, int n_shots,
-                                                          const uint8_t* __restrict__ syn,
-                                                          long long syn_stride,
-                                                          uint8_t* __restrict__ ehat,
-                                                          double* __restrict__ pm_out,
-                                                          int* __restrict__ flags_out,
-                                                          gdg_trace_dev tr) {
+__device__ __forceinline__ long long vn_phase(PathCtx<CPL, VPL>& P, bool hist) {
+  long long edges = 0;
+#pragma unroll
+  for (int r = 0; r < VPL; ++r) {
+    const int v = P.lane + kWave * r;
+    if (v < P.n && P.st[r] < 0) {
+      const int c0 = P.vc0[r], dg = P.vdg[r];
+      float s = P.llr[r];
+      for (int k0 = 0; k0 < dg; k0 += 4) {
+        float x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = P.c2v[c0 + min(k0 + i, dg - 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (k0 + i < dg) s += x[i];
+      }
+      P.post[v] = s;
+      edges += dg;
+      if (hist) {
+        P.hs[r] += s;
+        P.hmn[r] = fminf(P.hmn[r], s);
+        P.hmx[r] = fmaxf(P.hmx[r], s);
+      }
+    }
+  }
+  return edges;
+}
+
+template <int CPL, int VPL>
+__global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds L, int n_shots,
+                                                         const uint8_t* __restrict__ syn,
+                                                         long long syn_stride,
+                                                         uint8_t* __restrict__ ehat,
+                                                         double* __restrict__ pm_out,
+                                                         int* __restrict__ flags_out,
+                                                         gdg_trace_dev tr) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int shot = blockIdx.x;
   if (shot >= n_shots) return;
@@ -414,6 +515,7 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
   const int m = w.m, n = w.n, n_act = w.n_act;
 
   uint8_t* sorig = smem + L.sorig;
+  uint8_t* psyn = smem + L.psyn;                // syndrome in sub-graph row order
   int16_t* sel = (int16_t*)(smem + L.sel);
   uint16_t* rptr = (uint16_t*)(smem + L.rptr);
   uint16_t* rvn = (uint16_t*)(smem + L.rvn);
@@ -425,7 +527,7 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
   double* ppm = (double*)(smem + L.ppm);
   int* pend = (int*)(smem + L.pend);
   uint32_t* pbits = (uint32_t*)(smem + L.pbits);
-  int* misc = (int*)(smem + L.misc);            // [0] path counter, [1] pre-converged
+  int* misc = (int*)(smem + L.misc);            // [0] path counter, [2] answer path
   int* iscan = (int*)(smem + L.iscan);          // scratch for scans, max(m, n_act) + 1
   uint32_t* obits = (uint32_t*)(smem + L.obits);  // window bitmask of the answer
   unsigned long long* eacc = (unsigned long long*)(smem + L.eacc);
@@ -446,10 +548,12 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
   if (w.pre_iters > 0) {
     FullBP b;
     b.w = &w;
+    b.cs = (const uint32_t*)(U + L.p_cs);
     b.post = (float*)(U + L.p_post);
     b.c2v = (float*)(U + L.p_c2v);
     b.syn = sorig;
     float* lsum = (float*)(U + L.p_lsum);
+    stage_edges(w, (uint32_t*)(U + L.p_cs));
     for (int c = tid; c < n; c += blockDim.x) {
       b.post[c] = w.llr[c];
       lsum[c] = 0.0f;
@@ -495,7 +599,6 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
         }
         pm_out[shot] = pm;
         flags_out[shot] = 1;
-        misc[1] = 1;
       }
       for (int c = tid; c < n; c += blockDim.x)
         ehat[(long long)shot * n + c] = (uint8_t)((obits[c >> 5] >> (c & 31)) & 1u);
@@ -562,25 +665,48 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
     __syncthreads();
     for (int v = tid; v <= n_act; v += blockDim.x) cptr[v] = (uint16_t)iscan[v];
     __syncthreads();
+    // rows in order of decreasing sub-graph degree: the lanes' q-th rows then
+    // have similar degrees, which keeps the lanes of a CN phase equally busy
+    int16_t* perm = (int16_t*)(U + L.p_loc) + n;   // after loc
+    int* rdeg = iscan;
     for (int j = tid; j < m; j += blockDim.x) {
       int cnt = 0;
       for (int e = w.row_ptr[j]; e < w.row_ptr[j + 1]; ++e) cnt += loc[w.row_col[e]] >= 0;
-      iscan[j] = cnt;
+      rdeg[j] = cnt;
     }
+    __syncthreads();
+    if (tid == 0) {
+      int* cnt = (int*)(smem + L.rhist);   // 65 degree buckets
+      for (int d = 0; d <= 64; ++d) cnt[d] = 0;
+      for (int j = 0; j < m; ++j) ++cnt[rdeg[j]];
+      int pos = 0;
+      for (int d = 64; d >= 0; --d) {
+        const int c = cnt[d];
+        cnt[d] = pos;
+        pos += c;
+      }
+      for (int j = 0; j < m; ++j) perm[cnt[rdeg[j]]++] = (int16_t)j;
+    }
+    __syncthreads();
+    for (int pj = tid; pj < m; pj += blockDim.x) iscan[m + 1 + pj] = rdeg[perm[pj]];
+    __syncthreads();
+    for (int pj = tid; pj < m; pj += blockDim.x) rdeg[pj] = iscan[m + 1 + pj];
     __syncthreads();
     wg_exclusive_scan_wave0(iscan, m);
     __syncthreads();
     for (int j = tid; j <= m; j += blockDim.x) rptr[j] = (uint16_t)iscan[j];
     __syncthreads();
-    for (int j = tid; j < m; j += blockDim.x) {
-      int pos = rptr[j];
+    for (int pj = tid; pj < m; pj += blockDim.x) {
+      const int j = perm[pj];
+      psyn[pj] = sorig[j];
+      int pos = rptr[pj];
       for (int e = w.row_ptr[j]; e < w.row_ptr[j + 1]; ++e) {
         const int v = loc[w.row_col[e]];
         if (v < 0) continue;
         const int slot = cptr[v] + w.row_kcol[e];
         rvn[pos] = (uint16_t)v;
         rcsc[pos] = (uint16_t)slot;
-        crow[slot] = (uint16_t)j;
+        crow[slot] = (uint16_t)pj;
         ++pos;
       }
     }
@@ -593,14 +719,9 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
   {
     unsigned char* Wb = U + wave * L.w_stride;
     PathCtx<CPL, VPL> P;
-    P.rptr = rptr;
     P.rvn = rvn;
     P.rcsc = rcsc;
-    P.cptr = cptr;
     P.crow = crow;
-    P.llr = sllr;
-    P.deg = sdeg;
-    P.sorig = sorig;
     P.post = (float*)(Wb + L.w_post);
     P.status = (int8_t*)(Wb + L.w_status);
     P.c2v = (float*)(Wb + L.w_c2v);
@@ -612,6 +733,22 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
     P.n = n_act;
     const int T = w.iters;
     const float alpha = w.alpha, clip = w.clip;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int j = lane + kWave * q;
+      const int jj = j < m ? j : 0;
+      P.ce0[q] = rptr[jj];
+      P.cdg[q] = j < m ? rptr[jj + 1] - rptr[jj] : 0;
+      P.so[q] = j < m ? psyn[jj] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < VPL; ++r) {
+      const int v = lane + kWave * r;
+      const int vv = v < n_act ? v : 0;
+      P.vc0[r] = cptr[vv];
+      P.vdg[r] = v < n_act ? cptr[vv + 1] - cptr[vv] : 0;
+      P.llr[r] = sllr[vv];
+    }
     for (int i = lane; i < (n_act + 3) / 4; i += kWave) P.prop[i] = 0u;
     wave_sync();
 
@@ -637,9 +774,10 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
 #pragma unroll
       for (int r = 0; r < VPL; ++r) {
         const int v = lane + kWave * r;
+        P.st[r] = -1;
         if (v < n_act) {
           P.status[v] = -1;
-          P.post[v] = sllr[v];
+          P.post[v] = P.llr[r];
         }
       }
 #pragma unroll
@@ -649,6 +787,8 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
         P.idx[q] = 0;
         P.par[q] = 0;
         P.mask[q] = 0ull;
+        P.cdeg[q] = 0;   // slots past the last row keep degree 0 and residual 0
+        P.sres[q] = 0;
       }
       wave_sync();
       int end = 0, steps = 0;
@@ -669,23 +809,7 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
             break;
           }
           wave_sync();
-          const bool hist = t > T - 4;
-#pragma unroll
-          for (int r = 0; r < VPL; ++r) {
-            const int v = lane + kWave * r;
-            if (v < n_act && P.status[v] < 0) {
-              float s = sllr[v];
-              const int c0 = cptr[v], c1 = cptr[v + 1];
-              for (int e = c0; e < c1; ++e) s += P.c2v[e];
-              P.post[v] = s;
-              my_edges += c1 - c0;
-              if (hist) {
-                P.hs[r] += s;
-                P.hmn[r] = fminf(P.hmn[r], s);
-                P.hmx[r] = fmaxf(P.hmx[r], s);
-              }
-            }
-          }
+          my_edges += vn_phase(P, t > T - 4);
           wave_sync();
         }
         if (!conv) conv = !wave_any(check_pass(P, !w.low_error) != 0);
@@ -695,12 +819,16 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
 #pragma unroll
           for (int r = 0; r < VPL; ++r) {
             const int v = lane + kWave * r;
-            if (v < n_act) sl[v] = (!conv && P.status[v] < 0) ? P.hs[r] : __builtin_nanf("");
+            if (v < n_act) sl[v] = (!conv && P.st[r] < 0) ? P.hs[r] : __builtin_nanf("");
           }
         }
         if (tr.first_post && pid == 0 && D == 1) {
-          for (int v = lane; v < n_act; v += kWave)
-            tr.first_post[(long long)shot * n_act + v] = P.post[v];
+#pragma unroll
+          for (int r = 0; r < VPL; ++r) {
+            const int v = lane + kWave * r;
+            if (v < n_act)
+              tr.first_post[(long long)shot * n_act + v] = P.st[r] < 0 ? P.post[v] : __builtin_nanf("");
+          }
         }
         if (conv) {
           end = END_CONVERGED;
@@ -718,27 +846,29 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
 #pragma unroll
         for (int r = 0; r < VPL; ++r) {
           const int v = lane + kWave * r;
-          if (v < n_act && P.status[v] < 0 && sdeg[v] >= 3) {
+          if (v < n_act && P.st[r] < 0 && P.vdg[r] >= 3) {
+            bool taken = false;
             if (!w.low_error) {
               int nu = 0;
-              for (int e = cptr[v]; e < cptr[v + 1]; ++e) nu += P.unsat[crow[e]];
+              for (int e = P.vc0[r]; e < P.vc0[r] + P.vdg[r]; ++e) nu += P.unsat[P.crow[e]];
               const int b = agg_dec(P.hs[r], P.hmn[r], P.hmx[r], D, on_main, nu);
               if (b >= 0) {
-                P.status[v] = (int8_t)b;
-                P.post[v] = __builtin_nanf("");
+                set_status(P, r, v, b);
                 ++n_agg;
-                continue;
+                taken = true;
               }
             }
-            const unsigned long long key =
-                ((unsigned long long)ord_f32(P.hs[r]) << 32) | (unsigned)v;
-            kall = key < kall ? key : kall;
-            if (P.hmx[r] <= 0.0f) kneg = key < kneg ? key : kneg;
+            if (!taken) {
+              const unsigned long long key =
+                  ((unsigned long long)ord_f32(P.hs[r]) << 32) | (unsigned)v;
+              kall = key < kall ? key : kall;
+              if (P.hmx[r] <= 0.0f) kneg = key < kneg ? key : kneg;
+            }
           }
         }
         kall = wave_min_u64(kall);
         kneg = wave_min_u64(kneg);
-        n_agg = wave_sum_i32(n_agg);
+        if (dlog || !w.low_error) n_agg = wave_sum_i32(n_agg);
         int gsel, fav;
         if (kneg != ~0ull) {
           gsel = (int)(kneg & 0xffffffffu);
@@ -750,7 +880,6 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
           gsel = -1;
           fav = 0;
         }
-        wave_sync();
         if (gsel < 0) {
           if (dlog && lane == 0 && D - 1 < tr.log_cap) {
             dlog[(D - 1) * 3 + 0] = -1;
@@ -761,14 +890,13 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
           break;
         }
         const int val = path_value(w, pid, split, D, fav);
-        if (lane == 0) {
-          P.status[gsel] = (int8_t)val;
-          P.post[gsel] = __builtin_nanf("");
-          if (dlog && D - 1 < tr.log_cap) {
-            dlog[(D - 1) * 3 + 0] = gsel;
-            dlog[(D - 1) * 3 + 1] = val;
-            dlog[(D - 1) * 3 + 2] = n_agg;
-          }
+#pragma unroll
+        for (int r = 0; r < VPL; ++r)
+          if (lane + kWave * r == gsel) set_status(P, r, gsel, val);
+        if (dlog && lane == 0 && D - 1 < tr.log_cap) {
+          dlog[(D - 1) * 3 + 0] = gsel;
+          dlog[(D - 1) * 3 + 1] = val;
+          dlog[(D - 1) * 3 + 2] = n_agg;
         }
         wave_sync();
         if (!peel(P)) {
@@ -779,9 +907,10 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
       if (end == 0) end = END_EXHAUSTED;   // dmax < 1
       if (dlog) {
         // entries past the last logged step
-        const int first_free = (end == END_NO_CANDIDATE) ? steps : steps - (end == END_CONTRADICTION ? 0 : 1);
+        const int first_free =
+            (end == END_CONVERGED || end == END_EXHAUSTED) ? steps - 1 : steps;
         for (int i = lane; i < tr.log_cap; i += kWave) {
-          if (i >= first_free && i >= 0) {
+          if (i >= first_free) {
             dlog[i * 3 + 0] = -1;
             dlog[i * 3 + 1] = -1;
             dlog[i * 3 + 2] = -1;
@@ -804,10 +933,7 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
       for (int r = 0; r < VPL; ++r) {
         const int v = lane + kWave * r;
         bool one = false;
-        if (v < n_act) {
-          const int st = P.status[v];
-          one = st >= 0 ? st == 1 : P.post[v] <= 0.0f;
-        }
+        if (v < n_act) one = P.st[r] >= 0 ? P.st[r] == 1 : P.post[v] <= 0.0f;
         const unsigned long long bal = __ballot(one);
         if (lane == 0 && kWave * r < n_act) {
           mybits[2 * r] = (uint32_t)bal;
@@ -890,11 +1016,11 @@ __global__ __launch_bounds__(1024) void gdg_decode_kernel(gdg_win_dev w, gdg_lds
 
 // ------------------------------------------------------------------ plain BP
 
-__global__ __launch_bounds__(1024) void gdg_bp_kernel(gdg_win_dev w, int n_shots,
-                                                      const uint8_t* __restrict__ syn,
-                                                      long long syn_stride, int n_iters,
-                                                      float* __restrict__ post_out,
-                                                      int* __restrict__ first_ok) {
+__global__ __launch_bounds__(256) void gdg_bp_kernel(gdg_win_dev w, int n_shots,
+                                                     const uint8_t* __restrict__ syn,
+                                                     long long syn_stride, int n_iters,
+                                                     float* __restrict__ post_out,
+                                                     int* __restrict__ first_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int shot = blockIdx.x;
   if (shot >= n_shots) return;
@@ -902,12 +1028,15 @@ __global__ __launch_bounds__(1024) void gdg_bp_kernel(gdg_win_dev w, int n_shots
   uint8_t* s = smem;
   float* post = (float*)(smem + ((w.m + 15) & ~15));
   float* c2v = post + ((w.n + 3) & ~3);
+  uint32_t* cs = (uint32_t*)(c2v + w.e_full);
   for (int j = tid; j < w.m; j += blockDim.x) s[j] = syn[(long long)shot * syn_stride + j] & 1;
   for (int c = tid; c < w.n; c += blockDim.x) post[c] = w.llr[c];
   for (int e = tid; e < w.e_full; e += blockDim.x) c2v[e] = 0.0f;
+  stage_edges(w, cs);
   __syncthreads();
   FullBP b;
   b.w = &w;
+  b.cs = cs;
   b.post = post;
   b.c2v = c2v;
   b.syn = s;
@@ -1070,7 +1199,7 @@ hipError_t gdg_decode_set_lds_limit(const gdg_win_dev& w, int bytes) {
 hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, long long stride,
                          int n_iters, float* post, int* first_ok, hipStream_t st) {
   const size_t lds = (size_t)((w.m + 15) & ~15) + 4 * (size_t)((w.n + 3) & ~3) +
-                     4 * (size_t)w.e_full;
+                     8 * (size_t)w.e_full;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)gdg_bp_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
