@@ -173,7 +173,8 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
   };
   L.w_post = wtake(4 * na);
   L.w_status = wtake(na);
-  L.w_c2v = wtake(4 * E);
+  L.w_c2v = wtake(4 * (E + 1));   // + one slot that padded edges write into
+  L.w_c2v_dummy = E;
   L.w_unsat = wtake(m);
   L.w_prop = wtake(4 * ((na + 3) / 4));
   L.w_bits = wtake(4 * L.obits_words);

@@ -77,7 +77,6 @@ __device__ __forceinline__ int wave_incl_scan(int x, int lane) {
   return x;
 }
 
-__device__ __forceinline__ float clampf(float x, float c) { return fminf(fmaxf(x, -c), c); }
 
 // Exclusive prefix sum in place over a[0..len) (int32 in LDS) by wavefront 0;
 // a[len] receives the total. Caller synchronises the workgroup around it.
@@ -107,11 +106,19 @@ __device__ void wg_exclusive_scan_wave0(int* a, int len) {
 constexpr int kBatch = 8;
 
 // Running two smallest magnitudes and the position of the smallest (first
-// position on ties), without branches.
+// position on ties), without branches: with n1 <= n2 the new second smallest is
+// the median of (n1, n2, a) and the new smallest the median of (n1, a, -inf).
 __device__ __forceinline__ void two_min(float a, int k, float& n1, float& n2, int& nidx) {
-  n2 = fminf(n2, fmaxf(n1, a));
+  n2 = __builtin_amdgcn_fmed3f(n1, n2, a);
   nidx = a < n1 ? k : nidx;
-  n1 = fminf(n1, a);
+  n1 = __builtin_amdgcn_fmed3f(n1, a, -kInfF);
+}
+
+__device__ __forceinline__ float clip_to(float x, float c) { return __builtin_amdgcn_fmed3f(x, -c, c); }
+
+// Bit k (0..31) of w moved to the sign position.
+__device__ __forceinline__ uint32_t bit_to_sign(uint32_t w, int k) {
+  return (w << (31 - k)) & 0x80000000u;
 }
 
 struct FullBP {
@@ -124,14 +131,18 @@ struct FullBP {
 
 // CN phase: new messages from the posteriors and the previous messages; returns
 // this thread's OR of "row j unsatisfied by the hard decisions of post".
+// Edges past a row's end are padded with a +infinity posterior, which clips to
+// +clip with a + sign and a 0 hard decision (see set_status); with at least one
+// real edge this reproduces the single-neighbour rule, so no edge needs a branch.
 __device__ int full_cn_phase(const FullBP& b) {
   const gdg_win_dev& w = *b.w;
+  const float clip = w.clip;
   int bad = 0;
   for (int j = threadIdx.x; j < w.m; j += blockDim.x) {
     const int e0 = w.row_ptr[j], dg = w.row_ptr[j + 1] - e0;
     float n1 = kInfF, n2 = kInfF;
-    int nidx = 0, npar = b.syn[j], hx = b.syn[j];
-    unsigned long long nmask = 0ull;
+    int nidx = 0, hcnt = 0;
+    uint32_t nlo = 0u, nhi = 0u;
     for (int k0 = 0; k0 < dg; k0 += kBatch) {
       uint32_t cs[kBatch];
       float pv[kBatch], old[kBatch];
@@ -142,37 +153,38 @@ __device__ int full_cn_phase(const FullBP& b) {
         pv[i] = b.post[cs[i] & 0xffffu];
         old[i] = b.c2v[cs[i] >> 16];
       }
+      uint32_t nw = 0u;
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) {
         const int k = k0 + i;
-        if (k < dg) {
-          hx ^= (pv[i] <= 0.0f);
-          const float x = clampf(pv[i] - old[i], w.clip);
-          const float a = fabsf(x);
-          const int neg = x < 0.0f;
-          nmask |= (unsigned long long)neg << k;
-          npar ^= neg;
-          two_min(a, k, n1, n2, nidx);
-        }
+        const float p = k < dg ? pv[i] : kInfF;
+        hcnt += p <= 0.0f;
+        const float x = clip_to(p - old[i], clip);
+        nw |= (__float_as_uint(x) >> 31) << (k & 31);
+        two_min(fabsf(x), k, n1, n2, nidx);
       }
+      if (k0 < 32) nlo |= nw; else nhi |= nw;
     }
-    const float s2 = w.alpha * (n2 == kInfF ? w.clip : n2);
-    const float s1 = w.alpha * (n1 == kInfF ? w.clip : n1);
+    const int npar = (b.syn[j] ^ __builtin_popcount(nlo) ^ __builtin_popcount(nhi)) & 1;
+    const uint32_t flip = npar ? ~0u : 0u;
+    const uint32_t wlo = nlo ^ flip, whi = nhi ^ flip;   // sign bit of each new message
+    const float s2 = w.alpha * (n2 == kInfF ? clip : n2);
+    const float s1 = w.alpha * (n1 == kInfF ? clip : n1);
     for (int k0 = 0; k0 < dg; k0 += kBatch) {
       uint32_t cs[kBatch];
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) cs[i] = b.cs[e0 + min(k0 + i, dg - 1)];
+      const uint32_t ww = k0 < 32 ? wlo : whi;
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) {
         const int k = k0 + i;
         if (k < dg) {
-          float v = k == nidx ? s2 : s1;
-          if ((npar ^ (int)(nmask >> k)) & 1) v = -v;
-          b.c2v[cs[i] >> 16] = v;
+          const float mag = k == nidx ? s2 : s1;
+          b.c2v[cs[i] >> 16] = __uint_as_float(__float_as_uint(mag) ^ bit_to_sign(ww, k & 31));
         }
       }
     }
-    bad |= hx;
+    bad |= b.syn[j] ^ (hcnt & 1);
   }
   return bad;
 }
@@ -202,16 +214,15 @@ __device__ int full_check(const FullBP& b) {
   int bad = 0;
   for (int j = threadIdx.x; j < w.m; j += blockDim.x) {
     const int e0 = w.row_ptr[j], dg = w.row_ptr[j + 1] - e0;
-    int hx = b.syn[j];
+    int hcnt = 0;
     for (int k0 = 0; k0 < dg; k0 += kBatch) {
       float pv[kBatch];
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) pv[i] = b.post[b.cs[e0 + min(k0 + i, dg - 1)] & 0xffffu];
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i)
-        if (k0 + i < dg) hx ^= (pv[i] <= 0.0f);
+      for (int i = 0; i < kBatch; ++i) hcnt += (k0 + i < dg) && pv[i] <= 0.0f;
     }
-    bad |= hx;
+    bad |= b.syn[j] ^ (hcnt & 1);
   }
   return bad;
 }
@@ -270,11 +281,12 @@ struct PathCtx {
   uint8_t* unsat;         // [m]
   uint32_t* prop;         // [ceil(n_act/4)] peeling proposals, one byte per VN
   int lane, m, n;
+  int dummy;              // c2v slot written by padded edges
   // CN registers
   int ce0[CPL], cdg[CPL], so[CPL];            // CSR start, degree, window syndrome bit
   float m1[CPL], m2[CPL];
   int idx[CPL], par[CPL], cdeg[CPL], sres[CPL];
-  unsigned long long mask[CPL];
+  uint32_t mlo[CPL], mhi[CPL];                 // sign bits of the last messages into each CN
   // VN registers
   int vc0[VPL], vdg[VPL], st[VPL];             // CSC start, degree (sub-graph = window), status
   float llr[VPL];
@@ -290,30 +302,26 @@ __device__ __forceinline__ void cn_recount(PathCtx<CPL, VPL>& P, bool& dead, boo
   proposed = false;
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
-    const int j = P.lane + kWave * q;
-    if (j < P.m) {
-      const int e0 = P.ce0[q], dg = P.cdg[q];
-      int cnt = 0, x = P.so[q], only = 0;
-      for (int k0 = 0; k0 < dg; k0 += kBatch) {
-        int vv[kBatch], sv[kBatch];
+    const int e0 = P.ce0[q], dg = P.cdg[q];
+    int cnt = 0, x = P.so[q], only = 0;
+    for (int k0 = 0; k0 < dg; k0 += kBatch) {
+      int vv[kBatch], sv[kBatch];
 #pragma unroll
-        for (int i = 0; i < kBatch; ++i) vv[i] = P.rvn[e0 + min(k0 + i, dg - 1)];
+      for (int i = 0; i < kBatch; ++i) vv[i] = P.rvn[e0 + min(k0 + i, dg - 1)];
 #pragma unroll
-        for (int i = 0; i < kBatch; ++i) sv[i] = P.status[vv[i]];
+      for (int i = 0; i < kBatch; ++i) sv[i] = P.status[vv[i]];
 #pragma unroll
-        for (int i = 0; i < kBatch; ++i) {
-          if (k0 + i < dg) {
-            if (sv[i] < 0) {
-              ++cnt;
-              only = vv[i];
-            } else {
-              x ^= sv[i];
-            }
-          }
-        }
+      for (int i = 0; i < kBatch; ++i) {
+        const bool real = k0 + i < dg;
+        const bool act = real && sv[i] < 0;
+        cnt += act;
+        x ^= real && sv[i] == 1;
+        only = act ? vv[i] : only;
       }
-      P.cdeg[q] = cnt;
-      P.sres[q] = x;
+    }
+    P.cdeg[q] = cnt;
+    P.sres[q] = x;
+    if (P.lane + kWave * q < P.m) {
       if (cnt == 0 && x) dead = true;
       if (cnt == 1) {
         atomicOr(&P.prop[only >> 2], (1u << x) << ((only & 3) * 8));
@@ -380,7 +388,9 @@ __device__ bool peel(PathCtx<CPL, VPL>& P) {
 // VN-to-CN messages (Eq. 3, clipped) formed from the posteriors and each CN's
 // previous outgoing message. Returns this lane's OR of unsatisfied owned CNs
 // under the hard decisions (Eq. 4) of the posteriors it read. Decimated VNs
-// hold +infinity (see set_status), so no edge needs a branch.
+// and batch padding hold +infinity (see set_status), so no edge needs a branch.
+// The sign of a message is the sign bit of x: x is never -0, since posteriors
+// are sums that start at a positive prior (exact cancellation rounds to +0).
 template <int CPL, int VPL>
 __device__ __forceinline__ int cn_phase(PathCtx<CPL, VPL>& P, float alpha, float clip) {
   int bad = 0;
@@ -390,10 +400,11 @@ __device__ __forceinline__ int cn_phase(PathCtx<CPL, VPL>& P, float alpha, float
     const float om1 = alpha * P.m1[q];
     const float om2 = alpha * (P.m2[q] == kInfF ? clip : P.m2[q]);
     const int oidx = P.idx[q];
-    const unsigned long long oneg = P.par[q] ? ~P.mask[q] : P.mask[q];   // sign of each old message
+    const uint32_t oflip = P.par[q] ? ~0u : 0u;
+    const uint32_t olo = P.mlo[q] ^ oflip, ohi = P.mhi[q] ^ oflip;   // signs of the old messages
     float n1 = kInfF, n2 = kInfF;
-    int nidx = 0, npar = P.sres[q], hx = P.sres[q];
-    unsigned long long nmask = 0ull;
+    int nidx = 0, hcnt = 0;
+    uint32_t nlo = 0u, nhi = 0u;
     for (int k0 = 0; k0 < dg; k0 += kBatch) {
       int vv[kBatch];
       float pv[kBatch];
@@ -401,44 +412,46 @@ __device__ __forceinline__ int cn_phase(PathCtx<CPL, VPL>& P, float alpha, float
       for (int i = 0; i < kBatch; ++i) vv[i] = P.rvn[e0 + min(k0 + i, dg - 1)];
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) pv[i] = P.post[vv[i]];
+      const uint32_t ow = k0 < 32 ? olo : ohi;
+      uint32_t nw = 0u;
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) {
         const int k = k0 + i;
-        if (k < dg) {
-          hx ^= (pv[i] <= 0.0f);
-          float old = k == oidx ? om2 : om1;
-          if ((oneg >> k) & 1ull) old = -old;
-          const float x = clampf(pv[i] - old, clip);
-          const int neg = x < 0.0f;
-          nmask |= (unsigned long long)neg << k;
-          npar ^= neg;
-          two_min(fabsf(x), k, n1, n2, nidx);
-        }
+        const float p = k < dg ? pv[i] : kInfF;
+        hcnt += p <= 0.0f;
+        const float mag = k == oidx ? om2 : om1;
+        const float old = __uint_as_float(__float_as_uint(mag) ^ bit_to_sign(ow, k & 31));
+        const float x = clip_to(p - old, clip);
+        nw |= (__float_as_uint(x) >> 31) << (k & 31);
+        two_min(fabsf(x), k, n1, n2, nidx);
       }
+      if (k0 < 32) nlo |= nw; else nhi |= nw;
     }
+    const int npar = (P.sres[q] ^ __builtin_popcount(nlo) ^ __builtin_popcount(nhi)) & 1;
     P.m1[q] = n1;
     P.m2[q] = n2;
     P.idx[q] = nidx;
     P.par[q] = npar;
-    P.mask[q] = nmask;
+    P.mlo[q] = nlo;
+    P.mhi[q] = nhi;
     const float s1 = alpha * n1;
     const float s2 = alpha * (n2 == kInfF ? clip : n2);
-    const unsigned long long nneg = npar ? ~nmask : nmask;   // sign of each new message
+    const uint32_t nflip = npar ? ~0u : 0u;
+    const uint32_t wlo = nlo ^ nflip, whi = nhi ^ nflip;   // signs of the new messages
     for (int k0 = 0; k0 < dg; k0 += kBatch) {
       int sl[kBatch];
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) sl[i] = P.rcsc[e0 + min(k0 + i, dg - 1)];
+      const uint32_t ww = k0 < 32 ? wlo : whi;
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) {
         const int k = k0 + i;
-        if (k < dg) {
-          float v = k == nidx ? s2 : s1;
-          if ((nneg >> k) & 1ull) v = -v;
-          P.c2v[sl[i]] = v;
-        }
+        const float mag = k == nidx ? s2 : s1;
+        P.c2v[k < dg ? sl[i] : P.dummy] =
+            __uint_as_float(__float_as_uint(mag) ^ bit_to_sign(ww, k & 31));
       }
     }
-    bad |= hx;
+    bad |= P.sres[q] ^ (hcnt & 1);
   }
   return bad;
 }
@@ -449,20 +462,18 @@ __device__ __forceinline__ int check_pass(PathCtx<CPL, VPL>& P, bool write_unsat
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     const int j = P.lane + kWave * q;
-    if (j < P.m) {
-      const int e0 = P.ce0[q], dg = P.cdg[q];
-      int hx = P.sres[q];
-      for (int k0 = 0; k0 < dg; k0 += kBatch) {
-        float pv[kBatch];
+    const int e0 = P.ce0[q], dg = P.cdg[q];
+    int hcnt = 0;
+    for (int k0 = 0; k0 < dg; k0 += kBatch) {
+      float pv[kBatch];
 #pragma unroll
-        for (int i = 0; i < kBatch; ++i) pv[i] = P.post[P.rvn[e0 + min(k0 + i, dg - 1)]];
+      for (int i = 0; i < kBatch; ++i) pv[i] = P.post[P.rvn[e0 + min(k0 + i, dg - 1)]];
 #pragma unroll
-        for (int i = 0; i < kBatch; ++i)
-          if (k0 + i < dg) hx ^= (pv[i] <= 0.0f);
-      }
-      if (write_unsat) P.unsat[j] = (uint8_t)hx;
-      bad |= hx;
+      for (int i = 0; i < kBatch; ++i) hcnt += (k0 + i < dg) && pv[i] <= 0.0f;
     }
+    const int hx = P.sres[q] ^ (hcnt & 1);
+    if (write_unsat && j < P.m) P.unsat[j] = (uint8_t)hx;
+    bad |= hx;
   }
   return bad;
 }
@@ -483,8 +494,7 @@ __device__ __forceinline__ long long vn_phase(PathCtx<CPL, VPL>& P, bool hist) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) x[i] = P.c2v[c0 + min(k0 + i, dg - 1)];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (k0 + i < dg) s += x[i];
+        for (int i = 0; i < 4; ++i) s += k0 + i < dg ? x[i] : 0.0f;   // s is never -0
       }
       P.post[v] = s;
       edges += dg;
@@ -731,6 +741,7 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
     P.lane = lane;
     P.m = m;
     P.n = n_act;
+    P.dummy = L.w_c2v_dummy;
     const int T = w.iters;
     const float alpha = w.alpha, clip = w.clip;
 #pragma unroll
@@ -786,7 +797,8 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
         P.m2[q] = 0.0f;
         P.idx[q] = 0;
         P.par[q] = 0;
-        P.mask[q] = 0ull;
+        P.mlo[q] = 0u;
+        P.mhi[q] = 0u;
         P.cdeg[q] = 0;   // slots past the last row keep degree 0 and residual 0
         P.sres[q] = 0;
       }
