@@ -167,12 +167,12 @@ def main():
         cpu = cpu_baseline(dem, args, nwin)
 
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", "decode_traffic.json")
+    tpath = os.path.join(ROOT, "profiles", "decode_traffic.txt")
     if os.path.exists(tpath):
         with open(tpath) as f:
             t = json.load(f)
         if t.get("kernel_hash") == kernel_hash():
-            traffic = t.get("bytes_per_launch")
+            traffic = t["bytes_per_shot"] * B
 
     out = {
         "metric": "decoded windows/s and p99 window latency, [[144,12,12]] GDG at matched LER",
