@@ -116,6 +116,7 @@ namespace {
 gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
   gdg_lds L{};
   const int m = w.m, n = w.n, na = w.n_act, E = max_sub_edges, P = w.n_paths;
+  const int EP = E + 3 * m;   // rows padded to a multiple of 4 edges
   int off = 0;
   auto take = [&](int bytes) {
     int o = off;
@@ -129,8 +130,8 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
   L.rhist = take(4 * 65);
   L.sel = take(2 * na);
   L.rptr = take(2 * (m + 1));
-  L.rvn = take(2 * E);
-  L.rcsc = take(2 * E);
+  L.rvn = take(2 * EP);
+  L.cidx = take(2 * E);
   L.cptr = take(2 * (na + 1));
   L.crow = take(2 * E);
   L.llr = take(4 * na);
@@ -171,10 +172,9 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
     wo = align16(wo + bytes);
     return o;
   };
-  L.w_post = wtake(4 * na);
-  L.w_status = wtake(na);
-  L.w_c2v = wtake(4 * (E + 1));   // + one slot that padded edges write into
-  L.w_c2v_dummy = E;
+  L.w_post = wtake(4 * (na + 1));   // + the padding's dummy VN
+  L.w_status = wtake(na + 1);
+  L.w_c2v = wtake(4 * EP);
   L.w_unsat = wtake(m);
   L.w_prop = wtake(4 * ((na + 3) / 4));
   L.w_bits = wtake(4 * L.obits_words);
@@ -293,7 +293,7 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   std::sort(degs.begin(), degs.end(), std::greater<int>());
   int max_sub = 0;
   for (int i = 0; i < n_act; ++i) max_sub += degs[i];
-  if (max_sub > 65535 || n_act > 1024) return fail(GDG_ESHAPE, "truncated graph too large");
+  if (max_sub + 3 * m > 65535 || n_act > 1024) return fail(GDG_ESHAPE, "truncated graph too large");
   int n_paths = prm->g > 0 ? (1 << prm->g) : 1;
   if (prm->g > 0 && prm->side_max_depth > prm->g) n_paths += prm->side_max_depth - prm->g;
 

@@ -25,12 +25,12 @@ struct gdg_win_dev {
 struct gdg_lds {
   int total;
   // per shot
-  int sorig, psyn, rhist, sel, rptr, rvn, rcsc, cptr, crow, llr, deg, ppm, pend, pbits, misc, iscan, obits, eacc;
+  int sorig, psyn, rhist, sel, rptr, rvn, cidx, cptr, crow, llr, deg, ppm, pend, pbits, misc, iscan, obits, eacc;
   int pbits_words, obits_words;
   // phase union (relative to u_base)
   int u_base;
   int p_cs, p_post, p_c2v, p_lsum, p_keys, p_loc, sort_n;
-  int w_stride, w_post, w_status, w_c2v, w_c2v_dummy, w_unsat, w_prop, w_bits;
+  int w_stride, w_post, w_status, w_c2v, w_unsat, w_prop, w_bits;
 };
 
 struct gdg_trace_dev {

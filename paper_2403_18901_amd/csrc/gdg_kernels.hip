@@ -266,29 +266,31 @@ __device__ __forceinline__ int agg_dec(float hsum, float hmin, float hmax, int D
 enum { END_CONVERGED = 1, END_EXHAUSTED = 2, END_CONTRADICTION = 3, END_NO_CANDIDATE = 4 };
 
 // State of one decision path, held by one wavefront. CN j = lane + 64 q and
-// VN v = lane + 64 r belong to this lane; their static data and message state
-// sit in registers, what other lanes read sits in LDS.
+// VN v = lane + 64 r belong to this lane; their static data sit in registers,
+// what other lanes read sits in LDS. The truncated graph's rows are padded to
+// a multiple of kPad edges with a dummy VN (index n_act) whose posterior is
+// +infinity and whose status is "decimated to 0": a padded edge then behaves
+// exactly like an edge to a decimated VN (see set_status).
+constexpr int kPad = 4;
+
 template <int CPL, int VPL>
 struct PathCtx {
   // shared (per shot) sub-graph in LDS
-  const uint16_t* rvn;    // [E_sub] VN of each CSR edge
-  const uint16_t* rcsc;   // [E_sub] column-order slot of each CSR edge
+  const uint16_t* rvn;    // [E_pad] VN of each (padded) CSR edge
+  const uint16_t* cidx;   // [E_sub] CSR position of each column-order slot
   const uint16_t* crow;   // [E_sub] row of each column-order slot
   // per wavefront, LDS
-  float* post;            // [n_act]; +infinity once decimated
-  int8_t* status;         // [n_act] -1 active, 0/1 decimated
-  float* c2v;             // [E_sub] CN-to-VN messages in column order
+  float* post;            // [n_act + 1]; +infinity once decimated and for the dummy VN
+  int8_t* status;         // [n_act + 1] -1 active, 0/1 decimated
+  float* c2v;             // [E_pad] CN-to-VN messages in CSR order
   uint8_t* unsat;         // [m]
   uint32_t* prop;         // [ceil(n_act/4)] peeling proposals, one byte per VN
   int lane, m, n;
-  int dummy;              // c2v slot written by padded edges
   // CN registers
-  int ce0[CPL], cdg[CPL], so[CPL];            // CSR start, degree, window syndrome bit
-  float m1[CPL], m2[CPL];
-  int idx[CPL], par[CPL], cdeg[CPL], sres[CPL];
-  uint32_t mlo[CPL], mhi[CPL];                 // sign bits of the last messages into each CN
+  int ce0[CPL], cdg[CPL], so[CPL];            // CSR start, padded degree, window syndrome bit
+  int cdeg[CPL], sres[CPL];                    // active degree, residual syndrome
   // VN registers
-  int vc0[VPL], vdg[VPL], st[VPL];             // CSC start, degree (sub-graph = window), status
+  int vc0[VPL], vdg[VPL], st[VPL];             // CSC start, degree, status
   float llr[VPL];
   float hs[VPL], hmn[VPL], hmx[VPL];           // history over the last four iterations
 };
@@ -304,18 +306,17 @@ __device__ __forceinline__ void cn_recount(PathCtx<CPL, VPL>& P, bool& dead, boo
   for (int q = 0; q < CPL; ++q) {
     const int e0 = P.ce0[q], dg = P.cdg[q];
     int cnt = 0, x = P.so[q], only = 0;
-    for (int k0 = 0; k0 < dg; k0 += kBatch) {
-      int vv[kBatch], sv[kBatch];
+    for (int k0 = 0; k0 < dg; k0 += kPad) {
+      int vv[kPad], sv[kPad];
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i) vv[i] = P.rvn[e0 + min(k0 + i, dg - 1)];
+      for (int i = 0; i < kPad; ++i) vv[i] = P.rvn[e0 + k0 + i];
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i) sv[i] = P.status[vv[i]];
+      for (int i = 0; i < kPad; ++i) sv[i] = P.status[vv[i]];
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
-        const bool real = k0 + i < dg;
-        const bool act = real && sv[i] < 0;
+      for (int i = 0; i < kPad; ++i) {
+        const bool act = sv[i] < 0;
         cnt += act;
-        x ^= real && sv[i] == 1;
+        x ^= sv[i] == 1;
         only = act ? vv[i] : only;
       }
     }
@@ -385,70 +386,55 @@ __device__ bool peel(PathCtx<CPL, VPL>& P) {
 }
 
 // One flooding CN phase: new CN-to-VN messages (Eq. 1) from the extrinsic
-// VN-to-CN messages (Eq. 3, clipped) formed from the posteriors and each CN's
-// previous outgoing message. Returns this lane's OR of unsatisfied owned CNs
-// under the hard decisions (Eq. 4) of the posteriors it read. Decimated VNs
-// and batch padding hold +infinity (see set_status), so no edge needs a branch.
-// The sign of a message is the sign bit of x: x is never -0, since posteriors
-// are sums that start at a positive prior (exact cancellation rounds to +0).
+// VN-to-CN messages (Eq. 3, clipped), each formed from the posterior and the
+// CN's previous message on that edge (kept in CSR order next to it). Returns
+// this lane's OR of unsatisfied owned CNs under the hard decisions (Eq. 4) of
+// the posteriors it read. Decimated VNs and padding hold +infinity (see
+// set_status), so no edge needs a branch. The sign of a message is the sign bit
+// of x: x is never -0, since posteriors are sums that start at a positive prior
+// (exact cancellation rounds to +0).
 template <int CPL, int VPL>
 __device__ __forceinline__ int cn_phase(PathCtx<CPL, VPL>& P, float alpha, float clip) {
   int bad = 0;
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     const int e0 = P.ce0[q], dg = P.cdg[q];
-    const float om1 = alpha * P.m1[q];
-    const float om2 = alpha * (P.m2[q] == kInfF ? clip : P.m2[q]);
-    const int oidx = P.idx[q];
-    const uint32_t oflip = P.par[q] ? ~0u : 0u;
-    const uint32_t olo = P.mlo[q] ^ oflip, ohi = P.mhi[q] ^ oflip;   // signs of the old messages
     float n1 = kInfF, n2 = kInfF;
     int nidx = 0, hcnt = 0;
     uint32_t nlo = 0u, nhi = 0u;
-    for (int k0 = 0; k0 < dg; k0 += kBatch) {
-      int vv[kBatch];
-      float pv[kBatch];
+    for (int k0 = 0; k0 < dg; k0 += kPad) {
+      int vv[kPad];
+      float pv[kPad], ov[kPad];
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i) vv[i] = P.rvn[e0 + min(k0 + i, dg - 1)];
+      for (int i = 0; i < kPad; ++i) {
+        vv[i] = P.rvn[e0 + k0 + i];
+        ov[i] = P.c2v[e0 + k0 + i];
+      }
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i) pv[i] = P.post[vv[i]];
-      const uint32_t ow = k0 < 32 ? olo : ohi;
+      for (int i = 0; i < kPad; ++i) pv[i] = P.post[vv[i]];
       uint32_t nw = 0u;
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
+      for (int i = 0; i < kPad; ++i) {
         const int k = k0 + i;
-        const float p = k < dg ? pv[i] : kInfF;
-        hcnt += p <= 0.0f;
-        const float mag = k == oidx ? om2 : om1;
-        const float old = __uint_as_float(__float_as_uint(mag) ^ bit_to_sign(ow, k & 31));
-        const float x = clip_to(p - old, clip);
+        hcnt += pv[i] <= 0.0f;
+        const float x = clip_to(pv[i] - ov[i], clip);
         nw |= (__float_as_uint(x) >> 31) << (k & 31);
         two_min(fabsf(x), k, n1, n2, nidx);
       }
       if (k0 < 32) nlo |= nw; else nhi |= nw;
     }
     const int npar = (P.sres[q] ^ __builtin_popcount(nlo) ^ __builtin_popcount(nhi)) & 1;
-    P.m1[q] = n1;
-    P.m2[q] = n2;
-    P.idx[q] = nidx;
-    P.par[q] = npar;
-    P.mlo[q] = nlo;
-    P.mhi[q] = nhi;
     const float s1 = alpha * n1;
     const float s2 = alpha * (n2 == kInfF ? clip : n2);
     const uint32_t nflip = npar ? ~0u : 0u;
     const uint32_t wlo = nlo ^ nflip, whi = nhi ^ nflip;   // signs of the new messages
-    for (int k0 = 0; k0 < dg; k0 += kBatch) {
-      int sl[kBatch];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) sl[i] = P.rcsc[e0 + min(k0 + i, dg - 1)];
+    for (int k0 = 0; k0 < dg; k0 += kPad) {
       const uint32_t ww = k0 < 32 ? wlo : whi;
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
+      for (int i = 0; i < kPad; ++i) {
         const int k = k0 + i;
         const float mag = k == nidx ? s2 : s1;
-        P.c2v[k < dg ? sl[i] : P.dummy] =
-            __uint_as_float(__float_as_uint(mag) ^ bit_to_sign(ww, k & 31));
+        P.c2v[e0 + k] = __uint_as_float(__float_as_uint(mag) ^ bit_to_sign(ww, k & 31));
       }
     }
     bad |= P.sres[q] ^ (hcnt & 1);
@@ -464,12 +450,12 @@ __device__ __forceinline__ int check_pass(PathCtx<CPL, VPL>& P, bool write_unsat
     const int j = P.lane + kWave * q;
     const int e0 = P.ce0[q], dg = P.cdg[q];
     int hcnt = 0;
-    for (int k0 = 0; k0 < dg; k0 += kBatch) {
-      float pv[kBatch];
+    for (int k0 = 0; k0 < dg; k0 += kPad) {
+      float pv[kPad];
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i) pv[i] = P.post[P.rvn[e0 + min(k0 + i, dg - 1)]];
+      for (int i = 0; i < kPad; ++i) pv[i] = P.post[P.rvn[e0 + k0 + i]];
 #pragma unroll
-      for (int i = 0; i < kBatch; ++i) hcnt += (k0 + i < dg) && pv[i] <= 0.0f;
+      for (int i = 0; i < kPad; ++i) hcnt += pv[i] <= 0.0f;
     }
     const int hx = P.sres[q] ^ (hcnt & 1);
     if (write_unsat && j < P.m) P.unsat[j] = (uint8_t)hx;
@@ -490,9 +476,12 @@ __device__ __forceinline__ long long vn_phase(PathCtx<CPL, VPL>& P, bool hist) {
       const int c0 = P.vc0[r], dg = P.vdg[r];
       float s = P.llr[r];
       for (int k0 = 0; k0 < dg; k0 += 4) {
+        int ix[4];
         float x[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) x[i] = P.c2v[c0 + min(k0 + i, dg - 1)];
+        for (int i = 0; i < 4; ++i) ix[i] = P.cidx[c0 + min(k0 + i, dg - 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = P.c2v[ix[i]];
 #pragma unroll
         for (int i = 0; i < 4; ++i) s += k0 + i < dg ? x[i] : 0.0f;   // s is never -0
       }
@@ -529,7 +518,7 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
   int16_t* sel = (int16_t*)(smem + L.sel);
   uint16_t* rptr = (uint16_t*)(smem + L.rptr);
   uint16_t* rvn = (uint16_t*)(smem + L.rvn);
-  uint16_t* rcsc = (uint16_t*)(smem + L.rcsc);
+  uint16_t* cidx = (uint16_t*)(smem + L.cidx);
   uint16_t* cptr = (uint16_t*)(smem + L.cptr);
   uint16_t* crow = (uint16_t*)(smem + L.crow);
   float* sllr = (float*)(smem + L.llr);
@@ -698,7 +687,9 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
       for (int j = 0; j < m; ++j) perm[cnt[rdeg[j]]++] = (int16_t)j;
     }
     __syncthreads();
-    for (int pj = tid; pj < m; pj += blockDim.x) iscan[m + 1 + pj] = rdeg[perm[pj]];
+    // padded degree in sub-graph row order
+    for (int pj = tid; pj < m; pj += blockDim.x)
+      iscan[m + 1 + pj] = (rdeg[perm[pj]] + kPad - 1) / kPad * kPad;
     __syncthreads();
     for (int pj = tid; pj < m; pj += blockDim.x) rdeg[pj] = iscan[m + 1 + pj];
     __syncthreads();
@@ -715,10 +706,11 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
         if (v < 0) continue;
         const int slot = cptr[v] + w.row_kcol[e];
         rvn[pos] = (uint16_t)v;
-        rcsc[pos] = (uint16_t)slot;
+        cidx[slot] = (uint16_t)pos;
         crow[slot] = (uint16_t)pj;
         ++pos;
       }
+      for (; pos < rptr[pj + 1]; ++pos) rvn[pos] = (uint16_t)n_act;   // padding: dummy VN
     }
     if (tr.sel)
       for (int v = tid; v < n_act; v += blockDim.x) tr.sel[(long long)shot * n_act + v] = sel[v];
@@ -730,7 +722,7 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
     unsigned char* Wb = U + wave * L.w_stride;
     PathCtx<CPL, VPL> P;
     P.rvn = rvn;
-    P.rcsc = rcsc;
+    P.cidx = cidx;
     P.crow = crow;
     P.post = (float*)(Wb + L.w_post);
     P.status = (int8_t*)(Wb + L.w_status);
@@ -741,7 +733,6 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
     P.lane = lane;
     P.m = m;
     P.n = n_act;
-    P.dummy = L.w_c2v_dummy;
     const int T = w.iters;
     const float alpha = w.alpha, clip = w.clip;
 #pragma unroll
@@ -761,6 +752,11 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
       P.llr[r] = sllr[vv];
     }
     for (int i = lane; i < (n_act + 3) / 4; i += kWave) P.prop[i] = 0u;
+    if (lane == 0) {
+      P.post[n_act] = kInfF;   // dummy VN of the row padding
+      P.status[n_act] = 0;
+    }
+    const int e_pad = rptr[m];
     wave_sync();
 
     for (;;) {
@@ -793,15 +789,10 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
       }
 #pragma unroll
       for (int q = 0; q < CPL; ++q) {
-        P.m1[q] = 0.0f;
-        P.m2[q] = 0.0f;
-        P.idx[q] = 0;
-        P.par[q] = 0;
-        P.mlo[q] = 0u;
-        P.mhi[q] = 0u;
         P.cdeg[q] = 0;   // slots past the last row keep degree 0 and residual 0
         P.sres[q] = 0;
       }
+      for (int e = lane; e < e_pad; e += kWave) P.c2v[e] = 0.0f;   // t = 0: no CN message yet
       wave_sync();
       int end = 0, steps = 0;
       if (!peel(P)) end = END_CONTRADICTION;   // peel at init too
