@@ -164,6 +164,34 @@ int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_sy
                      void* hip_stream);
 
 /*
+ * Several decode jobs in one persistent launch: windows of different codes
+ * (sizes) and their shot batches share one kernel. Workgroup b decodes items
+ * b, b + workgroups, ... of the concatenated job list (jobs in the order given;
+ * put the costliest first). Same semantics per shot as gdg_decode_batch.
+ */
+#define GDG_MAX_JOBS 8
+typedef struct gdg_job {
+  const gdg_window* win;
+  int32_t n_shots;
+  const uint8_t* d_syndrome;   /* as in gdg_decode_batch */
+  int64_t syn_stride;
+  uint8_t* d_ehat;             /* [n_shots][n of this window] */
+  double* d_pm;                /* [n_shots] */
+  int32_t* d_flags;            /* [n_shots] */
+} gdg_job;
+
+typedef struct gdg_launch_cfg {
+  int32_t waves;        /* wavefronts per workgroup, 1..8 (0 = 4) */
+  int32_t workgroups;   /* persistent grid size (0 = one workgroup per shot) */
+} gdg_launch_cfg;
+
+int gdg_decode_jobs(const gdg_job* jobs, int32_t n_jobs, const gdg_launch_cfg* cfg,
+                    void* hip_stream);
+
+/* LDS bytes per workgroup the jobs need at `waves` wavefronts (negative on error). */
+int gdg_jobs_lds_bytes(const gdg_job* jobs, int32_t n_jobs, int32_t waves);
+
+/*
  * Commit (Eq. 7-8): for each shot, XOR the DEM columns of the committed window
  * columns with d_ehat = 1 into the detector record (updating the next window's
  * syndrome, s_2' = s_2 + H_2 e_1) and their observable effect into d_obs

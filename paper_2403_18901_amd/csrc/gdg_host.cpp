@@ -87,6 +87,11 @@ struct gdg_window {
   gdg_lds lds{};
   gdg_commit_dev cm{};
   int waves = 1;
+  int max_sub = 0;
+  int bucket = 0;
+  gdg_win_dev* d_dev = nullptr;   // device copy of dev
+  gdg_lds* d_plans = nullptr;     // device LDS plans for 1..8 wavefronts (index waves-1)
+  gdg_lds plans[8]{};
   std::vector<void*> allocs;
 
   ~gdg_window() {
@@ -352,28 +357,35 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   if ((rc = win->put(op, &win->cm.obs_ptr))) return rc;
   if ((rc = win->put(oc, &win->cm.obs_col))) return rc;
 
-  // LDS plan: four wavefronts (as many as paths if fewer and no whole-window
-  // preprocessing), within the per-workgroup LDS limit. Measured on MI355X for
-  // [[144,12,12]] windows: two 4-wave workgroups per CU beat one 8-wave one.
+  // Default LDS plan: four wavefronts (as many as paths if fewer and no
+  // whole-window preprocessing), within the per-workgroup LDS limit. Measured on
+  // MI355X for [[144,12,12]] windows: two 4-wave workgroups per CU beat one
+  // 8-wave one. gdg_decode_jobs may choose another shape per launch.
   const int limit = max_lds_per_block();
   int waves = std::min(4, n_paths);
   if (prm->pre_iters > 0) waves = 4;
-  if (const char* env = getenv("GDG_WAVES")) {
-    int v = atoi(env);
-    if (v >= 1 && v <= 8) waves = v;
-  }
   gdg_lds L = plan_lds(D, max_sub, waves);
   while (L.total > limit && waves > 1) {
     waves /= 2;
     L = plan_lds(D, max_sub, waves);
   }
   if (L.total > limit) return fail(GDG_ESHAPE, "window does not fit in LDS");
-  if (L.total > 65536) {
-    hipError_t e = gdg_decode_set_lds_limit(D, L.total);
-    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-  }
+  win->bucket = gdg_kernel_bucket(m, n_act);
+  if (win->bucket < 0) return fail(GDG_ESHAPE, "window exceeds the kernel's register tiling");
   win->lds = L;
   win->waves = waves;
+  win->max_sub = max_sub;
+  {
+    std::vector<gdg_win_dev> one(1, D);
+    const gdg_win_dev* p = nullptr;
+    if ((rc = win->put(one, &p))) return rc;
+    win->d_dev = const_cast<gdg_win_dev*>(p);
+    std::vector<gdg_lds> plans(8);
+    for (int wv = 1; wv <= 8; ++wv) plans[wv - 1] = win->plans[wv - 1] = plan_lds(D, max_sub, wv);
+    const gdg_lds* q = nullptr;
+    if ((rc = win->put(plans, &q))) return rc;
+    win->d_plans = const_cast<gdg_lds*>(q);
+  }
 
   gdg_window_info& I = win->info;
   I.k = k;
@@ -418,6 +430,61 @@ size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots) {
   return 0;   // the decode kernel keeps all of its state in LDS
 }
 
+}  // extern "C"
+
+namespace {
+
+int g_lds_set[3] = {65536, 65536, 65536};   // dynamic-LDS limit set per kernel bucket
+
+int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
+                const gdg_trace_dev& tr, hipStream_t st) {
+  if (!jobs || n_jobs < 1 || n_jobs > GDG_MAX_JOBS) return fail(GDG_EINVAL, "1..8 jobs per launch");
+  if (waves < 1 || waves > 8) return fail(GDG_EINVAL, "waves must be in 1..8");
+  if (workgroups < 0) return fail(GDG_EINVAL, "negative workgroup count");
+  gdg_jobs_dev J{};
+  int total = 0, lds = 0, bucket = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const gdg_job& jb = jobs[j];
+    if (!jb.win) return fail(GDG_EINVAL, "job without a window");
+    if (jb.n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+    if (jb.n_shots > 0) {
+      if (!jb.d_syndrome || !jb.d_ehat || !jb.d_pm || !jb.d_flags)
+        return fail(GDG_EINVAL, "null buffer");
+      if (jb.syn_stride < jb.win->info.m) return fail(GDG_EINVAL, "syn_stride < m");
+    }
+    gdg_job_dev& d = J.job[j];
+    d.w = jb.win->d_dev;
+    d.L = jb.win->d_plans + (waves - 1);
+    d.item0 = total;
+    d.n_shots = jb.n_shots;
+    d.syn = jb.d_syndrome;
+    d.syn_stride = jb.syn_stride;
+    d.ehat = jb.d_ehat;
+    d.pm = jb.d_pm;
+    d.flags = jb.d_flags;
+    total += jb.n_shots;
+    lds = std::max(lds, jb.win->plans[waves - 1].total);
+    bucket = std::max(bucket, jb.win->bucket);
+  }
+  J.n_jobs = n_jobs;
+  J.total = total;
+  if (total == 0) return GDG_OK;
+  if (lds > max_lds_per_block()) return fail(GDG_ESHAPE, "jobs do not fit in LDS at this shape");
+  if (lds > g_lds_set[bucket]) {
+    hipError_t e = gdg_decode_set_lds_limit(bucket, lds);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    g_lds_set[bucket] = lds;
+  }
+  const int grid = workgroups > 0 ? std::min(workgroups, total) : total;
+  hipError_t e = gdg_launch_jobs(J, bucket, waves, grid, lds, tr, st);
+  if (e != hipSuccess) return hip_fail(e, "decode launch");
+  return GDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
                      int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
                      void* d_workspace, size_t workspace_bytes, const gdg_trace* trace,
@@ -427,8 +494,6 @@ int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_sy
   if (!win) return fail(GDG_EINVAL, "null window");
   if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
   if (n_shots == 0) return GDG_OK;
-  if (!d_syndrome || !d_ehat || !d_pm || !d_flags) return fail(GDG_EINVAL, "null buffer");
-  if (syn_stride < win->info.m) return fail(GDG_EINVAL, "syn_stride < m");
   gdg_trace_dev tr{};
   if (trace) {
     tr.sel = trace->sel;
@@ -440,11 +505,29 @@ int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_sy
     tr.step_lsum = trace->step_lsum;
     if (tr.dec && tr.log_cap <= 0) return fail(GDG_EINVAL, "trace log_cap must be positive");
   }
-  hipError_t e = gdg_launch_decode(win->dev, win->lds, win->waves, n_shots, d_syndrome,
-                                   syn_stride, d_ehat, d_pm, d_flags, tr,
-                                   (hipStream_t)hip_stream);
-  if (e != hipSuccess) return hip_fail(e, "decode launch");
-  return GDG_OK;
+  gdg_job job{win, n_shots, d_syndrome, syn_stride, d_ehat, d_pm, d_flags};
+  return launch_jobs(&job, 1, win->waves, 0, tr, (hipStream_t)hip_stream);
+}
+
+int gdg_decode_jobs(const gdg_job* jobs, int32_t n_jobs, const gdg_launch_cfg* cfg,
+                    void* hip_stream) {
+  int waves = 4, workgroups = 0;
+  if (cfg) {
+    if (cfg->waves) waves = cfg->waves;
+    workgroups = cfg->workgroups;
+  }
+  gdg_trace_dev tr{};
+  return launch_jobs(jobs, n_jobs, waves, workgroups, tr, (hipStream_t)hip_stream);
+}
+
+int gdg_jobs_lds_bytes(const gdg_job* jobs, int32_t n_jobs, int32_t waves) {
+  if (!jobs || n_jobs < 1 || n_jobs > GDG_MAX_JOBS || waves < 1 || waves > 8) return GDG_EINVAL;
+  int lds = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    if (!jobs[j].win) return GDG_EINVAL;
+    lds = std::max(lds, jobs[j].win->plans[waves - 1].total);
+  }
+  return lds;
 }
 
 int gdg_commit(const gdg_window* win, int32_t n_shots, const uint8_t* d_ehat,

@@ -63,10 +63,28 @@ struct gdg_dem_dev_k {
   const uint32_t* thr;
 };
 
-hipError_t gdg_launch_decode(const gdg_win_dev& w, const gdg_lds& L, int waves, int n_shots,
-                             const uint8_t* syn, long long syn_stride, uint8_t* ehat, double* pm,
-                             int* flags, const gdg_trace_dev& tr, hipStream_t st);
-hipError_t gdg_decode_set_lds_limit(const gdg_win_dev& w, int bytes);
+// One decode job: shots [item0, item0 + n_shots) of the launch decode window
+// `w` (laid out in LDS as `L`) on syndromes syn[s*syn_stride ...].
+constexpr int kMaxJobs = 8;
+struct gdg_job_dev {
+  const gdg_win_dev* w;   // device copies, uploaded with the window
+  const gdg_lds* L;
+  int item0, n_shots;
+  const uint8_t* syn;
+  long long syn_stride;
+  uint8_t* ehat;
+  double* pm;
+  int* flags;
+};
+struct gdg_jobs_dev {
+  int n_jobs, total;
+  gdg_job_dev job[kMaxJobs];
+};
+
+hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
+                           const gdg_trace_dev& tr, hipStream_t st);
+int gdg_kernel_bucket(int m, int n_act);
+hipError_t gdg_decode_set_lds_limit(int bucket, int bytes);
 hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, long long stride,
                          int n_iters, float* post, int* first_ok, hipStream_t st);
 hipError_t gdg_launch_commit(const gdg_commit_dev& cm, int n_shots, const uint8_t* ehat,

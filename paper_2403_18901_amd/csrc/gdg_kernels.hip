@@ -497,17 +497,14 @@ __device__ __forceinline__ long long vn_phase(PathCtx<CPL, VPL>& P, bool hist) {
   return edges;
 }
 
+// Decodes shot `shot` of one window with the whole workgroup. Every thread
+// enters and leaves together; the caller synchronises before the LDS is reused.
 template <int CPL, int VPL>
-__global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds L, int n_shots,
-                                                         const uint8_t* __restrict__ syn,
-                                                         long long syn_stride,
-                                                         uint8_t* __restrict__ ehat,
-                                                         double* __restrict__ pm_out,
-                                                         int* __restrict__ flags_out,
-                                                         gdg_trace_dev tr) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int shot = blockIdx.x;
-  if (shot >= n_shots) return;
+__device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int shot,
+                            const uint8_t* __restrict__ syn, const long long syn_stride,
+                            uint8_t* __restrict__ ehat, double* __restrict__ pm_out,
+                            int* __restrict__ flags_out, const gdg_trace_dev& tr,
+                            unsigned char* smem) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid >> 6;
@@ -1017,6 +1014,25 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_win_dev w, gdg_lds 
     ehat[(long long)shot * n + c] = (uint8_t)((obits[c >> 5] >> (c & 31)) & 1u);
 }
 
+// Persistent decode: workgroup b takes items b, b + gridDim.x, ... of the job
+// table; item i belongs to the job whose first item is the largest <= i. Jobs
+// may use windows of different codes (sizes): each job carries its own LDS
+// layout within the launch's allocation.
+template <int CPL, int VPL>
+__global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int item = blockIdx.x; item < J.total; item += gridDim.x) {
+    // pick the job with static indices only (no dynamic indexing of kernel arguments)
+    gdg_job_dev jb = J.job[0];
+#pragma unroll
+    for (int t = 1; t < kMaxJobs; ++t)
+      if (t < J.n_jobs && item >= J.job[t].item0) jb = J.job[t];
+    decode_shot<CPL, VPL>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat, jb.pm,
+                          jb.flags, tr, smem);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ plain BP
 
 __global__ __launch_bounds__(256) void gdg_bp_kernel(gdg_win_dev w, int n_shots,
@@ -1165,38 +1181,37 @@ __global__ void gdg_evaluate_kernel(int n_shots, int n_rows, int n_obs,
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t gdg_launch_decode(const gdg_win_dev& w, const gdg_lds& L, int waves, int n_shots,
-                             const uint8_t* syn, long long syn_stride, uint8_t* ehat, double* pm,
-                             int* flags, const gdg_trace_dev& tr, hipStream_t st) {
-  dim3 grid(n_shots), block(waves * kWave);
-  const size_t lds = (size_t)L.total;
-  if (w.m <= 128 && w.n_act <= 384) {
-    hipLaunchKernelGGL((gdg_decode_kernel<2, 6>), grid, block, lds, st, w, L, n_shots, syn,
-                       syn_stride, ehat, pm, flags, tr);
-  } else if (w.m <= 256 && w.n_act <= 512) {
-    hipLaunchKernelGGL((gdg_decode_kernel<4, 8>), grid, block, lds, st, w, L, n_shots, syn,
-                       syn_stride, ehat, pm, flags, tr);
-  } else if (w.m <= 512 && w.n_act <= 1024) {
-    hipLaunchKernelGGL((gdg_decode_kernel<8, 16>), grid, block, lds, st, w, L, n_shots, syn,
-                       syn_stride, ehat, pm, flags, tr);
-  } else {
-    return hipErrorInvalidValue;
+hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
+                           const gdg_trace_dev& tr, hipStream_t st) {
+  dim3 g(grid), block(waves * kWave);
+  switch (bucket) {
+    case 0:
+      hipLaunchKernelGGL((gdg_decode_kernel<2, 6>), g, block, lds, st, J, tr);
+      break;
+    case 1:
+      hipLaunchKernelGGL((gdg_decode_kernel<4, 8>), g, block, lds, st, J, tr);
+      break;
+    case 2:
+      hipLaunchKernelGGL((gdg_decode_kernel<8, 16>), g, block, lds, st, J, tr);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t gdg_decode_set_lds_limit(const gdg_win_dev& w, int bytes) {
-  hipError_t e = hipSuccess;
-  if (w.m <= 128 && w.n_act <= 384)
-    e = hipFuncSetAttribute((const void*)gdg_decode_kernel<2, 6>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  else if (w.m <= 256 && w.n_act <= 512)
-    e = hipFuncSetAttribute((const void*)gdg_decode_kernel<4, 8>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  else
-    e = hipFuncSetAttribute((const void*)gdg_decode_kernel<8, 16>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  return e;
+int gdg_kernel_bucket(int m, int n_act) {
+  if (m <= 128 && n_act <= 384) return 0;
+  if (m <= 256 && n_act <= 512) return 1;
+  if (m <= 512 && n_act <= 1024) return 2;
+  return -1;
+}
+
+hipError_t gdg_decode_set_lds_limit(int bucket, int bytes) {
+  const void* f = bucket == 0   ? (const void*)gdg_decode_kernel<2, 6>
+                  : bucket == 1 ? (const void*)gdg_decode_kernel<4, 8>
+                                : (const void*)gdg_decode_kernel<8, 16>;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, long long stride,

@@ -21,8 +21,9 @@ GDG_FLAG_EXHAUSTED = 4
 GDG_FLAG_FALLBACK = 8
 
 EXPORTED = ["gdg_build_window", "gdg_window_free", "gdg_window_get_info", "gdg_window_columns",
-            "gdg_workspace_bytes", "gdg_decode_batch", "gdg_commit", "gdg_bp", "gdg_dem_upload",
-            "gdg_dem_free", "gdg_sample", "gdg_evaluate", "gdg_last_error"]
+            "gdg_workspace_bytes", "gdg_decode_batch", "gdg_decode_jobs", "gdg_jobs_lds_bytes",
+            "gdg_commit", "gdg_bp", "gdg_dem_upload", "gdg_dem_free", "gdg_sample", "gdg_evaluate",
+            "gdg_last_error"]
 
 
 class Dem(C.Structure):
@@ -51,6 +52,19 @@ class Trace(C.Structure):
                 ("step_lsum", C.c_void_p)]
 
 
+class Job(C.Structure):
+    _fields_ = [("win", C.c_void_p), ("n_shots", C.c_int32), ("d_syndrome", C.c_void_p),
+                ("syn_stride", C.c_int64), ("d_ehat", C.c_void_p), ("d_pm", C.c_void_p),
+                ("d_flags", C.c_void_p)]
+
+
+class LaunchCfg(C.Structure):
+    _fields_ = [("waves", C.c_int32), ("workgroups", C.c_int32)]
+
+
+MAX_JOBS = 8
+
+
 def params(alpha=1.0, clip=50.0, iters_per_step=6, pre_iters=0, trunc_factor=2, g=0,
            dmax_main=25, extra_steps=10, side_max_depth=0, low_error=1) -> Params:
     return Params(alpha, clip, iters_per_step, pre_iters, trunc_factor, g, dmax_main,
@@ -76,6 +90,8 @@ def lib():
         L.gdg_workspace_bytes.argtypes = [P, i32]
         L.gdg_workspace_bytes.restype = C.c_size_t
         L.gdg_decode_batch.argtypes = [P, i32, P, i64, P, P, P, P, C.c_size_t, P, P]
+        L.gdg_decode_jobs.argtypes = [P, i32, P, P]
+        L.gdg_jobs_lds_bytes.argtypes = [P, i32, i32]
         L.gdg_commit.argtypes = [P, i32, P, P, i64, P, i64, P]
         L.gdg_bp.argtypes = [P, i32, P, i64, i32, P, P, P]
         L.gdg_dem_upload.argtypes = [P, P]
@@ -188,6 +204,31 @@ class Window:
         _check(lib().gdg_bp(self.h, ns, _ptr(syn, syn_offset), syn.shape[1], n_iters, _ptr(post),
                             _ptr(first), _stream()))
         return post, first
+
+
+def decode_jobs(jobs, waves: int = 4, workgroups: int = 0):
+    """One persistent launch over several (window, syndromes, outputs) jobs.
+
+    jobs: list of (Window, syn tensor [n_shots, stride] uint8, syn_offset,
+    (ehat, pm, flags)) with ehat [n_shots, window.n] uint8, pm [n_shots] f64,
+    flags [n_shots] i32. Order matters for load balance: costliest first.
+    """
+    if not 1 <= len(jobs) <= MAX_JOBS:
+        raise ValueError(f"1..{MAX_JOBS} jobs per launch")
+    arr = (Job * len(jobs))()
+    for i, (w, syn, off, (ehat, pm, fl)) in enumerate(jobs):
+        assert syn.dtype == torch.uint8 and syn.is_contiguous() and ehat.shape[1] == w.n
+        arr[i] = Job(w.h, syn.shape[0], _ptr(syn, off), syn.shape[1], _ptr(ehat), _ptr(pm),
+                     _ptr(fl))
+    cfg = LaunchCfg(waves, workgroups)
+    _check(lib().gdg_decode_jobs(C.cast(arr, C.c_void_p), len(jobs), C.byref(cfg), _stream()))
+
+
+def jobs_lds_bytes(windows, waves: int) -> int:
+    arr = (Job * len(windows))()
+    for i, w in enumerate(windows):
+        arr[i] = Job(w.h, 0, None, w.m, None, None, None)
+    return lib().gdg_jobs_lds_bytes(C.cast(arr, C.c_void_p), len(windows), waves)
 
 
 class DeviceDem:

@@ -1,0 +1,134 @@
+"""Mixed-size persistent launches (gdg_decode_jobs) and the autotuner.
+
+A shot's result does not depend on the launch shape, so every launch shape and
+schedule must reproduce the single-window decode bit for bit (this also
+exercises the persistent item loop's LDS reuse between shots). The per-code
+windows are checked against the oracle directly, including the [[288,12,18]]
+window on the largest register tiling.
+"""
+import numpy as np
+import pytest
+
+from gdg_inputs.bb import CODE_D, get_code
+from gdg_inputs.dem import circuit_dem
+from gdg_inputs.philox import sample_errors, syndromes
+from oracle import oracle as O
+from test_gpu_parity import _compare_window, _residual_before, wilson
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+
+def _mods():
+    import paper_2403_18901_amd.batched as B
+    import paper_2403_18901_amd.gdg as G
+    return G, B
+
+
+def _prm(G, p):
+    return G.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=int(p <= 0.002))
+
+
+def _oprm(p):
+    return O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=int(p <= 0.002))
+
+
+CODES = ["72", "90", "108", "144"]
+
+
+@gpu
+def test_jobs_match_single_window_for_every_plan():
+    G, B = _mods()
+    p = 0.003
+    jobs_in = []
+    for i, key in enumerate(CODES):
+        dem = circuit_dem(get_code(key), 6, p)
+        det, _ = syndromes(dem, sample_errors(dem.thresholds(), 150 + 37 * i, seed=40 + i))
+        w = G.Window(dem, 2, 3, _prm(G, p))
+        jobs_in.append((w, torch.from_numpy(det).cuda()))
+    ref = []
+    for w, d in jobs_in:
+        e, pm, fl = w.decode(d, syn_offset=w.row0)
+        ref.append((e, pm, fl))
+    torch.cuda.synchronize()
+    windows = [w for w, _ in jobs_in]
+    plans = B.candidate_plans(windows)
+    assert len(plans) >= 6
+    for plan in plans:
+        outs = [(torch.full_like(r[0], 7), torch.full_like(r[1], -1.0), torch.full_like(r[2], -1))
+                for r in ref]
+        jobs = [(w, d, w.row0, o) for (w, d), o in zip(jobs_in, outs)]
+        jobs.sort(key=lambda j: -(j[0].n_paths * j[0].n_act))
+        plan.run(jobs)
+        torch.cuda.synchronize()
+        for (w, d), o, r in zip(jobs_in, outs, ref):
+            assert torch.equal(o[0], r[0]), plan
+            assert torch.equal(o[1], r[1]), plan
+            assert torch.equal(o[2], r[2]), plan
+
+
+@gpu
+@pytest.mark.parametrize("key", ["90", "108", "288"])
+def test_window_decode_other_codes(key):
+    """The window decoder on the other BB codes against the oracle (same bars
+    as the [[144,12,12]] windows)."""
+    G, _ = _mods()
+    p = 0.002
+    rounds = 6 if key != "288" else 4
+    dem = circuit_dem(get_code(key), rounds, p)
+    ns = 60 if key != "288" else 24
+    e = sample_errors(dem.thresholds(), ns, seed=5)
+    det, obs = syndromes(dem, e)
+    det = _residual_before(dem, _oprm(p), det, obs, 1)
+    _compare_window(dem, 1, _prm(G, p), _oprm(p), det, require_exact=0.9)
+
+
+@gpu
+def test_autotune_picks_a_measured_plan():
+    G, B = _mods()
+    p = 0.002
+    jobs = []
+    for key in ("144", "72"):
+        dem = circuit_dem(get_code(key), 6, p)
+        det, _ = syndromes(dem, sample_errors(dem.thresholds(), 2000, seed=9))
+        w = G.Window(dem, 1, 3, _prm(G, p))
+        d = torch.from_numpy(det).cuda()
+        outs = (torch.empty((d.shape[0], w.n), dtype=torch.uint8, device="cuda"),
+                torch.empty(d.shape[0], dtype=torch.float64, device="cuda"),
+                torch.empty(d.shape[0], dtype=torch.int32, device="cuda"))
+        jobs.append((w, d, w.row0, outs))
+    best, timings = B.autotune(jobs, reps=1)
+    assert best.key() in timings
+    assert timings[best.key()] == min(timings.values())
+    assert all(t > 0 for t in timings.values())
+
+
+@gpu
+def test_mixed_pipeline_ler_parity():
+    """Five BB codes decoded together window step by window step (one
+    persistent launch per step): per-code failures inside the oracle's 2-sigma
+    interval on the same shots, and residual detectors exactly zero on every
+    shot the GPU counts as a success."""
+    G, B = _mods()
+    p = 0.002
+    keys = ["72", "90", "108", "144", "288"]
+    dems, dets, obss, raw = [], [], [], []
+    for i, key in enumerate(keys):
+        rounds = min(CODE_D[key], 6)
+        dem = circuit_dem(get_code(key), rounds, p)
+        ns = 120 if key != "288" else 40
+        det, obs = syndromes(dem, sample_errors(dem.thresholds(), ns, seed=100 + i))
+        dems.append(dem)
+        raw.append((det, obs))
+        dets.append(torch.from_numpy(det).cuda())
+        obss.append(torch.from_numpy(obs).cuda())
+    md = B.MixedDecoder(dems, [_prm(G, p)] * len(dems))
+    md.plan = B.LaunchPlan(waves=4, wg_per_cu=2, split=False)
+    fails = md.decode(dets, obss)
+    torch.cuda.synchronize()
+    for key, dem, (det, obs), f, d in zip(keys, dems, raw, fails, dets):
+        gf = f.cpu().numpy().astype(bool)
+        assert not d.cpu().numpy()[~gf].any()
+        ref = O.decode_shots(dem, 3, _oprm(p), det, obs)
+        lo, hi = wilson(int(ref["fail"].sum()), len(gf))
+        assert lo * len(gf) - 1e-9 <= gf.sum() <= hi * len(gf) + 1e-9, key
