@@ -44,6 +44,9 @@ def parse():
                     help="single-shot windows timed for the latency figures")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--workload", choices=["c2", "mixed"], default="c2",
+                    help="c2: [[144,12,12]] (the headline); mixed: five BB codes in shared "
+                         "persistent launches with the autotuner")
     return ap.parse_args()
 
 
@@ -53,6 +56,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the decoder shards "
               "shots across GPUs with no communication, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "mixed":
+        return bench_mixed(args)
     import torch
     from gdg_inputs.bb import get_code
     from gdg_inputs.dem import circuit_dem
@@ -223,6 +228,80 @@ def main():
     print(json.dumps(out))
 
 
+def bench_mixed(args):
+    """Five BB codes ([[72]], [[90]], [[108]], [[144]], [[288]]), circuit-level
+    noise, d rounds each, g = 4: every window step decodes all codes still in
+    range in shared persistent launches whose shape the autotuner picked.
+    Compared with decoding the codes one after another at the default shape."""
+    import torch
+    from gdg_inputs.bb import CODE_D, get_code
+    from gdg_inputs.dem import circuit_dem
+    import paper_2403_18901_amd.batched as Bt
+    import paper_2403_18901_amd.gdg as G
+
+    dev = torch.device("cuda:0")
+    keys = ["72", "90", "108", "144", "288"]
+    B = args.shots
+    low = 1 if args.p <= 0.002 else 0
+    prm = G.params(alpha=1.0, g=args.g, pre_iters=8, trunc_factor=2, low_error=low)
+    dems = [circuit_dem(get_code(k), CODE_D[k], args.p) for k in keys]
+    md = Bt.MixedDecoder(dems, [prm] * len(dems))
+    ddems = [G.DeviceDem(d) for d in dems]
+
+    def batch(i):
+        out = [dd.sample(B, seed=args.seed, stream=c, shot0=i * B, device=dev)
+               for c, dd in enumerate(ddems)]
+        return [o[0] for o in out], [o[1] for o in out]
+
+    t = time.perf_counter()
+    dets, _ = batch(0)
+    plan, timings = md.tune(dets, reps=2)
+    tune_s = time.perf_counter() - t
+    n_windows = sum(d.n_windows for d in md.decoders) * B
+    batches = [batch(i + 1) for i in range(args.warmup + 2 * args.steps)]
+    outs = md.alloc(batches[0][0])
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        md.decode(*batches[i], outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fails = []
+    for i in range(args.warmup, args.warmup + args.steps):
+        fails.append(md.decode(*batches[i], outs=outs))
+    torch.cuda.synchronize()
+    mixed_s = time.perf_counter() - t0
+    # baseline: codes one after another, one window per launch, default shape
+    t0 = time.perf_counter()
+    for i in range(args.warmup + args.steps, args.warmup + 2 * args.steps):
+        dets, obss = batches[i]
+        for c, dec in enumerate(md.decoders):
+            dec.decode(dets[c], obss[c])
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    per_code = {}
+    for c, k in enumerate(keys):
+        nf = int(sum(int(f[c].sum().item()) for f in fails))
+        per_code[get_code(k).name] = {"rounds": CODE_D[k], "windows_per_shot": md.decoders[c].n_windows,
+                                      "failures": nf, "shots": args.steps * B}
+    out = {
+        "metric": "decoded windows/s, mixed BB codes in shared persistent launches",
+        "value": n_windows * args.steps / mixed_s,
+        "unit": "windows/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": mixed_s * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"[[72]], [[90]], [[108]], [[144]], [[288]] circuit-level p={args.p}, "
+                               f"d rounds, (3,1) windows, g={args.g}, {B} shots per code per step",
+                   "plan": repr(plan), "autotune_s": tune_s,
+                   "autotune_ms": {str(k): v for k, v in timings.items()}},
+        "sequential_windows_per_s": n_windows * args.steps / seq_s,
+        "speedup_vs_sequential": seq_s / mixed_s,
+        "per_code": per_code,
+    }
+    print(json.dumps(out))
+
+
 def kernel_hash():
     import hashlib
     h = hashlib.sha256()
@@ -238,8 +317,9 @@ def cpu_baseline(dem, args, nwin):
     threads = len(os.sched_getaffinity(0))
     op = O.params(alpha=1.0, g=args.g, pre_iters=8, trunc_factor=2,
                   low_error=1 if args.p <= 0.002 else 0)
-    # calibrate on a small sample, then size the sample to the time budget
-    n0 = max(threads, 16)
+    # calibrate on a small sample (large enough that building the windows does
+    # not dominate), then size the sample to the time budget
+    n0 = max(16 * threads, 256)
     e = sample_errors(dem.thresholds(), n0, seed=args.seed)
     det, obs = syndromes(dem, e)
     t = time.perf_counter()
