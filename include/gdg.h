@@ -39,6 +39,9 @@ extern "C" {
 #define GDG_FLAG_CONTRADICTION 2  /* every path ended in a peeling contradiction */
 #define GDG_FLAG_EXHAUSTED 4      /* no path met the syndrome and one ran to D_max */
 #define GDG_FLAG_FALLBACK 8       /* the learned proposer's answer failed; plain GDG was used */
+#define GDG_FLAG_CAPACITY 16      /* internal: the shot's truncated graph exceeded the window's
+                                     slot table (not expected: the table is sized for the worst
+                                     case); the output is not a decode */
 
 /*
  * Detector error model (Sec. II-B): the circuit-code parity-check matrix

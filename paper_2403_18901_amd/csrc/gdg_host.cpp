@@ -118,10 +118,13 @@ struct gdg_dem_dev {
 namespace {
 
 // LDS plan of the decode kernel for `waves` wavefronts per workgroup.
-gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
+// LDS layout of the decode kernel for one window. max_sub_edges bounds the
+// truncated graph's edges, col_slots its column slots padded to multiples of
+// four, tcols the slot columns of its row groups (see the kernel).
+gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tcols, int waves) {
   gdg_lds L{};
   const int m = w.m, n = w.n, na = w.n_act, E = max_sub_edges, P = w.n_paths;
-  const int EP = E + 3 * m;   // rows padded to a multiple of 4 edges
+  const int EP = E + 3 * m + 8;   // rows padded to a multiple of 4 edges, zero slot, dummy batch
   int off = 0;
   auto take = [&](int bytes) {
     int o = off;
@@ -130,22 +133,20 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
   };
   L.pbits_words = (na + 31) / 32;
   L.obits_words = (n + 31) / 32 + 1;
+  L.meta_cols = tcols;
   L.sorig = take(m);
   L.psyn = take(m);
-  L.rhist = take(4 * 65);
   L.sel = take(2 * na);
   L.rptr = take(2 * (m + 1));
   L.rvn = take(2 * EP);
-  L.cidx = take(2 * E);
+  L.cidx = take(2 * col_slots);
   L.cptr = take(2 * (na + 1));
-  L.crow = take(2 * E);
-  L.llr = take(4 * na);
-  L.deg = take(na);
+  L.crow = take(2 * col_slots);
+  L.meta = take(4 * 64 * tcols);
   L.ppm = take(8 * P);
   L.pend = take(4 * P);
   L.pbits = take(4 * P * L.pbits_words);
-  L.misc = take(16);
-  L.iscan = take(4 * (std::max(2 * m + 1, na + 1)));
+  L.misc = take(32);
   L.obits = take(4 * L.obits_words);
   L.eacc = take(8);
   L.u_base = off;
@@ -160,7 +161,6 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
       po = align16(po + bytes);
       return o;
     };
-    L.p_cs = ptake(4 * w.e_full);
     L.p_post = ptake(4 * n);
     const int c2v_bytes = std::max(4 * w.e_full, 8 * L.sort_n);
     L.p_c2v = ptake(c2v_bytes);
@@ -168,8 +168,18 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
     L.p_lsum = ptake(4 * n);
     prep = po;
   }
-  L.p_loc = 0;   // written after the preprocessing region is dead
-  const int loc_bytes = align16(2 * n + 2 * m);   // column map and row order
+  // sub-graph build scratch, written after the preprocessing region is dead
+  int bo = 0;
+  auto btake = [&](int bytes) {
+    int o = bo;
+    bo = align16(bo + bytes);
+    return o;
+  };
+  L.p_loc = btake(2 * n + 2 * m);   // column map and row order
+  L.p_iscan = btake(4 * std::max(2 * m + 2, na + 1));
+  L.p_llr = btake(4 * na);
+  L.p_deg = btake(na);
+  L.p_rhist = btake(4 * 65);
   // per-wavefront path region
   int wo = 0;
   auto wtake = [&](int bytes) {
@@ -184,9 +194,27 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int waves) {
   L.w_prop = wtake(4 * ((na + 3) / 4));
   L.w_bits = wtake(4 * L.obits_words);
   L.w_stride = wo;
-  const int uni = std::max(std::max(prep, loc_bytes), waves * L.w_stride);
+  const int uni = std::max(std::max(prep, bo), waves * L.w_stride);
   L.total = L.u_base + uni;
   return L;
+}
+
+// Most slot columns any truncation can need: rows of window degree D_j hold
+// d_j <= D_j kept edges, sum d_j <= max_sub; a row of d edges takes the power
+// of two >= ceil(d / 4) lanes. Knapsack over the edge budget.
+int slot_columns_bound(const std::vector<int>& row_deg, int max_sub) {
+  std::vector<int> dp(max_sub + 1, 0), nd;
+  static const int kD[] = {1, 5, 9, 17, 33, 65};
+  static const int kK[] = {1, 2, 4, 8, 16, 32};
+  for (int Dj : row_deg) {
+    nd = dp;
+    for (int c = 0; c < 6 && kD[c] <= Dj; ++c)
+      for (int e = kD[c]; e <= max_sub; ++e) nd[e] = std::max(nd[e], dp[e - kD[c]] + kK[c]);
+    dp.swap(nd);
+  }
+  int best = 0;
+  for (int v : dp) best = std::max(best, v);
+  return (best + 63) / 64;
 }
 
 int max_lds_per_block() {
@@ -296,9 +324,17 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   const int n_act = prm->pre_iters > 0 ? std::min(n, prm->trunc_factor * m) : n;
   std::vector<int> degs(deg.begin(), deg.end());
   std::sort(degs.begin(), degs.end(), std::greater<int>());
-  int max_sub = 0;
-  for (int i = 0; i < n_act; ++i) max_sub += degs[i];
-  if (max_sub + 3 * m > 65535 || n_act > 1024) return fail(GDG_ESHAPE, "truncated graph too large");
+  int max_sub = 0, col_slots = 0;
+  for (int i = 0; i < n_act; ++i) {
+    max_sub += degs[i];
+    col_slots += (degs[i] + 3) / 4 * 4;
+  }
+  // CSR positions (14-bit slot field) and byte offsets (16 bit) must fit
+  if (max_sub + 3 * m + 8 > 16383 || n_act > 1024) return fail(GDG_ESHAPE, "truncated graph too large");
+  std::vector<int> row_deg(m);
+  for (int r = 0; r < m; ++r) row_deg[r] = row_ptr[r + 1] - row_ptr[r];
+  const int tcols = slot_columns_bound(row_deg, max_sub);
+  if (tcols > 32) return fail(GDG_ESHAPE, "truncated graph needs more than 32 slot columns");
   int n_paths = prm->g > 0 ? (1 << prm->g) : 1;
   if (prm->g > 0 && prm->side_max_depth > prm->g) n_paths += prm->side_max_depth - prm->g;
 
@@ -364,10 +400,10 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   const int limit = max_lds_per_block();
   int waves = std::min(4, n_paths);
   if (prm->pre_iters > 0) waves = 4;
-  gdg_lds L = plan_lds(D, max_sub, waves);
+  gdg_lds L = plan_lds(D, max_sub, col_slots, tcols, waves);
   while (L.total > limit && waves > 1) {
     waves /= 2;
-    L = plan_lds(D, max_sub, waves);
+    L = plan_lds(D, max_sub, col_slots, tcols, waves);
   }
   if (L.total > limit) return fail(GDG_ESHAPE, "window does not fit in LDS");
   win->bucket = gdg_kernel_bucket(m, n_act);
@@ -381,7 +417,8 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
     if ((rc = win->put(one, &p))) return rc;
     win->d_dev = const_cast<gdg_win_dev*>(p);
     std::vector<gdg_lds> plans(8);
-    for (int wv = 1; wv <= 8; ++wv) plans[wv - 1] = win->plans[wv - 1] = plan_lds(D, max_sub, wv);
+    for (int wv = 1; wv <= 8; ++wv)
+      plans[wv - 1] = win->plans[wv - 1] = plan_lds(D, max_sub, col_slots, tcols, wv);
     const gdg_lds* q = nullptr;
     if ((rc = win->put(plans, &q))) return rc;
     win->d_plans = const_cast<gdg_lds*>(q);

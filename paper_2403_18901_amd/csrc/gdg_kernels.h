@@ -25,11 +25,13 @@ struct gdg_win_dev {
 struct gdg_lds {
   int total;
   // per shot
-  int sorig, psyn, rhist, sel, rptr, rvn, cidx, cptr, crow, llr, deg, ppm, pend, pbits, misc, iscan, obits, eacc;
-  int pbits_words, obits_words;
-  // phase union (relative to u_base)
+  int sorig, psyn, sel, rptr, rvn, cidx, cptr, crow, meta, ppm, pend, pbits, misc, obits, eacc;
+  int pbits_words, obits_words, meta_cols;
+  // phase union (relative to u_base): preprocessing, sub-graph build scratch,
+  // per-wavefront path regions
   int u_base;
-  int p_cs, p_post, p_c2v, p_lsum, p_keys, p_loc, sort_n;
+  int p_post, p_c2v, p_lsum, p_keys, sort_n;
+  int p_loc, p_iscan, p_llr, p_deg, p_rhist;
   int w_stride, w_post, w_status, w_c2v, w_unsat, w_prop, w_bits;
 };
 

@@ -8,20 +8,22 @@
 // Tanner graph in LDS. Each wavefront then runs whole decision paths of Fig. 2,
 // one at a time, taking the next path id from an LDS counter, so the long main
 // path starts first. A path's BP messages live in LDS and registers:
-//   * check node (CN) state lives in the registers of the lane that owns the
-//     CN: two smallest magnitudes, position of the smallest, the sign bits of
-//     the incoming messages and their parity (two-min + sign parity, Eq. 1);
-//   * the CN phase gathers posteriors from LDS, forms each extrinsic VN-to-CN
-//     message (Eq. 3) from the posterior and the CN's previous outgoing message,
-//     clips it, and writes the new CN-to-VN messages to an LDS array laid out
-//     by column, so the VN phase sums contiguous entries (Eq. 2);
+//   * check node (CN) rows are spread over lane groups, one batch of four
+//     edges per lane; a CN phase gathers posteriors from LDS, forms each
+//     extrinsic VN-to-CN message (Eq. 3) from the posterior and the CN's
+//     previous outgoing message, clips it, combines the group's two-min
+//     records and sign parities with cross-lane exchanges (Eq. 1) and writes
+//     the new CN-to-VN messages next to the old ones, in CSR order;
+//   * the VN phase sums each owned VN's messages through a column-order index
+//     (Eq. 2);
 //   * the syndrome check of the previous iteration's hard decisions (Eq. 4) is
 //     folded into the CN phase;
 //   * Alg. 1 is a wavefront min-reduction of 64-bit keys (order-preserving
 //     float bits << 32 | VN index), Alg. 3 and peeling are lane-parallel passes
 //     with wavefront ballots.
-// Decimated VNs keep NaN in the posterior array, which is how CNs skip their
-// stale messages (Sec. II-A). No matrix cores: the work is sparse gathers.
+// Decimated VNs hold +infinity in the posterior array, which is how CNs skip
+// their stale messages (Sec. II-A). No matrix cores: the work is sparse
+// gathers.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -265,71 +267,151 @@ __device__ __forceinline__ int agg_dec(float hsum, float hmin, float hmax, int D
 
 enum { END_CONVERGED = 1, END_EXHAUSTED = 2, END_CONTRADICTION = 3, END_NO_CANDIDATE = 4 };
 
-// State of one decision path, held by one wavefront. CN j = lane + 64 q and
-// VN v = lane + 64 r belong to this lane; their static data sit in registers,
-// what other lanes read sits in LDS. The truncated graph's rows are padded to
-// a multiple of kPad edges with a dummy VN (index n_act) whose posterior is
-// +infinity and whose status is "decimated to 0": a padded edge then behaves
-// exactly like an edge to a decimated VN (see set_status).
+// State of one decision path, held by one wavefront.
+//
+// Check nodes (CNs). The truncated graph's rows are stored in CSR order with
+// each row padded to a multiple of four edges by a dummy VN (index n_act)
+// whose posterior is +infinity and whose status is "decimated to 0": a padded
+// edge then behaves exactly like an edge to a decimated VN (see set_status).
+// A row of nb batches of four edges is spread over a group of k lanes, k the
+// power of two >= nb, one batch per lane, inside one "slot column" of 64 lanes;
+// rows sorted by decreasing degree are packed into consecutive slot columns,
+// which keeps every group aligned to its size. A CN phase walks the T slot
+// columns: each lane forms the VN-to-CN messages of its batch, the group
+// combines its two-min records and parities with cross-lane (DPP) exchanges,
+// and each lane writes the new CN-to-VN messages of its batch. Lanes of a
+// group with fewer batches than lanes, and idle lanes, point at a dummy batch
+// of four dummy edges: their messages clip to +clip and change nothing.
+//
+// Variable nodes (VNs). VN v = lane + 64 r belongs to this lane; its static
+// data sit in registers. Its column slots are padded to a multiple of four;
+// padded slots point at a CN-to-VN message fixed at zero.
 constexpr int kPad = 4;
 
-template <int CPL, int VPL>
+// Slot metadata word (one per lane and slot column).
+constexpr uint32_t kMetaEdge = 0x3fffu;      // first CSR edge of the batch
+constexpr int kMetaRowShift = 14;            // sub-graph row, 10 bits
+constexpr int kMetaLogKShift = 24;           // log2 of the group size, 3 bits
+constexpr uint32_t kMetaSyn = 1u << 27;      // window syndrome bit of the row
+constexpr uint32_t kMetaLead = 1u << 28;     // first lane of the group
+constexpr uint32_t kMetaValid = 1u << 29;    // the slot holds a row
+
+template <int VPL>
 struct PathCtx {
   // shared (per shot) sub-graph in LDS
-  const uint16_t* rvn;    // [E_pad] VN of each (padded) CSR edge
-  const uint16_t* cidx;   // [E_sub] CSR position of each column-order slot
-  const uint16_t* crow;   // [E_sub] row of each column-order slot
+  const uint16_t* rvn;    // [E_pad + 8] 4 * VN of each padded CSR edge (byte offset in post)
+  const uint16_t* cidx;   // [E_col] 4 * CSR position of each column-order slot (byte offset in c2v)
+  const uint16_t* crow;   // [E_col] row of each column-order slot
+  const uint32_t* meta;   // [T][64] slot metadata
   // per wavefront, LDS
   float* post;            // [n_act + 1]; +infinity once decimated and for the dummy VN
   int8_t* status;         // [n_act + 1] -1 active, 0/1 decimated
-  float* c2v;             // [E_pad] CN-to-VN messages in CSR order
+  float* c2v;             // [E_pad + 8] CN-to-VN messages in CSR order; [E_pad, +4) zero,
+                          // [E_pad + 4, +4) the dummy batch
   uint8_t* unsat;         // [m]
   uint32_t* prop;         // [ceil(n_act/4)] peeling proposals, one byte per VN
-  int lane, m, n;
-  // CN registers
-  int ce0[CPL], cdg[CPL], so[CPL];            // CSR start, padded degree, window syndrome bit
-  int cdeg[CPL], sres[CPL];                    // active degree, residual syndrome
+  int lane, m, n, T;
+  uint32_t sres;          // bit t: residual syndrome of the row in slot column t
   // VN registers
-  int vc0[VPL], vdg[VPL], st[VPL];             // CSC start, degree, status
+  int vc0[VPL], vdg[VPL], st[VPL];             // first column slot, degree, status
   float llr[VPL];
   float hs[VPL], hmn[VPL], hmx[VPL];           // history over the last four iterations
 };
 
-// Recount every owned CN's active degree and residual syndrome from the VN
-// status, find dead CNs (no active VN, residual 1) and post peeling proposals
-// of degree-one CNs (Sec. IV-D, Appendix C).
-template <int CPL, int VPL>
-__device__ __forceinline__ void cn_recount(PathCtx<CPL, VPL>& P, bool& dead, bool& proposed) {
+// Cross-lane exchange inside aligned lane groups (DPP): partner at lane ^ 1,
+// lane ^ 2, then the mirrored lane within 8 and within 16. After the steps
+// below the group size, every lane holds the group's combined value. The
+// steps run under the lane mask of the groups that need them; a partner is
+// always in the same group, hence active.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
+}
+constexpr int kDppXor1 = 0xB1;       // quad_perm(1, 0, 3, 2)
+constexpr int kDppXor2 = 0x4E;       // quad_perm(2, 3, 0, 1)
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+// Two-min record and parities of a set of VN-to-CN messages: n1 <= n2 the bit
+// patterns of the two smallest magnitudes (non-negative floats order like
+// their bits); bit 31 of sp / hp: parity of the message signs / of the hard
+// decisions.
+struct CnAcc {
+  uint32_t n1, n2, sp, hp;
+};
+
+template <int CTRL>
+__device__ __forceinline__ void cn_merge(CnAcc& a) {
+  const uint32_t o1 = dpp<CTRL>(a.n1), o2 = dpp<CTRL>(a.n2);
+  // second smallest of {a1 <= a2} u {o1 <= o2}: min(max(a1, o1), min(a2, o2))
+  a.n2 = min(max(a.n1, o1), min(a.n2, o2));
+  a.n1 = min(a.n1, o1);
+  a.sp ^= dpp<CTRL>(a.sp);
+  a.hp ^= dpp<CTRL>(a.hp);
+}
+
+__device__ __forceinline__ void cn_group(CnAcc& a, int lk) {
+  if (lk > 0) cn_merge<kDppXor1>(a);
+  if (lk > 1) cn_merge<kDppXor2>(a);
+  if (lk > 2) cn_merge<kDppHalfMirror>(a);
+  if (lk > 3) cn_merge<kDppMirror>(a);
+}
+
+__device__ __forceinline__ void hp_group(uint32_t& hp, int lk) {
+  if (lk > 0) hp ^= dpp<kDppXor1>(hp);
+  if (lk > 1) hp ^= dpp<kDppXor2>(hp);
+  if (lk > 2) hp ^= dpp<kDppHalfMirror>(hp);
+  if (lk > 3) hp ^= dpp<kDppMirror>(hp);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void cnt_merge(int& cnt, int& x, int& only) {
+  cnt += (int)dpp<CTRL>((uint32_t)cnt);
+  x ^= (int)dpp<CTRL>((uint32_t)x);
+  only = max(only, (int)dpp<CTRL>((uint32_t)only));
+}
+
+__device__ __forceinline__ const float& at_byte(const float* base, uint32_t off) {
+  return *(const float*)((const char*)base + off);
+}
+
+// Recount every row's active degree and residual syndrome from the VN status,
+// find dead CNs (no active VN, residual 1) and post peeling proposals of
+// degree-one CNs (Sec. IV-D, Appendix C). Updates P.sres.
+template <int VPL>
+__device__ __forceinline__ void cn_recount(PathCtx<VPL>& P, bool& dead, bool& proposed) {
   dead = false;
   proposed = false;
-#pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    const int e0 = P.ce0[q], dg = P.cdg[q];
-    int cnt = 0, x = P.so[q], only = 0;
-    for (int k0 = 0; k0 < dg; k0 += kPad) {
-      int vv[kPad], sv[kPad];
-#pragma unroll
-      for (int i = 0; i < kPad; ++i) vv[i] = P.rvn[e0 + k0 + i];
-#pragma unroll
-      for (int i = 0; i < kPad; ++i) sv[i] = P.status[vv[i]];
-#pragma unroll
-      for (int i = 0; i < kPad; ++i) {
-        const bool act = sv[i] < 0;
-        cnt += act;
-        x ^= sv[i] == 1;
-        only = act ? vv[i] : only;
-      }
-    }
-    P.cdeg[q] = cnt;
-    P.sres[q] = x;
-    if (P.lane + kWave * q < P.m) {
-      if (cnt == 0 && x) dead = true;
-      if (cnt == 1) {
-        atomicOr(&P.prop[only >> 2], (1u << x) << ((only & 3) * 8));
+  uint32_t sres = 0u;
+  for (int t = 0; t < P.T; ++t) {
+    const uint32_t mt = P.meta[t * kWave + P.lane];
+    const int e0 = mt & kMetaEdge;
+    const int lk = (mt >> kMetaLogKShift) & 7;
+    const uint2 vo = *(const uint2*)(P.rvn + e0);
+    const int v0 = (vo.x & 0xffffu) >> 2, v1 = vo.x >> 18, v2 = (vo.y & 0xffffu) >> 2, v3 = vo.y >> 18;
+    const int s0 = P.status[v0], s1 = P.status[v1], s2 = P.status[v2], s3 = P.status[v3];
+    int cnt = (s0 < 0) + (s1 < 0) + (s2 < 0) + (s3 < 0);
+    int x = (s0 == 1) ^ (s1 == 1) ^ (s2 == 1) ^ (s3 == 1);
+    int only = -1;
+    only = s0 < 0 ? v0 : only;
+    only = s1 < 0 ? v1 : only;
+    only = s2 < 0 ? v2 : only;
+    only = s3 < 0 ? v3 : only;
+    if (lk > 0) cnt_merge<kDppXor1>(cnt, x, only);
+    if (lk > 1) cnt_merge<kDppXor2>(cnt, x, only);
+    if (lk > 2) cnt_merge<kDppHalfMirror>(cnt, x, only);
+    if (lk > 3) cnt_merge<kDppMirror>(cnt, x, only);
+    const int r = (x ^ ((mt & kMetaSyn) ? 1 : 0)) & 1;
+    if (mt & kMetaValid) {
+      sres |= (uint32_t)r << t;
+      if (cnt == 0 && r) dead = true;
+      if (cnt == 1 && (mt & kMetaLead)) {
+        atomicOr(&P.prop[only >> 2], (1u << r) << ((only & 3) * 8));
         proposed = true;
       }
     }
   }
+  P.sres = sres;
 }
 
 // Decimate owned VN v (register slot r). Its posterior becomes +infinity: every
@@ -338,8 +420,8 @@ __device__ __forceinline__ void cn_recount(PathCtx<CPL, VPL>& P, bool& dead, boo
 // active neighbours plus entries at +clip -- which reproduces the rule that a
 // CN with a single active neighbour sends clip -- and its outgoing message to
 // the decimated VN is never read.
-template <int CPL, int VPL>
-__device__ __forceinline__ void set_status(PathCtx<CPL, VPL>& P, int r, int v, int value) {
+template <int VPL>
+__device__ __forceinline__ void set_status(PathCtx<VPL>& P, int r, int v, int value) {
   P.st[r] = value;
   P.status[v] = (int8_t)value;
   P.post[v] = kInfF;
@@ -347,9 +429,9 @@ __device__ __forceinline__ void set_status(PathCtx<CPL, VPL>& P, int r, int v, i
 
 // Peeling closure in synchronous rounds. Returns false on a contradiction
 // (a dead CN, or two different proposals for one VN; then the round is not
-// applied). Leaves the CN registers recounted.
-template <int CPL, int VPL>
-__device__ bool peel(PathCtx<CPL, VPL>& P) {
+// applied). Leaves P.sres recounted.
+template <int VPL>
+__device__ bool peel(PathCtx<VPL>& P) {
   for (;;) {
     bool dead, proposed;
     cn_recount(P, dead, proposed);
@@ -388,109 +470,186 @@ __device__ bool peel(PathCtx<CPL, VPL>& P) {
 // One flooding CN phase: new CN-to-VN messages (Eq. 1) from the extrinsic
 // VN-to-CN messages (Eq. 3, clipped), each formed from the posterior and the
 // CN's previous message on that edge (kept in CSR order next to it). Returns
-// this lane's OR of unsatisfied owned CNs under the hard decisions (Eq. 4) of
-// the posteriors it read. Decimated VNs and padding hold +infinity (see
-// set_status), so no edge needs a branch. The sign of a message is the sign bit
-// of x: x is never -0, since posteriors are sums that start at a positive prior
-// (exact cancellation rounds to +0).
-template <int CPL, int VPL>
-__device__ __forceinline__ int cn_phase(PathCtx<CPL, VPL>& P, float alpha, float clip) {
+// this lane's OR of unsatisfied rows under the hard decisions (Eq. 4) of the
+// posteriors it read: a posterior's sign bit is its hard decision (the VN
+// phase stores an exact zero as -0, and Eq. 4 maps 0 to 1). Decimated VNs and
+// padding hold +infinity (see set_status), so no edge needs a branch.
+//
+// An edge whose message magnitude equals the row's smallest one receives the
+// second smallest: when two edges tie at the smallest, both minima are equal,
+// so this is the usual "all but the minimising edge" rule. A message of zero
+// magnitude may carry either sign; it adds zero to every posterior.
+//
+// The slot columns are software-pipelined so that LDS latency overlaps work:
+// while slot t is computed, the posteriors of slot t + 1, the edges and
+// previous messages of slot t + 2 and the metadata of slot t + 3 are in
+// flight. Reading a later slot's previous messages before slot t writes its
+// own is safe: batches are disjoint except the dummy batch, whose messages
+// only need to be finite.
+struct CnSlot {
+  uint32_t mt;   // metadata
+  uint2 vo;      // VN byte offsets of the batch's edges
+  float4 ov;     // previous CN-to-VN messages
+  float4 p;      // posteriors
+};
+
+template <int VPL>
+__device__ __forceinline__ void cn_load_meta(const PathCtx<VPL>& P, CnSlot& s, int t) {
+  s.mt = P.meta[min(t, P.T - 1) * kWave + P.lane];
+}
+
+template <int VPL>
+__device__ __forceinline__ void cn_load(const PathCtx<VPL>& P, CnSlot& s) {
+  const int e0 = s.mt & kMetaEdge;
+  s.vo = *(const uint2*)(P.rvn + e0);
+  s.ov = *(const float4*)(P.c2v + e0);
+}
+
+template <int VPL>
+__device__ __forceinline__ void cn_gather(const PathCtx<VPL>& P, CnSlot& s) {
+  s.p.x = at_byte(P.post, s.vo.x & 0xffffu);
+  s.p.y = at_byte(P.post, s.vo.x >> 16);
+  s.p.z = at_byte(P.post, s.vo.y & 0xffffu);
+  s.p.w = at_byte(P.post, s.vo.y >> 16);
+}
+
+// New messages of slot column t (loaded and gathered in `c`).
+template <int VPL>
+__device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const CnSlot& c, int t, float alpha,
+                                       float clip) {
+  const uint32_t mt = c.mt;
+  const int e0 = mt & kMetaEdge;
+  const int lk = (mt >> kMetaLogKShift) & 7;
+  const float x0 = clip_to(c.p.x - c.ov.x, clip), x1 = clip_to(c.p.y - c.ov.y, clip);
+  const float x2 = clip_to(c.p.z - c.ov.z, clip), x3 = clip_to(c.p.w - c.ov.w, clip);
+  const uint32_t m0 = __float_as_uint(x0) & 0x7fffffffu, m1 = __float_as_uint(x1) & 0x7fffffffu;
+  const uint32_t m2 = __float_as_uint(x2) & 0x7fffffffu, m3 = __float_as_uint(x3) & 0x7fffffffu;
+  CnAcc a;
+  a.n1 = min(m0, m1);
+  a.n2 = max(m0, m1);
+  a.n2 = min(max(a.n1, m2), a.n2);
+  a.n1 = min(a.n1, m2);
+  a.n2 = min(max(a.n1, m3), a.n2);
+  a.n1 = min(a.n1, m3);
+  a.sp = __float_as_uint(x0) ^ __float_as_uint(x1) ^ __float_as_uint(x2) ^ __float_as_uint(x3);
+  a.hp = __float_as_uint(c.p.x) ^ __float_as_uint(c.p.y) ^ __float_as_uint(c.p.z) ^
+         __float_as_uint(c.p.w);
+  cn_group(a, lk);
+  const uint32_t srow = (P.sres >> t) & 1u;
+  const uint32_t sgn = (a.sp ^ (srow << 31)) & 0x80000000u;
+  const uint32_t s1 = __float_as_uint(alpha * __uint_as_float(a.n1)) | sgn;
+  const uint32_t s2 = __float_as_uint(alpha * __uint_as_float(a.n2)) | sgn;
+  float4 nv;
+  nv.x = __uint_as_float((m0 == a.n1 ? s2 : s1) ^ (__float_as_uint(x0) & 0x80000000u));
+  nv.y = __uint_as_float((m1 == a.n1 ? s2 : s1) ^ (__float_as_uint(x1) & 0x80000000u));
+  nv.z = __uint_as_float((m2 == a.n1 ? s2 : s1) ^ (__float_as_uint(x2) & 0x80000000u));
+  nv.w = __uint_as_float((m3 == a.n1 ? s2 : s1) ^ (__float_as_uint(x3) & 0x80000000u));
+  *(float4*)(P.c2v + e0) = nv;
+  return (int)(srow ^ (a.hp >> 31));
+}
+
+// One pipeline step: gather slot t + 1's posteriors into `b`, load slot t + 2's
+// edges and messages into `c`, slot t + 3's metadata into `d`, compute slot t
+// from `a`.
+template <int VPL>
+__device__ __forceinline__ int cn_step(PathCtx<VPL>& P, const CnSlot& a, CnSlot& b, CnSlot& c,
+                                       CnSlot& d, int t, float alpha, float clip) {
+  cn_gather(P, b);
+  cn_load(P, c);
+  cn_load_meta(P, d, t + 3);
+  return cn_slot(P, a, t, alpha, clip);
+}
+
+template <int VPL>
+__device__ __forceinline__ int cn_phase(PathCtx<VPL>& P, float alpha, float clip) {
+  const int T = P.T;
+  if (T == 0) return 0;
   int bad = 0;
-#pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    const int e0 = P.ce0[q], dg = P.cdg[q];
-    float n1 = kInfF, n2 = kInfF;
-    int nidx = 0, hcnt = 0;
-    uint32_t nlo = 0u, nhi = 0u;
-    for (int k0 = 0; k0 < dg; k0 += kPad) {
-      int vv[kPad];
-      float pv[kPad], ov[kPad];
-#pragma unroll
-      for (int i = 0; i < kPad; ++i) {
-        vv[i] = P.rvn[e0 + k0 + i];
-        ov[i] = P.c2v[e0 + k0 + i];
-      }
-#pragma unroll
-      for (int i = 0; i < kPad; ++i) pv[i] = P.post[vv[i]];
-      uint32_t nw = 0u;
-#pragma unroll
-      for (int i = 0; i < kPad; ++i) {
-        const int k = k0 + i;
-        hcnt += pv[i] <= 0.0f;
-        const float x = clip_to(pv[i] - ov[i], clip);
-        nw |= (__float_as_uint(x) >> 31) << (k & 31);
-        two_min(fabsf(x), k, n1, n2, nidx);
-      }
-      if (k0 < 32) nlo |= nw; else nhi |= nw;
-    }
-    const int npar = (P.sres[q] ^ __builtin_popcount(nlo) ^ __builtin_popcount(nhi)) & 1;
-    const float s1 = alpha * n1;
-    const float s2 = alpha * (n2 == kInfF ? clip : n2);
-    const uint32_t nflip = npar ? ~0u : 0u;
-    const uint32_t wlo = nlo ^ nflip, whi = nhi ^ nflip;   // signs of the new messages
-    for (int k0 = 0; k0 < dg; k0 += kPad) {
-      const uint32_t ww = k0 < 32 ? wlo : whi;
-#pragma unroll
-      for (int i = 0; i < kPad; ++i) {
-        const int k = k0 + i;
-        const float mag = k == nidx ? s2 : s1;
-        P.c2v[e0 + k] = __uint_as_float(__float_as_uint(mag) ^ bit_to_sign(ww, k & 31));
-      }
-    }
-    bad |= P.sres[q] ^ (hcnt & 1);
+  // four rotating slots, unrolled by hand so that the rotation is a renaming
+  // (slots past the last one re-read the last one, harmlessly)
+  CnSlot A, B, C, D;
+  cn_load_meta(P, A, 0);
+  cn_load_meta(P, B, 1);
+  cn_load_meta(P, C, 2);
+  cn_load(P, A);
+  cn_load(P, B);
+  cn_gather(P, A);
+  for (int t = 0; t < T; t += 4) {
+    bad |= cn_step(P, A, B, C, D, t, alpha, clip);
+    if (t + 1 >= T) break;
+    bad |= cn_step(P, B, C, D, A, t + 1, alpha, clip);
+    if (t + 2 >= T) break;
+    bad |= cn_step(P, C, D, A, B, t + 2, alpha, clip);
+    if (t + 3 >= T) break;
+    bad |= cn_step(P, D, A, B, C, t + 3, alpha, clip);
   }
   return bad;
 }
 
-template <int CPL, int VPL>
-__device__ __forceinline__ int check_pass(PathCtx<CPL, VPL>& P, bool write_unsat) {
+// Syndrome check of the current hard decisions; optionally records each
+// row's unsatisfied flag for Alg. 3.
+template <int VPL>
+__device__ __forceinline__ int check_pass(PathCtx<VPL>& P, bool write_unsat) {
   int bad = 0;
-#pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    const int j = P.lane + kWave * q;
-    const int e0 = P.ce0[q], dg = P.cdg[q];
-    int hcnt = 0;
-    for (int k0 = 0; k0 < dg; k0 += kPad) {
-      float pv[kPad];
-#pragma unroll
-      for (int i = 0; i < kPad; ++i) pv[i] = P.post[P.rvn[e0 + k0 + i]];
-#pragma unroll
-      for (int i = 0; i < kPad; ++i) hcnt += pv[i] <= 0.0f;
-    }
-    const int hx = P.sres[q] ^ (hcnt & 1);
-    if (write_unsat && j < P.m) P.unsat[j] = (uint8_t)hx;
+  for (int t = 0; t < P.T; ++t) {
+    const uint32_t mt = P.meta[t * kWave + P.lane];
+    const int e0 = mt & kMetaEdge;
+    const int lk = (mt >> kMetaLogKShift) & 7;
+    const uint2 vo = *(const uint2*)(P.rvn + e0);
+    uint32_t hp = __float_as_uint(at_byte(P.post, vo.x & 0xffffu)) ^
+                  __float_as_uint(at_byte(P.post, vo.x >> 16)) ^
+                  __float_as_uint(at_byte(P.post, vo.y & 0xffffu)) ^
+                  __float_as_uint(at_byte(P.post, vo.y >> 16));
+    hp_group(hp, lk);
+    const int hx = (int)(((P.sres >> t) & 1u) ^ (hp >> 31));
+    if (write_unsat && (mt & kMetaLead) && (mt & kMetaValid))
+      P.unsat[(mt >> kMetaRowShift) & 0x3ff] = (uint8_t)hx;
     bad |= hx;
   }
   return bad;
 }
 
-// VN phase: posteriors of the owned active VNs (Eq. 2), and the history of the
-// last four iterations of the step.
-template <int CPL, int VPL>
-__device__ __forceinline__ long long vn_phase(PathCtx<CPL, VPL>& P, bool hist) {
+// VN phase: posteriors of the owned active VNs (Eq. 2), summed in column slot
+// order, and the history of the last four iterations of the step. The first
+// four slots of every owned VN are gathered together (index loads, then
+// message loads) so that their LDS latencies overlap.
+template <int VPL>
+__device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist) {
+  uint2 ix[VPL];
+#pragma unroll
+  for (int r = 0; r < VPL; ++r) ix[r] = *(const uint2*)(P.cidx + P.vc0[r]);
+  __builtin_amdgcn_sched_barrier(0);
+  float g[VPL][4];
+#pragma unroll
+  for (int r = 0; r < VPL; ++r) {
+    g[r][0] = at_byte(P.c2v, ix[r].x & 0xffffu);
+    g[r][1] = at_byte(P.c2v, ix[r].x >> 16);
+    g[r][2] = at_byte(P.c2v, ix[r].y & 0xffffu);
+    g[r][3] = at_byte(P.c2v, ix[r].y >> 16);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  float s[VPL];
+#pragma unroll
+  for (int r = 0; r < VPL; ++r) s[r] = (((P.llr[r] + g[r][0]) + g[r][1]) + g[r][2]) + g[r][3];
   long long edges = 0;
 #pragma unroll
   for (int r = 0; r < VPL; ++r) {
     const int v = P.lane + kWave * r;
+    for (int k0 = 4; k0 < P.vdg[r]; k0 += 4) {
+      const uint2 jx = *(const uint2*)(P.cidx + P.vc0[r] + k0);
+      s[r] += at_byte(P.c2v, jx.x & 0xffffu);
+      s[r] += at_byte(P.c2v, jx.x >> 16);
+      s[r] += at_byte(P.c2v, jx.y & 0xffffu);
+      s[r] += at_byte(P.c2v, jx.y >> 16);
+    }
     if (v < P.n && P.st[r] < 0) {
-      const int c0 = P.vc0[r], dg = P.vdg[r];
-      float s = P.llr[r];
-      for (int k0 = 0; k0 < dg; k0 += 4) {
-        int ix[4];
-        float x[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ix[i] = P.cidx[c0 + min(k0 + i, dg - 1)];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) x[i] = P.c2v[ix[i]];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s += k0 + i < dg ? x[i] : 0.0f;   // s is never -0
-      }
-      P.post[v] = s;
-      edges += dg;
+      const float x = s[r] == 0.0f ? -0.0f : s[r];   // sign bit = hard decision
+      P.post[v] = x;
+      edges += P.vdg[r];
       if (hist) {
-        P.hs[r] += s;
-        P.hmn[r] = fminf(P.hmn[r], s);
-        P.hmx[r] = fmaxf(P.hmx[r], s);
+        P.hs[r] += x;
+        P.hmn[r] = fminf(P.hmn[r], x);
+        P.hmx[r] = fmaxf(P.hmx[r], x);
       }
     }
   }
@@ -499,7 +658,7 @@ __device__ __forceinline__ long long vn_phase(PathCtx<CPL, VPL>& P, bool hist) {
 
 // Decodes shot `shot` of one window with the whole workgroup. Every thread
 // enters and leaves together; the caller synchronises before the LDS is reused.
-template <int CPL, int VPL>
+template <int VPL>
 __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int shot,
                             const uint8_t* __restrict__ syn, const long long syn_stride,
                             uint8_t* __restrict__ ehat, double* __restrict__ pm_out,
@@ -518,16 +677,17 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
   uint16_t* cidx = (uint16_t*)(smem + L.cidx);
   uint16_t* cptr = (uint16_t*)(smem + L.cptr);
   uint16_t* crow = (uint16_t*)(smem + L.crow);
-  float* sllr = (float*)(smem + L.llr);
-  uint8_t* sdeg = smem + L.deg;
+  uint32_t* meta = (uint32_t*)(smem + L.meta);
   double* ppm = (double*)(smem + L.ppm);
   int* pend = (int*)(smem + L.pend);
   uint32_t* pbits = (uint32_t*)(smem + L.pbits);
   int* misc = (int*)(smem + L.misc);            // [0] path counter, [2] answer path
-  int* iscan = (int*)(smem + L.iscan);          // scratch for scans, max(m, n_act) + 1
   uint32_t* obits = (uint32_t*)(smem + L.obits);  // window bitmask of the answer
   unsigned long long* eacc = (unsigned long long*)(smem + L.eacc);
   unsigned char* U = smem + L.u_base;
+  int* iscan = (int*)(U + L.p_iscan);           // sub-graph build scratch (scans)
+  float* sllr = (float*)(U + L.p_llr);
+  uint8_t* sdeg = U + L.p_deg;
 
   for (int j = tid; j < m; j += blockDim.x) sorig[j] = syn[(long long)shot * syn_stride + j] & 1;
   if (tid == 0) {
@@ -544,12 +704,11 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
   if (w.pre_iters > 0) {
     FullBP b;
     b.w = &w;
-    b.cs = (const uint32_t*)(U + L.p_cs);
+    b.cs = w.row_cs;
     b.post = (float*)(U + L.p_post);
     b.c2v = (float*)(U + L.p_c2v);
     b.syn = sorig;
     float* lsum = (float*)(U + L.p_lsum);
-    stage_edges(w, (uint32_t*)(U + L.p_cs));
     for (int c = tid; c < n; c += blockDim.x) {
       b.post[c] = w.llr[c];
       lsum[c] = 0.0f;
@@ -646,24 +805,25 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
 
   // ---------------------------------------------------------- truncated sub-graph
   {
-    int16_t* loc = (int16_t*)(U + L.p_loc);
+    int16_t* loc = (int16_t*)(U + L.p_loc);   // [n] sub-graph VN of each window column, or -1
+    int16_t* perm = loc + n;                  // [m] rows by decreasing sub-graph degree
     for (int c = tid; c < n; c += blockDim.x) loc[c] = -1;
     __syncthreads();
     for (int v = tid; v < n_act; v += blockDim.x) loc[sel[v]] = (int16_t)v;
     for (int v = tid; v < n_act; v += blockDim.x) {
       const int c = sel[v];
-      iscan[v] = w.col_ptr[c + 1] - w.col_ptr[c];
+      const int d = w.col_ptr[c + 1] - w.col_ptr[c];
+      iscan[v] = (d + kPad - 1) / kPad * kPad;   // column slots padded to a multiple of 4
       sllr[v] = w.llr[c];
-      sdeg[v] = w.deg[c];
+      sdeg[v] = (uint8_t)d;
     }
     __syncthreads();
     wg_exclusive_scan_wave0(iscan, n_act);
     __syncthreads();
     for (int v = tid; v <= n_act; v += blockDim.x) cptr[v] = (uint16_t)iscan[v];
     __syncthreads();
-    // rows in order of decreasing sub-graph degree: the lanes' q-th rows then
-    // have similar degrees, which keeps the lanes of a CN phase equally busy
-    int16_t* perm = (int16_t*)(U + L.p_loc) + n;   // after loc
+    // rows in order of decreasing sub-graph degree; a row whose columns were
+    // all truncated away and whose syndrome bit is 1 can never be satisfied
     int* rdeg = iscan;
     for (int j = tid; j < m; j += blockDim.x) {
       int cnt = 0;
@@ -672,9 +832,13 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
     }
     __syncthreads();
     if (tid == 0) {
-      int* cnt = (int*)(smem + L.rhist);   // 65 degree buckets
+      int* cnt = (int*)(U + L.p_rhist);   // 65 degree buckets
       for (int d = 0; d <= 64; ++d) cnt[d] = 0;
-      for (int j = 0; j < m; ++j) ++cnt[rdeg[j]];
+      int dead0 = 0;
+      for (int j = 0; j < m; ++j) {
+        ++cnt[rdeg[j]];
+        if (rdeg[j] == 0 && sorig[j]) dead0 = 1;
+      }
       int pos = 0;
       for (int d = 64; d >= 0; --d) {
         const int c = cnt[d];
@@ -682,6 +846,7 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
         pos += c;
       }
       for (int j = 0; j < m; ++j) perm[cnt[rdeg[j]]++] = (int16_t)j;
+      misc[4] = dead0;
     }
     __syncthreads();
     // padded degree in sub-graph row order
@@ -694,6 +859,25 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
     __syncthreads();
     for (int j = tid; j <= m; j += blockDim.x) rptr[j] = (uint16_t)iscan[j];
     __syncthreads();
+    // lane-group size of each row: the power of two >= its number of batches;
+    // rows come by decreasing size, so the packing keeps groups aligned
+    for (int pj = tid; pj < m; pj += blockDim.x) {
+      const int nb = (rptr[pj + 1] - rptr[pj]) / kPad;
+      iscan[m + 1 + pj] = nb == 0 ? 0 : 1 << (32 - __builtin_clz((unsigned)(2 * nb - 1)) - 1);
+    }
+    __syncthreads();
+    wg_exclusive_scan_wave0(iscan + m + 1, m);
+    __syncthreads();
+    const int e_pad = rptr[m];
+    const int n_slots = iscan[2 * m + 1];
+    // the window's slot table is sized for the worst truncation; a shot past it
+    // is flagged instead of decoded
+    const int T = min((n_slots + kWave - 1) / kWave, L.meta_cols);
+    const int cap = L.meta_cols * kWave;
+    const uint32_t idle = (uint32_t)(e_pad + kPad);   // the dummy batch
+    for (int i = tid; i < T * kWave; i += blockDim.x) meta[i] = idle;
+    for (int i = tid; i < kPad; i += blockDim.x) rvn[e_pad + kPad + i] = (uint16_t)(4 * n_act);
+    __syncthreads();
     for (int pj = tid; pj < m; pj += blockDim.x) {
       const int j = perm[pj];
       psyn[pj] = sorig[j];
@@ -702,12 +886,32 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
         const int v = loc[w.row_col[e]];
         if (v < 0) continue;
         const int slot = cptr[v] + w.row_kcol[e];
-        rvn[pos] = (uint16_t)v;
-        cidx[slot] = (uint16_t)pos;
+        rvn[pos] = (uint16_t)(4 * v);
+        cidx[slot] = (uint16_t)(4 * pos);
         crow[slot] = (uint16_t)pj;
         ++pos;
       }
-      for (; pos < rptr[pj + 1]; ++pos) rvn[pos] = (uint16_t)n_act;   // padding: dummy VN
+      for (; pos < rptr[pj + 1]; ++pos) rvn[pos] = (uint16_t)(4 * n_act);   // padding: dummy VN
+      const int nb = (rptr[pj + 1] - rptr[pj]) / kPad;
+      if (nb > 0) {
+        const int g0 = iscan[m + 1 + pj];
+        const int k = (pj + 1 < m ? iscan[m + 2 + pj] : n_slots) - g0;
+        const int lk = 31 - __builtin_clz((unsigned)k);
+        for (int i = 0; i < k && g0 + i < cap; ++i) {
+          const int e0 = i < nb ? rptr[pj] + kPad * i : e_pad + kPad;
+          meta[g0 + i] = (uint32_t)e0 | ((uint32_t)pj << kMetaRowShift) |
+                         ((uint32_t)lk << kMetaLogKShift) | (sorig[j] ? kMetaSyn : 0u) |
+                         (i == 0 ? kMetaLead : 0u) | kMetaValid;
+        }
+      }
+    }
+    for (int v = tid; v < n_act; v += blockDim.x) {
+      const int c0 = cptr[v] + sdeg[v];
+      for (int i = c0; i < cptr[v + 1]; ++i) cidx[i] = (uint16_t)(4 * e_pad);   // zero message
+    }
+    if (tid == 0) {
+      misc[3] = T;
+      misc[5] = n_slots > cap;
     }
     if (tr.sel)
       for (int v = tid; v < n_act; v += blockDim.x) tr.sel[(long long)shot * n_act + v] = sel[v];
@@ -717,10 +921,11 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
   // ---------------------------------------------------------- decision paths
   {
     unsigned char* Wb = U + wave * L.w_stride;
-    PathCtx<CPL, VPL> P;
+    PathCtx<VPL> P;
     P.rvn = rvn;
     P.cidx = cidx;
     P.crow = crow;
+    P.meta = meta;
     P.post = (float*)(Wb + L.w_post);
     P.status = (int8_t*)(Wb + L.w_status);
     P.c2v = (float*)(Wb + L.w_c2v);
@@ -730,24 +935,21 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
     P.lane = lane;
     P.m = m;
     P.n = n_act;
+    P.T = misc[3];
+    P.sres = 0u;
+    const bool dead0 = misc[4] != 0;
     const int T = w.iters;
     const float alpha = w.alpha, clip = w.clip;
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-      const int j = lane + kWave * q;
-      const int jj = j < m ? j : 0;
-      P.ce0[q] = rptr[jj];
-      P.cdg[q] = j < m ? rptr[jj + 1] - rptr[jj] : 0;
-      P.so[q] = j < m ? psyn[jj] : 0;
-    }
 #pragma unroll
     for (int r = 0; r < VPL; ++r) {
       const int v = lane + kWave * r;
       const int vv = v < n_act ? v : 0;
-      P.vc0[r] = cptr[vv];
-      P.vdg[r] = v < n_act ? cptr[vv + 1] - cptr[vv] : 0;
+      P.vc0[r] = v < n_act ? cptr[vv] : 0;
+      P.vdg[r] = v < n_act ? sdeg[vv] : 0;
       P.llr[r] = sllr[vv];
     }
+    // the sub-graph build scratch (sllr, sdeg) shares LDS with the path regions
+    __syncthreads();
     for (int i = lane; i < (n_act + 3) / 4; i += kWave) P.prop[i] = 0u;
     if (lane == 0) {
       P.post[n_act] = kInfF;   // dummy VN of the row padding
@@ -784,15 +986,12 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
           P.post[v] = P.llr[r];
         }
       }
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        P.cdeg[q] = 0;   // slots past the last row keep degree 0 and residual 0
-        P.sres[q] = 0;
-      }
-      for (int e = lane; e < e_pad; e += kWave) P.c2v[e] = 0.0f;   // t = 0: no CN message yet
+      P.sres = 0u;
+      // t = 0: no CN message yet; also clears the zero slot and the dummy batch
+      for (int e = lane; e < e_pad + 2 * kPad; e += kWave) P.c2v[e] = 0.0f;
       wave_sync();
       int end = 0, steps = 0;
-      if (!peel(P)) end = END_CONTRADICTION;   // peel at init too
+      if (dead0 || !peel(P)) end = END_CONTRADICTION;   // peel at init too
       for (int D = 1; end == 0 && D <= dmax; ++D) {
 #pragma unroll
         for (int r = 0; r < VPL; ++r) {
@@ -996,6 +1195,7 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
       if (n_contra == w.n_paths) fl |= 2;
       if (n_exh > 0) fl |= 4;
     }
+    if (misc[5]) fl |= 16;
     misc[2] = best >= 0 ? best : 0;
     pm_out[shot] = bpm;
     flags_out[shot] = fl;
@@ -1018,8 +1218,8 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
 // table; item i belongs to the job whose first item is the largest <= i. Jobs
 // may use windows of different codes (sizes): each job carries its own LDS
 // layout within the launch's allocation.
-template <int CPL, int VPL>
-__global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
+template <int VPL>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) void gdg_decode_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int item = blockIdx.x; item < J.total; item += gridDim.x) {
     // pick the job with static indices only (no dynamic indexing of kernel arguments)
@@ -1027,7 +1227,7 @@ __global__ __launch_bounds__(512) void gdg_decode_kernel(gdg_jobs_dev J, gdg_tra
 #pragma unroll
     for (int t = 1; t < kMaxJobs; ++t)
       if (t < J.n_jobs && item >= J.job[t].item0) jb = J.job[t];
-    decode_shot<CPL, VPL>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat, jb.pm,
+    decode_shot<VPL>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat, jb.pm,
                           jb.flags, tr, smem);
     __syncthreads();
   }
@@ -1186,13 +1386,13 @@ hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int gri
   dim3 g(grid), block(waves * kWave);
   switch (bucket) {
     case 0:
-      hipLaunchKernelGGL((gdg_decode_kernel<2, 6>), g, block, lds, st, J, tr);
+      hipLaunchKernelGGL((gdg_decode_kernel<6>), g, block, lds, st, J, tr);
       break;
     case 1:
-      hipLaunchKernelGGL((gdg_decode_kernel<4, 8>), g, block, lds, st, J, tr);
+      hipLaunchKernelGGL((gdg_decode_kernel<8>), g, block, lds, st, J, tr);
       break;
     case 2:
-      hipLaunchKernelGGL((gdg_decode_kernel<8, 16>), g, block, lds, st, J, tr);
+      hipLaunchKernelGGL((gdg_decode_kernel<16>), g, block, lds, st, J, tr);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1201,16 +1401,17 @@ hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int gri
 }
 
 int gdg_kernel_bucket(int m, int n_act) {
-  if (m <= 128 && n_act <= 384) return 0;
-  if (m <= 256 && n_act <= 512) return 1;
-  if (m <= 512 && n_act <= 1024) return 2;
+  if (m > 1023) return -1;
+  if (n_act <= 384) return 0;
+  if (n_act <= 512) return 1;
+  if (n_act <= 1024) return 2;
   return -1;
 }
 
 hipError_t gdg_decode_set_lds_limit(int bucket, int bytes) {
-  const void* f = bucket == 0   ? (const void*)gdg_decode_kernel<2, 6>
-                  : bucket == 1 ? (const void*)gdg_decode_kernel<4, 8>
-                                : (const void*)gdg_decode_kernel<8, 16>;
+  const void* f = bucket == 0   ? (const void*)gdg_decode_kernel<6>
+                  : bucket == 1 ? (const void*)gdg_decode_kernel<8>
+                                : (const void*)gdg_decode_kernel<16>;
   return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 

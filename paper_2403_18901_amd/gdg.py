@@ -19,6 +19,7 @@ GDG_FLAG_SATISFIED = 1
 GDG_FLAG_CONTRADICTION = 2
 GDG_FLAG_EXHAUSTED = 4
 GDG_FLAG_FALLBACK = 8
+GDG_FLAG_CAPACITY = 16
 
 EXPORTED = ["gdg_build_window", "gdg_window_free", "gdg_window_get_info", "gdg_window_columns",
             "gdg_workspace_bytes", "gdg_decode_batch", "gdg_decode_jobs", "gdg_jobs_lds_bytes",
