@@ -49,19 +49,62 @@ __device__ __forceinline__ uint32_t ord_f32(float x) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+// Cross-lane exchange inside aligned lane groups (DPP): partner at lane ^ 1,
+// lane ^ 2, then the mirrored lane within 8 and within 16. After the steps
+// below the group size, every lane holds the group's combined value. The
+// steps run under the lane mask of the groups that need them; a partner is
+// always in the same group, hence active.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
+}
+constexpr int kDppXor1 = 0xB1;       // quad_perm(1, 0, 3, 2)
+constexpr int kDppXor2 = 0x4E;       // quad_perm(2, 3, 0, 1)
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long x) {
+  const uint32_t lo = dpp<CTRL>((uint32_t)x), hi = dpp<CTRL>((uint32_t)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long x, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Wavefront reductions without LDS round trips: four DPP steps leave every
+// lane of a row of 16 with the row's result, then the four rows' results are
+// read into scalar registers. All 64 lanes must be active.
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long u = __shfl_xor(v, o, kWave);
-    v = u < v ? u : v;
-  }
-  return v;
+  unsigned long long u;
+  u = dpp64<kDppXor1>(v);
+  v = u < v ? u : v;
+  u = dpp64<kDppXor2>(v);
+  v = u < v ? u : v;
+  u = dpp64<kDppHalfMirror>(v);
+  v = u < v ? u : v;
+  u = dpp64<kDppMirror>(v);
+  v = u < v ? u : v;
+  unsigned long long r = readlane64(v, 0);
+  u = readlane64(v, 16);
+  r = u < r ? u : r;
+  u = readlane64(v, 32);
+  r = u < r ? u : r;
+  u = readlane64(v, 48);
+  r = u < r ? u : r;
+  return r;
 }
 
 __device__ __forceinline__ int wave_sum_i32(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += (int)dpp<kDppXor1>((uint32_t)v);
+  v += (int)dpp<kDppXor2>((uint32_t)v);
+  v += (int)dpp<kDppHalfMirror>((uint32_t)v);
+  v += (int)dpp<kDppMirror>((uint32_t)v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+         __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
@@ -298,6 +341,12 @@ constexpr uint32_t kMetaValid = 1u << 29;    // the slot holds a row
 
 template <int VPL>
 struct PathCtx {
+  __device__ __forceinline__ int vc0(int r) const { return vinfo[r] & 0xffffu; }
+  __device__ __forceinline__ int vdg(int r) const { return (vinfo[r] >> 16) & 0xffu; }
+  __device__ __forceinline__ int st(int r) const { return (int)((vinfo[r] >> 24) & 3u) - 1; }
+  __device__ __forceinline__ void set_st(int r, int value) {
+    vinfo[r] = (vinfo[r] & 0x00ffffffu) | ((uint32_t)(value + 1) << 24);
+  }
   // shared (per shot) sub-graph in LDS
   const uint16_t* rvn;    // [E_pad + 8] 4 * VN of each padded CSR edge (byte offset in post)
   const uint16_t* cidx;   // [E_col] 4 * CSR position of each column-order slot (byte offset in c2v)
@@ -313,24 +362,10 @@ struct PathCtx {
   int lane, m, n, T;
   uint32_t sres;          // bit t: residual syndrome of the row in slot column t
   // VN registers
-  int vc0[VPL], vdg[VPL], st[VPL];             // first column slot, degree, status
+  uint32_t vinfo[VPL];   // first column slot | degree << 16 | (status + 1) << 24
   float llr[VPL];
   float hs[VPL], hmn[VPL], hmx[VPL];           // history over the last four iterations
 };
-
-// Cross-lane exchange inside aligned lane groups (DPP): partner at lane ^ 1,
-// lane ^ 2, then the mirrored lane within 8 and within 16. After the steps
-// below the group size, every lane holds the group's combined value. The
-// steps run under the lane mask of the groups that need them; a partner is
-// always in the same group, hence active.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
-}
-constexpr int kDppXor1 = 0xB1;       // quad_perm(1, 0, 3, 2)
-constexpr int kDppXor2 = 0x4E;       // quad_perm(2, 3, 0, 1)
-constexpr int kDppHalfMirror = 0x141;
-constexpr int kDppMirror = 0x140;
 
 // Two-min record and parities of a set of VN-to-CN messages: n1 <= n2 the bit
 // patterns of the two smallest magnitudes (non-negative floats order like
@@ -375,43 +410,112 @@ __device__ __forceinline__ const float& at_byte(const float* base, uint32_t off)
   return *(const float*)((const char*)base + off);
 }
 
+// Walk over the slot columns, software-pipelined so that LDS latency overlaps
+// work: while slot t is computed, slot t + 1's gathers (posteriors or
+// statuses), slot t + 2's edges (and previous messages) and slot t + 3's
+// metadata are in flight. Four rotating slots, unrolled by hand so that the
+// rotation is a renaming; slots past the last one re-read the last one. In the
+// CN phase, reading a later slot's previous messages before slot t writes its
+// own is safe: batches are disjoint except the dummy batch, whose messages
+// only need to be finite. Returns the OR of the per-slot results.
+struct Slot {
+  uint32_t mt;   // metadata
+  uint2 vo;      // VN byte offsets of the batch's edges
+  float4 ov;     // previous CN-to-VN messages (CN phase)
+  uint4 g;       // gathered posteriors or statuses
+};
+
+template <int VPL, bool OV>
+__device__ __forceinline__ void slot_edges(const PathCtx<VPL>& P, Slot& s) {
+  const int e0 = s.mt & kMetaEdge;
+  s.vo = *(const uint2*)(P.rvn + e0);
+  if (OV) s.ov = *(const float4*)(P.c2v + e0);
+}
+
+template <int VPL>
+__device__ __forceinline__ void slot_meta(const PathCtx<VPL>& P, Slot& s, int t) {
+  s.mt = P.meta[min(t, P.T - 1) * kWave + P.lane];
+}
+
+template <int VPL, bool OV, typename Gather, typename Compute>
+__device__ __forceinline__ int slot_step(const PathCtx<VPL>& P, const Slot& a, Slot& b, Slot& c,
+                                         Slot& d, int t, Gather& gather, Compute& compute) {
+  gather(b);
+  slot_edges<VPL, OV>(P, c);
+  slot_meta(P, d, t + 3);
+  return compute(a, t);
+}
+
+template <int VPL, bool OV, typename Gather, typename Compute>
+__device__ __forceinline__ int slot_walk(const PathCtx<VPL>& P, Gather gather, Compute compute) {
+  const int T = P.T;
+  if (T == 0) return 0;
+  int acc = 0;
+  Slot A, B, C, D;
+  slot_meta(P, A, 0);
+  slot_meta(P, B, 1);
+  slot_meta(P, C, 2);
+  slot_edges<VPL, OV>(P, A);
+  slot_edges<VPL, OV>(P, B);
+  gather(A);
+  for (int t = 0; t < T; t += 4) {
+    acc |= slot_step<VPL, OV>(P, A, B, C, D, t, gather, compute);
+    if (t + 1 >= T) break;
+    acc |= slot_step<VPL, OV>(P, B, C, D, A, t + 1, gather, compute);
+    if (t + 2 >= T) break;
+    acc |= slot_step<VPL, OV>(P, C, D, A, B, t + 2, gather, compute);
+    if (t + 3 >= T) break;
+    acc |= slot_step<VPL, OV>(P, D, A, B, C, t + 3, gather, compute);
+  }
+  return acc;
+}
+
 // Recount every row's active degree and residual syndrome from the VN status,
 // find dead CNs (no active VN, residual 1) and post peeling proposals of
 // degree-one CNs (Sec. IV-D, Appendix C). Updates P.sres.
 template <int VPL>
 __device__ __forceinline__ void cn_recount(PathCtx<VPL>& P, bool& dead, bool& proposed) {
-  dead = false;
-  proposed = false;
+  bool dd = false, pp = false;
   uint32_t sres = 0u;
-  for (int t = 0; t < P.T; ++t) {
-    const uint32_t mt = P.meta[t * kWave + P.lane];
-    const int e0 = mt & kMetaEdge;
-    const int lk = (mt >> kMetaLogKShift) & 7;
-    const uint2 vo = *(const uint2*)(P.rvn + e0);
-    const int v0 = (vo.x & 0xffffu) >> 2, v1 = vo.x >> 18, v2 = (vo.y & 0xffffu) >> 2, v3 = vo.y >> 18;
-    const int s0 = P.status[v0], s1 = P.status[v1], s2 = P.status[v2], s3 = P.status[v3];
-    int cnt = (s0 < 0) + (s1 < 0) + (s2 < 0) + (s3 < 0);
-    int x = (s0 == 1) ^ (s1 == 1) ^ (s2 == 1) ^ (s3 == 1);
-    int only = -1;
-    only = s0 < 0 ? v0 : only;
-    only = s1 < 0 ? v1 : only;
-    only = s2 < 0 ? v2 : only;
-    only = s3 < 0 ? v3 : only;
-    if (lk > 0) cnt_merge<kDppXor1>(cnt, x, only);
-    if (lk > 1) cnt_merge<kDppXor2>(cnt, x, only);
-    if (lk > 2) cnt_merge<kDppHalfMirror>(cnt, x, only);
-    if (lk > 3) cnt_merge<kDppMirror>(cnt, x, only);
-    const int r = (x ^ ((mt & kMetaSyn) ? 1 : 0)) & 1;
-    if (mt & kMetaValid) {
-      sres |= (uint32_t)r << t;
-      if (cnt == 0 && r) dead = true;
-      if (cnt == 1 && (mt & kMetaLead)) {
-        atomicOr(&P.prop[only >> 2], (1u << r) << ((only & 3) * 8));
-        proposed = true;
-      }
-    }
-  }
+  slot_walk<VPL, false>(
+      P,
+      [&](Slot& s) {
+        s.g.x = (uint32_t)(int)P.status[(s.vo.x & 0xffffu) >> 2];
+        s.g.y = (uint32_t)(int)P.status[s.vo.x >> 18];
+        s.g.z = (uint32_t)(int)P.status[(s.vo.y & 0xffffu) >> 2];
+        s.g.w = (uint32_t)(int)P.status[s.vo.y >> 18];
+      },
+      [&](const Slot& s, int t) {
+        const uint32_t mt = s.mt;
+        const int lk = (mt >> kMetaLogKShift) & 7;
+        const int v0 = (s.vo.x & 0xffffu) >> 2, v1 = s.vo.x >> 18;
+        const int v2 = (s.vo.y & 0xffffu) >> 2, v3 = s.vo.y >> 18;
+        const int s0 = (int)s.g.x, s1 = (int)s.g.y, s2 = (int)s.g.z, s3 = (int)s.g.w;
+        int cnt = (s0 < 0) + (s1 < 0) + (s2 < 0) + (s3 < 0);
+        int x = (s0 == 1) ^ (s1 == 1) ^ (s2 == 1) ^ (s3 == 1);
+        int only = -1;
+        only = s0 < 0 ? v0 : only;
+        only = s1 < 0 ? v1 : only;
+        only = s2 < 0 ? v2 : only;
+        only = s3 < 0 ? v3 : only;
+        if (lk > 0) cnt_merge<kDppXor1>(cnt, x, only);
+        if (lk > 1) cnt_merge<kDppXor2>(cnt, x, only);
+        if (lk > 2) cnt_merge<kDppHalfMirror>(cnt, x, only);
+        if (lk > 3) cnt_merge<kDppMirror>(cnt, x, only);
+        const int r = (x ^ ((mt & kMetaSyn) ? 1 : 0)) & 1;
+        if (mt & kMetaValid) {
+          sres |= (uint32_t)r << t;
+          if (cnt == 0 && r) dd = true;
+          if (cnt == 1 && (mt & kMetaLead)) {
+            atomicOr(&P.prop[only >> 2], (1u << r) << ((only & 3) * 8));
+            pp = true;
+          }
+        }
+        return 0;
+      });
   P.sres = sres;
+  dead = dd;
+  proposed = pp;
 }
 
 // Decimate owned VN v (register slot r). Its posterior becomes +infinity: every
@@ -422,7 +526,7 @@ __device__ __forceinline__ void cn_recount(PathCtx<VPL>& P, bool& dead, bool& pr
 // the decimated VN is never read.
 template <int VPL>
 __device__ __forceinline__ void set_status(PathCtx<VPL>& P, int r, int v, int value) {
-  P.st[r] = value;
+  P.set_st(r, value);
   P.status[v] = (int8_t)value;
   P.post[v] = kInfF;
 }
@@ -479,49 +583,18 @@ __device__ bool peel(PathCtx<VPL>& P) {
 // second smallest: when two edges tie at the smallest, both minima are equal,
 // so this is the usual "all but the minimising edge" rule. A message of zero
 // magnitude may carry either sign; it adds zero to every posterior.
-//
-// The slot columns are software-pipelined so that LDS latency overlaps work:
-// while slot t is computed, the posteriors of slot t + 1, the edges and
-// previous messages of slot t + 2 and the metadata of slot t + 3 are in
-// flight. Reading a later slot's previous messages before slot t writes its
-// own is safe: batches are disjoint except the dummy batch, whose messages
-// only need to be finite.
-struct CnSlot {
-  uint32_t mt;   // metadata
-  uint2 vo;      // VN byte offsets of the batch's edges
-  float4 ov;     // previous CN-to-VN messages
-  float4 p;      // posteriors
-};
-
+// cn_slot computes slot column t from its loaded edges, messages and gathered
+// posteriors; cn_phase walks the slot columns (see slot_walk).
 template <int VPL>
-__device__ __forceinline__ void cn_load_meta(const PathCtx<VPL>& P, CnSlot& s, int t) {
-  s.mt = P.meta[min(t, P.T - 1) * kWave + P.lane];
-}
-
-template <int VPL>
-__device__ __forceinline__ void cn_load(const PathCtx<VPL>& P, CnSlot& s) {
-  const int e0 = s.mt & kMetaEdge;
-  s.vo = *(const uint2*)(P.rvn + e0);
-  s.ov = *(const float4*)(P.c2v + e0);
-}
-
-template <int VPL>
-__device__ __forceinline__ void cn_gather(const PathCtx<VPL>& P, CnSlot& s) {
-  s.p.x = at_byte(P.post, s.vo.x & 0xffffu);
-  s.p.y = at_byte(P.post, s.vo.x >> 16);
-  s.p.z = at_byte(P.post, s.vo.y & 0xffffu);
-  s.p.w = at_byte(P.post, s.vo.y >> 16);
-}
-
-// New messages of slot column t (loaded and gathered in `c`).
-template <int VPL>
-__device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const CnSlot& c, int t, float alpha,
+__device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const Slot& c, int t, float alpha,
                                        float clip) {
   const uint32_t mt = c.mt;
   const int e0 = mt & kMetaEdge;
   const int lk = (mt >> kMetaLogKShift) & 7;
-  const float x0 = clip_to(c.p.x - c.ov.x, clip), x1 = clip_to(c.p.y - c.ov.y, clip);
-  const float x2 = clip_to(c.p.z - c.ov.z, clip), x3 = clip_to(c.p.w - c.ov.w, clip);
+  const float x0 = clip_to(__uint_as_float(c.g.x) - c.ov.x, clip);
+  const float x1 = clip_to(__uint_as_float(c.g.y) - c.ov.y, clip);
+  const float x2 = clip_to(__uint_as_float(c.g.z) - c.ov.z, clip);
+  const float x3 = clip_to(__uint_as_float(c.g.w) - c.ov.w, clip);
   const uint32_t m0 = __float_as_uint(x0) & 0x7fffffffu, m1 = __float_as_uint(x1) & 0x7fffffffu;
   const uint32_t m2 = __float_as_uint(x2) & 0x7fffffffu, m3 = __float_as_uint(x3) & 0x7fffffffu;
   CnAcc a;
@@ -532,8 +605,7 @@ __device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const CnSlot& c, int t, 
   a.n2 = min(max(a.n1, m3), a.n2);
   a.n1 = min(a.n1, m3);
   a.sp = __float_as_uint(x0) ^ __float_as_uint(x1) ^ __float_as_uint(x2) ^ __float_as_uint(x3);
-  a.hp = __float_as_uint(c.p.x) ^ __float_as_uint(c.p.y) ^ __float_as_uint(c.p.z) ^
-         __float_as_uint(c.p.w);
+  a.hp = c.g.x ^ c.g.y ^ c.g.z ^ c.g.w;
   cn_group(a, lk);
   const uint32_t srow = (P.sres >> t) & 1u;
   const uint32_t sgn = (a.sp ^ (srow << 31)) & 0x80000000u;
@@ -548,104 +620,80 @@ __device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const CnSlot& c, int t, 
   return (int)(srow ^ (a.hp >> 31));
 }
 
-// One pipeline step: gather slot t + 1's posteriors into `b`, load slot t + 2's
-// edges and messages into `c`, slot t + 3's metadata into `d`, compute slot t
-// from `a`.
-template <int VPL>
-__device__ __forceinline__ int cn_step(PathCtx<VPL>& P, const CnSlot& a, CnSlot& b, CnSlot& c,
-                                       CnSlot& d, int t, float alpha, float clip) {
-  cn_gather(P, b);
-  cn_load(P, c);
-  cn_load_meta(P, d, t + 3);
-  return cn_slot(P, a, t, alpha, clip);
-}
-
 template <int VPL>
 __device__ __forceinline__ int cn_phase(PathCtx<VPL>& P, float alpha, float clip) {
-  const int T = P.T;
-  if (T == 0) return 0;
-  int bad = 0;
-  // four rotating slots, unrolled by hand so that the rotation is a renaming
-  // (slots past the last one re-read the last one, harmlessly)
-  CnSlot A, B, C, D;
-  cn_load_meta(P, A, 0);
-  cn_load_meta(P, B, 1);
-  cn_load_meta(P, C, 2);
-  cn_load(P, A);
-  cn_load(P, B);
-  cn_gather(P, A);
-  for (int t = 0; t < T; t += 4) {
-    bad |= cn_step(P, A, B, C, D, t, alpha, clip);
-    if (t + 1 >= T) break;
-    bad |= cn_step(P, B, C, D, A, t + 1, alpha, clip);
-    if (t + 2 >= T) break;
-    bad |= cn_step(P, C, D, A, B, t + 2, alpha, clip);
-    if (t + 3 >= T) break;
-    bad |= cn_step(P, D, A, B, C, t + 3, alpha, clip);
-  }
-  return bad;
+  return slot_walk<VPL, true>(
+      P,
+      [&](Slot& s) {
+        s.g.x = __float_as_uint(at_byte(P.post, s.vo.x & 0xffffu));
+        s.g.y = __float_as_uint(at_byte(P.post, s.vo.x >> 16));
+        s.g.z = __float_as_uint(at_byte(P.post, s.vo.y & 0xffffu));
+        s.g.w = __float_as_uint(at_byte(P.post, s.vo.y >> 16));
+      },
+      [&](const Slot& s, int t) { return cn_slot(P, s, t, alpha, clip); });
 }
 
 // Syndrome check of the current hard decisions; optionally records each
 // row's unsatisfied flag for Alg. 3.
 template <int VPL>
 __device__ __forceinline__ int check_pass(PathCtx<VPL>& P, bool write_unsat) {
-  int bad = 0;
-  for (int t = 0; t < P.T; ++t) {
-    const uint32_t mt = P.meta[t * kWave + P.lane];
-    const int e0 = mt & kMetaEdge;
-    const int lk = (mt >> kMetaLogKShift) & 7;
-    const uint2 vo = *(const uint2*)(P.rvn + e0);
-    uint32_t hp = __float_as_uint(at_byte(P.post, vo.x & 0xffffu)) ^
-                  __float_as_uint(at_byte(P.post, vo.x >> 16)) ^
-                  __float_as_uint(at_byte(P.post, vo.y & 0xffffu)) ^
-                  __float_as_uint(at_byte(P.post, vo.y >> 16));
-    hp_group(hp, lk);
-    const int hx = (int)(((P.sres >> t) & 1u) ^ (hp >> 31));
-    if (write_unsat && (mt & kMetaLead) && (mt & kMetaValid))
-      P.unsat[(mt >> kMetaRowShift) & 0x3ff] = (uint8_t)hx;
-    bad |= hx;
-  }
-  return bad;
+  return slot_walk<VPL, false>(
+      P,
+      [&](Slot& s) {
+        s.g.x = __float_as_uint(at_byte(P.post, s.vo.x & 0xffffu));
+        s.g.y = __float_as_uint(at_byte(P.post, s.vo.x >> 16));
+        s.g.z = __float_as_uint(at_byte(P.post, s.vo.y & 0xffffu));
+        s.g.w = __float_as_uint(at_byte(P.post, s.vo.y >> 16));
+      },
+      [&](const Slot& s, int t) {
+        const uint32_t mt = s.mt;
+        uint32_t hp = s.g.x ^ s.g.y ^ s.g.z ^ s.g.w;
+        hp_group(hp, (mt >> kMetaLogKShift) & 7);
+        const int hx = (int)(((P.sres >> t) & 1u) ^ (hp >> 31));
+        if (write_unsat && (mt & kMetaLead) && (mt & kMetaValid))
+          P.unsat[(mt >> kMetaRowShift) & 0x3ff] = (uint8_t)hx;
+        return hx;
+      });
 }
 
 // VN phase: posteriors of the owned active VNs (Eq. 2), summed in column slot
 // order, and the history of the last four iterations of the step. The first
-// four slots of every owned VN are gathered together (index loads, then
-// message loads) so that their LDS latencies overlap.
+// five slots of every owned VN are gathered together (index loads, then
+// message loads) so that their LDS latencies overlap; VNs of degree above five
+// take a loop.
 template <int VPL>
 __device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist) {
   uint2 ix[VPL];
+  uint32_t ix5[VPL];
+  bool deg5[VPL];
 #pragma unroll
-  for (int r = 0; r < VPL; ++r) ix[r] = *(const uint2*)(P.cidx + P.vc0[r]);
+  for (int r = 0; r < VPL; ++r) {
+    ix[r] = *(const uint2*)(P.cidx + P.vc0(r));
+    deg5[r] = wave_any(P.vdg(r) > 4);
+    ix5[r] = deg5[r] && P.vdg(r) > 4 ? P.cidx[P.vc0(r) + 4] : 0u;   // 0: a valid, unused offset
+  }
   __builtin_amdgcn_sched_barrier(0);
-  float g[VPL][4];
+  float g[VPL][5];
 #pragma unroll
   for (int r = 0; r < VPL; ++r) {
     g[r][0] = at_byte(P.c2v, ix[r].x & 0xffffu);
     g[r][1] = at_byte(P.c2v, ix[r].x >> 16);
     g[r][2] = at_byte(P.c2v, ix[r].y & 0xffffu);
     g[r][3] = at_byte(P.c2v, ix[r].y >> 16);
+    g[r][4] = deg5[r] ? at_byte(P.c2v, ix5[r]) : 0.0f;
   }
   __builtin_amdgcn_sched_barrier(0);
-  float s[VPL];
-#pragma unroll
-  for (int r = 0; r < VPL; ++r) s[r] = (((P.llr[r] + g[r][0]) + g[r][1]) + g[r][2]) + g[r][3];
   long long edges = 0;
 #pragma unroll
   for (int r = 0; r < VPL; ++r) {
     const int v = P.lane + kWave * r;
-    for (int k0 = 4; k0 < P.vdg[r]; k0 += 4) {
-      const uint2 jx = *(const uint2*)(P.cidx + P.vc0[r] + k0);
-      s[r] += at_byte(P.c2v, jx.x & 0xffffu);
-      s[r] += at_byte(P.c2v, jx.x >> 16);
-      s[r] += at_byte(P.c2v, jx.y & 0xffffu);
-      s[r] += at_byte(P.c2v, jx.y >> 16);
-    }
-    if (v < P.n && P.st[r] < 0) {
-      const float x = s[r] == 0.0f ? -0.0f : s[r];   // sign bit = hard decision
+    float s = (((P.llr[r] + g[r][0]) + g[r][1]) + g[r][2]) + g[r][3];
+    if (deg5[r]) s += P.vdg(r) > 4 ? g[r][4] : 0.0f;   // + 0 is exact: s is never -0
+    for (int k = 5; k < P.vdg(r); ++k) s += at_byte(P.c2v, P.cidx[P.vc0(r) + k]);
+    if (v < P.n && P.st(r) < 0) {
+      const float x = s == 0.0f ? -0.0f : s;   // sign bit = hard decision
       P.post[v] = x;
-      edges += P.vdg[r];
+      edges += P.vdg(r);
       if (hist) {
         P.hs[r] += x;
         P.hmn[r] = fminf(P.hmn[r], x);
@@ -659,11 +707,12 @@ __device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist) {
 // Decodes shot `shot` of one window with the whole workgroup. Every thread
 // enters and leaves together; the caller synchronises before the LDS is reused.
 template <int VPL>
-__device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int shot,
+__device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int shot,
                             const uint8_t* __restrict__ syn, const long long syn_stride,
                             uint8_t* __restrict__ ehat, double* __restrict__ pm_out,
                             int* __restrict__ flags_out, const gdg_trace_dev& tr,
                             unsigned char* smem) {
+  const gdg_win_dev w = wref;   // uniform: kept in scalar registers, not re-read
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid >> 6;
@@ -944,8 +993,7 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
     for (int r = 0; r < VPL; ++r) {
       const int v = lane + kWave * r;
       const int vv = v < n_act ? v : 0;
-      P.vc0[r] = v < n_act ? cptr[vv] : 0;
-      P.vdg[r] = v < n_act ? sdeg[vv] : 0;
+      P.vinfo[r] = v < n_act ? (uint32_t)cptr[vv] | ((uint32_t)sdeg[vv] << 16) : 0u;
       P.llr[r] = sllr[vv];
     }
     // the sub-graph build scratch (sllr, sdeg) shares LDS with the path regions
@@ -961,7 +1009,7 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
     for (;;) {
       int pid = 0;
       if (lane == 0) pid = atomicAdd(&misc[0], 1);
-      pid = __shfl(pid, 0, kWave);
+      pid = __builtin_amdgcn_readfirstlane(pid);
       if (pid >= w.n_paths) break;
       int dmax, split;
       if (pid == 0) {
@@ -980,7 +1028,7 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
 #pragma unroll
       for (int r = 0; r < VPL; ++r) {
         const int v = lane + kWave * r;
-        P.st[r] = -1;
+        P.set_st(r, -1);
         if (v < n_act) {
           P.status[v] = -1;
           P.post[v] = P.llr[r];
@@ -1018,7 +1066,7 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
 #pragma unroll
           for (int r = 0; r < VPL; ++r) {
             const int v = lane + kWave * r;
-            if (v < n_act) sl[v] = (!conv && P.st[r] < 0) ? P.hs[r] : __builtin_nanf("");
+            if (v < n_act) sl[v] = (!conv && P.st(r) < 0) ? P.hs[r] : __builtin_nanf("");
           }
         }
         if (tr.first_post && pid == 0 && D == 1) {
@@ -1026,7 +1074,7 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
           for (int r = 0; r < VPL; ++r) {
             const int v = lane + kWave * r;
             if (v < n_act)
-              tr.first_post[(long long)shot * n_act + v] = P.st[r] < 0 ? P.post[v] : __builtin_nanf("");
+              tr.first_post[(long long)shot * n_act + v] = P.st(r) < 0 ? P.post[v] : __builtin_nanf("");
           }
         }
         if (conv) {
@@ -1045,11 +1093,11 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
 #pragma unroll
         for (int r = 0; r < VPL; ++r) {
           const int v = lane + kWave * r;
-          if (v < n_act && P.st[r] < 0 && P.vdg[r] >= 3) {
+          if (v < n_act && P.st(r) < 0 && P.vdg(r) >= 3) {
             bool taken = false;
             if (!w.low_error) {
               int nu = 0;
-              for (int e = P.vc0[r]; e < P.vc0[r] + P.vdg[r]; ++e) nu += P.unsat[P.crow[e]];
+              for (int e = P.vc0(r); e < P.vc0(r) + P.vdg(r); ++e) nu += P.unsat[P.crow[e]];
               const int b = agg_dec(P.hs[r], P.hmn[r], P.hmx[r], D, on_main, nu);
               if (b >= 0) {
                 set_status(P, r, v, b);
@@ -1132,7 +1180,7 @@ __device__ void decode_shot(const gdg_win_dev& w, const gdg_lds& L, const int sh
       for (int r = 0; r < VPL; ++r) {
         const int v = lane + kWave * r;
         bool one = false;
-        if (v < n_act) one = P.st[r] >= 0 ? P.st[r] == 1 : P.post[v] <= 0.0f;
+        if (v < n_act) one = P.st(r) >= 0 ? P.st(r) == 1 : P.post[v] <= 0.0f;
         const unsigned long long bal = __ballot(one);
         if (lane == 0 && kWave * r < n_act) {
           mybits[2 * r] = (uint32_t)bal;
