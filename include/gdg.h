@@ -208,6 +208,29 @@ int gdg_commit(const gdg_window* win, int32_t n_shots, const uint8_t* d_ehat,
                void* hip_stream);
 
 /*
+ * Streaming form of the sliding window (Sec. III, Eq. 6-8) for blocks that sit
+ * at different windows: a time-uniform DEM gives every middle window the same
+ * graph, priors and commit set up to a shift of w rows per window, so one
+ * window object serves all middle windows of all blocks.
+ *
+ * gdg_copy_rows copies n rows of m bytes between per-row offsets:
+ *   d_dst[d_dst_off[i] + j] = d_src[d_src_off[i] + j], j < m, or
+ *   d_dst[i*m + j] when d_dst_off is null (offsets: [n] int64 element offsets
+ *   on the device, e.g. block base + k*w to gather window k's syndrome).
+ *
+ * gdg_commit_indexed is gdg_commit with per-shot offsets: shot i's DEM row r
+ * of the window (row0 <= r, r - row0 < 2w) is d_detectors[d_det_off[i] + r - row0]
+ * and observable o is d_obs[d_obs_off[i] + o]; d_det_off / d_obs_off are [n]
+ * int64 on the device. Offsets are the caller's: they must stay inside the
+ * buffers. Both calls are asynchronous on hip_stream; errors as gdg_commit.
+ */
+int gdg_copy_rows(int32_t n, int32_t m, const uint8_t* d_src, const int64_t* d_src_off,
+                  uint8_t* d_dst, const int64_t* d_dst_off, void* hip_stream);
+int gdg_commit_indexed(const gdg_window* win, int32_t n_shots, const uint8_t* d_ehat,
+                       uint8_t* d_detectors, const int64_t* d_det_off, uint8_t* d_obs,
+                       const int64_t* d_obs_off, void* hip_stream);
+
+/*
  * Plain flooding min-sum BP on the whole window, no decimation (Eqs. 1-4):
  * n_iters iterations from fresh messages; d_post [n_shots][n_iters][n] float
  * receives every iteration's posteriors (Eq. 2), d_first_ok [n_shots] int32
@@ -242,6 +265,91 @@ int gdg_sample(const gdg_dem_dev* d, int32_t n_shots, uint64_t seed, uint32_t st
  */
 int gdg_evaluate(int32_t n_shots, int32_t n_rows, int32_t n_obs, const uint8_t* d_detectors,
                  const uint8_t* d_obs, uint8_t* d_fail, void* hip_stream);
+
+/*
+ * The error vectors behind gdg_sample's shots: d_err[s][c] = 1 iff DEM
+ * column c fired in shot shot0 + s (same seed/stream/shot convention).
+ * Training labels for the learned proposer; not part of decoding.
+ */
+int gdg_sample_errors(const gdg_dem_dev* d, int32_t n_shots, uint64_t seed, uint32_t stream,
+                      uint64_t shot0, uint8_t* d_err, void* hip_stream);
+
+/*
+ * Learned decimation proposer -- an addition to the paper's method (GDG's own
+ * selection is Alg. 1). A 17-64-64-1 perceptron with ReLU hidden layers
+ * scores a candidate VN from its last 16 BP posteriors and its degree; the
+ * output is the logit that the candidate is in error (its error bit is 1).
+ *
+ * Parameters: GDG_MLP_PARAMS floats, W1 [17][64] (input-major), b1 [64],
+ * W2 [64][64], b2 [64], w3 [64], b3. Features x [n][17]: posteriors squashed
+ * as p / (8 + |p|), oldest first, then degree / 8.
+ *
+ * Training (FP32, device buffers, asynchronous on hip_stream):
+ *   gdg_mlp_forward  z[n] = network(x);
+ *   gdg_mlp_grad     mean binary cross-entropy of logits z against labels
+ *                    y [n] (0/1 floats): d_grad [GDG_MLP_PARAMS] gradient,
+ *                    d_loss [1] (may be null); reduction order is fixed, so
+ *                    results are deterministic. d_work: caller's scratch of
+ *                    gdg_mlp_grad_work_bytes(n) bytes.
+ *   gdg_mlp_adam     one Adam step (Kingma and Ba, bias-corrected, step >= 1)
+ *                    on params with moment buffers d_m, d_v [GDG_MLP_PARAMS].
+ * Inference (BF16 matrix cores, FP32 accumulation):
+ *   gdg_model_create copies host FP32 parameters into a device model (weights
+ *                    rounded to BF16, nearest even); owned by the library.
+ *   gdg_mlp_infer    z[n] = network(x) with that model (for testing).
+ */
+#define GDG_MLP_PARAMS 5377
+/*
+ * Decoding with the proposer. Mode 1: each path of a small learned tree
+ * (2^guesses paths) decimates, at every step, the candidate with the highest
+ * logit among the first n_cand VNs in Alg. 1's order (ties: the earlier one),
+ * to 1 if that logit is >= 0, else to 0; a step whose best logit has
+ * magnitude below tau is a guess point (bit i of the path id: take the other
+ * value at the i-th guess point), up to `guesses` of them. The best
+ * converged path by Eq. 5 wins; if no learned path meets the syndrome, or the
+ * winner's metric exceeds pm_fallback, the window's plain GDG tree decodes
+ * the shot instead and its flags gain GDG_FLAG_FALLBACK. Mode 2 (training data): plain
+ * GDG, and on the main path's first rec_steps steps the features of the first
+ * 16 candidates go to d_rec_x [n_shots][rec_steps][16][17], their window
+ * columns to d_rec_col (entries not reached stay as the caller filled them)
+ * and their favoured values to d_rec_fav.
+ * Outputs as gdg_decode_batch. d_work: gdg_learned_work_bytes(win) bytes of
+ * device scratch (posterior history), not shared between concurrent calls.
+ */
+typedef struct gdg_learn_cfg {
+  int32_t mode;        /* 1 learned + plain fallback; 2 record */
+  int32_t n_cand;      /* candidates scored per step, 1..16 */
+  int32_t guesses;     /* mode 1: guess points per path (2^guesses <= window paths) */
+  float tau;           /* mode 1: guess when the best logit is below tau */
+  int32_t rec_steps;   /* mode 2 */
+  float* d_rec_x;
+  int32_t* d_rec_col;
+  int32_t* d_rec_fav;
+  int64_t* d_edge_iters;   /* optional [n_shots]: BP edge updates spent on each shot */
+  float pm_fallback;       /* mode 1: plain GDG also decodes when the best learned
+                              path metric (Eq. 5) exceeds this (+inf: only when no
+                              learned path meets the syndrome) */
+  int32_t tree;            /* mode 1: 1 = guess at depths 1..guesses instead (Fig. 2's
+                              tree, paths 1.. split and run g + extra_steps steps),
+                              0 = guess at low-confidence steps */
+} gdg_learn_cfg;
+typedef struct gdg_model gdg_model;
+int gdg_mlp_forward(int32_t n, const float* d_params, const float* d_x, float* d_z,
+                    void* hip_stream);
+size_t gdg_mlp_grad_work_bytes(int32_t n);
+int gdg_mlp_grad(int32_t n, const float* d_params, const float* d_x, const float* d_y,
+                 float* d_grad, float* d_loss, void* d_work, size_t work_bytes,
+                 void* hip_stream);
+int gdg_mlp_adam(int32_t step, float lr, float beta1, float beta2, float eps, float* d_params,
+                 const float* d_grad, float* d_m, float* d_v, void* hip_stream);
+int gdg_model_create(const float* h_params, gdg_model** out);
+void gdg_model_free(gdg_model* m);
+int gdg_mlp_infer(const gdg_model* m, int32_t n, const float* d_x, float* d_z, void* hip_stream);
+size_t gdg_learned_work_bytes(const gdg_window* win);
+int gdg_decode_learned(const gdg_window* win, const gdg_model* model, const gdg_learn_cfg* cfg,
+                       int32_t n_shots, const uint8_t* d_syndrome, int64_t syn_stride,
+                       uint8_t* d_ehat, double* d_pm, int32_t* d_flags, void* d_work,
+                       size_t work_bytes, void* hip_stream);
 
 const char* gdg_last_error(void);
 

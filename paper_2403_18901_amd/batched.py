@@ -23,10 +23,11 @@ N_CU = 256
 
 
 def _bucket(w) -> int:
-    m, na = w.m, w.n_act
-    if m <= 128 and na <= 384:
+    """The kernel's register tiling for a window (VNs per lane)."""
+    na = w.n_act
+    if na <= 384:
         return 0
-    if m <= 256 and na <= 512:
+    if na <= 512:
         return 1
     return 2
 

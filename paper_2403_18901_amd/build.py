@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgdg_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("gdg_kernels.hip", "gdg_host.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("gdg_kernels.hip", "gdg_mlp.hip", "gdg_host.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # keep the compiler from emitting packed-FP32 (v_pk_*_f32) instructions

@@ -16,6 +16,7 @@
 
 #include "../../include/gdg.h"
 #include "gdg_kernels.h"
+#include "gdg_mlp.h"
 
 namespace {
 
@@ -107,6 +108,14 @@ struct gdg_window {
   }
 };
 
+struct gdg_model {
+  gdg_model_dev dev{};
+  std::vector<void*> allocs;
+  ~gdg_model() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
 struct gdg_dem_dev {
   gdg_dem_dev_k k{};
   std::vector<void*> allocs;
@@ -143,6 +152,7 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   L.cptr = take(2 * (na + 1));
   L.crow = take(2 * col_slots);
   L.meta = take(4 * 64 * tcols);
+  L.vdeg = take(na);
   L.ppm = take(8 * P);
   L.pend = take(4 * P);
   L.pbits = take(4 * P * L.pbits_words);
@@ -474,7 +484,7 @@ namespace {
 int g_lds_set[3] = {65536, 65536, 65536};   // dynamic-LDS limit set per kernel bucket
 
 int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
-                const gdg_trace_dev& tr, hipStream_t st) {
+                const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn = nullptr) {
   if (!jobs || n_jobs < 1 || n_jobs > GDG_MAX_JOBS) return fail(GDG_EINVAL, "1..8 jobs per launch");
   if (waves < 1 || waves > 8) return fail(GDG_EINVAL, "waves must be in 1..8");
   if (workgroups < 0) return fail(GDG_EINVAL, "negative workgroup count");
@@ -505,6 +515,7 @@ int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
   }
   J.n_jobs = n_jobs;
   J.total = total;
+  if (learn) J.learn = *learn;
   if (total == 0) return GDG_OK;
   if (lds > max_lds_per_block()) return fail(GDG_ESHAPE, "jobs do not fit in LDS at this shape");
   if (lds > g_lds_set[bucket]) {
@@ -546,6 +557,50 @@ int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_sy
   return launch_jobs(&job, 1, win->waves, 0, tr, (hipStream_t)hip_stream);
 }
 
+// Persistent grid of the learned decode: two workgroups per CU on 256 CUs.
+constexpr int kLearnGrid = 512;
+
+size_t gdg_learned_work_bytes(const gdg_window* win) {
+  if (!win) return 0;
+  return (size_t)kLearnGrid * win->waves * 16 * win->info.n_act * sizeof(float);
+}
+
+int gdg_decode_learned(const gdg_window* win, const gdg_model* model, const gdg_learn_cfg* cfg,
+                       int32_t n_shots, const uint8_t* d_syndrome, int64_t syn_stride,
+                       uint8_t* d_ehat, double* d_pm, int32_t* d_flags, void* d_work,
+                       size_t work_bytes, void* hip_stream) {
+  if (!win || !cfg) return fail(GDG_EINVAL, "null argument");
+  if (cfg->mode != 1 && cfg->mode != 2) return fail(GDG_EINVAL, "mode must be 1 or 2");
+  if (cfg->mode == 1 && !model) return fail(GDG_EINVAL, "learned mode needs a model");
+  if (cfg->n_cand < 1 || cfg->n_cand > 16) return fail(GDG_EINVAL, "n_cand must be in 1..16");
+  if (cfg->mode == 1 && (cfg->guesses < 0 || (1 << cfg->guesses) > win->info.n_paths))
+    return fail(GDG_EINVAL, "2^guesses must not exceed the window's path count");
+  if (cfg->mode == 2 && (cfg->rec_steps < 1 || !cfg->d_rec_x || !cfg->d_rec_col || !cfg->d_rec_fav))
+    return fail(GDG_EINVAL, "record mode needs rec_steps >= 1 and its buffers");
+  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+  if (n_shots == 0) return GDG_OK;
+  if (!d_work || work_bytes < gdg_learned_work_bytes(win)) return fail(GDG_EINVAL, "workspace too small");
+  gdg_learn_dev ld{};
+  ld.mode = cfg->mode;
+  ld.n_cand = cfg->n_cand;
+  ld.guesses = cfg->mode == 1 ? cfg->guesses : 0;
+  ld.tau = cfg->tau;
+  ld.pm_fallback = cfg->pm_fallback;
+  ld.tree = cfg->tree ? 1 : 0;
+  if (model) ld.model = model->dev;
+  ld.ring = (float*)d_work;
+  ld.ring_stride = win->info.n_act;
+  ld.rec_steps = cfg->rec_steps;
+  ld.rec_x = cfg->d_rec_x;
+  ld.rec_col = cfg->d_rec_col;
+  ld.rec_fav = cfg->d_rec_fav;
+  gdg_job job{win, n_shots, d_syndrome, syn_stride, d_ehat, d_pm, d_flags};
+  gdg_trace_dev tr{};
+  tr.edge_iters = (long long*)cfg->d_edge_iters;
+  return launch_jobs(&job, 1, win->waves, std::min(n_shots, kLearnGrid), tr,
+                     (hipStream_t)hip_stream, &ld);
+}
+
 int gdg_decode_jobs(const gdg_job* jobs, int32_t n_jobs, const gdg_launch_cfg* cfg,
                     void* hip_stream) {
   int waves = 4, workgroups = 0;
@@ -576,8 +631,35 @@ int gdg_commit(const gdg_window* win, int32_t n_shots, const uint8_t* d_ehat,
   if (!d_ehat || !d_detectors || (!d_obs && win->cm.n_obs > 0))
     return fail(GDG_EINVAL, "null buffer");
   hipError_t e = gdg_launch_commit(win->cm, n_shots, d_ehat, d_detectors, det_stride, d_obs,
-                                   obs_stride, (hipStream_t)hip_stream);
+                                   obs_stride, nullptr, nullptr, 0, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "commit launch");
+  return GDG_OK;
+}
+
+int gdg_commit_indexed(const gdg_window* win, int32_t n_shots, const uint8_t* d_ehat,
+                       uint8_t* d_detectors, const int64_t* d_det_off, uint8_t* d_obs,
+                       const int64_t* d_obs_off, void* hip_stream) {
+  if (!win) return fail(GDG_EINVAL, "null window");
+  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+  if (n_shots == 0) return GDG_OK;
+  if (!d_ehat || !d_detectors || !d_det_off || (win->cm.n_obs > 0 && (!d_obs || !d_obs_off)))
+    return fail(GDG_EINVAL, "null buffer");
+  static_assert(sizeof(int64_t) == sizeof(long long), "offset type");
+  hipError_t e = gdg_launch_commit(win->cm, n_shots, d_ehat, d_detectors, 0, d_obs, 0,
+                                   (const long long*)d_det_off, (const long long*)d_obs_off,
+                                   win->info.row0, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "commit launch");
+  return GDG_OK;
+}
+
+int gdg_copy_rows(int32_t n, int32_t m, const uint8_t* d_src, const int64_t* d_src_off,
+                  uint8_t* d_dst, const int64_t* d_dst_off, void* hip_stream) {
+  if (n < 0 || m < 0) return fail(GDG_EINVAL, "negative size");
+  if (n == 0 || m == 0) return GDG_OK;
+  if (!d_src || !d_src_off || !d_dst) return fail(GDG_EINVAL, "null buffer");
+  hipError_t e = gdg_launch_copy_rows(n, m, d_src, (const long long*)d_src_off, d_dst,
+                                      (const long long*)d_dst_off, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "copy launch");
   return GDG_OK;
 }
 
@@ -645,6 +727,18 @@ int gdg_sample(const gdg_dem_dev* d, int32_t n_shots, uint64_t seed, uint32_t st
   return GDG_OK;
 }
 
+int gdg_sample_errors(const gdg_dem_dev* d, int32_t n_shots, uint64_t seed, uint32_t stream,
+                      uint64_t shot0, uint8_t* d_err, void* hip_stream) {
+  if (!d) return fail(GDG_EINVAL, "null dem");
+  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+  if (n_shots == 0) return GDG_OK;
+  if (!d_err) return fail(GDG_EINVAL, "null buffer");
+  hipError_t e = gdg_launch_sample_errors(d->k, n_shots, seed, stream, shot0, d_err,
+                                          (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "sample launch");
+  return GDG_OK;
+}
+
 int gdg_evaluate(int32_t n_shots, int32_t n_rows, int32_t n_obs, const uint8_t* d_detectors,
                  const uint8_t* d_obs, uint8_t* d_fail, void* hip_stream) {
   if (n_shots < 0 || n_rows < 0 || n_obs < 0) return fail(GDG_EINVAL, "bad sizes");
@@ -653,6 +747,126 @@ int gdg_evaluate(int32_t n_shots, int32_t n_rows, int32_t n_obs, const uint8_t* 
   hipError_t e = gdg_launch_evaluate(n_shots, n_rows, n_obs, d_detectors, d_obs, d_fail,
                                      (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "evaluate launch");
+  return GDG_OK;
+}
+
+// ------------------------------------------------------------------ learned proposer network
+
+int gdg_mlp_forward(int32_t n, const float* d_params, const float* d_x, float* d_z,
+                    void* hip_stream) {
+  if (n < 0) return fail(GDG_EINVAL, "negative n");
+  if (n == 0) return GDG_OK;
+  if (!d_params || !d_x || !d_z) return fail(GDG_EINVAL, "null buffer");
+  hipError_t e = gdg_launch_mlp_forward(n, d_params, d_x, d_z, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp forward launch");
+  return GDG_OK;
+}
+
+size_t gdg_mlp_grad_work_bytes(int32_t n) {
+  return n > 0 ? sizeof(float) * gdg_mlp_grad_work_floats(n) : 0;
+}
+
+int gdg_mlp_grad(int32_t n, const float* d_params, const float* d_x, const float* d_y,
+                 float* d_grad, float* d_loss, void* d_work, size_t work_bytes,
+                 void* hip_stream) {
+  if (n <= 0) return fail(GDG_EINVAL, "n must be positive");
+  if (!d_params || !d_x || !d_y || !d_grad || !d_work) return fail(GDG_EINVAL, "null buffer");
+  if (work_bytes < gdg_mlp_grad_work_bytes(n)) return fail(GDG_EINVAL, "workspace too small");
+  hipError_t e = gdg_launch_mlp_grad(n, d_params, d_x, d_y, d_grad, d_loss, (float*)d_work,
+                                     (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp grad launch");
+  return GDG_OK;
+}
+
+int gdg_mlp_adam(int32_t step, float lr, float beta1, float beta2, float eps, float* d_params,
+                 const float* d_grad, float* d_m, float* d_v, void* hip_stream) {
+  if (step < 1) return fail(GDG_EINVAL, "step must be >= 1");
+  if (!d_params || !d_grad || !d_m || !d_v) return fail(GDG_EINVAL, "null buffer");
+  hipError_t e = gdg_launch_mlp_adam(step, lr, beta1, beta2, eps, d_params, d_grad, d_m, d_v,
+                                     (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "adam launch");
+  return GDG_OK;
+}
+
+}  // extern "C"
+
+
+namespace {
+uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+}  // namespace
+
+extern "C" {
+
+int gdg_model_create(const float* h_params, gdg_model** out) {
+  if (!h_params || !out) return fail(GDG_EINVAL, "null argument");
+  *out = nullptr;
+  const int In = GDG_MLP_IN, H = GDG_MLP_H;
+  const float* W1 = h_params;
+  const float* b1 = W1 + In * H;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + H * H;
+  const float* w3 = b2 + H;
+  const float b3 = w3[H];
+  // A operands: tile mt, K step s, lane l -> W^T[16 mt + l % 16][16 s + 4 (l / 16) + j]
+  auto pack = [&](const float* W, int n_in, int steps, std::vector<uint32_t>& dst) {
+    dst.assign((size_t)4 * steps * 64 * 2, 0u);
+    for (int mt = 0; mt < 4; ++mt)
+      for (int s = 0; s < steps; ++s)
+        for (int l = 0; l < 64; ++l) {
+          uint16_t h[4];
+          for (int j = 0; j < 4; ++j) {
+            const int out_u = 16 * mt + l % 16, in_u = 16 * s + 4 * (l / 16) + j;
+            h[j] = in_u < n_in ? bf16_rne(W[in_u * H + out_u]) : 0;
+          }
+          const size_t at = (((size_t)mt * steps + s) * 64 + l) * 2;
+          dst[at] = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+          dst[at + 1] = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        }
+  };
+  std::vector<uint32_t> a1, a2;
+  pack(W1, In, 2, a1);
+  pack(W2, H, 4, a2);
+  std::unique_ptr<gdg_model> m(new gdg_model());
+  int rc;
+  uint32_t* d = nullptr;
+  if ((rc = upload(a1, &d))) return rc;
+  m->allocs.push_back(d);
+  m->dev.a1 = (const uint2*)d;
+  if ((rc = upload(a2, &d))) return rc;
+  m->allocs.push_back(d);
+  m->dev.a2 = (const uint2*)d;
+  float* f = nullptr;
+  std::vector<float> v(b1, b1 + H);
+  if ((rc = upload(v, &f))) return rc;
+  m->allocs.push_back(f);
+  m->dev.b1 = f;
+  v.assign(b2, b2 + H);
+  if ((rc = upload(v, &f))) return rc;
+  m->allocs.push_back(f);
+  m->dev.b2 = f;
+  v.assign(w3, w3 + H);
+  if ((rc = upload(v, &f))) return rc;
+  m->allocs.push_back(f);
+  m->dev.w3 = f;
+  m->dev.b3 = b3;
+  *out = m.release();
+  return GDG_OK;
+}
+
+void gdg_model_free(gdg_model* m) { delete m; }
+
+int gdg_mlp_infer(const gdg_model* m, int32_t n, const float* d_x, float* d_z, void* hip_stream) {
+  if (!m) return fail(GDG_EINVAL, "null model");
+  if (n < 0) return fail(GDG_EINVAL, "negative n");
+  if (n == 0) return GDG_OK;
+  if (!d_x || !d_z) return fail(GDG_EINVAL, "null buffer");
+  hipError_t e = gdg_launch_mlp_infer(m->dev, n, d_x, d_z, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp infer launch");
   return GDG_OK;
 }
 

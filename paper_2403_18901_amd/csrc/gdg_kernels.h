@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gdg_mlp.h"
+
 // Window graph on the device plus decoder parameters.
 struct gdg_win_dev {
   int m, n, n_act, e_full, n_paths;
@@ -25,7 +27,7 @@ struct gdg_win_dev {
 struct gdg_lds {
   int total;
   // per shot
-  int sorig, psyn, sel, rptr, rvn, cidx, cptr, crow, meta, ppm, pend, pbits, misc, obits, eacc;
+  int sorig, psyn, sel, rptr, rvn, cidx, cptr, crow, meta, vdeg, ppm, pend, pbits, misc, obits, eacc;
   int pbits_words, obits_words, meta_cols;
   // phase union (relative to u_base): preprocessing, sub-graph build scratch,
   // per-wavefront path regions
@@ -78,9 +80,27 @@ struct gdg_job_dev {
   double* pm;
   int* flags;
 };
+// Learned proposer settings of a launch (mode 0: plain GDG).
+struct gdg_learn_dev {
+  int mode;          // 0 plain; 1 learned paths, plain GDG fallback; 2 record candidates
+  int n_cand;        // candidates scored per step (<= 16)
+  int guesses;       // guess points of the learned path set (1 << guesses paths)
+  int tree;          // 1: guesses at depths 1..guesses (Fig. 2); 0: at low-confidence steps
+  float tau;         // a step is a guess point when the best logit is below tau
+  float pm_fallback; // plain GDG also runs when the best learned path metric exceeds this
+  gdg_model_dev model;
+  float* ring;       // posterior history: [gridDim.x][waves][16][ring_stride]
+  int ring_stride;   // >= n_act
+  int rec_steps;     // mode 2: main-path steps recorded per shot
+  float* rec_x;      // [n_shots][rec_steps][16][17] candidate features
+  int* rec_col;      // [n_shots][rec_steps][16] window column (caller fills -1)
+  int* rec_fav;      // [n_shots][rec_steps][16] favoured value
+};
+
 struct gdg_jobs_dev {
   int n_jobs, total;
   gdg_job_dev job[kMaxJobs];
+  gdg_learn_dev learn;
 };
 
 hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
@@ -91,8 +111,14 @@ hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, 
                          int n_iters, float* post, int* first_ok, hipStream_t st);
 hipError_t gdg_launch_commit(const gdg_commit_dev& cm, int n_shots, const uint8_t* ehat,
                              uint8_t* det, long long det_stride, uint8_t* obs,
-                             long long obs_stride, hipStream_t st);
+                             long long obs_stride, const long long* det_off,
+                             const long long* obs_off, int row0, hipStream_t st);
+hipError_t gdg_launch_copy_rows(int n, int m, const uint8_t* src, const long long* src_off,
+                                uint8_t* dst, const long long* dst_off, hipStream_t st);
 hipError_t gdg_launch_sample(const gdg_dem_dev_k& d, int n_shots, uint64_t seed, uint32_t stream,
                              uint64_t shot0, uint8_t* det, uint8_t* obs, hipStream_t st);
+hipError_t gdg_launch_sample_errors(const gdg_dem_dev_k& d, int n_shots, uint64_t seed,
+                                    uint32_t stream, uint64_t shot0, uint8_t* err,
+                                    hipStream_t st);
 hipError_t gdg_launch_evaluate(int n_shots, int n_rows, int n_obs, const uint8_t* det,
                                const uint8_t* obs, uint8_t* fail, hipStream_t st);

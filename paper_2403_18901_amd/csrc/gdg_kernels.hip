@@ -662,7 +662,7 @@ __device__ __forceinline__ int check_pass(PathCtx<VPL>& P, bool write_unsat) {
 // message loads) so that their LDS latencies overlap; VNs of degree above five
 // take a loop.
 template <int VPL>
-__device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist) {
+__device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist, float* ring_slot) {
   uint2 ix[VPL];
   uint32_t ix5[VPL];
   bool deg5[VPL];
@@ -693,6 +693,7 @@ __device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist) {
     if (v < P.n && P.st(r) < 0) {
       const float x = s == 0.0f ? -0.0f : s;   // sign bit = hard decision
       P.post[v] = x;
+      if (ring_slot) ring_slot[v] = x;
       edges += P.vdg(r);
       if (hist) {
         P.hs[r] += x;
@@ -706,12 +707,12 @@ __device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist) {
 
 // Decodes shot `shot` of one window with the whole workgroup. Every thread
 // enters and leaves together; the caller synchronises before the LDS is reused.
-template <int VPL>
+template <int VPL, bool kLearn>
 __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int shot,
                             const uint8_t* __restrict__ syn, const long long syn_stride,
                             uint8_t* __restrict__ ehat, double* __restrict__ pm_out,
                             int* __restrict__ flags_out, const gdg_trace_dev& tr,
-                            unsigned char* smem) {
+                            const gdg_learn_dev& lrn, unsigned char* smem) {
   const gdg_win_dev w = wref;   // uniform: kept in scalar registers, not re-read
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -727,6 +728,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
   uint16_t* cptr = (uint16_t*)(smem + L.cptr);
   uint16_t* crow = (uint16_t*)(smem + L.crow);
   uint32_t* meta = (uint32_t*)(smem + L.meta);
+  uint8_t* vdeg = smem + L.vdeg;                // sub-graph VN degrees (learned proposer)
   double* ppm = (double*)(smem + L.ppm);
   int* pend = (int*)(smem + L.pend);
   uint32_t* pbits = (uint32_t*)(smem + L.pbits);
@@ -865,6 +867,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       iscan[v] = (d + kPad - 1) / kPad * kPad;   // column slots padded to a multiple of 4
       sllr[v] = w.llr[c];
       sdeg[v] = (uint8_t)d;
+      vdeg[v] = (uint8_t)d;
     }
     __syncthreads();
     wg_exclusive_scan_wave0(iscan, n_act);
@@ -968,6 +971,11 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
   }
 
   // ---------------------------------------------------------- decision paths
+  // Run 0 is the configured path set: the plain tree of Fig. 2, or the learned
+  // proposer's paths; run 1 is the plain tree again, as the fallback when no
+  // learned path met the syndrome.
+  const int mode = kLearn ? lrn.mode : 0;
+  int fallback = 0;
   {
     unsigned char* Wb = U + wave * L.w_stride;
     PathCtx<VPL> P;
@@ -1004,252 +1012,368 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       P.status[n_act] = 0;
     }
     const int e_pad = rptr[m];
+    // this wavefront's posterior history ring (learned proposer): slot j holds
+    // the posteriors of BP iteration t with (t - 1) mod 16 = j
+    float* const ring = mode ? lrn.ring + ((long long)blockIdx.x * (blockDim.x >> 6) + wave) *
+                                              16 * lrn.ring_stride
+                             : nullptr;
     wave_sync();
 
-    for (;;) {
-      int pid = 0;
-      if (lane == 0) pid = atomicAdd(&misc[0], 1);
-      pid = __builtin_amdgcn_readfirstlane(pid);
-      if (pid >= w.n_paths) break;
-      int dmax, split;
-      if (pid == 0) {
-        dmax = w.dmax_main;
-        split = 0;
-      } else if (w.g > 0 && pid < (1 << w.g)) {
-        dmax = w.g + w.extra;
-        split = w.g;
-      } else {
-        split = w.g + 1 + (pid - (1 << w.g));
-        dmax = split + w.extra;
+    for (int run = 0; run < 2; ++run) {
+      if (run == 1) {
+        if (mode != 1 || misc[6]) break;
+        fallback = 1;
       }
-      int* dlog = tr.dec ? tr.dec + ((long long)shot * w.n_paths + pid) * tr.log_cap * 3 : nullptr;
+      const bool learned = run == 0 && mode == 1;
+      const int n_run = learned ? (1 << lrn.guesses) : w.n_paths;
+      for (;;) {
+        int pid = 0;
+        if (lane == 0) pid = atomicAdd(&misc[0], 1);
+        pid = __builtin_amdgcn_readfirstlane(pid);
+        if (pid >= n_run) break;
+        int dmax, split;
+        if (pid == 0 || (learned && !lrn.tree)) {
+          dmax = w.dmax_main;
+          split = 0;
+        } else if (learned) {   // Fig. 2's tree with `guesses` levels
+          dmax = lrn.guesses + w.extra;
+          split = lrn.guesses;
+        } else if (w.g > 0 && pid < (1 << w.g)) {
+          dmax = w.g + w.extra;
+          split = w.g;
+        } else {
+          split = w.g + 1 + (pid - (1 << w.g));
+          dmax = split + w.extra;
+        }
+        const bool record = run == 0 && mode == 2 && pid == 0;
+        const bool use_ring = learned || record;
+        int guess_used = 0;
+        bool deviated = false;
+        int* dlog = (tr.dec && !learned)
+                        ? tr.dec + ((long long)shot * w.n_paths + pid) * tr.log_cap * 3
+                        : nullptr;
 
-      // fresh path: every VN active, messages from the priors
-#pragma unroll
-      for (int r = 0; r < VPL; ++r) {
-        const int v = lane + kWave * r;
-        P.set_st(r, -1);
-        if (v < n_act) {
-          P.status[v] = -1;
-          P.post[v] = P.llr[r];
-        }
-      }
-      P.sres = 0u;
-      // t = 0: no CN message yet; also clears the zero slot and the dummy batch
-      for (int e = lane; e < e_pad + 2 * kPad; e += kWave) P.c2v[e] = 0.0f;
-      wave_sync();
-      int end = 0, steps = 0;
-      if (dead0 || !peel(P)) end = END_CONTRADICTION;   // peel at init too
-      for (int D = 1; end == 0 && D <= dmax; ++D) {
-#pragma unroll
-        for (int r = 0; r < VPL; ++r) {
-          P.hs[r] = 0.0f;
-          P.hmn[r] = kInfF;
-          P.hmx[r] = -kInfF;
-        }
-        bool conv = false;
-        for (int t = 1; t <= T; ++t) {
-          const int bad = cn_phase(P, alpha, clip);
-          const bool any_bad = wave_any(bad != 0);
-          if (t >= 2 && !any_bad) {
-            conv = true;
-            break;
-          }
-          wave_sync();
-          my_edges += vn_phase(P, t > T - 4);
-          wave_sync();
-        }
-        if (!conv) conv = !wave_any(check_pass(P, !w.low_error) != 0);
-        steps = D;
-        if (tr.step_lsum && D - 1 < tr.log_cap) {
-          float* sl = tr.step_lsum + (((long long)shot * w.n_paths + pid) * tr.log_cap + (D - 1)) * n_act;
-#pragma unroll
-          for (int r = 0; r < VPL; ++r) {
-            const int v = lane + kWave * r;
-            if (v < n_act) sl[v] = (!conv && P.st(r) < 0) ? P.hs[r] : __builtin_nanf("");
-          }
-        }
-        if (tr.first_post && pid == 0 && D == 1) {
-#pragma unroll
-          for (int r = 0; r < VPL; ++r) {
-            const int v = lane + kWave * r;
-            if (v < n_act)
-              tr.first_post[(long long)shot * n_act + v] = P.st(r) < 0 ? P.post[v] : __builtin_nanf("");
-          }
-        }
-        if (conv) {
-          end = END_CONVERGED;
-          break;
-        }
-        if (D == dmax) {
-          end = END_EXHAUSTED;
-          break;
-        }
-        // Alg. 1 with Alg. 3 inside it
-        wave_sync();
-        const bool on_main = path_on_main(w, pid, split, D);
-        unsigned long long kall = ~0ull, kneg = ~0ull;
-        int n_agg = 0;
+        // fresh path: every VN active, messages from the priors
 #pragma unroll
         for (int r = 0; r < VPL; ++r) {
           const int v = lane + kWave * r;
-          if (v < n_act && P.st(r) < 0 && P.vdg(r) >= 3) {
-            bool taken = false;
-            if (!w.low_error) {
-              int nu = 0;
-              for (int e = P.vc0(r); e < P.vc0(r) + P.vdg(r); ++e) nu += P.unsat[P.crow[e]];
-              const int b = agg_dec(P.hs[r], P.hmn[r], P.hmx[r], D, on_main, nu);
-              if (b >= 0) {
-                set_status(P, r, v, b);
-                ++n_agg;
-                taken = true;
+          P.set_st(r, -1);
+          if (v < n_act) {
+            P.status[v] = -1;
+            P.post[v] = P.llr[r];
+            if (use_ring)
+              for (int j = 0; j < 16; ++j) ring[j * lrn.ring_stride + v] = P.llr[r];
+          }
+        }
+        P.sres = 0u;
+        // t = 0: no CN message yet; also clears the zero slot and the dummy batch
+        for (int e = lane; e < e_pad + 2 * kPad; e += kWave) P.c2v[e] = 0.0f;
+        wave_sync();
+        int end = 0, steps = 0, it = 0;
+        if (dead0 || !peel(P)) end = END_CONTRADICTION;   // peel at init too
+        for (int D = 1; end == 0 && D <= dmax; ++D) {
+#pragma unroll
+          for (int r = 0; r < VPL; ++r) {
+            P.hs[r] = 0.0f;
+            P.hmn[r] = kInfF;
+            P.hmx[r] = -kInfF;
+          }
+          bool conv = false;
+          for (int t = 1; t <= T; ++t) {
+            const int bad = cn_phase(P, alpha, clip);
+            const bool any_bad = wave_any(bad != 0);
+            if (t >= 2 && !any_bad) {
+              conv = true;
+              break;
+            }
+            wave_sync();
+            my_edges += vn_phase(P, t > T - 4, use_ring ? ring + (it & 15) * lrn.ring_stride : nullptr);
+            ++it;
+            wave_sync();
+          }
+          if (!conv) conv = !wave_any(check_pass(P, !w.low_error) != 0);
+          steps = D;
+          if (tr.step_lsum && !learned && D - 1 < tr.log_cap) {
+            float* sl = tr.step_lsum + (((long long)shot * w.n_paths + pid) * tr.log_cap + (D - 1)) * n_act;
+#pragma unroll
+            for (int r = 0; r < VPL; ++r) {
+              const int v = lane + kWave * r;
+              if (v < n_act) sl[v] = (!conv && P.st(r) < 0) ? P.hs[r] : __builtin_nanf("");
+            }
+          }
+          if (tr.first_post && pid == 0 && D == 1 && run == 0) {
+#pragma unroll
+            for (int r = 0; r < VPL; ++r) {
+              const int v = lane + kWave * r;
+              if (v < n_act)
+                tr.first_post[(long long)shot * n_act + v] = P.st(r) < 0 ? P.post[v] : __builtin_nanf("");
+            }
+          }
+          if (conv) {
+            end = END_CONVERGED;
+            break;
+          }
+          if (D == dmax) {
+            end = END_EXHAUSTED;
+            break;
+          }
+          // Alg. 1 with Alg. 3 inside it
+          wave_sync();
+          const bool on_main = learned && !lrn.tree ? !deviated : path_on_main(w, pid, split, D);
+          unsigned long long kall = ~0ull, kneg = ~0ull;
+          int n_agg = 0;
+#pragma unroll
+          for (int r = 0; r < VPL; ++r) {
+            const int v = lane + kWave * r;
+            if (v < n_act && P.st(r) < 0 && P.vdg(r) >= 3) {
+              bool taken = false;
+              if (!w.low_error) {
+                int nu = 0;
+                for (int e = P.vc0(r); e < P.vc0(r) + P.vdg(r); ++e) nu += P.unsat[P.crow[e]];
+                const int b = agg_dec(P.hs[r], P.hmn[r], P.hmx[r], D, on_main, nu);
+                if (b >= 0) {
+                  set_status(P, r, v, b);
+                  ++n_agg;
+                  taken = true;
+                }
+              }
+              if (!taken) {
+                const uint32_t o = ord_f32(P.hs[r]);
+                const unsigned long long k = ((unsigned long long)o << 32) | (unsigned)v;
+                kall = k < kall ? k : kall;
+                if (P.hmx[r] <= 0.0f) kneg = k < kneg ? k : kneg;
               }
             }
-            if (!taken) {
-              const unsigned long long key =
-                  ((unsigned long long)ord_f32(P.hs[r]) << 32) | (unsigned)v;
-              kall = key < kall ? key : kall;
-              if (P.hmx[r] <= 0.0f) kneg = key < kneg ? key : kneg;
-            }
           }
-        }
-        kall = wave_min_u64(kall);
-        kneg = wave_min_u64(kneg);
-        if (dlog || !w.low_error) n_agg = wave_sum_i32(n_agg);
-        int gsel, fav;
-        if (kneg != ~0ull) {
-          gsel = (int)(kneg & 0xffffffffu);
-          fav = 1;
-        } else if (kall != ~0ull) {
-          gsel = (int)(kall & 0xffffffffu);
-          fav = (uint32_t)(kall >> 32) <= 0x80000000u ? 1 : 0;   // sum <= 0 -> 1
-        } else {
-          gsel = -1;
-          fav = 0;
-        }
-        if (gsel < 0) {
+          int gsel, fav, val;
+          if (kLearn && (learned || (record && D <= lrn.rec_steps))) {
+            // the proposer's candidates: the first n_cand VNs in Alg. 1's order
+            // key: all-<=0 class first, then L_sum, then index
+            unsigned long long mine = ~0ull;   // lane l: candidate l % 16
+            uint32_t used = 0u;                // bit r: VN lane + 64 r already taken
+            int n_found = 0;
+            for (int i = 0; i < lrn.n_cand; ++i) {
+              unsigned long long lm = ~0ull;
+#pragma unroll
+              for (int r = 0; r < VPL; ++r) {
+                const int v = lane + kWave * r;
+                if (v < n_act && P.st(r) < 0 && P.vdg(r) >= 3 && !((used >> r) & 1u)) {
+                  const unsigned long long k = ((P.hmx[r] <= 0.0f ? 0ull : 1ull) << 63) |
+                                               ((unsigned long long)ord_f32(P.hs[r]) << 31) |
+                                               (unsigned)v;
+                  lm = k < lm ? k : lm;
+                }
+              }
+              const unsigned long long km = wave_min_u64(lm);
+              if (km == ~0ull) break;
+              const int kv = (int)(km & 0x7fffffffu);
+              if ((kv & (kWave - 1)) == lane) used |= 1u << (kv >> 6);
+              if ((lane & 15) == i) mine = km;
+              ++n_found;
+            }
+            if (n_found == 0) {
+              end = END_NO_CANDIDATE;
+              break;
+            }
+            const bool valid = mine != ~0ull;
+            const int cv = valid ? (int)(mine & 0x7fffffffu) : 0;
+            const uint32_t co = (uint32_t)(mine >> 31);
+            const int cfav = (mine >> 63) == 0ull ? 1 : (co <= 0x80000000u ? 1 : 0);
+            // features: posteriors of iterations it - 15 .. it (priors before the
+            // first), squashed, and the degree
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            const int q = lane >> 4;
+            float f[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const float pv = ring[((it + 4 * q + j) & 15) * lrn.ring_stride + cv];
+              f[j] = pv / (8.0f + fabsf(pv));
+            }
+            const float fd = (float)vdeg[cv] * 0.125f;
+            if (record) {
+              const long long base = ((long long)shot * lrn.rec_steps + (D - 1)) * 16 + (lane & 15);
+              if (valid) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) lrn.rec_x[base * 17 + 4 * q + j] = f[j];
+                if (q == 0) {
+                  lrn.rec_x[base * 17 + 16] = fd;
+                  lrn.rec_col[base] = sel[cv];
+                  lrn.rec_fav[base] = cfav;
+                }
+              }
+              // the plain main path continues with Alg. 1's choice
+              const int c0 = __builtin_amdgcn_readlane(cv, 0);
+              gsel = c0;
+              fav = __builtin_amdgcn_readlane(cfav, 0);
+              val = fav;
+            } else {
+              float z = mlp_score_tile(lrn.model, f, fd);
+              z = valid ? z : -kInfF;
+              const unsigned long long zk = ((unsigned long long)(~ord_f32(z)) << 32) | (unsigned)(lane & 15);
+              const int cbest = (int)(wave_min_u64(zk) & 0xffffffffu);
+              const float zb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z), cbest));
+              // the candidate most likely in error, decimated to the network's
+              // decision; a guess point when that decision is not confident
+              gsel = __builtin_amdgcn_readlane(cv, cbest);
+              fav = zb >= 0.0f ? 1 : 0;
+              val = fav;
+              if (lrn.tree) {
+                // guesses at depths 1..guesses as in Fig. 2 (path bit D, MSB first)
+                if (pid > 0 && D <= lrn.guesses && ((pid >> (lrn.guesses - D)) & 1)) val = 1 - fav;
+              } else if (fabsf(zb) < lrn.tau && guess_used < lrn.guesses) {
+                const int bit = (pid >> guess_used) & 1;
+                ++guess_used;
+                if (bit) {
+                  val = 1 - fav;
+                  deviated = true;
+                }
+              }
+            }
+          } else {
+            kall = wave_min_u64(kall);
+            kneg = wave_min_u64(kneg);
+            if (kneg != ~0ull) {
+              gsel = (int)(kneg & 0xffffffffu);
+              fav = 1;
+            } else if (kall != ~0ull) {
+              gsel = (int)(kall & 0xffffffffu);
+              fav = (uint32_t)(kall >> 32) <= 0x80000000u ? 1 : 0;   // sum <= 0 -> 1
+            } else {
+              gsel = -1;
+              fav = 0;
+            }
+            val = gsel < 0 ? 0 : path_value(w, pid, split, D, fav);
+          }
+          if (dlog || !w.low_error) n_agg = wave_sum_i32(n_agg);
+          if (gsel < 0) {
+            if (dlog && lane == 0 && D - 1 < tr.log_cap) {
+              dlog[(D - 1) * 3 + 0] = -1;
+              dlog[(D - 1) * 3 + 1] = -1;
+              dlog[(D - 1) * 3 + 2] = n_agg;
+            }
+            end = END_NO_CANDIDATE;
+            break;
+          }
+#pragma unroll
+          for (int r = 0; r < VPL; ++r)
+            if (lane + kWave * r == gsel) set_status(P, r, gsel, val);
           if (dlog && lane == 0 && D - 1 < tr.log_cap) {
-            dlog[(D - 1) * 3 + 0] = -1;
-            dlog[(D - 1) * 3 + 1] = -1;
+            dlog[(D - 1) * 3 + 0] = gsel;
+            dlog[(D - 1) * 3 + 1] = val;
             dlog[(D - 1) * 3 + 2] = n_agg;
           }
-          end = END_NO_CANDIDATE;
-          break;
-        }
-        const int val = path_value(w, pid, split, D, fav);
-#pragma unroll
-        for (int r = 0; r < VPL; ++r)
-          if (lane + kWave * r == gsel) set_status(P, r, gsel, val);
-        if (dlog && lane == 0 && D - 1 < tr.log_cap) {
-          dlog[(D - 1) * 3 + 0] = gsel;
-          dlog[(D - 1) * 3 + 1] = val;
-          dlog[(D - 1) * 3 + 2] = n_agg;
-        }
-        wave_sync();
-        if (!peel(P)) {
-          end = END_CONTRADICTION;
-          break;
-        }
-      }
-      if (end == 0) end = END_EXHAUSTED;   // dmax < 1
-      if (dlog) {
-        // entries past the last logged step
-        const int first_free =
-            (end == END_CONVERGED || end == END_EXHAUSTED) ? steps - 1 : steps;
-        for (int i = lane; i < tr.log_cap; i += kWave) {
-          if (i >= first_free) {
-            dlog[i * 3 + 0] = -1;
-            dlog[i * 3 + 1] = -1;
-            dlog[i * 3 + 2] = -1;
+          wave_sync();
+          if (!peel(P)) {
+            end = END_CONTRADICTION;
+            break;
           }
         }
-      }
-      if (tr.step_lsum) {
-        for (int i = steps; i < tr.log_cap; ++i) {
-          float* sl = tr.step_lsum + (((long long)shot * w.n_paths + pid) * tr.log_cap + i) * n_act;
-          for (int v = lane; v < n_act; v += kWave) sl[v] = __builtin_nanf("");
-        }
-      }
-      if (tr.ends && lane == 0) {
-        tr.ends[((long long)shot * w.n_paths + pid) * 2 + 0] = end;
-        tr.ends[((long long)shot * w.n_paths + pid) * 2 + 1] = steps;
-      }
-      // path answer: bits over the sub-graph
-      uint32_t* mybits = pbits + pid * L.pbits_words;
-#pragma unroll
-      for (int r = 0; r < VPL; ++r) {
-        const int v = lane + kWave * r;
-        bool one = false;
-        if (v < n_act) one = P.st(r) >= 0 ? P.st(r) == 1 : P.post[v] <= 0.0f;
-        const unsigned long long bal = __ballot(one);
-        if (lane == 0 && kWave * r < n_act) {
-          mybits[2 * r] = (uint32_t)bal;
-          if (2 * r + 1 < L.pbits_words) mybits[2 * r + 1] = (uint32_t)(bal >> 32);
-        }
-      }
-      wave_sync();
-      double pm = __builtin_inf();
-      if (end == END_CONVERGED) {
-        // Eq. 5 in ascending window-column order
-        for (int i = lane; i < L.obits_words; i += kWave) wbits[i] = 0u;
-        wave_sync();
-        for (int v = lane; v < n_act; v += kWave) {
-          if ((mybits[v >> 5] >> (v & 31)) & 1u) {
-            const int c = sel[v];
-            atomicOr(&wbits[c >> 5], 1u << (c & 31));
-          }
-        }
-        wave_sync();
-        if (lane == 0) {
-          pm = 0.0;
-          for (int wd = 0; wd < L.obits_words; ++wd) {
-            uint32_t x = wbits[wd];
-            while (x) {
-              const int bt = __builtin_ctz(x);
-              x &= x - 1u;
-              pm += w.llr64[wd * 32 + bt];
+        if (end == 0) end = END_EXHAUSTED;   // dmax < 1
+        if (dlog) {
+          // entries past the last logged step
+          const int first_free =
+              (end == END_CONVERGED || end == END_EXHAUSTED) ? steps - 1 : steps;
+          for (int i = lane; i < tr.log_cap; i += kWave) {
+            if (i >= first_free) {
+              dlog[i * 3 + 0] = -1;
+              dlog[i * 3 + 1] = -1;
+              dlog[i * 3 + 2] = -1;
             }
           }
         }
+        if (tr.step_lsum && !learned) {
+          for (int i = steps; i < tr.log_cap; ++i) {
+            float* sl = tr.step_lsum + (((long long)shot * w.n_paths + pid) * tr.log_cap + i) * n_act;
+            for (int v = lane; v < n_act; v += kWave) sl[v] = __builtin_nanf("");
+          }
+        }
+        if (tr.ends && lane == 0 && !learned) {
+          tr.ends[((long long)shot * w.n_paths + pid) * 2 + 0] = end;
+          tr.ends[((long long)shot * w.n_paths + pid) * 2 + 1] = steps;
+        }
+        // path answer: bits over the sub-graph
+        uint32_t* mybits = pbits + pid * L.pbits_words;
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+          const int v = lane + kWave * r;
+          bool one = false;
+          if (v < n_act) one = P.st(r) >= 0 ? P.st(r) == 1 : P.post[v] <= 0.0f;
+          const unsigned long long bal = __ballot(one);
+          if (lane == 0 && kWave * r < n_act) {
+            mybits[2 * r] = (uint32_t)bal;
+            if (2 * r + 1 < L.pbits_words) mybits[2 * r + 1] = (uint32_t)(bal >> 32);
+          }
+        }
+        wave_sync();
+        double pm = __builtin_inf();
+        if (end == END_CONVERGED) {
+          // Eq. 5 in ascending window-column order
+          for (int i = lane; i < L.obits_words; i += kWave) wbits[i] = 0u;
+          wave_sync();
+          for (int v = lane; v < n_act; v += kWave) {
+            if ((mybits[v >> 5] >> (v & 31)) & 1u) {
+              const int c = sel[v];
+              atomicOr(&wbits[c >> 5], 1u << (c & 31));
+            }
+          }
+          wave_sync();
+          if (lane == 0) {
+            pm = 0.0;
+            for (int wd = 0; wd < L.obits_words; ++wd) {
+              uint32_t x = wbits[wd];
+              while (x) {
+                const int bt = __builtin_ctz(x);
+                x &= x - 1u;
+                pm += w.llr64[wd * 32 + bt];
+              }
+            }
+          }
+        }
+        if (lane == 0) {
+          ppm[pid] = pm;
+          pend[pid] = end;
+        }
+        wave_sync();
       }
-      if (lane == 0) {
-        ppm[pid] = pm;
-        pend[pid] = end;
+      __syncthreads();
+      // ---------------------------------------------------------- best path
+      if (tid == 0) {
+        int best = -1;
+        double bpm = __builtin_inf();
+        int n_contra = 0, n_exh = 0;
+        for (int p = 0; p < n_run; ++p) {
+          if (pend[p] == END_CONTRADICTION) ++n_contra;
+          if (pend[p] == END_EXHAUSTED) ++n_exh;
+          if (pend[p] == END_CONVERGED && ppm[p] < bpm) {
+            bpm = ppm[p];
+            best = p;
+          }
+        }
+        int fl = 0;
+        if (best >= 0) {
+          fl = 1;
+        } else {
+          if (n_contra == n_run) fl |= 2;
+          if (n_exh > 0) fl |= 4;
+        }
+        if (misc[5]) fl |= 16;
+        if (fallback) fl |= 8;
+        misc[2] = best >= 0 ? best : 0;
+        // a learned answer stands if its path metric is at most pm_fallback
+        misc[6] = best >= 0 && !(mode == 1 && run == 0 && bpm > (double)lrn.pm_fallback);
+        misc[0] = 0;   // path counter for a fallback run
+        pm_out[shot] = bpm;
+        flags_out[shot] = fl;
       }
-      wave_sync();
+      __syncthreads();
     }
   }
   my_edges = wave_sum_i64(my_edges);
   if (lane == 0 && my_edges) atomicAdd(eacc, (unsigned long long)my_edges);
   __syncthreads();
+  if (tid == 0 && tr.edge_iters) tr.edge_iters[shot] = (long long)*eacc;
 
-  // ---------------------------------------------------------- best path, output
-  if (tid == 0) {
-    int best = -1;
-    double bpm = __builtin_inf();
-    int n_contra = 0, n_exh = 0;
-    for (int p = 0; p < w.n_paths; ++p) {
-      if (pend[p] == END_CONTRADICTION) ++n_contra;
-      if (pend[p] == END_EXHAUSTED) ++n_exh;
-      if (pend[p] == END_CONVERGED && ppm[p] < bpm) {
-        bpm = ppm[p];
-        best = p;
-      }
-    }
-    int fl = 0;
-    if (best >= 0) {
-      fl = 1;
-    } else {
-      if (n_contra == w.n_paths) fl |= 2;
-      if (n_exh > 0) fl |= 4;
-    }
-    if (misc[5]) fl |= 16;
-    misc[2] = best >= 0 ? best : 0;
-    pm_out[shot] = bpm;
-    flags_out[shot] = fl;
-    if (tr.edge_iters) tr.edge_iters[shot] = (long long)*eacc;
-  }
-  __syncthreads();
+  // ---------------------------------------------------------- output
   const uint32_t* ansbits = pbits + misc[2] * L.pbits_words;
   for (int v = tid; v < n_act; v += blockDim.x) {
     if ((ansbits[v >> 5] >> (v & 31)) & 1u) {
@@ -1266,7 +1390,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
 // table; item i belongs to the job whose first item is the largest <= i. Jobs
 // may use windows of different codes (sizes): each job carries its own LDS
 // layout within the launch's allocation.
-template <int VPL>
+template <int VPL, bool kLearn>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) void gdg_decode_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int item = blockIdx.x; item < J.total; item += gridDim.x) {
@@ -1275,8 +1399,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
     for (int t = 1; t < kMaxJobs; ++t)
       if (t < J.n_jobs && item >= J.job[t].item0) jb = J.job[t];
-    decode_shot<VPL>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat, jb.pm,
-                          jb.flags, tr, smem);
+    decode_shot<VPL, kLearn>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat, jb.pm,
+                     jb.flags, tr, J.learn, smem);
     __syncthreads();
   }
 }
@@ -1327,9 +1451,15 @@ __global__ __launch_bounds__(256) void gdg_bp_kernel(gdg_win_dev w, int n_shots,
 // decided 1 that touch the row (Eq. 7-8 update). Rows are disjoint per thread,
 // so no atomics. Observables likewise, one thread per (shot, observable).
 
+// One thread per (shot, affected DEM row or observable). Shot s's row r lives
+// at det[s * det_stride + r] and observable o at obs[s * obs_stride + o]; with
+// per-shot offsets (det_off non-null) at det[det_off[s] + r - row0] and
+// obs[obs_off[s] + o] instead.
 __global__ void gdg_commit_kernel(gdg_commit_dev cm, int n_shots, const uint8_t* __restrict__ ehat,
                                   uint8_t* __restrict__ det, long long det_stride,
-                                  uint8_t* __restrict__ obs, long long obs_stride) {
+                                  uint8_t* __restrict__ obs, long long obs_stride,
+                                  const long long* __restrict__ det_off,
+                                  const long long* __restrict__ obs_off, int row0) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long per = (long long)cm.n_rows + cm.n_obs;
   const long long total = per * n_shots;
@@ -1340,13 +1470,30 @@ __global__ void gdg_commit_kernel(gdg_commit_dev cm, int n_shots, const uint8_t*
   if (r < cm.n_rows) {
     int x = 0;
     for (int t = cm.row_ptr[r]; t < cm.row_ptr[r + 1]; ++t) x ^= e[cm.row_col[t]];
-    if (x) det[(long long)shot * det_stride + cm.row_global[r]] ^= 1;
+    if (x) {
+      const long long at = det_off ? det_off[shot] + (cm.row_global[r] - row0)
+                                   : (long long)shot * det_stride + cm.row_global[r];
+      det[at] ^= 1;
+    }
   } else {
     const int o = r - cm.n_rows;
     int x = 0;
     for (int t = cm.obs_ptr[o]; t < cm.obs_ptr[o + 1]; ++t) x ^= e[cm.obs_col[t]];
-    if (x) obs[(long long)shot * obs_stride + o] ^= 1;
+    if (x) obs[(obs_off ? obs_off[shot] : (long long)shot * obs_stride) + o] ^= 1;
   }
+}
+
+// Row copies at per-row offsets: dst[dst_off[i] + j] = src[src_off[i] + j], j < m
+// (dst_off null: dst[i * m + j]).
+__global__ void gdg_copy_rows_kernel(int n, int m, const uint8_t* __restrict__ src,
+                                     const long long* __restrict__ src_off,
+                                     uint8_t* __restrict__ dst,
+                                     const long long* __restrict__ dst_off) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const long long s = src_off[i];
+  const long long d = dst_off ? dst_off[i] : (long long)i * m;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) dst[d + j] = src[s + j];
 }
 
 // ------------------------------------------------------------------ sampler
@@ -1414,6 +1561,28 @@ __global__ __launch_bounds__(256) void gdg_sample_kernel(gdg_dem_dev_k d, int n_
     obs[(long long)s * d.n_obs + o] = (uint8_t)((obits[o >> 5] >> (o & 31)) & 1u);
 }
 
+// The error vectors themselves: err[s][c] = 1 iff column c fired in shot s
+// (the same Philox words as gdg_sample_kernel).
+__global__ __launch_bounds__(256) void gdg_sample_err_kernel(gdg_dem_dev_k d, int n_shots,
+                                                             uint64_t seed, uint32_t stream,
+                                                             uint64_t shot0,
+                                                             uint8_t* __restrict__ err) {
+  const int s = blockIdx.x;
+  if (s >= n_shots) return;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const uint32_t sh = (uint32_t)(shot0 + (uint64_t)s);
+  const int ngroups = (d.n_cols + 3) >> 2;
+  for (int gq = threadIdx.x; gq < ngroups; gq += blockDim.x) {
+    uint32_t c[4] = {(uint32_t)gq, sh, stream, 0xC0DEu};
+    philox(c, k0, k1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int col = gq * 4 + t;
+      if (col < d.n_cols) err[(long long)s * d.n_cols + col] = c[t] < d.thr[col] ? 1 : 0;
+    }
+  }
+}
+
 __global__ void gdg_evaluate_kernel(int n_shots, int n_rows, int n_obs,
                                     const uint8_t* __restrict__ det, const uint8_t* __restrict__ obs,
                                     uint8_t* __restrict__ fail) {
@@ -1432,15 +1601,25 @@ __global__ void gdg_evaluate_kernel(int n_shots, int n_rows, int n_obs,
 hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
                            const gdg_trace_dev& tr, hipStream_t st) {
   dim3 g(grid), block(waves * kWave);
-  switch (bucket) {
+  const bool learn = J.learn.mode != 0;
+  switch (bucket * 2 + (learn ? 1 : 0)) {
     case 0:
-      hipLaunchKernelGGL((gdg_decode_kernel<6>), g, block, lds, st, J, tr);
+      hipLaunchKernelGGL((gdg_decode_kernel<6, false>), g, block, lds, st, J, tr);
       break;
     case 1:
-      hipLaunchKernelGGL((gdg_decode_kernel<8>), g, block, lds, st, J, tr);
+      hipLaunchKernelGGL((gdg_decode_kernel<6, true>), g, block, lds, st, J, tr);
       break;
     case 2:
-      hipLaunchKernelGGL((gdg_decode_kernel<16>), g, block, lds, st, J, tr);
+      hipLaunchKernelGGL((gdg_decode_kernel<8, false>), g, block, lds, st, J, tr);
+      break;
+    case 3:
+      hipLaunchKernelGGL((gdg_decode_kernel<8, true>), g, block, lds, st, J, tr);
+      break;
+    case 4:
+      hipLaunchKernelGGL((gdg_decode_kernel<16, false>), g, block, lds, st, J, tr);
+      break;
+    case 5:
+      hipLaunchKernelGGL((gdg_decode_kernel<16, true>), g, block, lds, st, J, tr);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1457,10 +1636,16 @@ int gdg_kernel_bucket(int m, int n_act) {
 }
 
 hipError_t gdg_decode_set_lds_limit(int bucket, int bytes) {
-  const void* f = bucket == 0   ? (const void*)gdg_decode_kernel<6>
-                  : bucket == 1 ? (const void*)gdg_decode_kernel<8>
-                                : (const void*)gdg_decode_kernel<16>;
-  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  static const void* const fs[6] = {
+      (const void*)gdg_decode_kernel<6, false>,  (const void*)gdg_decode_kernel<6, true>,
+      (const void*)gdg_decode_kernel<8, false>,  (const void*)gdg_decode_kernel<8, true>,
+      (const void*)gdg_decode_kernel<16, false>, (const void*)gdg_decode_kernel<16, true>};
+  for (int l = 0; l < 2; ++l) {
+    const hipError_t e =
+        hipFuncSetAttribute(fs[bucket * 2 + l], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, long long stride,
@@ -1479,13 +1664,21 @@ hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, 
 
 hipError_t gdg_launch_commit(const gdg_commit_dev& cm, int n_shots, const uint8_t* ehat,
                              uint8_t* det, long long det_stride, uint8_t* obs,
-                             long long obs_stride, hipStream_t st) {
+                             long long obs_stride, const long long* det_off,
+                             const long long* obs_off, int row0, hipStream_t st) {
   const long long total = ((long long)cm.n_rows + cm.n_obs) * n_shots;
   if (total == 0) return hipSuccess;
   const int bs = 256;
   const long long nb = (total + bs - 1) / bs;
   hipLaunchKernelGGL(gdg_commit_kernel, dim3((unsigned)nb), dim3(bs), 0, st, cm, n_shots, ehat,
-                     det, det_stride, obs, obs_stride);
+                     det, det_stride, obs, obs_stride, det_off, obs_off, row0);
+  return hipGetLastError();
+}
+
+hipError_t gdg_launch_copy_rows(int n, int m, const uint8_t* src, const long long* src_off,
+                                uint8_t* dst, const long long* dst_off, hipStream_t st) {
+  hipLaunchKernelGGL(gdg_copy_rows_kernel, dim3((unsigned)n), dim3(m >= 256 ? 256 : 64), 0, st, n,
+                     m, src, src_off, dst, dst_off);
   return hipGetLastError();
 }
 
@@ -1494,6 +1687,14 @@ hipError_t gdg_launch_sample(const gdg_dem_dev_k& d, int n_shots, uint64_t seed,
   const size_t lds = 4 * (size_t)(((d.n_rows + 31) >> 5) + ((d.n_obs + 31) >> 5));
   hipLaunchKernelGGL(gdg_sample_kernel, dim3(n_shots), dim3(256), lds, st, d, n_shots, seed,
                      stream, shot0, det, obs);
+  return hipGetLastError();
+}
+
+hipError_t gdg_launch_sample_errors(const gdg_dem_dev_k& d, int n_shots, uint64_t seed,
+                                    uint32_t stream, uint64_t shot0, uint8_t* err,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(gdg_sample_err_kernel, dim3(n_shots), dim3(256), 0, st, d, n_shots, seed,
+                     stream, shot0, err);
   return hipGetLastError();
 }
 

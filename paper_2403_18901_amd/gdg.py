@@ -23,8 +23,14 @@ GDG_FLAG_CAPACITY = 16
 
 EXPORTED = ["gdg_build_window", "gdg_window_free", "gdg_window_get_info", "gdg_window_columns",
             "gdg_workspace_bytes", "gdg_decode_batch", "gdg_decode_jobs", "gdg_jobs_lds_bytes",
-            "gdg_commit", "gdg_bp", "gdg_dem_upload", "gdg_dem_free", "gdg_sample", "gdg_evaluate",
-            "gdg_last_error"]
+            "gdg_commit", "gdg_commit_indexed", "gdg_copy_rows", "gdg_bp", "gdg_dem_upload",
+            "gdg_dem_free", "gdg_sample", "gdg_sample_errors", "gdg_evaluate",
+            "gdg_mlp_forward", "gdg_mlp_grad_work_bytes", "gdg_mlp_grad", "gdg_mlp_adam",
+            "gdg_model_create", "gdg_model_free", "gdg_mlp_infer", "gdg_learned_work_bytes",
+            "gdg_decode_learned", "gdg_last_error"]
+
+MLP_IN, MLP_H = 17, 64
+MLP_PARAMS = 5377
 
 
 class Dem(C.Structure):
@@ -63,6 +69,13 @@ class LaunchCfg(C.Structure):
     _fields_ = [("waves", C.c_int32), ("workgroups", C.c_int32)]
 
 
+class LearnCfg(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("n_cand", C.c_int32), ("guesses", C.c_int32),
+                ("tau", C.c_float), ("rec_steps", C.c_int32), ("d_rec_x", C.c_void_p),
+                ("d_rec_col", C.c_void_p), ("d_rec_fav", C.c_void_p),
+                ("d_edge_iters", C.c_void_p), ("pm_fallback", C.c_float), ("tree", C.c_int32)]
+
+
 MAX_JOBS = 8
 
 
@@ -94,11 +107,25 @@ def lib():
         L.gdg_decode_jobs.argtypes = [P, i32, P, P]
         L.gdg_jobs_lds_bytes.argtypes = [P, i32, i32]
         L.gdg_commit.argtypes = [P, i32, P, P, i64, P, i64, P]
+        L.gdg_commit_indexed.argtypes = [P, i32, P, P, P, P, P, P]
+        L.gdg_copy_rows.argtypes = [i32, i32, P, P, P, P, P]
         L.gdg_bp.argtypes = [P, i32, P, i64, i32, P, P, P]
         L.gdg_dem_upload.argtypes = [P, P]
         L.gdg_dem_free.argtypes = [P]
         L.gdg_sample.argtypes = [P, i32, u64, u32, u64, P, P, P]
         L.gdg_evaluate.argtypes = [i32, i32, i32, P, P, P, P]
+        L.gdg_sample_errors.argtypes = [P, i32, u64, u32, u64, P, P]
+        L.gdg_mlp_forward.argtypes = [i32, P, P, P, P]
+        L.gdg_mlp_grad_work_bytes.argtypes = [i32]
+        L.gdg_mlp_grad_work_bytes.restype = C.c_size_t
+        L.gdg_mlp_grad.argtypes = [i32, P, P, P, P, P, P, C.c_size_t, P]
+        L.gdg_mlp_adam.argtypes = [i32, C.c_float, C.c_float, C.c_float, C.c_float, P, P, P, P, P]
+        L.gdg_model_create.argtypes = [P, P]
+        L.gdg_model_free.argtypes = [P]
+        L.gdg_mlp_infer.argtypes = [P, i32, P, P, P]
+        L.gdg_learned_work_bytes.argtypes = [P]
+        L.gdg_learned_work_bytes.restype = C.c_size_t
+        L.gdg_decode_learned.argtypes = [P, P, P, i32, P, i64, P, P, P, P, C.c_size_t, P]
         L.gdg_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -198,6 +225,14 @@ class Window:
         _check(lib().gdg_commit(self.h, ns, _ptr(ehat), _ptr(det), det.shape[1], _ptr(obs),
                                 obs.shape[1] if obs.dim() == 2 else 0, _stream()))
 
+    def commit_indexed(self, ehat: torch.Tensor, det: torch.Tensor, det_off: torch.Tensor,
+                       obs: torch.Tensor, obs_off: torch.Tensor):
+        """Commit for shots whose window rows start at det_off[i] (int64 element
+        offsets into det) and whose observables start at obs_off[i]."""
+        ns = ehat.shape[0]
+        _check(lib().gdg_commit_indexed(self.h, ns, _ptr(ehat), _ptr(det), _ptr(det_off),
+                                        _ptr(obs), _ptr(obs_off), _stream()))
+
     def bp(self, syn: torch.Tensor, n_iters: int, syn_offset: int = 0):
         ns = syn.shape[0]
         post = torch.empty((ns, n_iters, self.n), dtype=torch.float32, device=syn.device)
@@ -259,6 +294,16 @@ class DeviceDem:
         return det, obs
 
 
+def copy_rows(src: torch.Tensor, src_off: torch.Tensor, m: int, dst: torch.Tensor,
+              dst_off: torch.Tensor = None):
+    """dst[dst_off[i] + j] = src[src_off[i] + j] for j < m (flat uint8 element
+    offsets, int64 on the device); dst_off None: row i of a [n, m] dst."""
+    n = src_off.shape[0]
+    _check(lib().gdg_copy_rows(n, m, _ptr(src), _ptr(src_off), _ptr(dst), _ptr(dst_off),
+                               _stream()))
+    return dst
+
+
 def evaluate(det: torch.Tensor, obs: torch.Tensor, out=None) -> torch.Tensor:
     ns = det.shape[0]
     fail = out if out is not None else torch.empty(ns, dtype=torch.uint8, device=det.device)
@@ -297,3 +342,102 @@ class SlidingWindowDecoder:
         if trace:
             return fail, wflags, traces
         return fail, wflags
+
+
+# ------------------------------------------------------------------ learned proposer
+
+def mlp_forward(params: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """FP32 logits of the proposer network for features x [n, 17]."""
+    n = x.shape[0]
+    z = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(lib().gdg_mlp_forward(n, _ptr(params), _ptr(x), _ptr(z), _stream()))
+    return z
+
+
+class MlpTrainer:
+    """Buffers for gradient steps of the proposer network on the device."""
+
+    def __init__(self, params: torch.Tensor, max_batch: int):
+        self.params = params
+        self.grad = torch.zeros_like(params)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        nb = lib().gdg_mlp_grad_work_bytes(max_batch)
+        self.work = torch.empty(max(nb, 4), dtype=torch.uint8, device=params.device)
+        self.max_batch = max_batch
+        self.t = 0
+
+    def gradient(self, x: torch.Tensor, y: torch.Tensor):
+        n = x.shape[0]
+        if n > self.max_batch:
+            raise ValueError("batch larger than the trainer's workspace")
+        _check(lib().gdg_mlp_grad(n, _ptr(self.params), _ptr(x), _ptr(y), _ptr(self.grad),
+                                  _ptr(self.loss), _ptr(self.work), self.work.numel(), _stream()))
+        return self.grad, self.loss
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.t += 1
+        _check(lib().gdg_mlp_adam(self.t, lr, b1, b2, eps, _ptr(self.params), _ptr(self.grad),
+                                  _ptr(self.m), _ptr(self.v), _stream()))
+
+    def step(self, x, y, lr=1e-3):
+        self.gradient(x, y)
+        self.adam(lr)
+        return self.loss
+
+
+class Model:
+    """Device inference copy (BF16 weights) of FP32 proposer parameters."""
+
+    def __init__(self, params):
+        p = np.ascontiguousarray(
+            params.detach().float().cpu().numpy() if isinstance(params, torch.Tensor) else params,
+            np.float32)
+        if p.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters")
+        h = C.c_void_p()
+        _check(lib().gdg_model_create(p.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.gdg_model_free(self.h)
+            self.h = None
+
+    def infer(self, x: torch.Tensor) -> torch.Tensor:
+        n = x.shape[0]
+        z = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(lib().gdg_mlp_infer(self.h, n, _ptr(x), _ptr(z), _stream()))
+        return z
+
+
+def sample_errors(ddem: "DeviceDem", n_shots: int, seed: int, stream: int = 0, shot0: int = 0,
+                  device="cuda") -> torch.Tensor:
+    err = torch.empty((n_shots, ddem.n_cols), dtype=torch.uint8, device=device)
+    _check(lib().gdg_sample_errors(ddem.h, n_shots, seed, stream, shot0, _ptr(err), _stream()))
+    return err
+
+
+def learned_work(win: "Window") -> torch.Tensor:
+    nb = lib().gdg_learned_work_bytes(win.h)
+    return torch.empty(nb, dtype=torch.uint8, device="cuda")
+
+
+def decode_learned(win: "Window", syn: torch.Tensor, syn_offset: int, cfg: LearnCfg, model=None,
+                   work=None, out=None):
+    """Mode 1 or 2 decode of one window (see gdg_decode_learned)."""
+    ns = syn.shape[0]
+    dev = syn.device
+    if out is None:
+        out = (torch.empty((ns, win.n), dtype=torch.uint8, device=dev),
+               torch.empty(ns, dtype=torch.float64, device=dev),
+               torch.empty(ns, dtype=torch.int32, device=dev))
+    if work is None:
+        work = learned_work(win)
+    ehat, pm, fl = out
+    _check(lib().gdg_decode_learned(win.h, model.h if model is not None else None, C.byref(cfg),
+                                    ns, _ptr(syn, syn_offset), syn.shape[1], _ptr(ehat), _ptr(pm),
+                                    _ptr(fl), _ptr(work), work.numel(), _stream()))
+    return out
+

@@ -1,0 +1,229 @@
+"""The learned proposer on the GPU: FP32 training kernels against the FP64
+reference (forward, gradient, Adam), BF16 matrix-core inference against the
+bfloat16 reference arithmetic, record mode against plain GDG, and the learned
+decode's invariants (syndrome consistency, plain fallback)."""
+import numpy as np
+import pytest
+
+from gdg_inputs.bb import get_code
+from gdg_inputs.dem import circuit_dem
+from gdg_inputs.philox import sample_errors, syndromes
+from oracle import mlp_oracle as M
+from oracle import oracle as O
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+
+def _G():
+    import paper_2403_18901_amd.gdg as G
+    return G
+
+
+def _data(rng, n):
+    x = np.concatenate([rng.uniform(-1, 1, (n, 16)), rng.integers(1, 6, (n, 1)) / 8.0], axis=1)
+    y = rng.integers(0, 2, n).astype(np.float64)
+    return x.astype(np.float32), y.astype(np.float32)
+
+
+def _params(rng, scale=0.3):
+    return rng.normal(0, scale, M.N_PARAMS).astype(np.float32)
+
+
+@gpu
+@pytest.mark.parametrize("n", [1, 64, 300])
+def test_mlp_gradient_matches_oracle(n):
+    G = _G()
+    rng = np.random.default_rng(n)
+    p, (x, y) = _params(rng), _data(rng, n)
+    tr = G.MlpTrainer(torch.from_numpy(p).cuda(), 512)
+    g, loss = tr.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+    L, go = M.loss_grad(p, x, y)
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(float(loss.item()) - L) <= 1e-5 * max(1.0, L)
+    assert np.max(np.abs(g - go)) <= 2e-5 * np.max(np.abs(go)) + 1e-8
+
+
+@gpu
+def test_mlp_forward_and_adam_match_oracle():
+    G = _G()
+    rng = np.random.default_rng(7)
+    p, (x, y) = _params(rng), _data(rng, 200)
+    z = G.mlp_forward(torch.from_numpy(p).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+    zo = M.forward(p, x)
+    assert np.max(np.abs(z - zo)) <= 1e-5 * (1 + np.max(np.abs(zo)))
+    # Adam: the kernel's update against the reference update from the same
+    # parameters, gradient and moments
+    pt = torch.from_numpy(p).cuda()
+    tr = G.MlpTrainer(pt, 256)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    m, v = np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS)
+    for t in range(1, 4):
+        p0 = pt.cpu().numpy().astype(np.float64)
+        g, _ = tr.gradient(xt, yt)
+        g = g.cpu().numpy().astype(np.float64)
+        tr.adam(lr=1e-2)
+        pr, m, v = M.adam(p0, g, m, v, t, lr=1e-2)
+        assert np.max(np.abs(pt.cpu().numpy() - pr)) <= 1e-6
+        assert np.max(np.abs(tr.m.cpu().numpy() - m)) <= 1e-6 * (1 + np.max(np.abs(m)))
+
+
+@gpu
+@pytest.mark.parametrize("n", [16, 50])
+def test_bf16_inference_matches_reference(n):
+    G = _G()
+    rng = np.random.default_rng(11 + n)
+    p, (x, _) = _params(rng, 0.25), _data(rng, n)
+    z = G.Model(p).infer(torch.from_numpy(x).cuda()).cpu().numpy()
+    zr = M.forward_bf16(p, x)
+    assert np.max(np.abs(z - zr) / (1 + np.abs(zr))) <= 5e-3
+    assert np.mean(np.abs(z - zr)) <= 1e-3 * (1 + np.mean(np.abs(zr)))
+
+
+def _c2_window(G, low_error):
+    p = 0.003
+    dem = circuit_dem(get_code("144"), 12, p)
+    prm = G.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=low_error)
+    return dem, prm, G.Window(dem, 0, 3, prm)
+
+
+@gpu
+def test_record_mode_is_plain_gdg_and_logs_alg1_candidates():
+    G = _G()
+    dem, prm, win = _c2_window(G, 0)
+    ddem = G.DeviceDem(dem)
+    det, _ = ddem.sample(300, seed=21)
+    e0, pm0, f0, tr = win.decode(det, syn_offset=win.row0, trace=True, log_cap=8)
+    n, R = 300, 4
+    rx = torch.zeros((n, R, 16, 17), dtype=torch.float32, device="cuda")
+    rc = torch.full((n, R, 16), -1, dtype=torch.int32, device="cuda")
+    rf = torch.zeros((n, R, 16), dtype=torch.int32, device="cuda")
+    cfg = G.LearnCfg(2, 16, 0, 0.0, R, rx.data_ptr(), rc.data_ptr(), rf.data_ptr(), None,
+                     float("inf"))
+    e1, pm1, f1 = G.decode_learned(win, det, win.row0, cfg)
+    assert torch.equal(e0, e1) and torch.equal(pm0, pm1) and torch.equal(f0, f1)
+    dec = tr["dec"].cpu().numpy()          # [n, paths, cap, 3]
+    sel = tr["sel"].cpu().numpy()
+    rc, rx, rf = rc.cpu().numpy(), rx.cpu().numpy(), rf.cpu().numpy()
+    src, _, _ = win.columns()
+    H = O.OracleWindow(dem, 0, 3).export()["H"]
+    n_steps = 0
+    for s in range(n):
+        for d in range(R):
+            g = dec[s, 0, d, 0]
+            if g < 0:
+                assert (rc[s, d] < 0).all()
+                continue
+            n_steps += 1
+            cols = rc[s, d][rc[s, d] >= 0]
+            assert cols.size >= 1 and cols[0] == sel[s, g]         # Alg. 1's choice first
+            assert len(set(cols.tolist())) == cols.size
+            assert (H[:, cols].sum(0) >= 3).all()                   # degree >= 3
+            assert rf[s, d, 0] == dec[s, 0, d, 1]                   # favoured = main-path value
+            f = rx[s, d, :cols.size]
+            assert np.all(np.abs(f[:, :16]) < 1.0)
+            assert np.allclose(f[:, 16], H[:, cols].sum(0) / 8.0)
+    assert n_steps > 20
+
+
+@gpu
+def test_learned_decode_consistent_and_falls_back_to_plain():
+    G = _G()
+    dem, prm, win = _c2_window(G, 0)
+    ddem = G.DeviceDem(dem)
+    det, _ = ddem.sample(400, seed=33)
+    e0, pm0, f0 = win.decode(det, syn_offset=win.row0)
+    rng = np.random.default_rng(5)
+    model = G.Model(_params(rng, 0.3))
+    H = O.OracleWindow(dem, 0, 3).export()["H"].astype(np.int64)
+    s = det[:, win.row0:win.row0 + win.m].cpu().numpy().astype(np.int64)
+    for guesses, tau, pmf in [(2, 0.0, float("inf")), (0, 0.0, 10.0), (4, 1e9, float("inf"))]:
+        cfg = G.LearnCfg(1, 16, guesses, tau, 0, None, None, None, None, pmf)
+        e1, pm1, f1 = G.decode_learned(win, det, win.row0, cfg, model)
+        e1n, f1n = e1.cpu().numpy().astype(np.int64), f1.cpu().numpy()
+        sat = (f1n & 1) != 0
+        assert np.array_equal((e1n[sat] @ H.T) % 2, s[sat])        # Eq. 5's constraint holds
+        fb = (f1n & 8) != 0
+        assert torch.equal(e1[torch.from_numpy(fb).cuda()], e0[torch.from_numpy(fb).cuda()])
+        assert np.array_equal(pm1.cpu().numpy()[fb], pm0.cpu().numpy()[fb])
+        assert np.array_equal(f1n[fb] & ~8, f0.cpu().numpy()[fb])
+        # shots that converged in preprocessing never reach the proposer
+        pre = (f0.cpu().numpy() & 1) != 0
+        assert sat[pre].all()
+
+
+def _trained():
+    import os
+    import paper_2403_18901_amd.learned as LRN
+    path = LRN.default_model_path("144")
+    if not os.path.exists(path):
+        pytest.skip("no trained proposer weights in the package")
+    return LRN, LRN.load(path)
+
+
+@gpu
+def test_trained_proposer_picks_errors_more_often_than_alg1():
+    """On held-out shots (a seed and stream the training never used), the
+    candidate the trained network ranks first is in error more often than
+    Alg. 1's choice, on the plain main path's recorded steps."""
+    G = _G()
+    LRN, params = _trained()
+    pt = torch.from_numpy(params).cuda()
+    for p in (0.002, 0.003):
+        dem = circuit_dem(get_code("144"), 12, p)
+        prm = G.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=int(p <= 0.002))
+        win = G.Window(dem, 0, 3, prm)
+        src = torch.from_numpy(win.columns()[0].astype(np.int64)).cuda()
+        ddem = G.DeviceDem(dem)
+        n, R = 6000, 8
+        det, _ = ddem.sample(n, seed=4242, stream=9)
+        err = G.sample_errors(ddem, n, seed=4242, stream=9)
+        rx = torch.zeros((n, R, 16, 17), dtype=torch.float32, device="cuda")
+        rc = torch.full((n, R, 16), -1, dtype=torch.int32, device="cuda")
+        rf = torch.zeros((n, R, 16), dtype=torch.int32, device="cuda")
+        cfg = G.LearnCfg(2, 16, 0, 0.0, R, rx.data_ptr(), rc.data_ptr(), rf.data_ptr(), None,
+                         float("inf"))
+        G.decode_learned(win, det, win.row0, cfg)
+        valid = rc >= 0
+        steps = valid[:, :, 0]
+        z = G.mlp_forward(pt, rx.view(-1, 17)).view(n, R, 16)
+        pick = torch.where(valid, z, torch.full_like(z, -1e30)).argmax(dim=2)
+        shot = torch.arange(n, device="cuda").view(n, 1, 1).expand_as(rc)
+        col = torch.where(valid, rc, torch.zeros_like(rc)).long()
+        in_err = (err[shot, src[col]] == 1) & valid
+        alg1 = in_err[:, :, 0][steps].float().mean().item()
+        net = torch.gather(in_err, 2, pick.unsqueeze(2)).squeeze(2)[steps].float().mean().item()
+        assert int(steps.sum()) > 1000
+        assert net > alg1, (p, net, alg1)
+
+
+@gpu
+def test_trained_proposer_saves_work_at_matched_ler():
+    """[[144,12,12]], p = 0.002, held-out shots: the learned decoder spends
+    fewer BP edge updates than plain GDG, and its failure count lies inside
+    plain GDG's 2-sigma Wilson interval."""
+    from test_gpu_parity import wilson
+    G = _G()
+    LRN, params = _trained()
+    p = 0.002
+    dem = circuit_dem(get_code("144"), 12, p)
+    prm = G.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=1)
+    n = 8000
+    det0, obs0 = G.DeviceDem(dem).sample(n, seed=9090, stream=5)
+    plain = G.SlidingWindowDecoder(dem, prm)
+    det, obs = det0.clone(), obs0.clone()
+    work_plain = 0
+    for w in plain.windows:
+        e, pm, fl, tr = w.decode(det, syn_offset=w.row0, trace=True, log_cap=1)
+        work_plain += int(tr["edge_iters"].sum().item())
+        w.commit(e, det, obs)
+    f_plain = int(G.evaluate(det, obs).sum().item())
+    dec = LRN.LearnedSlidingWindowDecoder(dem, prm, params)
+    det, obs = det0.clone(), obs0.clone()
+    ei = torch.zeros((n, dec.n_windows), dtype=torch.int64, device="cuda")
+    fail, _ = dec.decode(det, obs, edge_iters=ei)
+    f_learn = int(fail.sum().item())
+    work_learn = int(ei.sum().item())
+    lo, hi = wilson(f_plain, n)
+    assert work_learn < 0.8 * work_plain, (work_learn, work_plain)
+    assert lo * n - 1e-9 <= f_learn <= hi * n + 1e-9, (f_learn, f_plain)

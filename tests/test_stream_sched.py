@@ -1,0 +1,72 @@
+"""Host bookkeeping of the streaming service (arrivals, admission, readiness)."""
+import numpy as np
+
+from paper_2403_18901_amd.stream import StreamScheduler
+
+
+def test_poisson_experiment_starts():
+    """Experiments are n_rounds consecutive rounds of a Poisson round stream:
+    starts by time T are about rate * T / n_rounds per block."""
+    s = StreamScheduler(50, 13, 3, rate=1e4, n_slots=10**6, seed=3)
+    T = 0.5
+    s.advance_to(T)
+    expect = 50 * 1e4 * T / 13
+    assert abs(s.n_exp_started - expect) < 5 * np.sqrt(expect)
+    assert s.n_rejected == 0 and s.n_admitted == s.n_exp_started
+    # round times of every admitted experiment are increasing and start <= T
+    used = s.slot_block >= 0
+    t = s.slot_times[used]
+    assert (np.diff(t, axis=1) > 0).all() and (t[:, 0] <= T).all()
+
+
+def test_admission_cap_and_rejections():
+    s = StreamScheduler(8, 7, 3, rate=1e3, n_slots=3, seed=1)
+    slots, ids = s.advance_to(0.2)
+    assert slots.size == 3 and list(ids) == [0, 1, 2]
+    assert s.n_admitted == 3 and s.n_rejected == s.n_exp_started - 3
+    assert sum(len(p) for p in s.pending) == 3
+
+
+def test_windows_in_order_per_block():
+    """A block's window k is ready only when its round k+W-1 has arrived, one
+    window per block at a time, and the slot frees after K windows."""
+    s = StreamScheduler(1, 6, 3, rate=100.0, n_slots=2, seed=0)
+    now = 0.0
+    s.advance_to(now)
+    while not any(s.pending):
+        now = s.next_start()
+        s.advance_to(now)
+    slot = s.pending[0][0]
+    times = s.slot_times[slot].copy()
+    K = s.K
+    for k in range(K):
+        avail = times[k + 2]
+        assert s.ready(avail - 1e-12).size == 0 or s.slot_k[slot] != k
+        r = s.ready(avail)
+        assert list(r) == [slot] and s.slot_k[slot] == k
+        assert abs(s.next_event() - avail) < 1e-15
+        done = s.complete(r)
+        assert (done.size == 1) == (k == K - 1)
+    assert s.slot_block[slot] == -1 and slot in s.free
+
+
+def test_fake_service_drains_every_admitted_experiment():
+    """Constant-time fake decode ticks: every admitted experiment completes,
+    latencies are non-negative, and the backlog is empty at the end."""
+    s = StreamScheduler(5, 8, 3, rate=2e3, n_slots=7, seed=4)
+    now, lat, done = 0.0, [], 0
+    while now < 0.3 or any(s.pending):
+        if now < 0.3:
+            s.advance_to(now)
+        r = s.ready(now)
+        if r.size == 0:
+            nxt = s.next_event()
+            if now < 0.3:
+                nxt = min(nxt, s.next_start())
+            now = max(now, nxt)
+            continue
+        now += 1e-4
+        lat.extend((now - s.avail_time(r)).tolist())
+        done += s.complete(r).size
+    assert done == s.n_admitted and min(lat) >= 0.0
+    assert s.backlog(now) == 0
