@@ -4,9 +4,10 @@ The proposer is this project's addition to GDG (the paper selects with
 Alg. 1). At every decimation step it scores the first 16 candidates in
 Alg. 1's order -- features: a candidate's last 16 BP posteriors, squashed
 as p / (8 + |p|), and its degree / 8 -- with a 17-64-64-1 network whose
-output is the logit that the candidate is in error, decimates the candidate
-most likely in error to the network's decision, and guesses (forks) only at
-steps where that decision is not confident. Plain GDG decodes any window
+output is the logit that the candidate is in error, and decimates the
+candidate most likely in error to the network's decision. The learned paths
+guess either at depths 1..g as in Fig. 2 (the default, g = 2: 4 paths) or at
+the steps where the decision is not confident. Plain GDG decodes any window
 the learned paths cannot satisfy, so every committed correction still meets
 its window syndrome when plain GDG's would.
 
