@@ -171,8 +171,10 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
       po = align16(po + bytes);
       return o;
     };
-    L.p_post = ptake(4 * n);
-    const int c2v_bytes = std::max(4 * w.e_full, 8 * L.sort_n);
+    L.p_post = ptake(4 * (n + 1));   // + the padding's dummy VN
+    // the ranking's radix-select scratch reuses the message array
+    const int rank_bytes = 4 * (256 + 4) + 8 * na;
+    const int c2v_bytes = std::max(std::max(4 * (w.fr_epad + 8), 8 * L.sort_n), rank_bytes);
     L.p_c2v = ptake(c2v_bytes);
     L.p_keys = L.p_c2v;   // the sort keys reuse the message array
     L.p_lsum = ptake(4 * n);
@@ -206,7 +208,67 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   L.w_stride = wo;
   const int uni = std::max(std::max(prep, bo), waves * L.w_stride);
   L.total = L.u_base + uni;
+  // the preprocessing keeps up to 64 slot columns' syndrome bits per wavefront
+  if (w.pre_iters > 0 && (w.fr_T + waves - 1) / waves > 64) L.total = 1 << 30;
   return L;
+}
+
+// Lane-group layout of the whole window graph (the scheme the decode kernel
+// builds per shot for the truncated graph; see gdg_kernels.hip).
+struct FullLayout {
+  std::vector<uint32_t> meta;
+  std::vector<uint16_t> rvn, cidx;
+  std::vector<int> cptr;
+  int T = 0, epad = 0;
+};
+
+bool full_layout(int m, int n, const std::vector<int>& row_ptr, const std::vector<uint16_t>& row_col,
+                 const std::vector<uint8_t>& row_kcol, const std::vector<int>& col_ptr,
+                 FullLayout& F) {
+  std::vector<int> order(m);
+  for (int j = 0; j < m; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return row_ptr[a + 1] - row_ptr[a] > row_ptr[b + 1] - row_ptr[b];
+  });
+  std::vector<int> start(m), nb(m), k(m);
+  int epad = 0, slots = 0;
+  for (int pj = 0; pj < m; ++pj) {
+    const int j = order[pj], d = row_ptr[j + 1] - row_ptr[j];
+    start[pj] = epad;
+    nb[pj] = (d + 3) / 4;
+    int kk = nb[pj] ? 1 : 0;
+    while (kk && kk < nb[pj]) kk *= 2;
+    k[pj] = kk;
+    epad += 4 * nb[pj];
+    slots += kk;
+  }
+  if (epad + 8 > 16383 || 4 * n > 65535 || m > 1023) return false;
+  F.epad = epad;
+  F.T = (slots + 63) / 64;
+  F.cptr.assign(n + 1, 0);
+  for (int c = 0; c < n; ++c) F.cptr[c + 1] = F.cptr[c] + (col_ptr[c + 1] - col_ptr[c] + 3) / 4 * 4;
+  F.cidx.assign(std::max(F.cptr[n], 4), (uint16_t)(4 * epad));   // padding: the zero message
+  F.rvn.assign(epad + 8, (uint16_t)(4 * n));                        // padding: the dummy VN
+  F.meta.assign((size_t)F.T * 64, (uint32_t)(epad + 4));             // idle lanes: the dummy batch
+  int g = 0;
+  for (int pj = 0; pj < m; ++pj) {
+    const int j = order[pj];
+    int pos = start[pj];
+    for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e, ++pos) {
+      const int c = row_col[e];
+      F.rvn[pos] = (uint16_t)(4 * c);
+      F.cidx[F.cptr[c] + row_kcol[e]] = (uint16_t)(4 * pos);
+    }
+    if (!k[pj]) continue;
+    int lk = 0;
+    while ((1 << lk) < k[pj]) ++lk;
+    for (int i = 0; i < k[pj]; ++i, ++g) {
+      const int e0 = i < nb[pj] ? start[pj] + 4 * i : epad + 4;
+      F.meta[g] = (uint32_t)e0 | ((uint32_t)j << 14) | ((uint32_t)lk << 24) |
+                  (i == 0 ? (1u << 28) : 0u) | (1u << 29);
+    }
+  }
+  return true;
 }
 
 // Most slot columns any truncation can need: rows of window degree D_j hold
@@ -371,6 +433,17 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   if ((rc = win->put(llr, &D.llr))) return rc;
   if ((rc = win->put(win->llr64, &D.llr64))) return rc;
   if ((rc = win->put(deg, &D.deg))) return rc;
+  {
+    FullLayout F;
+    if (!full_layout(m, n, row_ptr, row_col, row_kcol, col_ptr, F))
+      return fail(GDG_ESHAPE, "window too large for the preprocessing layout");
+    D.fr_T = F.T;
+    D.fr_epad = F.epad;
+    if ((rc = win->put(F.meta, &D.fr_meta))) return rc;
+    if ((rc = win->put(F.rvn, &D.fr_rvn))) return rc;
+    if ((rc = win->put(F.cidx, &D.fr_cidx))) return rc;
+    if ((rc = win->put(F.cptr, &D.fr_cptr))) return rc;
+  }
 
   // commit tables
   std::vector<std::vector<int>> by_row(dem->n_rows);

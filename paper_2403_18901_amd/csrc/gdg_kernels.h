@@ -21,6 +21,14 @@ struct gdg_win_dev {
   const float* llr;         // [n] prior LLR rounded to float
   const double* llr64;      // [n] prior LLR in double (path metric, Eq. 5)
   const uint8_t* deg;       // [n] column degree
+  // the whole window graph in the decode kernel's lane-group layout (used by
+  // the preprocessing BP): rows by decreasing degree, padded to multiples of 4
+  // edges with dummy VN n; column slots padded to multiples of 4
+  int fr_T, fr_epad;        // slot columns, padded CSR edges
+  const uint32_t* fr_meta;  // [fr_T][64] slot metadata (row field: window row)
+  const uint16_t* fr_rvn;   // [fr_epad + 8] 4 * column of each padded CSR edge
+  const uint16_t* fr_cidx;  // [padded column slots] 4 * CSR position (padding: 4 * fr_epad)
+  const int* fr_cptr;       // [n + 1] first column slot
 };
 
 // Byte offsets of the decode kernel's dynamic LDS regions.

@@ -360,6 +360,7 @@ struct PathCtx {
   uint8_t* unsat;         // [m]
   uint32_t* prop;         // [ceil(n_act/4)] peeling proposals, one byte per VN
   int lane, m, n, T;
+  int t0 = 0, tstride = 1;   // slot column i of this walk is table column t0 + i * tstride
   uint32_t sres;          // bit t: residual syndrome of the row in slot column t
   // VN registers
   uint32_t vinfo[VPL];   // first column slot | degree << 16 | (status + 1) << 24
@@ -434,7 +435,7 @@ __device__ __forceinline__ void slot_edges(const PathCtx<VPL>& P, Slot& s) {
 
 template <int VPL>
 __device__ __forceinline__ void slot_meta(const PathCtx<VPL>& P, Slot& s, int t) {
-  s.mt = P.meta[min(t, P.T - 1) * kWave + P.lane];
+  s.mt = P.meta[(P.t0 + min(t, P.T - 1) * P.tstride) * kWave + P.lane];
 }
 
 template <int VPL, bool OV, typename Gather, typename Compute>
@@ -705,6 +706,45 @@ __device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist, float*
   return edges;
 }
 
+// VN phase of the whole-window BP: posteriors (Eq. 2) of the workgroup's VNs,
+// summed in column-slot order (padding adds the zero message), exact zeros
+// stored as -0 (sign bit = hard decision), plus the running sum of the last
+// iterations when lsum is given. Four VNs per thread per round, their index
+// and message loads issued together.
+__device__ __forceinline__ void full_vn_pass(const gdg_win_dev& w, float* post, const float* c2v,
+                                             float* lsum) {
+  const int n = w.n, bs = blockDim.x;
+  for (int v0 = threadIdx.x; v0 < n; v0 += 4 * bs) {
+    int c0[4], dg[4];
+    uint2 ix[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int v = min(v0 + j * bs, n - 1);
+      c0[j] = w.fr_cptr[v];
+      dg[j] = w.deg[v];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ix[j] = *(const uint2*)(w.fr_cidx + c0[j]);
+    float s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int v = min(v0 + j * bs, n - 1);
+      const float g0 = at_byte(c2v, ix[j].x & 0xffffu), g1 = at_byte(c2v, ix[j].x >> 16);
+      const float g2 = at_byte(c2v, ix[j].y & 0xffffu), g3 = at_byte(c2v, ix[j].y >> 16);
+      s[j] = (((w.llr[v] + g0) + g1) + g2) + g3;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int v = v0 + j * bs;
+      if (v >= n) continue;
+      for (int k = 4; k < dg[j]; ++k) s[j] += at_byte(c2v, w.fr_cidx[c0[j] + k]);
+      const float x = s[j] == 0.0f ? -0.0f : s[j];
+      post[v] = x;
+      if (lsum) lsum[v] += x;
+    }
+  }
+}
+
 // Decodes shot `shot` of one window with the whole workgroup. Every thread
 // enters and leaves together; the caller synchronises before the LDS is reused.
 template <int VPL, bool kLearn>
@@ -753,39 +793,71 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
 
   // ---------------------------------------------------------- preprocessing
   if (w.pre_iters > 0) {
-    FullBP b;
-    b.w = &w;
-    b.cs = w.row_cs;
-    b.post = (float*)(U + L.p_post);
-    b.c2v = (float*)(U + L.p_c2v);
-    b.syn = sorig;
-    float* lsum = (float*)(U + L.p_lsum);
+    // Flooding min-sum on the whole window with the path BP's CN code: the
+    // window graph's lane-group slot table (built on the host) is split over
+    // the wavefronts, column i of wavefront wv being table column wv + i W.
+    float* const ppost = (float*)(U + L.p_post);
+    float* const pc2v = (float*)(U + L.p_c2v);
+    float* const lsum = (float*)(U + L.p_lsum);
     for (int c = tid; c < n; c += blockDim.x) {
-      b.post[c] = w.llr[c];
+      ppost[c] = w.llr[c];
       lsum[c] = 0.0f;
     }
-    for (int e = tid; e < w.e_full; e += blockDim.x) b.c2v[e] = 0.0f;
+    if (tid == 0) ppost[n] = kInfF;   // dummy VN of the row padding
+    for (int e = tid; e < w.fr_epad + 2 * kPad; e += blockDim.x) pc2v[e] = 0.0f;
+    const int nw = blockDim.x >> 6;
+    const int my_T = wave < w.fr_T ? (w.fr_T - wave + nw - 1) / nw : 0;
+    PathCtx<VPL> F;
+    F.rvn = w.fr_rvn;
+    F.meta = w.fr_meta;
+    F.post = ppost;
+    F.c2v = pc2v;
+    F.lane = lane;
+    F.m = m;
+    F.n = n;
+    F.tstride = nw;
+    // syndrome bits of this wavefront's slot columns (at most 64)
+    uint32_t syn0 = 0u, syn1 = 0u;
+    for (int i = 0; i < my_T; ++i) {
+      const uint32_t mt = w.fr_meta[(wave + i * nw) * kWave + lane];
+      const uint32_t b = (mt & kMetaValid) ? (uint32_t)sorig[(mt >> kMetaRowShift) & 0x3ff] : 0u;
+      if (i < 32)
+        syn0 |= b << i;
+      else
+        syn1 |= b << (i - 32);
+    }
     __syncthreads();
+    auto walk = [&](bool messages) {
+      int bad = 0;
+      for (int c = 0; c < 2; ++c) {
+        if (my_T <= 32 * c) break;
+        F.t0 = wave + 32 * c * nw;
+        F.T = min(32, my_T - 32 * c);
+        F.sres = c ? syn1 : syn0;
+        bad |= messages ? cn_phase(F, w.alpha, w.clip) : check_pass(F, false);
+      }
+      return bad;
+    };
     bool conv = false;
     int iters_done = 0;
     for (int t = 1; t <= w.pre_iters; ++t) {
-      const int bad = full_cn_phase(b);
+      const int bad = walk(true);
       const int any_bad = __syncthreads_or(bad);
       if (t >= 2 && !any_bad) {
         conv = true;
         break;
       }
-      full_vn_phase(b, t > w.pre_iters - 4 ? lsum : nullptr);
+      full_vn_pass(w, ppost, pc2v, t > w.pre_iters - 4 ? lsum : nullptr);
       iters_done = t;
       __syncthreads();
     }
-    if (!conv) conv = !__syncthreads_or(full_check(b));
+    if (!conv) conv = !__syncthreads_or(walk(false));
     if (tid == 0) *eacc = (unsigned long long)iters_done * (unsigned long long)w.e_full;
     if (conv) {
       // the hard decision of the preprocessing BP is the answer
       for (int base = wave * kWave; base < n; base += blockDim.x) {
         const int c = base + lane;
-        const bool one = c < n && b.post[c] <= 0.0f;
+        const bool one = c < n && ppost[c] <= 0.0f;
         const unsigned long long bal = __ballot(one);
         if (lane == 0) {
           obits[base >> 5] = (uint32_t)bal;
@@ -825,30 +897,75 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       if (tr.edge_iters && tid == 0) tr.edge_iters[shot] = (long long)*eacc;
       return;
     }
-    // rank: ascending sum of the last four posteriors, ties by column index
+    // rank: ascending sum of the last four posteriors, ties by column index;
+    // keep the n_act smallest keys (order-preserving float bits, column). A
+    // radix select over the key's 32 + 16 bits (six 8-bit passes) finds the
+    // n_act-th smallest key K; the kept keys (<= K) are gathered in any order
+    // and each one's position is the count of smaller kept keys.
     __syncthreads();
-    unsigned long long* keys = (unsigned long long*)(U + L.p_keys);
-    const int NP = L.sort_n;
-    for (int i = tid; i < NP; i += blockDim.x)
-      keys[i] = i < n ? (((unsigned long long)ord_f32(lsum[i]) << 32) | (unsigned)i) : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= NP; k <<= 1) {
-      for (int jj = k >> 1; jj > 0; jj >>= 1) {
-        for (int i = tid; i < NP; i += blockDim.x) {
-          const int ixj = i ^ jj;
-          if (ixj > i) {
-            const unsigned long long a = keys[i], bb = keys[ixj];
-            const bool up = (i & k) == 0;
-            if ((a > bb) == up) {
-              keys[i] = bb;
-              keys[ixj] = a;
-            }
+    int* hist = (int*)(U + L.p_keys);                 // [256]
+    int* ctl = hist + 256;                            // [0], [1] key prefix, [2] still needed, [3] count
+    unsigned long long* ck = (unsigned long long*)(ctl + 4);   // [n_act]
+    const int bs = blockDim.x;
+    if (tid == 0) {
+      ctl[0] = 0;
+      ctl[1] = 0;
+      ctl[2] = n_act;
+      ctl[3] = 0;
+    }
+    unsigned long long kmask = 0ull;
+    for (int pass = 0; pass < 6; ++pass) {
+      const int shift = 40 - 8 * pass;   // key bits 47..0: ord(sum) << 16 | column
+      for (int i = tid; i < 256; i += bs) hist[i] = 0;
+      __syncthreads();
+      const unsigned long long prefix =
+          ((unsigned long long)(uint32_t)ctl[0] << 32) | (uint32_t)ctl[1];
+      for (int c = tid; c < n; c += bs) {
+        const unsigned long long k = ((unsigned long long)ord_f32(lsum[c]) << 16) | (unsigned)c;
+        if ((k & kmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1);
+      }
+      __syncthreads();
+      if (wave == 0) {
+        int h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h[j] = hist[4 * lane + j];
+        const int tot = h[0] + h[1] + h[2] + h[3];
+        int run = wave_incl_scan(tot, lane) - tot;
+        const int need = ctl[2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (run < need && run + h[j] >= need) {
+            const unsigned long long np = prefix | ((unsigned long long)(4 * lane + j) << shift);
+            ctl[0] = (int)(uint32_t)(np >> 32);
+            ctl[1] = (int)(uint32_t)np;
+            ctl[2] = need - run;
           }
+          run += h[j];
         }
-        __syncthreads();
+      }
+      kmask |= 0xffull << shift;
+      __syncthreads();
+    }
+    const unsigned long long kthr = ((unsigned long long)(uint32_t)ctl[0] << 32) | (uint32_t)ctl[1];
+    for (int c = tid; c < n; c += bs) {
+      const unsigned long long k = ((unsigned long long)ord_f32(lsum[c]) << 16) | (unsigned)c;
+      if (k <= kthr) {
+        const int pos = atomicAdd(&ctl[3], 1);
+        if (pos < n_act) ck[pos] = k;
       }
     }
-    for (int v = tid; v < n_act; v += blockDim.x) sel[v] = (int16_t)(keys[v] & 0xffffu);
+    __syncthreads();
+    for (int i = tid; i < n_act; i += bs) {
+      const unsigned long long ki = ck[i];
+      int r = 0;
+      int j = 0;
+      for (; j + 1 < n_act; j += 2) {
+        const ulonglong2 kj = *(const ulonglong2*)(ck + j);
+        r += (kj.x < ki) + (kj.y < ki);
+      }
+      if (j < n_act) r += ck[j] < ki;
+      sel[r] = (int16_t)(ki & 0xffffu);
+    }
   } else {
     for (int v = tid; v < n_act; v += blockDim.x) sel[v] = (int16_t)v;
   }
