@@ -995,29 +995,32 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     // all truncated away and whose syndrome bit is 1 can never be satisfied
     int* rdeg = iscan;
     for (int j = tid; j < m; j += blockDim.x) {
+      const int e1 = w.row_ptr[j + 1];
       int cnt = 0;
-      for (int e = w.row_ptr[j]; e < w.row_ptr[j + 1]; ++e) cnt += loc[w.row_col[e]] >= 0;
+      for (int e = w.row_ptr[j]; e < e1; e += 8) {   // loads issued 8 at a time
+        int cc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cc[i] = e + i < e1 ? w.row_col[e + i] : -1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cnt += cc[i] >= 0 && loc[cc[i]] >= 0;
+      }
       rdeg[j] = cnt;
     }
     __syncthreads();
-    if (tid == 0) {
-      int* cnt = (int*)(U + L.p_rhist);   // 65 degree buckets
-      for (int d = 0; d <= 64; ++d) cnt[d] = 0;
-      int dead0 = 0;
-      for (int j = 0; j < m; ++j) {
-        ++cnt[rdeg[j]];
-        if (rdeg[j] == 0 && sorig[j]) dead0 = 1;
+    // position of each row: decreasing degree, ties by row index
+    int dead = 0;
+    for (int j = tid; j < m; j += blockDim.x) {
+      const int dj = rdeg[j];
+      int r = 0;
+      for (int i = 0; i < m; ++i) {
+        const int di = rdeg[i];
+        r += di > dj || (di == dj && i < j);
       }
-      int pos = 0;
-      for (int d = 64; d >= 0; --d) {
-        const int c = cnt[d];
-        cnt[d] = pos;
-        pos += c;
-      }
-      for (int j = 0; j < m; ++j) perm[cnt[rdeg[j]]++] = (int16_t)j;
-      misc[4] = dead0;
+      perm[r] = (int16_t)j;
+      dead |= dj == 0 && sorig[j];
     }
-    __syncthreads();
+    dead = __syncthreads_or(dead);
+    if (tid == 0) misc[4] = dead;
     // padded degree in sub-graph row order
     for (int pj = tid; pj < m; pj += blockDim.x)
       iscan[m + 1 + pj] = (rdeg[perm[pj]] + kPad - 1) / kPad * kPad;
@@ -1051,14 +1054,24 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       const int j = perm[pj];
       psyn[pj] = sorig[j];
       int pos = rptr[pj];
-      for (int e = w.row_ptr[j]; e < w.row_ptr[j + 1]; ++e) {
-        const int v = loc[w.row_col[e]];
-        if (v < 0) continue;
-        const int slot = cptr[v] + w.row_kcol[e];
-        rvn[pos] = (uint16_t)(4 * v);
-        cidx[slot] = (uint16_t)(4 * pos);
-        crow[slot] = (uint16_t)pj;
-        ++pos;
+      const int e1 = w.row_ptr[j + 1];
+      for (int e = w.row_ptr[j]; e < e1; e += 8) {   // loads issued 8 at a time
+        int cc[8], kc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          cc[i] = e + i < e1 ? w.row_col[e + i] : 0;
+          kc[i] = e + i < e1 ? w.row_kcol[e + i] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int v = e + i < e1 ? loc[cc[i]] : -1;
+          if (v < 0) continue;
+          const int slot = cptr[v] + kc[i];
+          rvn[pos] = (uint16_t)(4 * v);
+          cidx[slot] = (uint16_t)(4 * pos);
+          crow[slot] = (uint16_t)pj;
+          ++pos;
+        }
       }
       for (; pos < rptr[pj + 1]; ++pos) rvn[pos] = (uint16_t)(4 * n_act);   // padding: dummy VN
       const int nb = (rptr[pj + 1] - rptr[pj]) / kPad;
