@@ -148,7 +148,7 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   L.sel = take(2 * na);
   L.rptr = take(2 * (m + 1));
   L.rvn = take(2 * EP);
-  L.cidx = take(2 * col_slots);
+  L.cidx = take(2 * (col_slots + 4));   // + four entries read past the last column
   L.cptr = take(2 * (na + 1));
   L.crow = take(2 * col_slots);
   L.meta = take(4 * 64 * tcols);

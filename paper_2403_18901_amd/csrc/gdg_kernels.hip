@@ -407,6 +407,20 @@ __device__ __forceinline__ void cnt_merge(int& cnt, int& x, int& only) {
   only = max(only, (int)dpp<CTRL>((uint32_t)only));
 }
 
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// bit 31 of a ^ b, other bits zero
+__device__ __forceinline__ uint32_t xor_sign(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_bitop3_b32(a, b, 0x80000000u, 0x28);
+}
+
+__device__ __forceinline__ uint32_t med3_bits(uint32_t a, uint32_t b, uint32_t c) {
+  return __float_as_uint(
+      __builtin_amdgcn_fmed3f(__uint_as_float(a), __uint_as_float(b), __uint_as_float(c)));
+}
+
 __device__ __forceinline__ const float& at_byte(const float* base, uint32_t off) {
   return *(const float*)((const char*)base + off);
 }
@@ -589,6 +603,7 @@ __device__ bool peel(PathCtx<VPL>& P) {
 template <int VPL>
 __device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const Slot& c, int t, float alpha,
                                        float clip) {
+  constexpr uint32_t kSign = 0x80000000u;
   const uint32_t mt = c.mt;
   const int e0 = mt & kMetaEdge;
   const int lk = (mt >> kMetaLogKShift) & 7;
@@ -596,29 +611,34 @@ __device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const Slot& c, int t, fl
   const float x1 = clip_to(__uint_as_float(c.g.y) - c.ov.y, clip);
   const float x2 = clip_to(__uint_as_float(c.g.z) - c.ov.z, clip);
   const float x3 = clip_to(__uint_as_float(c.g.w) - c.ov.w, clip);
-  const uint32_t m0 = __float_as_uint(x0) & 0x7fffffffu, m1 = __float_as_uint(x1) & 0x7fffffffu;
-  const uint32_t m2 = __float_as_uint(x2) & 0x7fffffffu, m3 = __float_as_uint(x3) & 0x7fffffffu;
+  const uint32_t b0 = __float_as_uint(x0), b1 = __float_as_uint(x1);
+  const uint32_t b2 = __float_as_uint(x2), b3 = __float_as_uint(x3);
+  const uint32_t m0 = b0 & ~kSign, m1 = b1 & ~kSign, m2 = b2 & ~kSign, m3 = b3 & ~kSign;
+  // two smallest of four: inserting m into n1 <= n2 gives min(n1, m) and the
+  // median of {n1, n2, m}; the magnitudes are non-negative floats, so the
+  // float median orders them as their bit patterns do
   CnAcc a;
   a.n1 = min(m0, m1);
   a.n2 = max(m0, m1);
-  a.n2 = min(max(a.n1, m2), a.n2);
+  a.n2 = med3_bits(a.n1, a.n2, m2);
   a.n1 = min(a.n1, m2);
-  a.n2 = min(max(a.n1, m3), a.n2);
+  a.n2 = med3_bits(a.n1, a.n2, m3);
   a.n1 = min(a.n1, m3);
-  a.sp = __float_as_uint(x0) ^ __float_as_uint(x1) ^ __float_as_uint(x2) ^ __float_as_uint(x3);
-  a.hp = c.g.x ^ c.g.y ^ c.g.z ^ c.g.w;
+  // parities of the message signs and of the hard decisions, kept in bit 31
+  a.sp = xor_sign(xor3(b0, b1, b2), b3);
+  a.hp = xor_sign(xor3(c.g.x, c.g.y, c.g.z), c.g.w);
   cn_group(a, lk);
-  const uint32_t srow = (P.sres >> t) & 1u;
-  const uint32_t sgn = (a.sp ^ (srow << 31)) & 0x80000000u;
+  const uint32_t srow = (P.sres << (31 - t)) & kSign;   // residual syndrome bit of the row
+  const uint32_t sgn = a.sp ^ srow;
   const uint32_t s1 = __float_as_uint(alpha * __uint_as_float(a.n1)) | sgn;
   const uint32_t s2 = __float_as_uint(alpha * __uint_as_float(a.n2)) | sgn;
   float4 nv;
-  nv.x = __uint_as_float((m0 == a.n1 ? s2 : s1) ^ (__float_as_uint(x0) & 0x80000000u));
-  nv.y = __uint_as_float((m1 == a.n1 ? s2 : s1) ^ (__float_as_uint(x1) & 0x80000000u));
-  nv.z = __uint_as_float((m2 == a.n1 ? s2 : s1) ^ (__float_as_uint(x2) & 0x80000000u));
-  nv.w = __uint_as_float((m3 == a.n1 ? s2 : s1) ^ (__float_as_uint(x3) & 0x80000000u));
+  nv.x = __uint_as_float((m0 == a.n1 ? s2 : s1) ^ (b0 & kSign));
+  nv.y = __uint_as_float((m1 == a.n1 ? s2 : s1) ^ (b1 & kSign));
+  nv.z = __uint_as_float((m2 == a.n1 ? s2 : s1) ^ (b2 & kSign));
+  nv.w = __uint_as_float((m3 == a.n1 ? s2 : s1) ^ (b3 & kSign));
   *(float4*)(P.c2v + e0) = nv;
-  return (int)(srow ^ (a.hp >> 31));
+  return (int)(srow ^ a.hp);   // bit 31: the row is unsatisfied
 }
 
 template <int VPL>
@@ -648,7 +668,7 @@ __device__ __forceinline__ int check_pass(PathCtx<VPL>& P, bool write_unsat) {
       },
       [&](const Slot& s, int t) {
         const uint32_t mt = s.mt;
-        uint32_t hp = s.g.x ^ s.g.y ^ s.g.z ^ s.g.w;
+        uint32_t hp = xor3(s.g.x, s.g.y, s.g.z) ^ s.g.w;
         hp_group(hp, (mt >> kMetaLogKShift) & 7);
         const int hx = (int)(((P.sres >> t) & 1u) ^ (hp >> 31));
         if (write_unsat && (mt & kMetaLead) && (mt & kMetaValid))
@@ -659,19 +679,20 @@ __device__ __forceinline__ int check_pass(PathCtx<VPL>& P, bool write_unsat) {
 
 // VN phase: posteriors of the owned active VNs (Eq. 2), summed in column slot
 // order, and the history of the last four iterations of the step. The first
-// five slots of every owned VN are gathered together (index loads, then
-// message loads) so that their LDS latencies overlap; VNs of degree above five
-// take a loop.
+// five slots of every owned VN are gathered together, without a branch between
+// the loads (index loads, then message loads), so that their LDS latencies
+// overlap: the fifth index is read for every VN -- the column slot table keeps
+// four readable entries past its end -- and its message added only to VNs of
+// degree above four. VNs of degree above five take a loop. Returns the number
+// of edges of the active VNs.
 template <int VPL>
-__device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist, float* ring_slot) {
+__device__ __forceinline__ int vn_phase(PathCtx<VPL>& P, bool hist, float* ring_slot) {
   uint2 ix[VPL];
   uint32_t ix5[VPL];
-  bool deg5[VPL];
 #pragma unroll
   for (int r = 0; r < VPL; ++r) {
     ix[r] = *(const uint2*)(P.cidx + P.vc0(r));
-    deg5[r] = wave_any(P.vdg(r) > 4);
-    ix5[r] = deg5[r] && P.vdg(r) > 4 ? P.cidx[P.vc0(r) + 4] : 0u;   // 0: a valid, unused offset
+    ix5[r] = P.cidx[P.vc0(r) + 4];
   }
   __builtin_amdgcn_sched_barrier(0);
   float g[VPL][5];
@@ -681,25 +702,36 @@ __device__ __forceinline__ long long vn_phase(PathCtx<VPL>& P, bool hist, float*
     g[r][1] = at_byte(P.c2v, ix[r].x >> 16);
     g[r][2] = at_byte(P.c2v, ix[r].y & 0xffffu);
     g[r][3] = at_byte(P.c2v, ix[r].y >> 16);
-    g[r][4] = deg5[r] ? at_byte(P.c2v, ix5[r]) : 0.0f;
+    g[r][4] = at_byte(P.c2v, ix5[r]);
   }
   __builtin_amdgcn_sched_barrier(0);
-  long long edges = 0;
+  float s[VPL];
+  bool deep = false;
+#pragma unroll
+  for (int r = 0; r < VPL; ++r) {
+    const float s4 = (((P.llr[r] + g[r][0]) + g[r][1]) + g[r][2]) + g[r][3];
+    s[r] = P.vdg(r) > 4 ? s4 + g[r][4] : s4;
+    deep |= P.vdg(r) > 5;
+  }
+  if (wave_any(deep)) {
+#pragma unroll
+    for (int r = 0; r < VPL; ++r)
+      for (int k = 5; k < P.vdg(r); ++k) s[r] += at_byte(P.c2v, P.cidx[P.vc0(r) + k]);
+  }
+  int edges = 0;
 #pragma unroll
   for (int r = 0; r < VPL; ++r) {
     const int v = P.lane + kWave * r;
-    float s = (((P.llr[r] + g[r][0]) + g[r][1]) + g[r][2]) + g[r][3];
-    if (deg5[r]) s += P.vdg(r) > 4 ? g[r][4] : 0.0f;   // + 0 is exact: s is never -0
-    for (int k = 5; k < P.vdg(r); ++k) s += at_byte(P.c2v, P.cidx[P.vc0(r) + k]);
     if (v < P.n && P.st(r) < 0) {
-      const float x = s == 0.0f ? -0.0f : s;   // sign bit = hard decision
+      const float x = s[r] == 0.0f ? -0.0f : s[r];   // sign bit = hard decision
       P.post[v] = x;
       if (ring_slot) ring_slot[v] = x;
       edges += P.vdg(r);
       if (hist) {
+        // min and max as medians with -inf and +inf: no NaN reaches here
         P.hs[r] += x;
-        P.hmn[r] = fminf(P.hmn[r], x);
-        P.hmx[r] = fmaxf(P.hmx[r], x);
+        P.hmn[r] = __builtin_amdgcn_fmed3f(P.hmn[r], x, -kInfF);
+        P.hmx[r] = __builtin_amdgcn_fmed3f(P.hmx[r], x, kInfF);
       }
     }
   }
@@ -756,7 +788,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
   const gdg_win_dev w = wref;   // uniform: kept in scalar registers, not re-read
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = w.m, n = w.n, n_act = w.n_act;
 
   uint8_t* sorig = smem + L.sorig;
@@ -1091,6 +1123,9 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       const int c0 = cptr[v] + sdeg[v];
       for (int i = c0; i < cptr[v + 1]; ++i) cidx[i] = (uint16_t)(4 * e_pad);   // zero message
     }
+    // four readable entries past the last column (the VN phase reads a fifth
+    // index of every VN)
+    for (int i = tid; i < kPad; i += blockDim.x) cidx[cptr[n_act] + i] = (uint16_t)(4 * e_pad);
     if (tid == 0) {
       misc[3] = T;
       misc[5] = n_slots > cap;
@@ -1122,7 +1157,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     P.lane = lane;
     P.m = m;
     P.n = n_act;
-    P.T = misc[3];
+    P.T = __builtin_amdgcn_readfirstlane(misc[3]);
     P.sres = 0u;
     const bool dead0 = misc[4] != 0;
     const int T = w.iters;

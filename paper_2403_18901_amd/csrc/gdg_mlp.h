@@ -7,7 +7,13 @@
 
 #define GDG_MLP_IN 17
 #define GDG_MLP_H 64
-#define GDG_MLP_PARAMS (GDG_MLP_IN * GDG_MLP_H + GDG_MLP_H + GDG_MLP_H * GDG_MLP_H + 3 * GDG_MLP_H + 1)
+#ifndef GDG_MLP_PARAMS
+#define GDG_MLP_PARAMS 5377
+#endif
+// W1 [IN][H], b1 [H], W2 [H][H], b2 [H], w3 [H], b3
+static_assert(GDG_MLP_PARAMS ==
+                  GDG_MLP_IN * GDG_MLP_H + GDG_MLP_H + GDG_MLP_H * GDG_MLP_H + 2 * GDG_MLP_H + 1,
+              "parameter count of the 17-64-64-1 network");
 
 // Inference copy of the network: the weight matrices transposed and rounded
 // to BF16 (round to nearest even), laid out as the A operands of
