@@ -25,11 +25,10 @@ N_CU = 256
 def _bucket(w) -> int:
     """The kernel's register tiling for a window (VNs per lane)."""
     na = w.n_act
-    if na <= 384:
-        return 0
-    if na <= 512:
-        return 1
-    return 2
+    for b, cap in enumerate((384, 448, 512)):
+        if na <= cap:
+            return b
+    return 3
 
 
 class LaunchPlan:

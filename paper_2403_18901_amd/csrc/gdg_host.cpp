@@ -153,6 +153,8 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   L.crow = take(2 * col_slots);
   L.meta = take(4 * 64 * tcols);
   L.vdeg = take(na);
+  L.st0 = take(na);        // VN status after the peeling at a path's start
+  L.sres0 = take(4 * 64);  // per lane, the residual syndrome bits after it
   L.ppm = take(8 * P);
   L.pend = take(4 * P);
   L.pbits = take(4 * P * L.pbits_words);
@@ -554,7 +556,7 @@ size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots) {
 
 namespace {
 
-int g_lds_set[3] = {65536, 65536, 65536};   // dynamic-LDS limit set per kernel bucket
+int g_lds_set[4] = {65536, 65536, 65536, 65536};   // dynamic-LDS limit set per kernel bucket
 
 int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
                 const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn = nullptr) {

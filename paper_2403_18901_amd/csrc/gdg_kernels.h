@@ -35,7 +35,8 @@ struct gdg_win_dev {
 struct gdg_lds {
   int total;
   // per shot
-  int sorig, psyn, sel, rptr, rvn, cidx, cptr, crow, meta, vdeg, ppm, pend, pbits, misc, obits, eacc;
+  int sorig, psyn, sel, rptr, rvn, cidx, cptr, crow, meta, vdeg, st0, sres0, ppm, pend, pbits, misc,
+      obits, eacc;
   int pbits_words, obits_words, meta_cols;
   // phase union (relative to u_base): preprocessing, sub-graph build scratch,
   // per-wavefront path regions

@@ -798,6 +798,8 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
   uint16_t* rvn = (uint16_t*)(smem + L.rvn);
   uint16_t* cidx = (uint16_t*)(smem + L.cidx);
   uint16_t* cptr = (uint16_t*)(smem + L.cptr);
+  int8_t* st0 = (int8_t*)(smem + L.st0);
+  uint32_t* sres0 = (uint32_t*)(smem + L.sres0);
   uint16_t* crow = (uint16_t*)(smem + L.crow);
   uint32_t* meta = (uint32_t*)(smem + L.meta);
   uint8_t* vdeg = smem + L.vdeg;                // sub-graph VN degrees (learned proposer)
@@ -1183,6 +1185,28 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
                                               16 * lrn.ring_stride
                              : nullptr;
     wave_sync();
+    // The peeling at the start of a path (Sec. IV-D) depends only on the
+    // shot's syndrome and sub-graph: wavefront 0 runs it once and every path
+    // starts from its result.
+    if (wave == 0) {
+#pragma unroll
+      for (int r = 0; r < VPL; ++r) {
+        const int v = lane + kWave * r;
+        P.set_st(r, -1);
+        if (v < n_act) P.status[v] = -1;
+      }
+      wave_sync();
+      const bool ok = !dead0 && peel(P);
+#pragma unroll
+      for (int r = 0; r < VPL; ++r) {
+        const int v = lane + kWave * r;
+        if (v < n_act) st0[v] = (int8_t)P.st(r);
+      }
+      sres0[lane] = P.sres;
+      if (lane == 0) misc[7] = ok;
+    }
+    __syncthreads();
+    const bool peel0_ok = misc[7] != 0;
 
     for (int run = 0; run < 2; ++run) {
       if (run == 1) {
@@ -1218,24 +1242,26 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
                         ? tr.dec + ((long long)shot * w.n_paths + pid) * tr.log_cap * 3
                         : nullptr;
 
-        // fresh path: every VN active, messages from the priors
+        // fresh path: the VNs left active by the initial peeling take their
+        // priors as posteriors
 #pragma unroll
         for (int r = 0; r < VPL; ++r) {
           const int v = lane + kWave * r;
-          P.set_st(r, -1);
+          const int st = v < n_act ? (int)st0[v] : -1;
+          P.set_st(r, st);
           if (v < n_act) {
-            P.status[v] = -1;
-            P.post[v] = P.llr[r];
+            P.status[v] = (int8_t)st;
+            P.post[v] = st < 0 ? P.llr[r] : kInfF;
             if (use_ring)
               for (int j = 0; j < 16; ++j) ring[j * lrn.ring_stride + v] = P.llr[r];
           }
         }
-        P.sres = 0u;
+        P.sres = sres0[lane];
         // t = 0: no CN message yet; also clears the zero slot and the dummy batch
         for (int e = lane; e < e_pad + 2 * kPad; e += kWave) P.c2v[e] = 0.0f;
         wave_sync();
         int end = 0, steps = 0, it = 0;
-        if (dead0 || !peel(P)) end = END_CONTRADICTION;   // peel at init too
+        if (!peel0_ok) end = END_CONTRADICTION;
         for (int D = 1; end == 0 && D <= dmax; ++D) {
 #pragma unroll
           for (int r = 0; r < VPL; ++r) {
@@ -1763,48 +1789,44 @@ __global__ void gdg_evaluate_kernel(int n_shots, int n_rows, int n_obs,
 
 // ------------------------------------------------------------------ launchers
 
+// Register tilings of the decode kernel: VNs per lane of each bucket.
+#define GDG_DECODE_TILINGS(X) X(6) X(7) X(8) X(16)
+constexpr int kBuckets = 4;
+
 hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
                            const gdg_trace_dev& tr, hipStream_t st) {
   dim3 g(grid), block(waves * kWave);
   const bool learn = J.learn.mode != 0;
-  switch (bucket * 2 + (learn ? 1 : 0)) {
-    case 0:
-      hipLaunchKernelGGL((gdg_decode_kernel<6, false>), g, block, lds, st, J, tr);
-      break;
-    case 1:
-      hipLaunchKernelGGL((gdg_decode_kernel<6, true>), g, block, lds, st, J, tr);
-      break;
-    case 2:
-      hipLaunchKernelGGL((gdg_decode_kernel<8, false>), g, block, lds, st, J, tr);
-      break;
-    case 3:
-      hipLaunchKernelGGL((gdg_decode_kernel<8, true>), g, block, lds, st, J, tr);
-      break;
-    case 4:
-      hipLaunchKernelGGL((gdg_decode_kernel<16, false>), g, block, lds, st, J, tr);
-      break;
-    case 5:
-      hipLaunchKernelGGL((gdg_decode_kernel<16, true>), g, block, lds, st, J, tr);
-      break;
-    default:
-      return hipErrorInvalidValue;
+  int b = 0;
+#define GDG_LAUNCH(V)                                                                   \
+  if (b++ == bucket) {                                                                  \
+    if (learn)                                                                          \
+      hipLaunchKernelGGL((gdg_decode_kernel<V, true>), g, block, lds, st, J, tr);       \
+    else                                                                                \
+      hipLaunchKernelGGL((gdg_decode_kernel<V, false>), g, block, lds, st, J, tr);      \
+    return hipGetLastError();                                                           \
   }
-  return hipGetLastError();
+  GDG_DECODE_TILINGS(GDG_LAUNCH)
+#undef GDG_LAUNCH
+  return hipErrorInvalidValue;
 }
 
 int gdg_kernel_bucket(int m, int n_act) {
   if (m > 1023) return -1;
   if (n_act <= 384) return 0;
-  if (n_act <= 512) return 1;
-  if (n_act <= 1024) return 2;
+  if (n_act <= 448) return 1;
+  if (n_act <= 512) return 2;
+  if (n_act <= 1024) return 3;
   return -1;
 }
 
 hipError_t gdg_decode_set_lds_limit(int bucket, int bytes) {
-  static const void* const fs[6] = {
-      (const void*)gdg_decode_kernel<6, false>,  (const void*)gdg_decode_kernel<6, true>,
-      (const void*)gdg_decode_kernel<8, false>,  (const void*)gdg_decode_kernel<8, true>,
-      (const void*)gdg_decode_kernel<16, false>, (const void*)gdg_decode_kernel<16, true>};
+  static const void* const fs[2 * kBuckets] = {
+#define GDG_FN(V) (const void*)gdg_decode_kernel<V, false>, (const void*)gdg_decode_kernel<V, true>,
+      GDG_DECODE_TILINGS(GDG_FN)
+#undef GDG_FN
+  };
+  if (bucket < 0 || bucket >= kBuckets) return hipErrorInvalidValue;
   for (int l = 0; l < 2; ++l) {
     const hipError_t e =
         hipFuncSetAttribute(fs[bucket * 2 + l], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
