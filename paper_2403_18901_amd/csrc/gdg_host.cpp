@@ -203,7 +203,7 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   };
   L.w_post = wtake(4 * (na + 1));   // + the padding's dummy VN
   L.w_status = wtake(na + 1);
-  L.w_c2v = wtake(4 * EP);
+  L.w_c2v = wtake(std::max(4 * EP, 8 * na));   // also the path metric's staging (doubles)
   L.w_unsat = wtake(m);
   L.w_prop = wtake(4 * ((na + 3) / 4));
   L.w_bits = wtake(4 * L.obits_words);

@@ -1216,10 +1216,13 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       const bool learned = run == 0 && mode == 1;
       const int n_run = learned ? (1 << lrn.guesses) : w.n_paths;
       for (;;) {
+        // paths are taken in decreasing id: the later paths of the tree
+        // deviate more often and run longer, so starting them first leaves
+        // the short ones to fill the end
         int pid = 0;
-        if (lane == 0) pid = atomicAdd(&misc[0], 1);
+        if (lane == 0) pid = n_run - 1 - atomicAdd(&misc[0], 1);
         pid = __builtin_amdgcn_readfirstlane(pid);
-        if (pid >= n_run) break;
+        if (pid < 0) break;
         int dmax, split;
         if (pid == 0 || (learned && !lrn.tree)) {
           dmax = w.dmax_main;
@@ -1508,16 +1511,28 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             }
           }
           wave_sync();
+          // the set columns' priors are gathered in column order by all lanes
+          // into the wavefront's message array (dead once the path has ended,
+          // sized for n_act doubles), then summed in that order by one lane
+          double* stage = (double*)P.c2v;
+          int n_set = 0;
+          for (int w0 = 0; w0 < L.obits_words; w0 += kWave) {
+            const int wd = w0 + lane;
+            uint32_t x = wd < L.obits_words ? wbits[wd] : 0u;
+            const int cnt = __builtin_popcount(x);
+            const int incl = wave_incl_scan(cnt, lane);
+            int pos = n_set + incl - cnt;
+            while (x) {
+              const int bt = __builtin_ctz(x);
+              x &= x - 1u;
+              stage[pos++] = w.llr64[wd * 32 + bt];
+            }
+            n_set += __builtin_amdgcn_readlane(incl, kWave - 1);
+          }
+          wave_sync();
           if (lane == 0) {
             pm = 0.0;
-            for (int wd = 0; wd < L.obits_words; ++wd) {
-              uint32_t x = wbits[wd];
-              while (x) {
-                const int bt = __builtin_ctz(x);
-                x &= x - 1u;
-                pm += w.llr64[wd * 32 + bt];
-              }
-            }
+            for (int i = 0; i < n_set; ++i) pm += stage[i];
           }
         }
         if (lane == 0) {
