@@ -129,11 +129,13 @@ namespace {
 // LDS plan of the decode kernel for `waves` wavefronts per workgroup.
 // LDS layout of the decode kernel for one window. max_sub_edges bounds the
 // truncated graph's edges, col_slots its column slots padded to multiples of
-// four, tcols the slot columns of its row groups (see the kernel).
+// four, tcols the slot columns of its row groups (see the kernel). The total
+// is the least allocation that decodes any shot: the preprocessing, the
+// sub-graph build with the worst truncation, and one path wavefront on it.
 gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tcols, int waves) {
   gdg_lds L{};
   const int m = w.m, n = w.n, na = w.n_act, E = max_sub_edges, P = w.n_paths;
-  const int EP = E + 3 * m + 8;   // rows padded to a multiple of 4 edges, zero slot, dummy batch
+  const int e_pad_max = E + 3 * m;   // rows padded to a multiple of 4 edges
   int off = 0;
   auto take = [&](int bytes) {
     int o = off;
@@ -144,20 +146,7 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   L.obits_words = (n + 31) / 32 + 1;
   L.meta_cols = tcols;
   L.sorig = take(m);
-  L.psyn = take(m);
   L.sel = take(2 * na);
-  L.rptr = take(2 * (m + 1));
-  L.rvn = take(2 * EP);
-  L.cidx = take(2 * (col_slots + 4));   // + four entries read past the last column
-  L.cptr = take(2 * (na + 1));
-  L.crow = take(2 * col_slots);
-  L.meta = take(4 * 64 * tcols);
-  L.vdeg = take(na);
-  L.st0 = take(na);        // VN status after the peeling at a path's start
-  L.sres0 = take(4 * 64);  // per lane, the residual syndrome bits after it
-  L.ppm = take(8 * P);
-  L.pend = take(4 * P);
-  L.pbits = take(4 * P * L.pbits_words);
   L.misc = take(32);
   L.obits = take(4 * L.obits_words);
   L.eacc = take(8);
@@ -182,8 +171,26 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
     L.p_lsum = ptake(4 * n);
     prep = po;
   }
-  // sub-graph build scratch, written after the preprocessing region is dead
-  int bo = 0;
+  // sub-graph arrays of fixed size, written after the preprocessing is dead
+  int so = 0;
+  auto stake = [&](int bytes) {
+    int o = so;
+    so = align16(so + bytes);
+    return o;
+  };
+  L.psyn = stake(m);
+  L.rptr = stake(2 * (m + 1));
+  L.cptr = stake(2 * (na + 1));
+  L.vdeg = stake(na);
+  L.st0 = stake(na);        // VN status after the peeling at a path's start
+  L.sres0 = stake(4 * 64);  // per lane, the residual syndrome bits after it
+  L.ppm = stake(8 * P);
+  L.pend = stake(4 * P);
+  L.pbits = stake(4 * P * L.pbits_words);
+  L.dyn_base = so;
+  const gdg_dyn_layout worst = gdg_dyn(L.dyn_base, e_pad_max, col_slots, tcols);
+  // sub-graph build scratch above the largest variable part
+  int bo = worst.end;
   auto btake = [&](int bytes) {
     int o = bo;
     bo = align16(bo + bytes);
@@ -193,23 +200,8 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   L.p_iscan = btake(4 * std::max(2 * m + 2, na + 1));
   L.p_llr = btake(4 * na);
   L.p_deg = btake(na);
-  L.p_rhist = btake(4 * 65);
-  // per-wavefront path region
-  int wo = 0;
-  auto wtake = [&](int bytes) {
-    int o = wo;
-    wo = align16(wo + bytes);
-    return o;
-  };
-  L.w_post = wtake(4 * (na + 1));   // + the padding's dummy VN
-  L.w_status = wtake(na + 1);
-  L.w_c2v = wtake(std::max(4 * EP, 8 * na));   // also the path metric's staging (doubles)
-  L.w_unsat = wtake(m);
-  L.w_prop = wtake(4 * ((na + 3) / 4));
-  L.w_bits = wtake(4 * L.obits_words);
-  L.w_stride = wo;
-  const int uni = std::max(std::max(prep, bo), waves * L.w_stride);
-  L.total = L.u_base + uni;
+  const int one_path = worst.end + gdg_paths(e_pad_max, na, m, L.obits_words).stride;
+  L.total = L.u_base + std::max(prep, std::max(bo, one_path));
   // the preprocessing keeps up to 64 slot columns' syndrome bits per wavefront
   if (w.pre_iters > 0 && (w.fr_T + waves - 1) / waves > 64) L.total = 1 << 30;
   return L;
@@ -295,6 +287,15 @@ int max_lds_per_block() {
   int dev = 0, v = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 65536;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 65536;
+  return v > 0 ? v : 65536;
+}
+
+int lds_per_cu() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+      hipSuccess)
     return 65536;
   return v > 0 ? v : 65536;
 }
@@ -593,6 +594,14 @@ int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
   if (learn) J.learn = *learn;
   if (total == 0) return GDG_OK;
   if (lds > max_lds_per_block()) return fail(GDG_ESHAPE, "jobs do not fit in LDS at this shape");
+  // Allocate the CU's LDS share at the occupancy the kernel is built for (or
+  // the plans' minimum if larger): shots with larger sub-graphs then still
+  // get all their path wavefronts.
+  const int wps = gdg_decode_waves_per_simd(bucket, J.learn.mode != 0);
+  const int wg_per_cu = 4 * wps / waves;
+  if (wg_per_cu >= 2)   // whole 2 KiB granules, so that the shares add up within the CU
+    lds = std::max(lds, std::min(lds_per_cu() / wg_per_cu / 2048 * 2048, max_lds_per_block()));
+  J.lds = lds;
   if (lds > g_lds_set[bucket]) {
     hipError_t e = gdg_decode_set_lds_limit(bucket, lds);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");

@@ -31,20 +31,61 @@ struct gdg_win_dev {
   const int* fr_cptr;       // [n + 1] first column slot
 };
 
-// Byte offsets of the decode kernel's dynamic LDS regions.
+// Byte offsets of the decode kernel's dynamic LDS regions. A header lives for
+// the whole shot; the area from u_base holds first the preprocessing and the
+// ranking, then the truncated sub-graph and the per-wavefront path regions.
+// The sub-graph's variable-size arrays and the path regions are placed per
+// shot from its actual sizes (gdg_dyn_layout, gdg_path_layout): the plan only
+// guarantees room for the worst truncation with one path wavefront, and a shot
+// uses as many path wavefronts as fit in the launch's allocation.
 struct gdg_lds {
-  int total;
-  // per shot
-  int sorig, psyn, sel, rptr, rvn, cidx, cptr, crow, meta, vdeg, st0, sres0, ppm, pend, pbits, misc,
-      obits, eacc;
+  int total;   // minimum dynamic LDS bytes
+  // header (offsets from the start of the dynamic LDS)
+  int sorig, sel, misc, obits, eacc;
   int pbits_words, obits_words, meta_cols;
-  // phase union (relative to u_base): preprocessing, sub-graph build scratch,
-  // per-wavefront path regions
   int u_base;
+  // from u_base: preprocessing and ranking
   int p_post, p_c2v, p_lsum, p_keys, sort_n;
-  int p_loc, p_iscan, p_llr, p_deg, p_rhist;
-  int w_stride, w_post, w_status, w_c2v, w_unsat, w_prop, w_bits;
+  // from u_base: sub-graph arrays of fixed size, then the variable part
+  int psyn, rptr, cptr, vdeg, st0, sres0, ppm, pend, pbits;
+  int dyn_base;
+  // from u_base: sub-graph build scratch, above the largest variable part
+  int p_loc, p_iscan, p_llr, p_deg;
 };
+
+__host__ __device__ inline int gdg_align16(int x) { return (x + 15) & ~15; }
+
+// Variable-size sub-graph arrays (offsets from u_base) for e_pad padded CSR
+// edges, col_slots padded column slots and T slot columns.
+struct gdg_dyn_layout {
+  int rvn, cidx, crow, meta, end;
+};
+__host__ __device__ inline gdg_dyn_layout gdg_dyn(int dyn_base, int e_pad, int col_slots, int T) {
+  gdg_dyn_layout d;
+  d.rvn = dyn_base;                                        // [e_pad + 8] u16
+  d.cidx = gdg_align16(d.rvn + 2 * (e_pad + 8));           // [col_slots + 4] u16
+  d.crow = gdg_align16(d.cidx + 2 * (col_slots + 4));      // [col_slots] u16
+  d.meta = gdg_align16(d.crow + 2 * col_slots);            // [T][64] u32
+  d.end = gdg_align16(d.meta + 4 * 64 * T);
+  return d;
+}
+
+// One path wavefront's region (offsets within it) for e_pad padded CSR edges.
+struct gdg_path_layout {
+  int post, status, c2v, unsat, prop, bits, stride;
+};
+__host__ __device__ inline gdg_path_layout gdg_paths(int e_pad, int n_act, int m, int obits_words) {
+  gdg_path_layout p;
+  p.post = 0;                                              // [n_act + 1] f32
+  p.status = gdg_align16(4 * (n_act + 1));                 // [n_act + 1] i8
+  p.c2v = gdg_align16(p.status + n_act + 1);               // [e_pad + 8] f32, also n_act f64
+  const int c2v_bytes = 4 * (e_pad + 8) > 8 * n_act ? 4 * (e_pad + 8) : 8 * n_act;
+  p.unsat = gdg_align16(p.c2v + c2v_bytes);                // [m] u8
+  p.prop = gdg_align16(p.unsat + m);                       // [ceil(n_act / 4)] u32
+  p.bits = gdg_align16(p.prop + 4 * ((n_act + 3) / 4));    // [obits_words] u32
+  p.stride = gdg_align16(p.bits + 4 * obits_words);
+  return p;
+}
 
 struct gdg_trace_dev {
   int* sel;
@@ -108,6 +149,7 @@ struct gdg_learn_dev {
 
 struct gdg_jobs_dev {
   int n_jobs, total;
+  int lds;   // the launch's dynamic LDS bytes
   gdg_job_dev job[kMaxJobs];
   gdg_learn_dev learn;
 };
@@ -115,6 +157,7 @@ struct gdg_jobs_dev {
 hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
                            const gdg_trace_dev& tr, hipStream_t st);
 int gdg_kernel_bucket(int m, int n_act);
+int gdg_decode_waves_per_simd(int bucket, bool learn);   // occupancy the kernel is built for
 hipError_t gdg_decode_set_lds_limit(int bucket, int bytes);
 hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, long long stride,
                          int n_iters, float* post, int* first_ok, hipStream_t st);

@@ -784,32 +784,33 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
                             const uint8_t* __restrict__ syn, const long long syn_stride,
                             uint8_t* __restrict__ ehat, double* __restrict__ pm_out,
                             int* __restrict__ flags_out, const gdg_trace_dev& tr,
-                            const gdg_learn_dev& lrn, unsigned char* smem) {
+                            const gdg_learn_dev& lrn, unsigned char* smem, const int lds_alloc) {
   const gdg_win_dev w = wref;   // uniform: kept in scalar registers, not re-read
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = w.m, n = w.n, n_act = w.n_act;
 
+  // header
   uint8_t* sorig = smem + L.sorig;
-  uint8_t* psyn = smem + L.psyn;                // syndrome in sub-graph row order
   int16_t* sel = (int16_t*)(smem + L.sel);
-  uint16_t* rptr = (uint16_t*)(smem + L.rptr);
-  uint16_t* rvn = (uint16_t*)(smem + L.rvn);
-  uint16_t* cidx = (uint16_t*)(smem + L.cidx);
-  uint16_t* cptr = (uint16_t*)(smem + L.cptr);
-  int8_t* st0 = (int8_t*)(smem + L.st0);
-  uint32_t* sres0 = (uint32_t*)(smem + L.sres0);
-  uint16_t* crow = (uint16_t*)(smem + L.crow);
-  uint32_t* meta = (uint32_t*)(smem + L.meta);
-  uint8_t* vdeg = smem + L.vdeg;                // sub-graph VN degrees (learned proposer)
-  double* ppm = (double*)(smem + L.ppm);
-  int* pend = (int*)(smem + L.pend);
-  uint32_t* pbits = (uint32_t*)(smem + L.pbits);
   int* misc = (int*)(smem + L.misc);            // [0] path counter, [2] answer path
   uint32_t* obits = (uint32_t*)(smem + L.obits);  // window bitmask of the answer
   unsigned long long* eacc = (unsigned long long*)(smem + L.eacc);
+  // after the preprocessing: the sub-graph and the path regions
   unsigned char* U = smem + L.u_base;
+  uint8_t* psyn = U + L.psyn;                   // syndrome in sub-graph row order
+  uint16_t* rptr = (uint16_t*)(U + L.rptr);
+  uint16_t* cptr = (uint16_t*)(U + L.cptr);
+  int8_t* st0 = (int8_t*)(U + L.st0);
+  uint32_t* sres0 = (uint32_t*)(U + L.sres0);
+  uint8_t* vdeg = U + L.vdeg;                   // sub-graph VN degrees (learned proposer)
+  double* ppm = (double*)(U + L.ppm);
+  int* pend = (int*)(U + L.pend);
+  uint32_t* pbits = (uint32_t*)(U + L.pbits);
+  uint16_t *rvn = nullptr, *cidx = nullptr, *crow = nullptr;   // sized per shot
+  uint32_t* meta = nullptr;
+  int path_base = 0;                            // first path region, from u_base
   int* iscan = (int*)(U + L.p_iscan);           // sub-graph build scratch (scans)
   float* sllr = (float*)(U + L.p_llr);
   uint8_t* sdeg = U + L.p_deg;
@@ -1080,6 +1081,14 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     // is flagged instead of decoded
     const int T = min((n_slots + kWave - 1) / kWave, L.meta_cols);
     const int cap = L.meta_cols * kWave;
+    {
+      const gdg_dyn_layout dl = gdg_dyn(L.dyn_base, e_pad, cptr[n_act], T);
+      rvn = (uint16_t*)(U + dl.rvn);
+      cidx = (uint16_t*)(U + dl.cidx);
+      crow = (uint16_t*)(U + dl.crow);
+      meta = (uint32_t*)(U + dl.meta);
+      path_base = dl.end;
+    }
     const uint32_t idle = (uint32_t)(e_pad + kPad);   // the dummy batch
     for (int i = tid; i < T * kWave; i += blockDim.x) meta[i] = idle;
     for (int i = tid; i < kPad; i += blockDim.x) rvn[e_pad + kPad + i] = (uint16_t)(4 * n_act);
@@ -1144,18 +1153,24 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
   const int mode = kLearn ? lrn.mode : 0;
   int fallback = 0;
   {
-    unsigned char* Wb = U + wave * L.w_stride;
+    const int e_pad = rptr[m];
+    const gdg_path_layout pl = gdg_paths(e_pad, n_act, m, L.obits_words);
+    // path wavefronts that fit in this launch's allocation (the LDS plan
+    // guarantees one); the others only join the workgroup's barriers
+    const int nwp = max(1, min((int)(blockDim.x >> 6), (lds_alloc - L.u_base - path_base) / pl.stride));
+    const bool path_wave = wave < nwp;
+    unsigned char* Wb = U + path_base + (path_wave ? wave : 0) * pl.stride;
     PathCtx<VPL> P;
     P.rvn = rvn;
     P.cidx = cidx;
     P.crow = crow;
     P.meta = meta;
-    P.post = (float*)(Wb + L.w_post);
-    P.status = (int8_t*)(Wb + L.w_status);
-    P.c2v = (float*)(Wb + L.w_c2v);
-    P.unsat = Wb + L.w_unsat;
-    P.prop = (uint32_t*)(Wb + L.w_prop);
-    uint32_t* wbits = (uint32_t*)(Wb + L.w_bits);
+    P.post = (float*)(Wb + pl.post);
+    P.status = (int8_t*)(Wb + pl.status);
+    P.c2v = (float*)(Wb + pl.c2v);
+    P.unsat = Wb + pl.unsat;
+    P.prop = (uint32_t*)(Wb + pl.prop);
+    uint32_t* wbits = (uint32_t*)(Wb + pl.bits);
     P.lane = lane;
     P.m = m;
     P.n = n_act;
@@ -1173,12 +1188,13 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     }
     // the sub-graph build scratch (sllr, sdeg) shares LDS with the path regions
     __syncthreads();
-    for (int i = lane; i < (n_act + 3) / 4; i += kWave) P.prop[i] = 0u;
-    if (lane == 0) {
-      P.post[n_act] = kInfF;   // dummy VN of the row padding
-      P.status[n_act] = 0;
+    if (path_wave) {
+      for (int i = lane; i < (n_act + 3) / 4; i += kWave) P.prop[i] = 0u;
+      if (lane == 0) {
+        P.post[n_act] = kInfF;   // dummy VN of the row padding
+        P.status[n_act] = 0;
+      }
     }
-    const int e_pad = rptr[m];
     // this wavefront's posterior history ring (learned proposer): slot j holds
     // the posteriors of BP iteration t with (t - 1) mod 16 = j
     float* const ring = mode ? lrn.ring + ((long long)blockIdx.x * (blockDim.x >> 6) + wave) *
@@ -1215,7 +1231,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       }
       const bool learned = run == 0 && mode == 1;
       const int n_run = learned ? (1 << lrn.guesses) : w.n_paths;
-      for (;;) {
+      while (path_wave) {
         // paths are taken in decreasing id: the later paths of the tree
         // deviate more often and run longer, so starting them first leaves
         // the short ones to fill the end
@@ -1596,8 +1612,14 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
 // table; item i belongs to the job whose first item is the largest <= i. Jobs
 // may use windows of different codes (sizes): each job carries its own LDS
 // layout within the launch's allocation.
+// Register budget: three wavefronts per SIMD for the plain kernel with up to 7
+// VNs per lane (168 VGPRs; spills stay outside the BP loops), two otherwise.
 template <int VPL, bool kLearn>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) void gdg_decode_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
+constexpr int kDecodeWavesPerSimd = (!kLearn && VPL <= 7) ? 3 : 2;
+
+template <int VPL, bool kLearn>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
+    kDecodeWavesPerSimd<VPL, kLearn>, kDecodeWavesPerSimd<VPL, kLearn>))) void gdg_decode_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int item = blockIdx.x; item < J.total; item += gridDim.x) {
     // pick the job with static indices only (no dynamic indexing of kernel arguments)
@@ -1606,7 +1628,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     for (int t = 1; t < kMaxJobs; ++t)
       if (t < J.n_jobs && item >= J.job[t].item0) jb = J.job[t];
     decode_shot<VPL, kLearn>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat, jb.pm,
-                     jb.flags, tr, J.learn, smem);
+                             jb.flags, tr, J.learn, smem, J.lds);
     __syncthreads();
   }
 }
@@ -1824,6 +1846,15 @@ hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int gri
   GDG_DECODE_TILINGS(GDG_LAUNCH)
 #undef GDG_LAUNCH
   return hipErrorInvalidValue;
+}
+
+int gdg_decode_waves_per_simd(int bucket, bool learn) {
+  int b = 0, r = 2;
+#define GDG_WPS(V) \
+  if (b++ == bucket) r = learn ? kDecodeWavesPerSimd<V, true> : kDecodeWavesPerSimd<V, false>;
+  GDG_DECODE_TILINGS(GDG_WPS)
+#undef GDG_WPS
+  return r;
 }
 
 int gdg_kernel_bucket(int m, int n_act) {
