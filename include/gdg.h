@@ -87,7 +87,8 @@ typedef struct gdg_window_info {
   int32_t max_sub_edges;    /* bound on edges of a truncated sub-graph */
   int32_t n_commit;         /* committed columns */
   int32_t last;             /* 1 for the final window (commits everything) */
-  int32_t lds_bytes;        /* LDS per workgroup of the decode kernel */
+  int32_t lds_bytes;        /* least LDS per workgroup of the decode kernel (a launch
+                               allocates up to its CU share at full occupancy) */
   int32_t waves;            /* wavefronts per workgroup of the decode kernel */
 } gdg_window_info;
 
@@ -191,7 +192,9 @@ typedef struct gdg_launch_cfg {
 int gdg_decode_jobs(const gdg_job* jobs, int32_t n_jobs, const gdg_launch_cfg* cfg,
                     void* hip_stream);
 
-/* LDS bytes per workgroup the jobs need at `waves` wavefronts (negative on error). */
+/* Least LDS bytes per workgroup the jobs need at `waves` wavefronts (negative on
+ * error); a launch allocates up to the CU's share at the kernel's occupancy, and
+ * each shot uses as many path wavefronts as fit in it. */
 int gdg_jobs_lds_bytes(const gdg_job* jobs, int32_t n_jobs, int32_t waves);
 
 /*

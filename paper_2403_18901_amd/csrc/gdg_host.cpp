@@ -243,7 +243,9 @@ bool full_layout(int m, int n, const std::vector<int>& row_ptr, const std::vecto
   for (int c = 0; c < n; ++c) F.cptr[c + 1] = F.cptr[c] + (col_ptr[c + 1] - col_ptr[c] + 3) / 4 * 4;
   F.cidx.assign(std::max(F.cptr[n], 4), (uint16_t)(4 * epad));   // padding: the zero message
   F.rvn.assign(epad + 8, (uint16_t)(4 * n));                        // padding: the dummy VN
-  F.meta.assign((size_t)F.T * 64, (uint32_t)(epad + 4));             // idle lanes: the dummy batch
+  // idle lanes point at the dummy batch; 3 idle columns per wavefront (up to 8)
+  // past the end take the loads the CN walk issues ahead of its last slots
+  F.meta.assign((size_t)(F.T + 3 * 8) * 64, (uint32_t)(epad + 4));
   int g = 0;
   for (int pj = 0; pj < m; ++pj) {
     const int j = order[pj];

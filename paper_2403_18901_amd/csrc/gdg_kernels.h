@@ -65,8 +65,8 @@ __host__ __device__ inline gdg_dyn_layout gdg_dyn(int dyn_base, int e_pad, int c
   d.rvn = dyn_base;                                        // [e_pad + 8] u16
   d.cidx = gdg_align16(d.rvn + 2 * (e_pad + 8));           // [col_slots + 4] u16
   d.crow = gdg_align16(d.cidx + 2 * (col_slots + 4));      // [col_slots] u16
-  d.meta = gdg_align16(d.crow + 2 * col_slots);            // [T][64] u32
-  d.end = gdg_align16(d.meta + 4 * 64 * T);
+  d.meta = gdg_align16(d.crow + 2 * col_slots);            // [T + 3][64] u32
+  d.end = gdg_align16(d.meta + 4 * 64 * (T + 3));
   return d;
 }
 

@@ -386,18 +386,31 @@ __device__ __forceinline__ void cn_merge(CnAcc& a) {
   a.hp ^= dpp<CTRL>(a.hp);
 }
 
+// The steps nest: a step no lane of the wavefront needs ends the sequence.
 __device__ __forceinline__ void cn_group(CnAcc& a, int lk) {
-  if (lk > 0) cn_merge<kDppXor1>(a);
-  if (lk > 1) cn_merge<kDppXor2>(a);
-  if (lk > 2) cn_merge<kDppHalfMirror>(a);
-  if (lk > 3) cn_merge<kDppMirror>(a);
+  if (lk > 0) {
+    cn_merge<kDppXor1>(a);
+    if (lk > 1) {
+      cn_merge<kDppXor2>(a);
+      if (lk > 2) {
+        cn_merge<kDppHalfMirror>(a);
+        if (lk > 3) cn_merge<kDppMirror>(a);
+      }
+    }
+  }
 }
 
 __device__ __forceinline__ void hp_group(uint32_t& hp, int lk) {
-  if (lk > 0) hp ^= dpp<kDppXor1>(hp);
-  if (lk > 1) hp ^= dpp<kDppXor2>(hp);
-  if (lk > 2) hp ^= dpp<kDppHalfMirror>(hp);
-  if (lk > 3) hp ^= dpp<kDppMirror>(hp);
+  if (lk > 0) {
+    hp ^= dpp<kDppXor1>(hp);
+    if (lk > 1) {
+      hp ^= dpp<kDppXor2>(hp);
+      if (lk > 2) {
+        hp ^= dpp<kDppHalfMirror>(hp);
+        if (lk > 3) hp ^= dpp<kDppMirror>(hp);
+      }
+    }
+  }
 }
 
 template <int CTRL>
@@ -416,11 +429,6 @@ __device__ __forceinline__ uint32_t xor_sign(uint32_t a, uint32_t b) {
   return __builtin_amdgcn_bitop3_b32(a, b, 0x80000000u, 0x28);
 }
 
-__device__ __forceinline__ uint32_t med3_bits(uint32_t a, uint32_t b, uint32_t c) {
-  return __float_as_uint(
-      __builtin_amdgcn_fmed3f(__uint_as_float(a), __uint_as_float(b), __uint_as_float(c)));
-}
-
 __device__ __forceinline__ const float& at_byte(const float* base, uint32_t off) {
   return *(const float*)((const char*)base + off);
 }
@@ -429,7 +437,9 @@ __device__ __forceinline__ const float& at_byte(const float* base, uint32_t off)
 // work: while slot t is computed, slot t + 1's gathers (posteriors or
 // statuses), slot t + 2's edges (and previous messages) and slot t + 3's
 // metadata are in flight. Four rotating slots, unrolled by hand so that the
-// rotation is a renaming; slots past the last one re-read the last one. In the
+// rotation is a renaming; the slot table has three idle columns past its
+// end (and past every wavefront's share of the whole-window table) for the
+// loads issued ahead of the last slots. In the
 // CN phase, reading a later slot's previous messages before slot t writes its
 // own is safe: batches are disjoint except the dummy batch, whose messages
 // only need to be finite. Returns the OR of the per-slot results.
@@ -449,7 +459,7 @@ __device__ __forceinline__ void slot_edges(const PathCtx<VPL>& P, Slot& s) {
 
 template <int VPL>
 __device__ __forceinline__ void slot_meta(const PathCtx<VPL>& P, Slot& s, int t) {
-  s.mt = P.meta[(P.t0 + min(t, P.T - 1) * P.tstride) * kWave + P.lane];
+  s.mt = P.meta[(P.t0 + t * P.tstride) * kWave + P.lane];
 }
 
 template <int VPL, bool OV, typename Gather, typename Compute>
@@ -513,10 +523,16 @@ __device__ __forceinline__ void cn_recount(PathCtx<VPL>& P, bool& dead, bool& pr
         only = s1 < 0 ? v1 : only;
         only = s2 < 0 ? v2 : only;
         only = s3 < 0 ? v3 : only;
-        if (lk > 0) cnt_merge<kDppXor1>(cnt, x, only);
-        if (lk > 1) cnt_merge<kDppXor2>(cnt, x, only);
-        if (lk > 2) cnt_merge<kDppHalfMirror>(cnt, x, only);
-        if (lk > 3) cnt_merge<kDppMirror>(cnt, x, only);
+        if (lk > 0) {
+          cnt_merge<kDppXor1>(cnt, x, only);
+          if (lk > 1) {
+            cnt_merge<kDppXor2>(cnt, x, only);
+            if (lk > 2) {
+              cnt_merge<kDppHalfMirror>(cnt, x, only);
+              if (lk > 3) cnt_merge<kDppMirror>(cnt, x, only);
+            }
+          }
+        }
         const int r = (x ^ ((mt & kMetaSyn) ? 1 : 0)) & 1;
         if (mt & kMetaValid) {
           sres |= (uint32_t)r << t;
@@ -613,30 +629,34 @@ __device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const Slot& c, int t, fl
   const float x3 = clip_to(__uint_as_float(c.g.w) - c.ov.w, clip);
   const uint32_t b0 = __float_as_uint(x0), b1 = __float_as_uint(x1);
   const uint32_t b2 = __float_as_uint(x2), b3 = __float_as_uint(x3);
-  const uint32_t m0 = b0 & ~kSign, m1 = b1 & ~kSign, m2 = b2 & ~kSign, m3 = b3 & ~kSign;
-  // two smallest of four: inserting m into n1 <= n2 gives min(n1, m) and the
-  // median of {n1, n2, m}; the magnitudes are non-negative floats, so the
-  // float median orders them as their bit patterns do
-  CnAcc a;
-  a.n1 = min(m0, m1);
-  a.n2 = max(m0, m1);
-  a.n2 = med3_bits(a.n1, a.n2, m2);
-  a.n1 = min(a.n1, m2);
-  a.n2 = med3_bits(a.n1, a.n2, m3);
-  a.n1 = min(a.n1, m3);
+  const float a0 = fabsf(x0), a1 = fabsf(x1), a2 = fabsf(x2), a3 = fabsf(x3);
+  // two smallest of four magnitudes: inserting a into n1 <= n2 gives min(n1, a)
+  // and the median of {n1, n2, a}; as the magnitudes lie in [0, clip], min and
+  // max are medians with -clip and clip (three-operand medians take the
+  // absolute values as operand modifiers)
+  float f1 = __builtin_amdgcn_fmed3f(a0, a1, -clip);
+  float f2 = __builtin_amdgcn_fmed3f(a0, a1, clip);
+  f2 = __builtin_amdgcn_fmed3f(f1, f2, a2);
+  f1 = __builtin_amdgcn_fmed3f(f1, a2, -clip);
+  f2 = __builtin_amdgcn_fmed3f(f1, f2, a3);
+  f1 = __builtin_amdgcn_fmed3f(f1, a3, -clip);
+  CnAcc a;   // non-negative floats order like their bit patterns
+  a.n1 = __float_as_uint(f1);
+  a.n2 = __float_as_uint(f2);
   // parities of the message signs and of the hard decisions, kept in bit 31
   a.sp = xor_sign(xor3(b0, b1, b2), b3);
   a.hp = xor_sign(xor3(c.g.x, c.g.y, c.g.z), c.g.w);
   cn_group(a, lk);
-  const uint32_t srow = (P.sres << (31 - t)) & kSign;   // residual syndrome bit of the row
+  const uint32_t srow = (P.sres >> t) << 31;   // residual syndrome bit of the row
   const uint32_t sgn = a.sp ^ srow;
-  const uint32_t s1 = __float_as_uint(alpha * __uint_as_float(a.n1)) | sgn;
+  const float n1 = __uint_as_float(a.n1);
+  const uint32_t s1 = __float_as_uint(alpha * n1) | sgn;
   const uint32_t s2 = __float_as_uint(alpha * __uint_as_float(a.n2)) | sgn;
   float4 nv;
-  nv.x = __uint_as_float((m0 == a.n1 ? s2 : s1) ^ (b0 & kSign));
-  nv.y = __uint_as_float((m1 == a.n1 ? s2 : s1) ^ (b1 & kSign));
-  nv.z = __uint_as_float((m2 == a.n1 ? s2 : s1) ^ (b2 & kSign));
-  nv.w = __uint_as_float((m3 == a.n1 ? s2 : s1) ^ (b3 & kSign));
+  nv.x = __uint_as_float((a0 == n1 ? s2 : s1) ^ (b0 & kSign));
+  nv.y = __uint_as_float((a1 == n1 ? s2 : s1) ^ (b1 & kSign));
+  nv.z = __uint_as_float((a2 == n1 ? s2 : s1) ^ (b2 & kSign));
+  nv.w = __uint_as_float((a3 == n1 ? s2 : s1) ^ (b3 & kSign));
   *(float4*)(P.c2v + e0) = nv;
   return (int)(srow ^ a.hp);   // bit 31: the row is unsatisfied
 }
@@ -1090,7 +1110,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       path_base = dl.end;
     }
     const uint32_t idle = (uint32_t)(e_pad + kPad);   // the dummy batch
-    for (int i = tid; i < T * kWave; i += blockDim.x) meta[i] = idle;
+    for (int i = tid; i < (T + 3) * kWave; i += blockDim.x) meta[i] = idle;   // + 3 idle columns
     for (int i = tid; i < kPad; i += blockDim.x) rvn[e_pad + kPad + i] = (uint16_t)(4 * n_act);
     __syncthreads();
     for (int pj = tid; pj < m; pj += blockDim.x) {
