@@ -362,6 +362,7 @@ struct PathCtx {
   int lane, m, n, T;
   int t0 = 0, tstride = 1;   // slot column i of this walk is table column t0 + i * tstride
   uint32_t sres;          // bit t: residual syndrome of the row in slot column t
+  int act_edges;          // edges of this lane's active VNs
   // VN registers
   uint32_t vinfo[VPL];   // first column slot | degree << 16 | (status + 1) << 24
   float llr[VPL];
@@ -558,6 +559,7 @@ __device__ __forceinline__ void cn_recount(PathCtx<VPL>& P, bool& dead, bool& pr
 template <int VPL>
 __device__ __forceinline__ void set_status(PathCtx<VPL>& P, int r, int v, int value) {
   P.set_st(r, value);
+  P.act_edges -= P.vdg(r);
   P.status[v] = (int8_t)value;
   P.post[v] = kInfF;
 }
@@ -703,8 +705,11 @@ __device__ __forceinline__ int check_pass(PathCtx<VPL>& P, bool write_unsat) {
 // the loads (index loads, then message loads), so that their LDS latencies
 // overlap: the fifth index is read for every VN -- the column slot table keeps
 // four readable entries past its end -- and its message added only to VNs of
-// degree above four. VNs of degree above five take a loop. Returns the number
-// of edges of the active VNs.
+// degree above four. VNs of degree above five take a loop. The sum is formed
+// negated, t = -L - m1 - m2 - ..., in the same order: round-to-nearest is
+// symmetric, so -t is the sum exactly, and an exact zero (t = +0) comes out as
+// -0 -- the sign bit is then the hard decision of Eq. 4. Returns the number of
+// edges of the active VNs.
 template <int VPL>
 __device__ __forceinline__ int vn_phase(PathCtx<VPL>& P, bool hist, float* ring_slot) {
   uint2 ix[VPL];
@@ -725,28 +730,26 @@ __device__ __forceinline__ int vn_phase(PathCtx<VPL>& P, bool hist, float* ring_
     g[r][4] = at_byte(P.c2v, ix5[r]);
   }
   __builtin_amdgcn_sched_barrier(0);
-  float s[VPL];
+  float t[VPL];
   bool deep = false;
 #pragma unroll
   for (int r = 0; r < VPL; ++r) {
-    const float s4 = (((P.llr[r] + g[r][0]) + g[r][1]) + g[r][2]) + g[r][3];
-    s[r] = P.vdg(r) > 4 ? s4 + g[r][4] : s4;
+    const float t4 = (((-P.llr[r] - g[r][0]) - g[r][1]) - g[r][2]) - g[r][3];
+    t[r] = P.vdg(r) > 4 ? t4 - g[r][4] : t4;
     deep |= P.vdg(r) > 5;
   }
   if (wave_any(deep)) {
 #pragma unroll
     for (int r = 0; r < VPL; ++r)
-      for (int k = 5; k < P.vdg(r); ++k) s[r] += at_byte(P.c2v, P.cidx[P.vc0(r) + k]);
+      for (int k = 5; k < P.vdg(r); ++k) t[r] -= at_byte(P.c2v, P.cidx[P.vc0(r) + k]);
   }
-  int edges = 0;
 #pragma unroll
   for (int r = 0; r < VPL; ++r) {
     const int v = P.lane + kWave * r;
     if (v < P.n && P.st(r) < 0) {
-      const float x = s[r] == 0.0f ? -0.0f : s[r];   // sign bit = hard decision
+      const float x = __uint_as_float(__float_as_uint(t[r]) ^ 0x80000000u);   // -t, -0 for +0
       P.post[v] = x;
       if (ring_slot) ring_slot[v] = x;
-      edges += P.vdg(r);
       if (hist) {
         // min and max as medians with -inf and +inf: no NaN reaches here
         P.hs[r] += x;
@@ -755,7 +758,7 @@ __device__ __forceinline__ int vn_phase(PathCtx<VPL>& P, bool hist, float* ring_
       }
     }
   }
-  return edges;
+  return P.act_edges;
 }
 
 // VN phase of the whole-window BP: posteriors (Eq. 2) of the workgroup's VNs,
@@ -1225,6 +1228,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     // shot's syndrome and sub-graph: wavefront 0 runs it once and every path
     // starts from its result.
     if (wave == 0) {
+      P.act_edges = 0;
 #pragma unroll
       for (int r = 0; r < VPL; ++r) {
         const int v = lane + kWave * r;
@@ -1288,6 +1292,8 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           const int v = lane + kWave * r;
           const int st = v < n_act ? (int)st0[v] : -1;
           P.set_st(r, st);
+          if (r == 0) P.act_edges = 0;
+          if (v < n_act && st < 0) P.act_edges += P.vdg(r);
           if (v < n_act) {
             P.status[v] = (int8_t)st;
             P.post[v] = st < 0 ? P.llr[r] : kInfF;
