@@ -448,6 +448,21 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
     if ((rc = win->put(F.rvn, &D.fr_rvn))) return rc;
     if ((rc = win->put(F.cidx, &D.fr_cidx))) return rc;
     if ((rc = win->put(F.cptr, &D.fr_cptr))) return rc;
+    std::vector<uint32_t> vrec(4 * (size_t)n);
+    const uint32_t zero = (uint32_t)(4 * F.epad);
+    for (int c = 0; c < n; ++c) {
+      const int c0 = F.cptr[c], d = deg[c];
+      auto slot = [&](int k) { return k < d ? (uint32_t)F.cidx[c0 + k] : zero; };
+      vrec[4 * c + 0] = slot(0) | slot(1) << 16;
+      vrec[4 * c + 1] = slot(2) | slot(3) << 16;
+      vrec[4 * c + 2] = slot(4) | (uint32_t)d << 16;
+      uint32_t lb;
+      std::memcpy(&lb, &llr[c], 4);
+      vrec[4 * c + 3] = lb;
+    }
+    const uint32_t* vp = nullptr;
+    if ((rc = win->put(vrec, &vp))) return rc;
+    D.fr_vrec = reinterpret_cast<const uint4*>(vp);
   }
 
   // commit tables

@@ -29,6 +29,10 @@ struct gdg_win_dev {
   const uint16_t* fr_rvn;   // [fr_epad + 8] 4 * column of each padded CSR edge
   const uint16_t* fr_cidx;  // [padded column slots] 4 * CSR position (padding: 4 * fr_epad)
   const int* fr_cptr;       // [n + 1] first column slot
+  // per VN, one 16-byte record for the preprocessing VN pass: the message
+  // offsets of its first four column slots (u16 each), the fifth's (the zero
+  // message below degree five) | degree << 16, the prior's float bits
+  const uint4* fr_vrec;     // [n]
 };
 
 // Byte offsets of the decode kernel's dynamic LDS regions. A header lives for

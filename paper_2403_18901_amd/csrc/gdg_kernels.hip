@@ -763,37 +763,46 @@ __device__ __forceinline__ int vn_phase(PathCtx<VPL>& P, bool hist, float* ring_
 
 // VN phase of the whole-window BP: posteriors (Eq. 2) of the workgroup's VNs,
 // summed in column-slot order (padding adds the zero message), exact zeros
-// stored as -0 (sign bit = hard decision), plus the running sum of the last
-// iterations when lsum is given. Four VNs per thread per round, their index
-// and message loads issued together.
+// stored as -0 (sign bit = hard decision; the sum is formed negated as in
+// vn_phase), plus the running sum of the last iterations when lsum is given.
+// Four VNs per thread per round: one 16-byte record load each (first five
+// message offsets, degree, prior), then all their message loads together.
 __device__ __forceinline__ void full_vn_pass(const gdg_win_dev& w, float* post, const float* c2v,
                                              float* lsum) {
   const int n = w.n, bs = blockDim.x;
   for (int v0 = threadIdx.x; v0 < n; v0 += 4 * bs) {
-    int c0[4], dg[4];
-    uint2 ix[4];
+    uint4 rc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rc[j] = w.fr_vrec[min(v0 + j * bs, n - 1)];
+    float g[4][5];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int v = min(v0 + j * bs, n - 1);
-      c0[j] = w.fr_cptr[v];
-      dg[j] = w.deg[v];
+      g[j][0] = at_byte(c2v, rc[j].x & 0xffffu);
+      g[j][1] = at_byte(c2v, rc[j].x >> 16);
+      g[j][2] = at_byte(c2v, rc[j].y & 0xffffu);
+      g[j][3] = at_byte(c2v, rc[j].y >> 16);
+      g[j][4] = at_byte(c2v, rc[j].z & 0xffffu);
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) ix[j] = *(const uint2*)(w.fr_cidx + c0[j]);
-    float s[4];
+    float t[4];
+    bool deep = false;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int v = min(v0 + j * bs, n - 1);
-      const float g0 = at_byte(c2v, ix[j].x & 0xffffu), g1 = at_byte(c2v, ix[j].x >> 16);
-      const float g2 = at_byte(c2v, ix[j].y & 0xffffu), g3 = at_byte(c2v, ix[j].y >> 16);
-      s[j] = (((w.llr[v] + g0) + g1) + g2) + g3;
+      t[j] = ((((-__uint_as_float(rc[j].w) - g[j][0]) - g[j][1]) - g[j][2]) - g[j][3]) - g[j][4];
+      deep |= (rc[j].z >> 16) > 5;
+    }
+    if (wave_any(deep)) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int v = min(v0 + j * bs, n - 1);
+        const int dg = rc[j].z >> 16;
+        for (int k = 5; k < dg; ++k) t[j] -= at_byte(c2v, w.fr_cidx[w.fr_cptr[v] + k]);
+      }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int v = v0 + j * bs;
       if (v >= n) continue;
-      for (int k = 4; k < dg[j]; ++k) s[j] += at_byte(c2v, w.fr_cidx[c0[j] + k]);
-      const float x = s[j] == 0.0f ? -0.0f : s[j];
+      const float x = __uint_as_float(__float_as_uint(t[j]) ^ 0x80000000u);
       post[v] = x;
       if (lsum) lsum[v] += x;
     }
