@@ -130,7 +130,8 @@ size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots);
  *             3 contradiction, 4 no eligible VN) and steps taken
  *  first_post [n_shots][n_act] float: main-path posteriors after its first
  *             step (NaN for decimated VNs)
- *  edge_iters [n_shots] int64: active edges summed over all BP iterations
+ *  edge_iters [n_shots] int64: active edges summed over the BP iterations run
+ *             (paths of Fig. 2's tree share their iterations until they split)
  *  step_lsum  [n_shots][n_paths][log_cap][n_act] float: each VN's sum of its
  *             last four posteriors at the end of every step's BP run (the
  *             Alg. 1 key), NaN for decimated VNs and unused steps

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -147,7 +148,7 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   L.meta_cols = tcols;
   L.sorig = take(m);
   L.sel = take(2 * na);
-  L.misc = take(32);
+  L.misc = take(64);
   L.obits = take(4 * L.obits_words);
   L.eacc = take(8);
   L.u_base = off;
@@ -187,6 +188,8 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   L.ppm = stake(8 * P);
   L.pend = stake(4 * P);
   L.pbits = stake(4 * P * L.pbits_words);
+  L.tq = stake(4 * 8 * P);    // path task queue: 8 ints per task
+  L.tready = stake(4 * P);
   L.dyn_base = so;
   const gdg_dyn_layout worst = gdg_dyn(L.dyn_base, e_pad_max, col_slots, tcols);
   // sub-graph build scratch above the largest variable part
@@ -291,6 +294,61 @@ int max_lds_per_block() {
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return 65536;
   return v > 0 ? v : 65536;
+}
+
+int cu_count() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+  return v > 0 ? v : 1;
+}
+
+// Device scratch of the decode launches on one stream: the shot counter of the
+// persistent grid and the path checkpoints. Launches on one stream run in
+// order, so they can share it; it grows on demand and lives until the process
+// ends.
+struct StreamScratch {
+  int dev = 0;
+  hipStream_t st = nullptr;
+  int* ctr = nullptr;
+  char* ckpt = nullptr;
+  size_t ckpt_bytes = 0;
+};
+std::mutex g_scratch_mu;
+std::vector<StreamScratch> g_scratch;
+
+int stream_scratch(hipStream_t st, size_t ckpt_bytes, StreamScratch* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  StreamScratch* s = nullptr;
+  for (StreamScratch& x : g_scratch)
+    if (x.dev == dev && x.st == st) s = &x;
+  if (!s) {
+    g_scratch.push_back(StreamScratch{});
+    s = &g_scratch.back();
+    s->dev = dev;
+    s->st = st;
+  }
+  if (!s->ctr) {
+    e = hipMalloc((void**)&s->ctr, 256);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (shot counter)");
+  }
+  if (ckpt_bytes > s->ckpt_bytes) {
+    if (s->ckpt) {
+      e = hipStreamSynchronize(st);   // earlier launches may still use the old block
+      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+      (void)hipFree(s->ckpt);
+      s->ckpt = nullptr;
+      s->ckpt_bytes = 0;
+    }
+    e = hipMalloc((void**)&s->ckpt, ckpt_bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (path checkpoints)");
+    s->ckpt_bytes = ckpt_bytes;
+  }
+  *out = *s;
+  return GDG_OK;
 }
 
 int lds_per_cu() {
@@ -624,8 +682,32 @@ int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
     g_lds_set[bucket] = lds;
   }
-  const int grid = workgroups > 0 ? std::min(workgroups, total) : total;
-  hipError_t e = gdg_launch_jobs(J, bucket, waves, grid, lds, tr, st);
+  // Persistent grid at the resident workgroup count (or the caller's count):
+  // workgroups take shots from a counter, and each owns the checkpoints where
+  // its paths' decision tree splits.
+  const int by_lds = std::max(1, lds_per_cu() / ((lds + 2047) / 2048 * 2048));
+  const int by_waves = std::max(1, 4 * wps / waves);
+  const int resident = std::min(by_lds, by_waves) * cu_count();
+  const int grid = workgroups > 0 ? std::min(workgroups, total) : std::min(total, resident);
+  long long stride = 0;
+  int slots = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const gdg_window* win = jobs[j].win;
+    const int n_tree = win->dev.g > 0 ? 1 << win->dev.g : 1;
+    slots = std::max(slots, n_tree - 1);
+    const int e_pad_max = win->max_sub + 3 * win->dev.m;
+    stride = std::max(stride, (long long)(gdg_ck(win->dev.n_act, e_pad_max).bytes + 255) / 256 * 256);
+  }
+  StreamScratch sc;
+  int rc = stream_scratch(st, slots > 0 ? (size_t)grid * slots * stride : 256, &sc);
+  if (rc) return rc;
+  J.work = sc.ctr;
+  J.ckpt = slots > 0 ? sc.ckpt : nullptr;
+  J.ckpt_stride = stride;
+  J.ckpt_slots = slots;
+  hipError_t e = gdg_launch_zero(sc.ctr, 1, st);
+  if (e != hipSuccess) return hip_fail(e, "counter reset");
+  e = gdg_launch_jobs(J, bucket, waves, grid, lds, tr, st);
   if (e != hipSuccess) return hip_fail(e, "decode launch");
   return GDG_OK;
 }

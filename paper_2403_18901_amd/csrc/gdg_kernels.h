@@ -51,7 +51,7 @@ struct gdg_lds {
   // from u_base: preprocessing and ranking
   int p_post, p_c2v, p_lsum, p_keys, sort_n;
   // from u_base: sub-graph arrays of fixed size, then the variable part
-  int psyn, rptr, cptr, vdeg, st0, sres0, ppm, pend, pbits;
+  int psyn, rptr, cptr, vdeg, st0, sres0, ppm, pend, pbits, tq, tready;
   int dyn_base;
   // from u_base: sub-graph build scratch, above the largest variable part
   int p_loc, p_iscan, p_llr, p_deg;
@@ -151,13 +151,33 @@ struct gdg_learn_dev {
   int* rec_fav;      // [n_shots][rec_steps][16] favoured value
 };
 
+// A path checkpoint (global memory): the state of a decision path where the
+// tree splits, so that one branch continues and the other restarts from it.
+struct gdg_ck_layout {
+  int post, status, c2v, sres, bytes;
+};
+__host__ __device__ inline gdg_ck_layout gdg_ck(int n_act, int e_pad) {
+  gdg_ck_layout c;
+  c.post = 0;                                           // [n_act + 1] f32
+  c.status = gdg_align16(4 * (n_act + 1));              // [n_act + 1] i8
+  c.c2v = gdg_align16(c.status + n_act + 1);            // [e_pad + 8] f32
+  c.sres = gdg_align16(c.c2v + 4 * (e_pad + 8));        // [64] u32
+  c.bytes = c.sres + 4 * 64;
+  return c;
+}
+
 struct gdg_jobs_dev {
   int n_jobs, total;
   int lds;   // the launch's dynamic LDS bytes
+  int* work;             // shot counter of a persistent launch (zeroed), or null: grid stride
+  char* ckpt;            // path checkpoints: [gridDim.x][ckpt_slots] of ckpt_stride bytes, or null
+  long long ckpt_stride;
+  int ckpt_slots;
   gdg_job_dev job[kMaxJobs];
   gdg_learn_dev learn;
 };
 
+hipError_t gdg_launch_zero(int* p, int n, hipStream_t st);
 hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
                            const gdg_trace_dev& tr, hipStream_t st);
 int gdg_kernel_bucket(int m, int n_act);

@@ -809,6 +809,17 @@ __device__ __forceinline__ void full_vn_pass(const gdg_win_dev& w, float* post, 
   }
 }
 
+// Path checkpoint copies (whole 16-byte words; the regions are padded to 16).
+__device__ __forceinline__ void ck_copy(void* dst, const uint4* src, int bytes, int lane) {
+  uint4* d = (uint4*)dst;
+  for (int i = lane; i < (bytes + 15) / 16; i += kWave) d[i] = src[i];
+}
+
+__device__ __forceinline__ void ck_save(uint4* dst, const void* src, int bytes, int lane) {
+  const uint4* q = (const uint4*)src;
+  for (int i = lane; i < (bytes + 15) / 16; i += kWave) dst[i] = q[i];
+}
+
 // Decodes shot `shot` of one window with the whole workgroup. Every thread
 // enters and leaves together; the caller synchronises before the LDS is reused.
 template <int VPL, bool kLearn>
@@ -816,7 +827,8 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
                             const uint8_t* __restrict__ syn, const long long syn_stride,
                             uint8_t* __restrict__ ehat, double* __restrict__ pm_out,
                             int* __restrict__ flags_out, const gdg_trace_dev& tr,
-                            const gdg_learn_dev& lrn, unsigned char* smem, const int lds_alloc) {
+                            const gdg_learn_dev& lrn, unsigned char* smem, const int lds_alloc,
+                            char* const ck, const long long ck_stride) {
   const gdg_win_dev w = wref;   // uniform: kept in scalar registers, not re-read
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -840,6 +852,8 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
   double* ppm = (double*)(U + L.ppm);
   int* pend = (int*)(U + L.pend);
   uint32_t* pbits = (uint32_t*)(U + L.pbits);
+  int* tq = (int*)(U + L.tq);                   // path tasks, 8 ints each
+  int* tready = (int*)(U + L.tready);           // task pushed
   uint16_t *rvn = nullptr, *cidx = nullptr, *crow = nullptr;   // sized per shot
   uint32_t* meta = nullptr;
   int path_base = 0;                            // first path region, from u_base
@@ -1264,14 +1278,74 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       }
       const bool learned = run == 0 && mode == 1;
       const int n_run = learned ? (1 << lrn.guesses) : w.n_paths;
+      // Path tasks. A task is a range [lo, lo + size) of paths that share one
+      // state up to depth d0 - 1 (the representative, path lo, stands for all
+      // of them), starting fresh (d0 = 1) or from a checkpoint that the task's
+      // parent left where Fig. 2's tree split: there the paths of the parent's
+      // range whose bit for that depth is 1 take the other value of the
+      // pending decision (gsel, val). Replaying a path from the root gives the
+      // same state, messages included, so sharing changes no result. Learned
+      // paths run one per task.
+      const int n_tree = w.g > 0 ? 1 << w.g : 1;
+      const bool share = !learned && ck != nullptr && n_tree > 1;
+      if (tid == 0) {
+        int nt = 0;
+        auto push0 = [&](int plo, int psize) {
+          int* t = tq + 8 * nt;
+          t[0] = plo;
+          t[1] = psize;
+          t[2] = 1;
+          t[3] = -1;
+          t[4] = 0;
+          t[5] = -1;
+          t[6] = 0;
+          t[7] = 0;
+          tready[nt++] = 1;
+        };
+        if (share) {
+          push0(0, n_tree);
+          for (int p = n_run - 1; p >= n_tree; --p) push0(p, 1);   // side branches
+        } else {
+          // decreasing id: the later paths of the tree deviate more often and
+          // run longer, so starting them first leaves the short ones to the end
+          for (int p = n_run - 1; p >= 0; --p) push0(p, 1);
+        }
+        for (int t = nt; t < w.n_paths; ++t) tready[t] = 0;
+        misc[0] = 0;    // tasks claimed
+        misc[1] = nt;   // tasks pushed
+        misc[8] = 0;    // paths finished
+        misc[9] = 0;    // checkpoints taken
+      }
+      __syncthreads();
       while (path_wave) {
-        // paths are taken in decreasing id: the later paths of the tree
-        // deviate more often and run longer, so starting them first leaves
-        // the short ones to fill the end
-        int pid = 0;
-        if (lane == 0) pid = n_run - 1 - atomicAdd(&misc[0], 1);
-        pid = __builtin_amdgcn_readfirstlane(pid);
-        if (pid < 0) break;
+        // claim the next task; wait for it to be pushed, or for every path to
+        // finish (a claim past the last task)
+        int ti = 0;
+        if (lane == 0) ti = atomicAdd(&misc[0], 1);
+        ti = __builtin_amdgcn_readfirstlane(ti);
+        bool have = false;
+        for (;;) {
+          int rd = 0, fin = 0;
+          if (lane == 0) {
+            rd = ti < w.n_paths
+                     ? __hip_atomic_load(&tready[ti], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)
+                     : 0;
+            fin = __hip_atomic_load(&misc[8], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+          rd = __builtin_amdgcn_readfirstlane(rd);
+          fin = __builtin_amdgcn_readfirstlane(fin);
+          if (rd) {
+            have = true;
+            break;
+          }
+          if (fin >= n_run) break;
+          __builtin_amdgcn_s_sleep(2);
+        }
+        if (!have) break;
+        const int lo = __builtin_amdgcn_readfirstlane(tq[8 * ti + 0]);
+        int size = __builtin_amdgcn_readfirstlane(tq[8 * ti + 1]);
+        const int d0 = __builtin_amdgcn_readfirstlane(tq[8 * ti + 2]);
+        const int pid = lo;
         int dmax, split;
         if (pid == 0 || (learned && !lrn.tree)) {
           dmax = w.dmax_main;
@@ -1290,33 +1364,72 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
         const bool use_ring = learned || record;
         int guess_used = 0;
         bool deviated = false;
+        // decision log rows of the range's paths: path lo + i at dlog + i * dlog_step
         int* dlog = (tr.dec && !learned)
                         ? tr.dec + ((long long)shot * w.n_paths + pid) * tr.log_cap * 3
                         : nullptr;
+        const int dlog_step = tr.log_cap * 3;
 
-        // fresh path: the VNs left active by the initial peeling take their
-        // priors as posteriors
+        if (d0 == 1) {
+          // fresh path: the VNs left active by the initial peeling take their
+          // priors as posteriors
 #pragma unroll
-        for (int r = 0; r < VPL; ++r) {
-          const int v = lane + kWave * r;
-          const int st = v < n_act ? (int)st0[v] : -1;
-          P.set_st(r, st);
-          if (r == 0) P.act_edges = 0;
-          if (v < n_act && st < 0) P.act_edges += P.vdg(r);
-          if (v < n_act) {
-            P.status[v] = (int8_t)st;
-            P.post[v] = st < 0 ? P.llr[r] : kInfF;
-            if (use_ring)
-              for (int j = 0; j < 16; ++j) ring[j * lrn.ring_stride + v] = P.llr[r];
+          for (int r = 0; r < VPL; ++r) {
+            const int v = lane + kWave * r;
+            const int st = v < n_act ? (int)st0[v] : -1;
+            P.set_st(r, st);
+            if (r == 0) P.act_edges = 0;
+            if (v < n_act && st < 0) P.act_edges += P.vdg(r);
+            if (v < n_act) {
+              P.status[v] = (int8_t)st;
+              P.post[v] = st < 0 ? P.llr[r] : kInfF;
+              if (use_ring)
+                for (int j = 0; j < 16; ++j) ring[j * lrn.ring_stride + v] = P.llr[r];
+            }
+          }
+          P.sres = sres0[lane];
+          // t = 0: no CN message yet; also clears the zero slot and the dummy batch
+          for (int e = lane; e < e_pad + 2 * kPad; e += kWave) P.c2v[e] = 0.0f;
+        } else {
+          // the parent's checkpoint: posteriors, statuses, messages, residual bits
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          const gdg_ck_layout cl = gdg_ck(n_act, e_pad);
+          const char* cb = ck + (long long)__builtin_amdgcn_readfirstlane(tq[8 * ti + 5]) * ck_stride;
+          ck_copy(P.post, (const uint4*)(cb + cl.post), 4 * (n_act + 1), lane);
+          ck_copy(P.status, (const uint4*)(cb + cl.status), n_act + 1, lane);
+          ck_copy(P.c2v, (const uint4*)(cb + cl.c2v), 4 * (e_pad + 2 * kPad), lane);
+          P.sres = ((const uint32_t*)(cb + cl.sres))[lane];
+          wave_sync();
+          P.act_edges = 0;
+#pragma unroll
+          for (int r = 0; r < VPL; ++r) {
+            const int v = lane + kWave * r;
+            const int st = v < n_act ? (int)P.status[v] : -1;
+            P.set_st(r, st);
+            if (v < n_act && st < 0) P.act_edges += P.vdg(r);
           }
         }
-        P.sres = sres0[lane];
-        // t = 0: no CN message yet; also clears the zero slot and the dummy batch
-        for (int e = lane; e < e_pad + 2 * kPad; e += kWave) P.c2v[e] = 0.0f;
         wave_sync();
-        int end = 0, steps = 0, it = 0;
-        if (!peel0_ok) end = END_CONTRADICTION;
-        for (int D = 1; end == 0 && D <= dmax; ++D) {
+        int end = 0, steps = d0 - 1, it = 0;
+        if (d0 == 1 && !peel0_ok) end = END_CONTRADICTION;
+        if (d0 > 1) {
+          // the decision of depth d0 - 1 with this range's value
+          const int gsel = __builtin_amdgcn_readfirstlane(tq[8 * ti + 3]);
+          const int val = __builtin_amdgcn_readfirstlane(tq[8 * ti + 4]);
+          const int n_agg = __builtin_amdgcn_readfirstlane(tq[8 * ti + 7]);
+#pragma unroll
+          for (int r = 0; r < VPL; ++r)
+            if (lane + kWave * r == gsel) set_status(P, r, gsel, val);
+          if (dlog && lane < size && d0 - 2 < tr.log_cap) {
+            int* row = dlog + lane * dlog_step + (d0 - 2) * 3;
+            row[0] = gsel;
+            row[1] = val;
+            row[2] = n_agg;
+          }
+          wave_sync();
+          if (!peel(P)) end = END_CONTRADICTION;
+        }
+        for (int D = d0; end == 0 && D <= dmax; ++D) {
 #pragma unroll
           for (int r = 0; r < VPL; ++r) {
             P.hs[r] = 0.0f;
@@ -1339,11 +1452,14 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           if (!conv) conv = !wave_any(check_pass(P, !w.low_error) != 0);
           steps = D;
           if (tr.step_lsum && !learned && D - 1 < tr.log_cap) {
-            float* sl = tr.step_lsum + (((long long)shot * w.n_paths + pid) * tr.log_cap + (D - 1)) * n_act;
+            for (int i = 0; i < size; ++i) {
+              float* sl = tr.step_lsum +
+                          (((long long)shot * w.n_paths + pid + i) * tr.log_cap + (D - 1)) * n_act;
 #pragma unroll
-            for (int r = 0; r < VPL; ++r) {
-              const int v = lane + kWave * r;
-              if (v < n_act) sl[v] = (!conv && P.st(r) < 0) ? P.hs[r] : __builtin_nanf("");
+              for (int r = 0; r < VPL; ++r) {
+                const int v = lane + kWave * r;
+                if (v < n_act) sl[v] = (!conv && P.st(r) < 0) ? P.hs[r] : __builtin_nanf("");
+              }
             }
           }
           if (tr.first_post && pid == 0 && D == 1 && run == 0) {
@@ -1491,21 +1607,55 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           }
           if (dlog || !w.low_error) n_agg = wave_sum_i32(n_agg);
           if (gsel < 0) {
-            if (dlog && lane == 0 && D - 1 < tr.log_cap) {
-              dlog[(D - 1) * 3 + 0] = -1;
-              dlog[(D - 1) * 3 + 1] = -1;
-              dlog[(D - 1) * 3 + 2] = n_agg;
+            if (dlog && lane < size && D - 1 < tr.log_cap) {
+              int* row = dlog + lane * dlog_step + (D - 1) * 3;
+              row[0] = -1;
+              row[1] = -1;
+              row[2] = n_agg;
             }
             end = END_NO_CANDIDATE;
             break;
           }
+          if (share && size > 1 && D <= w.g) {
+            // Fig. 2's tree splits the range here: its upper half (bit g - D
+            // set) takes 1 - fav from a checkpoint of the state before this
+            // decision; this wavefront goes on with the lower half (fav)
+            const int h = size >> 1;
+            int slot = 0, tn = 0;
+            if (lane == 0) slot = atomicAdd(&misc[9], 1);
+            slot = __builtin_amdgcn_readfirstlane(slot);
+            const gdg_ck_layout cl = gdg_ck(n_act, e_pad);
+            char* cb = ck + (long long)slot * ck_stride;
+            ck_save((uint4*)(cb + cl.post), P.post, 4 * (n_act + 1), lane);
+            ck_save((uint4*)(cb + cl.status), P.status, n_act + 1, lane);
+            ck_save((uint4*)(cb + cl.c2v), P.c2v, 4 * (e_pad + 2 * kPad), lane);
+            ((uint32_t*)(cb + cl.sres))[lane] = P.sres;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            wave_sync();
+            if (lane == 0) {
+              tn = atomicAdd(&misc[1], 1);
+              int* t = tq + 8 * tn;
+              t[0] = lo + h;
+              t[1] = h;
+              t[2] = D + 1;
+              t[3] = gsel;
+              t[4] = 1 - fav;
+              t[5] = slot;
+              t[6] = lo;
+              t[7] = n_agg;
+              __hip_atomic_store(&tready[tn], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            size = h;
+            val = fav;
+          }
 #pragma unroll
           for (int r = 0; r < VPL; ++r)
             if (lane + kWave * r == gsel) set_status(P, r, gsel, val);
-          if (dlog && lane == 0 && D - 1 < tr.log_cap) {
-            dlog[(D - 1) * 3 + 0] = gsel;
-            dlog[(D - 1) * 3 + 1] = val;
-            dlog[(D - 1) * 3 + 2] = n_agg;
+          if (dlog && lane < size && D - 1 < tr.log_cap) {
+            int* row = dlog + lane * dlog_step + (D - 1) * 3;
+            row[0] = gsel;
+            row[1] = val;
+            row[2] = n_agg;
           }
           wave_sync();
           if (!peel(P)) {
@@ -1514,27 +1664,31 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           }
         }
         if (end == 0) end = END_EXHAUSTED;   // dmax < 1
+        // traces of every path of the range
         if (dlog) {
           // entries past the last logged step
           const int first_free =
               (end == END_CONVERGED || end == END_EXHAUSTED) ? steps - 1 : steps;
-          for (int i = lane; i < tr.log_cap; i += kWave) {
-            if (i >= first_free) {
-              dlog[i * 3 + 0] = -1;
-              dlog[i * 3 + 1] = -1;
-              dlog[i * 3 + 2] = -1;
+          for (int p = 0; p < size; ++p)
+            for (int i = lane; i < tr.log_cap; i += kWave) {
+              if (i >= first_free) {
+                int* row = dlog + p * dlog_step + i * 3;
+                row[0] = -1;
+                row[1] = -1;
+                row[2] = -1;
+              }
             }
-          }
         }
         if (tr.step_lsum && !learned) {
-          for (int i = steps; i < tr.log_cap; ++i) {
-            float* sl = tr.step_lsum + (((long long)shot * w.n_paths + pid) * tr.log_cap + i) * n_act;
-            for (int v = lane; v < n_act; v += kWave) sl[v] = __builtin_nanf("");
-          }
+          for (int p = 0; p < size; ++p)
+            for (int i = steps; i < tr.log_cap; ++i) {
+              float* sl = tr.step_lsum + (((long long)shot * w.n_paths + pid + p) * tr.log_cap + i) * n_act;
+              for (int v = lane; v < n_act; v += kWave) sl[v] = __builtin_nanf("");
+            }
         }
-        if (tr.ends && lane == 0 && !learned) {
-          tr.ends[((long long)shot * w.n_paths + pid) * 2 + 0] = end;
-          tr.ends[((long long)shot * w.n_paths + pid) * 2 + 1] = steps;
+        if (tr.ends && lane < size && !learned) {
+          tr.ends[((long long)shot * w.n_paths + pid + lane) * 2 + 0] = end;
+          tr.ends[((long long)shot * w.n_paths + pid + lane) * 2 + 1] = steps;
         }
         // path answer: bits over the sub-graph
         uint32_t* mybits = pbits + pid * L.pbits_words;
@@ -1586,11 +1740,18 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             for (int i = 0; i < n_set; ++i) pm += stage[i];
           }
         }
-        if (lane == 0) {
-          ppm[pid] = pm;
-          pend[pid] = end;
+        // every path of the range has this answer
+        for (int p = 1; p < size; ++p)
+          for (int i = lane; i < L.pbits_words; i += kWave) pbits[(pid + p) * L.pbits_words + i] = mybits[i];
+        if (lane < size) {
+          // Eq. 5 came out on lane 0
+          ppm[pid + lane] = __longlong_as_double(
+              (long long)readlane64((unsigned long long)__double_as_longlong(pm), 0));
+          pend[pid + lane] = end;
         }
         wave_sync();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0) atomicAdd(&misc[8], size);
       }
       __syncthreads();
       // ---------------------------------------------------------- best path
@@ -1618,7 +1779,6 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
         misc[2] = best >= 0 ? best : 0;
         // a learned answer stands if its path metric is at most pm_fallback
         misc[6] = best >= 0 && !(mode == 1 && run == 0 && bpm > (double)lrn.pm_fallback);
-        misc[0] = 0;   // path counter for a fallback run
         pm_out[shot] = bpm;
         flags_out[shot] = fl;
       }
@@ -1656,16 +1816,33 @@ template <int VPL, bool kLearn>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     kDecodeWavesPerSimd<VPL, kLearn>, kDecodeWavesPerSimd<VPL, kLearn>))) void gdg_decode_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
   extern __shared__ __align__(16) unsigned char smem[];
-  for (int item = blockIdx.x; item < J.total; item += gridDim.x) {
+  char* const ck = J.ckpt ? J.ckpt + (long long)blockIdx.x * J.ckpt_slots * J.ckpt_stride : nullptr;
+  int item = blockIdx.x;
+  for (;;) {
+    if (J.work) {
+      // the next shot from the launch's counter, passed through the first LDS
+      // word (the syndrome, written only once the shot starts)
+      if (threadIdx.x == 0) *(int*)smem = atomicAdd(J.work, 1);
+      __syncthreads();
+      item = *(volatile int*)smem;
+      __syncthreads();
+    }
+    if (item >= J.total) break;
     // pick the job with static indices only (no dynamic indexing of kernel arguments)
     gdg_job_dev jb = J.job[0];
 #pragma unroll
     for (int t = 1; t < kMaxJobs; ++t)
       if (t < J.n_jobs && item >= J.job[t].item0) jb = J.job[t];
     decode_shot<VPL, kLearn>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat, jb.pm,
-                             jb.flags, tr, J.learn, smem, J.lds);
+                             jb.flags, tr, J.learn, smem, J.lds, ck, J.ckpt_stride);
     __syncthreads();
+    if (!J.work) item += gridDim.x;
   }
+}
+
+__global__ void gdg_zero_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // ------------------------------------------------------------------ plain BP
@@ -1864,6 +2041,11 @@ __global__ void gdg_evaluate_kernel(int n_shots, int n_rows, int n_obs,
 // Register tilings of the decode kernel: VNs per lane of each bucket.
 #define GDG_DECODE_TILINGS(X) X(6) X(7) X(8) X(16)
 constexpr int kBuckets = 4;
+
+hipError_t gdg_launch_zero(int* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(gdg_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
 
 hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
                            const gdg_trace_dev& tr, hipStream_t st) {
