@@ -1392,7 +1392,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           for (int e = lane; e < e_pad + 2 * kPad; e += kWave) P.c2v[e] = 0.0f;
         } else {
           // the parent's checkpoint: posteriors, statuses, messages, residual bits
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
           const gdg_ck_layout cl = gdg_ck(n_act, e_pad);
           const char* cb = ck + (long long)__builtin_amdgcn_readfirstlane(tq[8 * ti + 5]) * ck_stride;
           ck_copy(P.post, (const uint4*)(cb + cl.post), 4 * (n_act + 1), lane);
@@ -1630,7 +1630,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             ck_save((uint4*)(cb + cl.status), P.status, n_act + 1, lane);
             ck_save((uint4*)(cb + cl.c2v), P.c2v, 4 * (e_pad + 2 * kPad), lane);
             ((uint32_t*)(cb + cl.sres))[lane] = P.sres;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             wave_sync();
             if (lane == 0) {
               tn = atomicAdd(&misc[1], 1);
