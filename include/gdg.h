@@ -17,6 +17,12 @@
  *    NULL = the null stream). Results are ready once the stream is synchronised.
  *  - A decode failure is not a call failure: it shows in d_pm (+infinity) and
  *    d_flags, and the shot counts as a logical failure (Sec. III).
+ *  - The decode entry points keep device scratch per (device, stream): a shot
+ *    counter and the path checkpoints where Fig. 2's tree splits (C2: about
+ *    150 MB). It is allocated on the first decode on a stream, grown (after
+ *    synchronising that stream) when a larger window needs more, and kept
+ *    until the process ends. Decodes on one stream therefore run in order;
+ *    decodes on different streams do not share it.
  */
 #ifndef GDG_H
 #define GDG_H

@@ -980,9 +980,10 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     }
     // rank: ascending sum of the last four posteriors, ties by column index;
     // keep the n_act smallest keys (order-preserving float bits, column). A
-    // radix select over the key's 32 + 16 bits (six 8-bit passes) finds the
-    // n_act-th smallest key K; the kept keys (<= K) are gathered in any order
-    // and each one's position is the count of smaller kept keys.
+    // radix select over the key's 32 + 16 bits (up to six 8-bit passes; it
+    // stops once the bucket holding the n_act-th smallest key is kept whole)
+    // finds a threshold K; the kept keys (<= K) are gathered in any order and
+    // each one's position is the count of smaller kept keys.
     __syncthreads();
     int* hist = (int*)(U + L.p_keys);                 // [256]
     int* ctl = hist + 256;                            // [0], [1] key prefix, [2] still needed, [3] count
@@ -1016,16 +1017,20 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (run < need && run + h[j] >= need) {
-            const unsigned long long np = prefix | ((unsigned long long)(4 * lane + j) << shift);
+            unsigned long long np = prefix | ((unsigned long long)(4 * lane + j) << shift);
+            // the whole bucket is kept: every key of it is <= the prefix with
+            // all lower bits set, and the select ends here
+            if (run + h[j] == need) np |= (1ull << shift) - 1ull;
             ctl[0] = (int)(uint32_t)(np >> 32);
             ctl[1] = (int)(uint32_t)np;
-            ctl[2] = need - run;
+            ctl[2] = run + h[j] == need ? 0 : need - run;
           }
           run += h[j];
         }
       }
       kmask |= 0xffull << shift;
       __syncthreads();
+      if (ctl[2] == 0) break;
     }
     const unsigned long long kthr = ((unsigned long long)(uint32_t)ctl[0] << 32) | (uint32_t)ctl[1];
     for (int c = tid; c < n; c += bs) {
