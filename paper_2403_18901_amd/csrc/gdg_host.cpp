@@ -191,7 +191,7 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
   L.tq = stake(4 * 8 * P);    // path task queue: 8 ints per task
   L.tready = stake(4 * P);
   L.dyn_base = so;
-  const gdg_dyn_layout worst = gdg_dyn(L.dyn_base, e_pad_max, col_slots, tcols);
+  const gdg_dyn_layout worst = gdg_dyn(L.dyn_base, e_pad_max, col_slots, tcols, !w.low_error);
   // sub-graph build scratch above the largest variable part
   int bo = worst.end;
   auto btake = [&](int bytes) {
@@ -263,8 +263,8 @@ bool full_layout(int m, int n, const std::vector<int>& row_ptr, const std::vecto
     while ((1 << lk) < k[pj]) ++lk;
     for (int i = 0; i < k[pj]; ++i, ++g) {
       const int e0 = i < nb[pj] ? start[pj] + 4 * i : epad + 4;
-      F.meta[g] = (uint32_t)e0 | ((uint32_t)j << 14) | ((uint32_t)lk << 24) |
-                  (i == 0 ? (1u << 28) : 0u) | (1u << 29);
+      F.meta[g] = (uint32_t)e0 | ((uint32_t)j << kMetaRowShift) | ((uint32_t)lk << kMetaLogKShift) |
+                  (i == 0 ? kMetaLead : 0u) | kMetaValid;
     }
   }
   return true;
@@ -503,6 +503,19 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
     D.fr_T = F.T;
     D.fr_epad = F.epad;
     if ((rc = win->put(F.meta, &D.fr_meta))) return rc;
+    {
+      std::vector<uint32_t> rec(4 * F.meta.size());
+      for (size_t i = 0; i < F.meta.size(); ++i) {
+        const uint32_t e0 = F.meta[i] & kMetaEdge;
+        rec[4 * i + 0] = F.meta[i];
+        rec[4 * i + 1] = F.rvn[e0] | (uint32_t)F.rvn[e0 + 1] << 16;
+        rec[4 * i + 2] = F.rvn[e0 + 2] | (uint32_t)F.rvn[e0 + 3] << 16;
+        rec[4 * i + 3] = 0;
+      }
+      const uint32_t* rp = nullptr;
+      if ((rc = win->put(rec, &rp))) return rc;
+      D.fr_rec = reinterpret_cast<const uint4*>(rp);
+    }
     if ((rc = win->put(F.rvn, &D.fr_rvn))) return rc;
     if ((rc = win->put(F.cidx, &D.fr_cidx))) return rc;
     if ((rc = win->put(F.cptr, &D.fr_cptr))) return rc;

@@ -8,6 +8,14 @@
 
 #include "gdg_mlp.h"
 
+// Slot metadata word of the lane-group CN layout (one per lane and slot column).
+constexpr uint32_t kMetaEdge = 0x3fffu;      // first CSR edge of the batch
+constexpr int kMetaRowShift = 14;            // row, 10 bits
+constexpr int kMetaLogKShift = 24;           // log2 of the group size, 3 bits
+constexpr uint32_t kMetaSyn = 1u << 27;      // window syndrome bit of the row
+constexpr uint32_t kMetaLead = 1u << 28;     // first lane of the group
+constexpr uint32_t kMetaValid = 1u << 29;    // the slot holds a row
+
 // Window graph on the device plus decoder parameters.
 struct gdg_win_dev {
   int m, n, n_act, e_full, n_paths;
@@ -25,7 +33,8 @@ struct gdg_win_dev {
   // the preprocessing BP): rows by decreasing degree, padded to multiples of 4
   // edges with dummy VN n; column slots padded to multiples of 4
   int fr_T, fr_epad;        // slot columns, padded CSR edges
-  const uint32_t* fr_meta;  // [fr_T][64] slot metadata (row field: window row)
+  const uint32_t* fr_meta;  // [fr_T + 24][64] slot metadata (row field: window row)
+  const uint4* fr_rec;      // [fr_T + 24][64] (metadata, the batch's four VN offsets)
   const uint16_t* fr_rvn;   // [fr_epad + 8] 4 * column of each padded CSR edge
   const uint16_t* fr_cidx;  // [padded column slots] 4 * CSR position (padding: 4 * fr_epad)
   const int* fr_cptr;       // [n + 1] first column slot
@@ -64,12 +73,14 @@ __host__ __device__ inline int gdg_align16(int x) { return (x + 15) & ~15; }
 struct gdg_dyn_layout {
   int rvn, cidx, crow, meta, end;
 };
-__host__ __device__ inline gdg_dyn_layout gdg_dyn(int dyn_base, int e_pad, int col_slots, int T) {
+// The column slots' rows (crow) serve Alg. 3 only, so low-error mode has none.
+__host__ __device__ inline gdg_dyn_layout gdg_dyn(int dyn_base, int e_pad, int col_slots, int T,
+                                                  bool with_crow) {
   gdg_dyn_layout d;
   d.rvn = dyn_base;                                        // [e_pad + 8] u16
   d.cidx = gdg_align16(d.rvn + 2 * (e_pad + 8));           // [col_slots + 4] u16
-  d.crow = gdg_align16(d.cidx + 2 * (col_slots + 4));      // [col_slots] u16
-  d.meta = gdg_align16(d.crow + 2 * col_slots);            // [T + 3][64] u32
+  d.crow = gdg_align16(d.cidx + 2 * (col_slots + 4));      // [col_slots] u16, or none
+  d.meta = gdg_align16(d.crow + (with_crow ? 2 * col_slots : 0));   // [T + 3][64] u32
   d.end = gdg_align16(d.meta + 4 * 64 * (T + 3));
   return d;
 }

@@ -331,13 +331,6 @@ enum { END_CONVERGED = 1, END_EXHAUSTED = 2, END_CONTRADICTION = 3, END_NO_CANDI
 // padded slots point at a CN-to-VN message fixed at zero.
 constexpr int kPad = 4;
 
-// Slot metadata word (one per lane and slot column).
-constexpr uint32_t kMetaEdge = 0x3fffu;      // first CSR edge of the batch
-constexpr int kMetaRowShift = 14;            // sub-graph row, 10 bits
-constexpr int kMetaLogKShift = 24;           // log2 of the group size, 3 bits
-constexpr uint32_t kMetaSyn = 1u << 27;      // window syndrome bit of the row
-constexpr uint32_t kMetaLead = 1u << 28;     // first lane of the group
-constexpr uint32_t kMetaValid = 1u << 29;    // the slot holds a row
 
 template <int VPL>
 struct PathCtx {
@@ -352,6 +345,7 @@ struct PathCtx {
   const uint16_t* cidx;   // [E_col] 4 * CSR position of each column-order slot (byte offset in c2v)
   const uint16_t* crow;   // [E_col] row of each column-order slot
   const uint32_t* meta;   // [T][64] slot metadata
+  const uint4* rec;       // or [T][64] records (metadata, edge offsets) in global memory
   // per wavefront, LDS
   float* post;            // [n_act + 1]; +infinity once decimated and for the dummy VN
   int8_t* status;         // [n_act + 1] -1 active, 0/1 decimated
@@ -451,47 +445,57 @@ struct Slot {
   uint4 g;       // gathered posteriors or statuses
 };
 
-template <int VPL, bool OV>
+// REC: the slot table is a global array of (metadata, edge offsets) records
+// (the whole-window layout of the preprocessing), one 16-byte load per slot
+// instead of a metadata load and a dependent edge load.
+template <int VPL, bool OV, bool REC>
 __device__ __forceinline__ void slot_edges(const PathCtx<VPL>& P, Slot& s) {
   const int e0 = s.mt & kMetaEdge;
-  s.vo = *(const uint2*)(P.rvn + e0);
+  if (!REC) s.vo = *(const uint2*)(P.rvn + e0);
   if (OV) s.ov = *(const float4*)(P.c2v + e0);
 }
 
-template <int VPL>
+template <int VPL, bool REC>
 __device__ __forceinline__ void slot_meta(const PathCtx<VPL>& P, Slot& s, int t) {
-  s.mt = P.meta[(P.t0 + t * P.tstride) * kWave + P.lane];
+  const int i = (P.t0 + t * P.tstride) * kWave + P.lane;
+  if (REC) {
+    const uint4 r = P.rec[i];
+    s.mt = r.x;
+    s.vo = make_uint2(r.y, r.z);
+  } else {
+    s.mt = P.meta[i];
+  }
 }
 
-template <int VPL, bool OV, typename Gather, typename Compute>
+template <int VPL, bool OV, bool REC, typename Gather, typename Compute>
 __device__ __forceinline__ int slot_step(const PathCtx<VPL>& P, const Slot& a, Slot& b, Slot& c,
                                          Slot& d, int t, Gather& gather, Compute& compute) {
   gather(b);
-  slot_edges<VPL, OV>(P, c);
-  slot_meta(P, d, t + 3);
+  slot_edges<VPL, OV, REC>(P, c);
+  slot_meta<VPL, REC>(P, d, t + 3);
   return compute(a, t);
 }
 
-template <int VPL, bool OV, typename Gather, typename Compute>
+template <int VPL, bool OV, bool REC = false, typename Gather, typename Compute>
 __device__ __forceinline__ int slot_walk(const PathCtx<VPL>& P, Gather gather, Compute compute) {
   const int T = P.T;
   if (T == 0) return 0;
   int acc = 0;
   Slot A, B, C, D;
-  slot_meta(P, A, 0);
-  slot_meta(P, B, 1);
-  slot_meta(P, C, 2);
-  slot_edges<VPL, OV>(P, A);
-  slot_edges<VPL, OV>(P, B);
+  slot_meta<VPL, REC>(P, A, 0);
+  slot_meta<VPL, REC>(P, B, 1);
+  slot_meta<VPL, REC>(P, C, 2);
+  slot_edges<VPL, OV, REC>(P, A);
+  slot_edges<VPL, OV, REC>(P, B);
   gather(A);
   for (int t = 0; t < T; t += 4) {
-    acc |= slot_step<VPL, OV>(P, A, B, C, D, t, gather, compute);
+    acc |= slot_step<VPL, OV, REC>(P, A, B, C, D, t, gather, compute);
     if (t + 1 >= T) break;
-    acc |= slot_step<VPL, OV>(P, B, C, D, A, t + 1, gather, compute);
+    acc |= slot_step<VPL, OV, REC>(P, B, C, D, A, t + 1, gather, compute);
     if (t + 2 >= T) break;
-    acc |= slot_step<VPL, OV>(P, C, D, A, B, t + 2, gather, compute);
+    acc |= slot_step<VPL, OV, REC>(P, C, D, A, B, t + 2, gather, compute);
     if (t + 3 >= T) break;
-    acc |= slot_step<VPL, OV>(P, D, A, B, C, t + 3, gather, compute);
+    acc |= slot_step<VPL, OV, REC>(P, D, A, B, C, t + 3, gather, compute);
   }
   return acc;
 }
@@ -663,9 +667,9 @@ __device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const Slot& c, int t, fl
   return (int)(srow ^ a.hp);   // bit 31: the row is unsatisfied
 }
 
-template <int VPL>
+template <int VPL, bool REC = false>
 __device__ __forceinline__ int cn_phase(PathCtx<VPL>& P, float alpha, float clip) {
-  return slot_walk<VPL, true>(
+  return slot_walk<VPL, true, REC>(
       P,
       [&](Slot& s) {
         s.g.x = __float_as_uint(at_byte(P.post, s.vo.x & 0xffffu));
@@ -678,9 +682,9 @@ __device__ __forceinline__ int cn_phase(PathCtx<VPL>& P, float alpha, float clip
 
 // Syndrome check of the current hard decisions; optionally records each
 // row's unsatisfied flag for Alg. 3.
-template <int VPL>
+template <int VPL, bool REC = false>
 __device__ __forceinline__ int check_pass(PathCtx<VPL>& P, bool write_unsat) {
-  return slot_walk<VPL, false>(
+  return slot_walk<VPL, false, REC>(
       P,
       [&](Slot& s) {
         s.g.x = __float_as_uint(at_byte(P.post, s.vo.x & 0xffffu));
@@ -751,10 +755,12 @@ __device__ __forceinline__ int vn_phase(PathCtx<VPL>& P, bool hist, float* ring_
       P.post[v] = x;
       if (ring_slot) ring_slot[v] = x;
       if (hist) {
-        // min and max as medians with -inf and +inf: no NaN reaches here
+        // min and max as medians with -/+FLT_MAX (the posteriors are finite;
+        // a median with an infinity would be turned into a min or max that
+        // quiets NaNs first)
         P.hs[r] += x;
-        P.hmn[r] = __builtin_amdgcn_fmed3f(P.hmn[r], x, -kInfF);
-        P.hmx[r] = __builtin_amdgcn_fmed3f(P.hmx[r], x, kInfF);
+        P.hmn[r] = __builtin_amdgcn_fmed3f(P.hmn[r], x, -__FLT_MAX__);
+        P.hmx[r] = __builtin_amdgcn_fmed3f(P.hmx[r], x, __FLT_MAX__);
       }
     }
   }
@@ -891,6 +897,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     PathCtx<VPL> F;
     F.rvn = w.fr_rvn;
     F.meta = w.fr_meta;
+    F.rec = w.fr_rec;
     F.post = ppost;
     F.c2v = pc2v;
     F.lane = lane;
@@ -915,7 +922,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
         F.t0 = wave + 32 * c * nw;
         F.T = min(32, my_T - 32 * c);
         F.sres = c ? syn1 : syn0;
-        bad |= messages ? cn_phase(F, w.alpha, w.clip) : check_pass(F, false);
+        bad |= messages ? cn_phase<VPL, true>(F, w.alpha, w.clip) : check_pass<VPL, true>(F, false);
       }
       return bad;
     };
@@ -1133,7 +1140,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     const int T = min((n_slots + kWave - 1) / kWave, L.meta_cols);
     const int cap = L.meta_cols * kWave;
     {
-      const gdg_dyn_layout dl = gdg_dyn(L.dyn_base, e_pad, cptr[n_act], T);
+      const gdg_dyn_layout dl = gdg_dyn(L.dyn_base, e_pad, cptr[n_act], T, !w.low_error);
       rvn = (uint16_t*)(U + dl.rvn);
       cidx = (uint16_t*)(U + dl.cidx);
       crow = (uint16_t*)(U + dl.crow);
@@ -1163,7 +1170,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           const int slot = cptr[v] + kc[i];
           rvn[pos] = (uint16_t)(4 * v);
           cidx[slot] = (uint16_t)(4 * pos);
-          crow[slot] = (uint16_t)pj;
+          if (!w.low_error) crow[slot] = (uint16_t)pj;
           ++pos;
         }
       }
@@ -1216,6 +1223,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     P.cidx = cidx;
     P.crow = crow;
     P.meta = meta;
+    P.rec = nullptr;
     P.post = (float*)(Wb + pl.post);
     P.status = (int8_t*)(Wb + pl.status);
     P.c2v = (float*)(Wb + pl.c2v);
@@ -1292,7 +1300,9 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       // same state, messages included, so sharing changes no result. Learned
       // paths run one per task.
       const int n_tree = w.g > 0 ? 1 << w.g : 1;
-      const bool share = !learned && ck != nullptr && n_tree > 1;
+      // (every path of a range must reach the split's decision: the tree
+      // paths run past depth g when extra >= 1)
+      const bool share = !learned && ck != nullptr && n_tree > 1 && w.extra > 0;
       if (tid == 0) {
         int nt = 0;
         auto push0 = [&](int plo, int psize) {
