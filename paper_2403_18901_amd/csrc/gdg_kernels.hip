@@ -815,6 +815,33 @@ __device__ __forceinline__ void full_vn_pass(const gdg_win_dev& w, float* post, 
   }
 }
 
+// Eq. 5 in ascending window-column order: the wavefront's lanes gather the
+// priors of the columns set in `bits` into `stage` in that order (a prefix sum
+// over the words), then lane 0 adds them up in that order. The sum is valid on
+// lane 0; `stage` holds at least as many doubles as bits can be set.
+__device__ __forceinline__ double eq5_sum(const uint32_t* bits, int words, const double* llr64,
+                                          double* stage, int lane) {
+  int n_set = 0;
+  for (int w0 = 0; w0 < words; w0 += kWave) {
+    const int wd = w0 + lane;
+    uint32_t x = wd < words ? bits[wd] : 0u;
+    const int cnt = __builtin_popcount(x);
+    const int incl = wave_incl_scan(cnt, lane);
+    int pos = n_set + incl - cnt;
+    while (x) {
+      const int bt = __builtin_ctz(x);
+      x &= x - 1u;
+      stage[pos++] = llr64[wd * 32 + bt];
+    }
+    n_set += __builtin_amdgcn_readlane(incl, kWave - 1);
+  }
+  wave_sync();
+  double pm = 0.0;
+  if (lane == 0)
+    for (int i = 0; i < n_set; ++i) pm += stage[i];
+  return pm;
+}
+
 // Path checkpoint copies (whole 16-byte words; the regions are padded to 16).
 __device__ __forceinline__ void ck_copy(void* dst, const uint4* src, int bytes, int lane) {
   uint4* d = (uint4*)dst;
@@ -953,18 +980,13 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
         }
       }
       __syncthreads();
-      if (tid == 0) {
-        double pm = 0.0;
-        for (int wd = 0; wd < L.obits_words; ++wd) {
-          uint32_t x = obits[wd];
-          while (x) {
-            const int bt = __builtin_ctz(x);
-            x &= x - 1u;
-            pm += w.llr64[wd * 32 + bt];
-          }
+      if (wave == 0) {
+        // the message array is dead; it holds n doubles (sort_n >= n)
+        const double pm = eq5_sum(obits, L.obits_words, w.llr64, (double*)pc2v, lane);
+        if (lane == 0) {
+          pm_out[shot] = pm;
+          flags_out[shot] = 1;
         }
-        pm_out[shot] = pm;
-        flags_out[shot] = 1;
       }
       for (int c = tid; c < n; c += blockDim.x)
         ehat[(long long)shot * n + c] = (uint8_t)((obits[c >> 5] >> (c & 31)) & 1u);
@@ -1731,29 +1753,9 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             }
           }
           wave_sync();
-          // the set columns' priors are gathered in column order by all lanes
-          // into the wavefront's message array (dead once the path has ended,
-          // sized for n_act doubles), then summed in that order by one lane
-          double* stage = (double*)P.c2v;
-          int n_set = 0;
-          for (int w0 = 0; w0 < L.obits_words; w0 += kWave) {
-            const int wd = w0 + lane;
-            uint32_t x = wd < L.obits_words ? wbits[wd] : 0u;
-            const int cnt = __builtin_popcount(x);
-            const int incl = wave_incl_scan(cnt, lane);
-            int pos = n_set + incl - cnt;
-            while (x) {
-              const int bt = __builtin_ctz(x);
-              x &= x - 1u;
-              stage[pos++] = w.llr64[wd * 32 + bt];
-            }
-            n_set += __builtin_amdgcn_readlane(incl, kWave - 1);
-          }
-          wave_sync();
-          if (lane == 0) {
-            pm = 0.0;
-            for (int i = 0; i < n_set; ++i) pm += stage[i];
-          }
+          // staged in the wavefront's message array (dead once the path has
+          // ended, sized for n_act doubles)
+          pm = eq5_sum(wbits, L.obits_words, w.llr64, (double*)P.c2v, lane);
         }
         // every path of the range has this answer
         for (int p = 1; p < size; ++p)
