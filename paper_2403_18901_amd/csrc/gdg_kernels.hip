@@ -842,15 +842,26 @@ __device__ __forceinline__ double eq5_sum(const uint32_t* bits, int words, const
   return pm;
 }
 
-// Path checkpoint copies (whole 16-byte words; the regions are padded to 16).
+// Path checkpoint copies between global memory (the checkpoint) and the
+// LDS (the path's state), in whole 16-byte words (the regions are padded to
+// 16). The address spaces are explicit so the copies are global and ds
+// operations rather than flat ones.
+typedef unsigned int gdg_u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) gdg_u32x4 gdg_glb_u4;
+typedef __attribute__((address_space(3))) gdg_u32x4 gdg_lds_u4;
+
+template <typename D, typename S>
+__device__ __forceinline__ void ck_move(D* d, const S* s, int bytes, int lane) {
+  const int n = (bytes + 15) / 16;
+  for (int i = lane; i < n; i += kWave) d[i] = s[i];
+}
+
 __device__ __forceinline__ void ck_copy(void* dst, const uint4* src, int bytes, int lane) {
-  uint4* d = (uint4*)dst;
-  for (int i = lane; i < (bytes + 15) / 16; i += kWave) d[i] = src[i];
+  ck_move((gdg_lds_u4*)dst, (const gdg_glb_u4*)src, bytes, lane);
 }
 
 __device__ __forceinline__ void ck_save(uint4* dst, const void* src, int bytes, int lane) {
-  const uint4* q = (const uint4*)src;
-  for (int i = lane; i < (bytes + 15) / 16; i += kWave) dst[i] = q[i];
+  ck_move((gdg_glb_u4*)dst, (const gdg_lds_u4*)src, bytes, lane);
 }
 
 // Decodes shot `shot` of one window with the whole workgroup. Every thread
@@ -1379,32 +1390,36 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           __builtin_amdgcn_s_sleep(2);
         }
         if (!have) break;
-        const int lo = __builtin_amdgcn_readfirstlane(tq[8 * ti + 0]);
+        int lo = __builtin_amdgcn_readfirstlane(tq[8 * ti + 0]);
         int size = __builtin_amdgcn_readfirstlane(tq[8 * ti + 1]);
         const int d0 = __builtin_amdgcn_readfirstlane(tq[8 * ti + 2]);
-        const int pid = lo;
-        int dmax, split;
-        if (pid == 0 || (learned && !lrn.tree)) {
-          dmax = w.dmax_main;
-          split = 0;
-        } else if (learned) {   // Fig. 2's tree with `guesses` levels
-          dmax = lrn.guesses + w.extra;
-          split = lrn.guesses;
-        } else if (w.g > 0 && pid < (1 << w.g)) {
-          dmax = w.g + w.extra;
-          split = w.g;
-        } else {
-          split = w.g + 1 + (pid - (1 << w.g));
-          dmax = split + w.extra;
-        }
+        // the range's representative path and its depth limits
+        int pid, dmax, split;
+        auto represent = [&](int p) {
+          pid = p;
+          if (pid == 0 || (learned && !lrn.tree)) {
+            dmax = w.dmax_main;
+            split = 0;
+          } else if (learned) {   // Fig. 2's tree with `guesses` levels
+            dmax = lrn.guesses + w.extra;
+            split = lrn.guesses;
+          } else if (w.g > 0 && pid < (1 << w.g)) {
+            dmax = w.g + w.extra;
+            split = w.g;
+          } else {
+            split = w.g + 1 + (pid - (1 << w.g));
+            dmax = split + w.extra;
+          }
+        };
+        represent(lo);
         const bool record = run == 0 && mode == 2 && pid == 0;
         const bool use_ring = learned || record;
         int guess_used = 0;
         bool deviated = false;
         // decision log rows of the range's paths: path lo + i at dlog + i * dlog_step
-        int* dlog = (tr.dec && !learned)
-                        ? tr.dec + ((long long)shot * w.n_paths + pid) * tr.log_cap * 3
-                        : nullptr;
+        int* const dlog0 = (tr.dec && !learned) ? tr.dec + (long long)shot * w.n_paths * tr.log_cap * 3
+                                                : nullptr;
+        int* dlog = dlog0 ? dlog0 + (long long)pid * tr.log_cap * 3 : nullptr;
         const int dlog_step = tr.log_cap * 3;
 
         if (d0 == 1) {
@@ -1655,9 +1670,13 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           }
           if (share && size > 1 && D <= w.g) {
             // Fig. 2's tree splits the range here: its upper half (bit g - D
-            // set) takes 1 - fav from a checkpoint of the state before this
-            // decision; this wavefront goes on with the lower half (fav)
+            // set) takes 1 - fav, its lower half fav. This wavefront goes on
+            // with the upper half -- the deviating paths tend to run longer, so
+            // the longest chain of steps starts first -- and leaves the lower
+            // half a checkpoint of the state before this decision. (The
+            // recording path stays the plain main path.)
             const int h = size >> 1;
+            const bool keep_upper = !record;
             int slot = 0, tn = 0;
             if (lane == 0) slot = atomicAdd(&misc[9], 1);
             slot = __builtin_amdgcn_readfirstlane(slot);
@@ -1672,11 +1691,11 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             if (lane == 0) {
               tn = atomicAdd(&misc[1], 1);
               int* t = tq + 8 * tn;
-              t[0] = lo + h;
+              t[0] = keep_upper ? lo : lo + h;
               t[1] = h;
               t[2] = D + 1;
               t[3] = gsel;
-              t[4] = 1 - fav;
+              t[4] = keep_upper ? fav : 1 - fav;
               t[5] = slot;
               t[6] = lo;
               t[7] = n_agg;
@@ -1684,6 +1703,12 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             }
             size = h;
             val = fav;
+            if (keep_upper) {
+              lo += h;
+              represent(lo);
+              if (dlog0) dlog = dlog0 + (long long)pid * tr.log_cap * 3;
+              val = 1 - fav;
+            }
           }
 #pragma unroll
           for (int r = 0; r < VPL; ++r)
