@@ -486,6 +486,9 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   D.low_error = prm->low_error ? 1 : 0;
   D.iters = prm->iters_per_step;
   D.pre_iters = prm->pre_iters;
+  D.bound_ok = 1;
+  for (double x : win->llr64)
+    if (!(x > 0.0)) D.bound_ok = 0;
   D.alpha = prm->alpha;
   D.clip = prm->clip;
   if ((rc = win->put(row_ptr, &D.row_ptr))) return rc;

@@ -20,6 +20,7 @@ constexpr uint32_t kMetaValid = 1u << 29;    // the slot holds a row
 struct gdg_win_dev {
   int m, n, n_act, e_full, n_paths;
   int g, dmax_main, extra, side_max_depth, low_error, iters, pre_iters;
+  int bound_ok;             // every prior LLR > 0: a path's fixed 1s bound its Eq. 5 metric
   float alpha, clip;
   const int* row_ptr;       // [m+1] window CSR
   const uint16_t* row_col;  // [e_full] column of each CSR edge (ascending per row)

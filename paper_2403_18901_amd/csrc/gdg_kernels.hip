@@ -107,6 +107,19 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
          __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
+// Sum over the wavefront (any order; every lane gets it).
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  v += __uint_as_float(dpp<kDppXor1>(__float_as_uint(v)));
+  v += __uint_as_float(dpp<kDppXor2>(__float_as_uint(v)));
+  v += __uint_as_float(dpp<kDppHalfMirror>(__float_as_uint(v)));
+  v += __uint_as_float(dpp<kDppMirror>(__float_as_uint(v)));
+  const float a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+  const float b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+  const float c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+  const float d = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+  return (a + b) + (c + d);
+}
+
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -308,7 +321,7 @@ __device__ __forceinline__ int agg_dec(float hsum, float hmin, float hmax, int D
   return -1;
 }
 
-enum { END_CONVERGED = 1, END_EXHAUSTED = 2, END_CONTRADICTION = 3, END_NO_CANDIDATE = 4 };
+enum { END_CONVERGED = 1, END_EXHAUSTED = 2, END_CONTRADICTION = 3, END_NO_CANDIDATE = 4, END_BOUND = 5 };
 
 // State of one decision path, held by one wavefront.
 //
@@ -566,6 +579,18 @@ __device__ __forceinline__ void set_status(PathCtx<VPL>& P, int r, int v, int va
   P.act_edges -= P.vdg(r);
   P.status[v] = (int8_t)value;
   P.post[v] = kInfF;
+}
+
+// Whether the priors of the path's VNs fixed to 1 (decimated or peeled) sum
+// past the stopping threshold *thr (+infinity until a path has converged).
+template <int VPL>
+__device__ __forceinline__ bool over_bound(const PathCtx<VPL>& P, int* thr) {
+  const float t = __int_as_float(
+      __builtin_amdgcn_readfirstlane(__hip_atomic_load(thr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)));
+  float lb = 0.0f;
+#pragma unroll
+  for (int r = 0; r < VPL; ++r) lb += P.st(r) == 1 ? P.llr[r] : 0.0f;
+  return t < kInfF && wave_sum_f32(lb) > t;
 }
 
 // Peeling closure in synchronous rounds. Returns false on a contradiction
@@ -1336,6 +1361,15 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       // (every path of a range must reach the split's decision: the tree
       // paths run past depth g when extra >= 1)
       const bool share = !learned && ck != nullptr && n_tree > 1 && w.extra > 0;
+      // Branch and bound over the paths: with positive priors a path's Eq. 5
+      // metric is at least the sum of the priors of its VNs fixed to 1 (they
+      // stay 1 in its answer), so a path whose sum already exceeds a converged
+      // path's metric cannot be the answer and stops. The comparison is in
+      // FP32 against the metric widened by 2e-5, far above the rounding of
+      // either side; the answer, its metric and the flags are unchanged (a
+      // stop needs a converged path). Off when traces of every path are asked
+      // for.
+      const bool bound = !learned && mode == 0 && w.bound_ok && !tr.dec && !tr.ends && !tr.step_lsum;
       if (tid == 0) {
         int nt = 0;
         auto push0 = [&](int plo, int psize) {
@@ -1363,6 +1397,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
         misc[1] = nt;   // tasks pushed
         misc[8] = 0;    // paths finished
         misc[9] = 0;    // checkpoints taken
+        misc[10] = 0x7f800000;   // stopping threshold: least converged Eq. 5 metric, widened
       }
       __syncthreads();
       while (path_wave) {
@@ -1480,6 +1515,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           }
           wave_sync();
           if (!peel(P)) end = END_CONTRADICTION;
+          if (end == 0 && bound && over_bound(P, misc + 10)) end = END_BOUND;
         }
         for (int D = d0; end == 0 && D <= dmax; ++D) {
 #pragma unroll
@@ -1724,6 +1760,10 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             end = END_CONTRADICTION;
             break;
           }
+          if (bound && over_bound(P, misc + 10)) {
+            end = END_BOUND;
+            break;
+          }
         }
         if (end == 0) end = END_EXHAUSTED;   // dmax < 1
         // traces of every path of the range
@@ -1790,6 +1830,12 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           ppm[pid + lane] = __longlong_as_double(
               (long long)readlane64((unsigned long long)__double_as_longlong(pm), 0));
           pend[pid + lane] = end;
+        }
+        if (bound && end == END_CONVERGED && lane == 0) {
+          // the metric widened by 2e-5 in FP32 (non-negative floats order like
+          // their bit patterns)
+          __hip_atomic_fetch_min(misc + 10, __float_as_int((float)(pm * (1.0 + 2e-5))), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         wave_sync();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

@@ -386,3 +386,41 @@ def test_pipeline_c2_ler_parity(p):
     assert not resid[~gf].any()
     lo, hi = wilson(int(ref["fail"].sum()), 200)
     assert lo * 200 - 1e-9 <= gf.sum() <= hi * 200 + 1e-9
+
+
+@gpu
+@pytest.mark.parametrize("p,k", [(0.002, 0), (0.002, 5), (0.003, 5)])
+def test_path_bound_changes_no_answer(p, k):
+    """The bound that stops paths early (a path whose priors fixed to 1 already
+    sum past a converged path's Eq. 5 metric) is off when per-path traces are
+    asked for: the traced decode is the unbounded reference. Both decodes must
+    give the same answer, metric and flags on every shot, the bounded one with
+    no more BP work, and at this size it must have stopped some path."""
+    g = _g()
+    dem = c2_dem("144", 12, p)
+    prm = g.params(**c2_params(p))
+    dec = g.SlidingWindowDecoder(dem, prm, W=3)
+    dd = g.DeviceDem(dem)
+    dev = torch.device("cuda")
+    det, obs = dd.sample(6000, seed=11, stream=0, shot0=0, device=dev)
+    for w in dec.windows[:k]:
+        eh, _, _ = w.decode(det, syn_offset=w.row0)
+        w.commit(eh, det, obs)
+    w = dec.windows[k]
+    ns = det.shape[0]
+    e_ref, pm_ref, fl_ref, tr = w.decode(det, syn_offset=w.row0, trace=True)
+    ehat = torch.empty((ns, w.n), dtype=torch.uint8, device=dev)
+    pm = torch.empty(ns, dtype=torch.float64, device=dev)
+    fl = torch.empty(ns, dtype=torch.int32, device=dev)
+    ei = torch.empty(ns, dtype=torch.int64, device=dev)
+    trace = g.Trace(None, None, 0, None, None, g._ptr(ei), None)
+    g._check(g.lib().gdg_decode_batch(w.h, ns, g._ptr(det, w.row0), det.shape[1], g._ptr(ehat),
+                                      g._ptr(pm), g._ptr(fl), None, 0, g.C.byref(trace),
+                                      g._stream()))
+    torch.cuda.synchronize()
+    assert torch.equal(ehat, e_ref)
+    assert torch.equal(fl, fl_ref)
+    assert torch.equal(pm.view(torch.int64), pm_ref.view(torch.int64))
+    ref_ei = tr["edge_iters"]
+    assert bool((ei <= ref_ei).all())
+    assert int(ei.sum()) < int(ref_ei.sum())
