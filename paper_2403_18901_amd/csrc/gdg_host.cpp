@@ -657,6 +657,7 @@ int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
   if (workgroups < 0) return fail(GDG_EINVAL, "negative workgroup count");
   gdg_jobs_dev J{};
   int total = 0, lds = 0, bucket = 0;
+  bool low = true;   // every window in low-error mode: the kernel built without Alg. 3
   for (int j = 0; j < n_jobs; ++j) {
     const gdg_job& jb = jobs[j];
     if (!jb.win) return fail(GDG_EINVAL, "job without a window");
@@ -679,6 +680,7 @@ int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
     total += jb.n_shots;
     lds = std::max(lds, jb.win->plans[waves - 1].total);
     bucket = std::max(bucket, jb.win->bucket);
+    low = low && jb.win->dev.low_error;
   }
   J.n_jobs = n_jobs;
   J.total = total;
@@ -723,7 +725,7 @@ int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
   J.ckpt_slots = slots;
   hipError_t e = gdg_launch_zero(sc.ctr, 1, st);
   if (e != hipSuccess) return hip_fail(e, "counter reset");
-  e = gdg_launch_jobs(J, bucket, waves, grid, lds, tr, st);
+  e = gdg_launch_jobs(J, bucket, low, waves, grid, lds, tr, st);
   if (e != hipSuccess) return hip_fail(e, "decode launch");
   return GDG_OK;
 }

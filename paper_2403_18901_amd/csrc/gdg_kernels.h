@@ -190,8 +190,8 @@ struct gdg_jobs_dev {
 };
 
 hipError_t gdg_launch_zero(int* p, int n, hipStream_t st);
-hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
-                           const gdg_trace_dev& tr, hipStream_t st);
+hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, bool low, int waves, int grid,
+                           int lds, const gdg_trace_dev& tr, hipStream_t st);
 int gdg_kernel_bucket(int m, int n_act);
 int gdg_decode_waves_per_simd(int bucket, bool learn);   // occupancy the kernel is built for
 hipError_t gdg_decode_set_lds_limit(int bucket, int bytes);

@@ -891,7 +891,9 @@ __device__ __forceinline__ void ck_save(uint4* dst, const void* src, int bytes, 
 
 // Decodes shot `shot` of one window with the whole workgroup. Every thread
 // enters and leaves together; the caller synchronises before the LDS is reused.
-template <int VPL, bool kLearn>
+// kLow: every window of the launch is in low-error mode (Alg. 3 off), which
+// frees the registers only Alg. 3 reads.
+template <int VPL, bool kLearn, bool kLow>
 __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int shot,
                             const uint8_t* __restrict__ syn, const long long syn_stride,
                             uint8_t* __restrict__ ehat, double* __restrict__ pm_out,
@@ -899,6 +901,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
                             const gdg_learn_dev& lrn, unsigned char* smem, const int lds_alloc,
                             char* const ck, const long long ck_stride) {
   const gdg_win_dev w = wref;   // uniform: kept in scalar registers, not re-read
+  const bool low_err = kLow || w.low_error;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1198,7 +1201,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     const int T = min((n_slots + kWave - 1) / kWave, L.meta_cols);
     const int cap = L.meta_cols * kWave;
     {
-      const gdg_dyn_layout dl = gdg_dyn(L.dyn_base, e_pad, cptr[n_act], T, !w.low_error);
+      const gdg_dyn_layout dl = gdg_dyn(L.dyn_base, e_pad, cptr[n_act], T, !low_err);
       rvn = (uint16_t*)(U + dl.rvn);
       cidx = (uint16_t*)(U + dl.cidx);
       crow = (uint16_t*)(U + dl.crow);
@@ -1228,7 +1231,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           const int slot = cptr[v] + kc[i];
           rvn[pos] = (uint16_t)(4 * v);
           cidx[slot] = (uint16_t)(4 * pos);
-          if (!w.low_error) crow[slot] = (uint16_t)pj;
+          if (!low_err) crow[slot] = (uint16_t)pj;
           ++pos;
         }
       }
@@ -1537,7 +1540,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             ++it;
             wave_sync();
           }
-          if (!conv) conv = !wave_any(check_pass(P, !w.low_error) != 0);
+          if (!conv) conv = !wave_any(check_pass(P, !low_err) != 0);
           steps = D;
           if (tr.step_lsum && !learned && D - 1 < tr.log_cap) {
             for (int i = 0; i < size; ++i) {
@@ -1576,7 +1579,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             const int v = lane + kWave * r;
             if (v < n_act && P.st(r) < 0 && P.vdg(r) >= 3) {
               bool taken = false;
-              if (!w.low_error) {
+              if (!low_err) {
                 int nu = 0;
                 for (int e = P.vc0(r); e < P.vc0(r) + P.vdg(r); ++e) nu += P.unsat[P.crow[e]];
                 const int b = agg_dec(P.hs[r], P.hmn[r], P.hmx[r], D, on_main, nu);
@@ -1693,7 +1696,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             }
             val = gsel < 0 ? 0 : path_value(w, pid, split, D, fav);
           }
-          if (dlog || !w.low_error) n_agg = wave_sum_i32(n_agg);
+          if (dlog || !low_err) n_agg = wave_sum_i32(n_agg);
           if (gsel < 0) {
             if (dlog && lane < size && D - 1 < tr.log_cap) {
               int* row = dlog + lane * dlog_step + (D - 1) * 3;
@@ -1900,7 +1903,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
 template <int VPL, bool kLearn>
 constexpr int kDecodeWavesPerSimd = (!kLearn && VPL <= 7) ? 3 : 2;
 
-template <int VPL, bool kLearn>
+template <int VPL, bool kLearn, bool kLow>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     kDecodeWavesPerSimd<VPL, kLearn>, kDecodeWavesPerSimd<VPL, kLearn>))) void gdg_decode_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1921,8 +1924,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int t = 1; t < kMaxJobs; ++t)
       if (t < J.n_jobs && item >= J.job[t].item0) jb = J.job[t];
-    decode_shot<VPL, kLearn>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat, jb.pm,
-                             jb.flags, tr, J.learn, smem, J.lds, ck, J.ckpt_stride);
+    decode_shot<VPL, kLearn, kLow>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat,
+                                   jb.pm, jb.flags, tr, J.learn, smem, J.lds, ck, J.ckpt_stride);
     __syncthreads();
     if (!J.work) item += gridDim.x;
   }
@@ -2135,18 +2138,20 @@ hipError_t gdg_launch_zero(int* p, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, int waves, int grid, int lds,
-                           const gdg_trace_dev& tr, hipStream_t st) {
+hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, bool low, int waves, int grid,
+                           int lds, const gdg_trace_dev& tr, hipStream_t st) {
   dim3 g(grid), block(waves * kWave);
   const bool learn = J.learn.mode != 0;
   int b = 0;
-#define GDG_LAUNCH(V)                                                                   \
-  if (b++ == bucket) {                                                                  \
-    if (learn)                                                                          \
-      hipLaunchKernelGGL((gdg_decode_kernel<V, true>), g, block, lds, st, J, tr);       \
-    else                                                                                \
-      hipLaunchKernelGGL((gdg_decode_kernel<V, false>), g, block, lds, st, J, tr);      \
-    return hipGetLastError();                                                           \
+#define GDG_LAUNCH(V)                                                                      \
+  if (b++ == bucket) {                                                                     \
+    if (learn)                                                                             \
+      hipLaunchKernelGGL((gdg_decode_kernel<V, true, false>), g, block, lds, st, J, tr);   \
+    else if (low)                                                                          \
+      hipLaunchKernelGGL((gdg_decode_kernel<V, false, true>), g, block, lds, st, J, tr);   \
+    else                                                                                   \
+      hipLaunchKernelGGL((gdg_decode_kernel<V, false, false>), g, block, lds, st, J, tr);  \
+    return hipGetLastError();                                                              \
   }
   GDG_DECODE_TILINGS(GDG_LAUNCH)
 #undef GDG_LAUNCH
@@ -2172,15 +2177,17 @@ int gdg_kernel_bucket(int m, int n_act) {
 }
 
 hipError_t gdg_decode_set_lds_limit(int bucket, int bytes) {
-  static const void* const fs[2 * kBuckets] = {
-#define GDG_FN(V) (const void*)gdg_decode_kernel<V, false>, (const void*)gdg_decode_kernel<V, true>,
+  static const void* const fs[3 * kBuckets] = {
+#define GDG_FN(V)                                                                           \
+  (const void*)gdg_decode_kernel<V, false, false>, (const void*)gdg_decode_kernel<V, true, false>, \
+      (const void*)gdg_decode_kernel<V, false, true>,
       GDG_DECODE_TILINGS(GDG_FN)
 #undef GDG_FN
   };
   if (bucket < 0 || bucket >= kBuckets) return hipErrorInvalidValue;
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < 3; ++l) {
     const hipError_t e =
-        hipFuncSetAttribute(fs[bucket * 2 + l], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        hipFuncSetAttribute(fs[bucket * 3 + l], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
