@@ -581,6 +581,25 @@ __device__ __forceinline__ void set_status(PathCtx<VPL>& P, int r, int v, int va
   P.post[v] = kInfF;
 }
 
+// set_status for a VN index v that is uniform over the wavefront (a
+// decision): the stores address v directly, and only the owning lane's
+// register r = v / 64 changes.
+template <int VPL>
+__device__ __forceinline__ void set_status_uniform(PathCtx<VPL>& P, int v, int value) {
+  const bool own = P.lane == (v & (kWave - 1));
+  if (own) {
+    P.status[v] = (int8_t)value;
+    P.post[v] = kInfF;
+  }
+  const int rv = v >> 6;
+#pragma unroll
+  for (int r = 0; r < VPL; ++r)
+    if (own && r == rv) {
+      P.set_st(r, value);
+      P.act_edges -= P.vdg(r);
+    }
+}
+
 // Whether the priors of the path's VNs fixed to 1 (decimated or peeled) sum
 // past the stopping threshold *thr (+infinity until a path has converged).
 template <int VPL>
@@ -1448,6 +1467,10 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             split = w.g + 1 + (pid - (1 << w.g));
             dmax = split + w.extra;
           }
+          // uniform: scalar registers
+          pid = __builtin_amdgcn_readfirstlane(pid);
+          dmax = __builtin_amdgcn_readfirstlane(dmax);
+          split = __builtin_amdgcn_readfirstlane(split);
         };
         represent(lo);
         const bool record = run == 0 && mode == 2 && pid == 0;
@@ -1507,9 +1530,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           const int gsel = __builtin_amdgcn_readfirstlane(tq[8 * ti + 3]);
           const int val = __builtin_amdgcn_readfirstlane(tq[8 * ti + 4]);
           const int n_agg = __builtin_amdgcn_readfirstlane(tq[8 * ti + 7]);
-#pragma unroll
-          for (int r = 0; r < VPL; ++r)
-            if (lane + kWave * r == gsel) set_status(P, r, gsel, val);
+          set_status_uniform(P, gsel, val);
           if (dlog && lane < size && d0 - 2 < tr.log_cap) {
             int* row = dlog + lane * dlog_step + (d0 - 2) * 3;
             row[0] = gsel;
@@ -1749,9 +1770,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
               val = 1 - fav;
             }
           }
-#pragma unroll
-          for (int r = 0; r < VPL; ++r)
-            if (lane + kWave * r == gsel) set_status(P, r, gsel, val);
+          set_status_uniform(P, gsel, val);
           if (dlog && lane < size && D - 1 < tr.log_cap) {
             int* row = dlog + lane * dlog_step + (D - 1) * 3;
             row[0] = gsel;
