@@ -900,8 +900,21 @@ __device__ __forceinline__ void ck_move(D* d, const S* s, int bytes, int lane) {
   for (int i = lane; i < n; i += kWave) d[i] = s[i];
 }
 
+// The restore is on the claiming wavefront's critical path: four loads in
+// flight per lane rather than one.
 __device__ __forceinline__ void ck_copy(void* dst, const uint4* src, int bytes, int lane) {
-  ck_move((gdg_lds_u4*)dst, (const gdg_glb_u4*)src, bytes, lane);
+  gdg_lds_u4* d = (gdg_lds_u4*)dst;
+  const gdg_glb_u4* q = (const gdg_glb_u4*)src;
+  const int n = (bytes + 15) / 16;
+  int i = lane;
+  for (; i + 3 * kWave < n; i += 4 * kWave) {
+    const gdg_u32x4 a = q[i], b = q[i + kWave], c = q[i + 2 * kWave], e = q[i + 3 * kWave];
+    d[i] = a;
+    d[i + kWave] = b;
+    d[i + 2 * kWave] = c;
+    d[i + 3 * kWave] = e;
+  }
+  for (; i < n; i += kWave) d[i] = q[i];
 }
 
 __device__ __forceinline__ void ck_save(uint4* dst, const void* src, int bytes, int lane) {
