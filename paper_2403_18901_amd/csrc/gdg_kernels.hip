@@ -2014,35 +2014,43 @@ __global__ __launch_bounds__(256) void gdg_bp_kernel(gdg_win_dev w, int n_shots,
 // decided 1 that touch the row (Eq. 7-8 update). Rows are disjoint per thread,
 // so no atomics. Observables likewise, one thread per (shot, observable).
 
-// One thread per (shot, affected DEM row or observable). Shot s's row r lives
+// Folds a window's committed correction into the later rows and the
+// observables of each shot (one workgroup per shot). Shot s's row r lives
 // at det[s * det_stride + r] and observable o at obs[s * obs_stride + o]; with
 // per-shot offsets (det_off non-null) at det[det_off[s] + r - row0] and
 // obs[obs_off[s] + o] instead.
-__global__ void gdg_commit_kernel(gdg_commit_dev cm, int n_shots, const uint8_t* __restrict__ ehat,
-                                  uint8_t* __restrict__ det, long long det_stride,
-                                  uint8_t* __restrict__ obs, long long obs_stride,
-                                  const long long* __restrict__ det_off,
-                                  const long long* __restrict__ obs_off, int row0) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long per = (long long)cm.n_rows + cm.n_obs;
-  const long long total = per * n_shots;
-  if (i >= total) return;
-  const int shot = (int)(i / per);
-  const int r = (int)(i % per);
+__global__ __launch_bounds__(256) void gdg_commit_kernel(
+    gdg_commit_dev cm, int n_shots, const uint8_t* __restrict__ ehat, uint8_t* __restrict__ det,
+    long long det_stride, uint8_t* __restrict__ obs, long long obs_stride,
+    const long long* __restrict__ det_off, const long long* __restrict__ obs_off, int row0) {
+  // one workgroup per shot: its correction bytes are staged in LDS with
+  // coalesced loads, then each thread folds whole rows / observables
+  extern __shared__ __align__(16) unsigned char es[];
+  const int shot = blockIdx.x;
+  if (shot >= n_shots) return;
   const uint8_t* e = ehat + (long long)shot * cm.n_win;
-  if (r < cm.n_rows) {
-    int x = 0;
-    for (int t = cm.row_ptr[r]; t < cm.row_ptr[r + 1]; ++t) x ^= e[cm.row_col[t]];
-    if (x) {
-      const long long at = det_off ? det_off[shot] + (cm.row_global[r] - row0)
-                                   : (long long)shot * det_stride + cm.row_global[r];
-      det[at] ^= 1;
-    }
+  if ((cm.n_win & 3) == 0 && (((uintptr_t)ehat) & 3) == 0) {
+    const uint32_t* e4 = (const uint32_t*)e;
+    for (int c = threadIdx.x; c < cm.n_win / 4; c += blockDim.x) ((uint32_t*)es)[c] = e4[c];
   } else {
-    const int o = r - cm.n_rows;
-    int x = 0;
-    for (int t = cm.obs_ptr[o]; t < cm.obs_ptr[o + 1]; ++t) x ^= e[cm.obs_col[t]];
-    if (x) obs[(obs_off ? obs_off[shot] : (long long)shot * obs_stride) + o] ^= 1;
+    for (int c = threadIdx.x; c < cm.n_win; c += blockDim.x) es[c] = e[c];
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < cm.n_rows + cm.n_obs; r += blockDim.x) {
+    if (r < cm.n_rows) {
+      int x = 0;
+      for (int t = cm.row_ptr[r]; t < cm.row_ptr[r + 1]; ++t) x ^= es[cm.row_col[t]];
+      if (x) {
+        const long long at = det_off ? det_off[shot] + (cm.row_global[r] - row0)
+                                     : (long long)shot * det_stride + cm.row_global[r];
+        det[at] ^= 1;
+      }
+    } else {
+      const int o = r - cm.n_rows;
+      int x = 0;
+      for (int t = cm.obs_ptr[o]; t < cm.obs_ptr[o + 1]; ++t) x ^= es[cm.obs_col[t]];
+      if (x) obs[(obs_off ? obs_off[shot] : (long long)shot * obs_stride) + o] ^= 1;
+    }
   }
 }
 
@@ -2243,12 +2251,11 @@ hipError_t gdg_launch_commit(const gdg_commit_dev& cm, int n_shots, const uint8_
                              uint8_t* det, long long det_stride, uint8_t* obs,
                              long long obs_stride, const long long* det_off,
                              const long long* obs_off, int row0, hipStream_t st) {
-  const long long total = ((long long)cm.n_rows + cm.n_obs) * n_shots;
-  if (total == 0) return hipSuccess;
-  const int bs = 256;
-  const long long nb = (total + bs - 1) / bs;
-  hipLaunchKernelGGL(gdg_commit_kernel, dim3((unsigned)nb), dim3(bs), 0, st, cm, n_shots, ehat,
-                     det, det_stride, obs, obs_stride, det_off, obs_off, row0);
+  if (n_shots <= 0 || cm.n_rows + cm.n_obs == 0) return hipSuccess;
+  // n_win <= 65535 (a window's column limit): within the default LDS limit
+  const size_t lds = ((size_t)cm.n_win + 15) & ~(size_t)15;
+  hipLaunchKernelGGL(gdg_commit_kernel, dim3((unsigned)n_shots), dim3(256), lds, st, cm, n_shots,
+                     ehat, det, det_stride, obs, obs_stride, det_off, obs_off, row0);
   return hipGetLastError();
 }
 
