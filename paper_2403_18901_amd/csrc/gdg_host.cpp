@@ -691,9 +691,19 @@ int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
   // the plans' minimum if larger): shots with larger sub-graphs then still
   // get all their path wavefronts.
   const int wps = gdg_decode_waves_per_simd(bucket, J.learn.mode != 0);
-  const int wg_per_cu = 4 * wps / waves;
+  int wg_per_cu = 4 * wps / waves;
+  // A launch with fewer shots than that many workgroups per CU (small
+  // streaming batches) needs fewer per CU: each then gets a larger share, so
+  // large sub-graphs still fit all their path wavefronts and a shot's latency
+  // does not grow.
+  if (workgroups <= 0) {
+    const int need = (int)((total + (long long)cu_count() - 1) / cu_count());
+    wg_per_cu = std::max(1, std::min(wg_per_cu, need));
+  }
   if (wg_per_cu >= 2)   // whole 2 KiB granules, so that the shares add up within the CU
     lds = std::max(lds, std::min(lds_per_cu() / wg_per_cu / 2048 * 2048, max_lds_per_block()));
+  else   // one per CU: most of the CU's LDS (the full 160 KiB is refused as a dynamic size)
+    lds = std::max(lds, (max_lds_per_block() - 16384) / 2048 * 2048);
   J.lds = lds;
   if (lds > g_lds_set[bucket]) {
     hipError_t e = gdg_decode_set_lds_limit(bucket, lds);
