@@ -1402,9 +1402,10 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       // path's metric cannot be the answer and stops. The comparison is in
       // FP32 against the metric widened by 2e-5, far above the rounding of
       // either side; the answer, its metric and the flags are unchanged (a
-      // stop needs a converged path). Off when traces of every path are asked
-      // for.
-      const bool bound = !learned && mode == 0 && w.bound_ok && !tr.dec && !tr.ends && !tr.step_lsum;
+      // stop needs a converged path; a learned answer's fallback test reads
+      // only the best metric). Off in record mode and when traces of every
+      // path are asked for.
+      const bool bound = mode != 2 && w.bound_ok && !tr.dec && !tr.ends && !tr.step_lsum;
       if (tid == 0) {
         int nt = 0;
         auto push0 = [&](int plo, int psize) {
