@@ -2016,41 +2016,57 @@ __global__ __launch_bounds__(256) void gdg_bp_kernel(gdg_win_dev w, int n_shots,
 // so no atomics. Observables likewise, one thread per (shot, observable).
 
 // Folds a window's committed correction into the later rows and the
-// observables of each shot (one workgroup per shot). Shot s's row r lives
+// observables of each shot (a workgroup per few shots). Shot s's row r lives
 // at det[s * det_stride + r] and observable o at obs[s * obs_stride + o]; with
 // per-shot offsets (det_off non-null) at det[det_off[s] + r - row0] and
 // obs[obs_off[s] + o] instead.
 __global__ __launch_bounds__(256) void gdg_commit_kernel(
-    gdg_commit_dev cm, int n_shots, const uint8_t* __restrict__ ehat, uint8_t* __restrict__ det,
-    long long det_stride, uint8_t* __restrict__ obs, long long obs_stride,
-    const long long* __restrict__ det_off, const long long* __restrict__ obs_off, int row0) {
-  // one workgroup per shot: its correction bytes are staged in LDS with
-  // coalesced loads, then each thread folds whole rows / observables
+    gdg_commit_dev cm, int n_shots, int spw, const uint8_t* __restrict__ ehat,
+    uint8_t* __restrict__ det, long long det_stride, uint8_t* __restrict__ obs,
+    long long obs_stride, const long long* __restrict__ det_off,
+    const long long* __restrict__ obs_off, int row0) {
+  // spw shots per workgroup: their correction bytes are staged in LDS with
+  // coalesced loads, then each thread folds whole rows / observables for all
+  // of them (one read of the row's column list serves every shot)
   extern __shared__ __align__(16) unsigned char es[];
-  const int shot = blockIdx.x;
-  if (shot >= n_shots) return;
-  const uint8_t* e = ehat + (long long)shot * cm.n_win;
+  const int nw = (cm.n_win + 15) & ~15;
+  const int s0 = blockIdx.x * spw;
+  const int ns = min(spw, n_shots - s0);
+  if (ns <= 0) return;
   if ((cm.n_win & 3) == 0 && (((uintptr_t)ehat) & 3) == 0) {
-    const uint32_t* e4 = (const uint32_t*)e;
-    for (int c = threadIdx.x; c < cm.n_win / 4; c += blockDim.x) ((uint32_t*)es)[c] = e4[c];
+    const int n4 = cm.n_win / 4;
+    for (int q = 0; q < ns; ++q) {
+      const uint32_t* e4 = (const uint32_t*)(ehat + (long long)(s0 + q) * cm.n_win);
+      for (int c = threadIdx.x; c < n4; c += blockDim.x) ((uint32_t*)(es + q * nw))[c] = e4[c];
+    }
   } else {
-    for (int c = threadIdx.x; c < cm.n_win; c += blockDim.x) es[c] = e[c];
+    for (int q = 0; q < ns; ++q) {
+      const uint8_t* e = ehat + (long long)(s0 + q) * cm.n_win;
+      for (int c = threadIdx.x; c < cm.n_win; c += blockDim.x) es[q * nw + c] = e[c];
+    }
   }
   __syncthreads();
   for (int r = threadIdx.x; r < cm.n_rows + cm.n_obs; r += blockDim.x) {
-    if (r < cm.n_rows) {
-      int x = 0;
-      for (int t = cm.row_ptr[r]; t < cm.row_ptr[r + 1]; ++t) x ^= es[cm.row_col[t]];
-      if (x) {
+    const bool is_row = r < cm.n_rows;
+    const int o = r - cm.n_rows;
+    const int t0 = is_row ? cm.row_ptr[r] : cm.obs_ptr[o];
+    const int t1 = is_row ? cm.row_ptr[r + 1] : cm.obs_ptr[o + 1];
+    const int* cols = is_row ? cm.row_col : cm.obs_col;
+    uint32_t xm = 0u;   // bit q: the parity for shot s0 + q
+    for (int t = t0; t < t1; ++t) {
+      const int c = cols[t];
+      for (int q = 0; q < ns; ++q) xm ^= (uint32_t)(es[q * nw + c] & 1u) << q;
+    }
+    for (int q = 0; q < ns; ++q) {
+      if (!((xm >> q) & 1u)) continue;
+      const int shot = s0 + q;
+      if (is_row) {
         const long long at = det_off ? det_off[shot] + (cm.row_global[r] - row0)
                                      : (long long)shot * det_stride + cm.row_global[r];
         det[at] ^= 1;
+      } else {
+        obs[(obs_off ? obs_off[shot] : (long long)shot * obs_stride) + o] ^= 1;
       }
-    } else {
-      const int o = r - cm.n_rows;
-      int x = 0;
-      for (int t = cm.obs_ptr[o]; t < cm.obs_ptr[o + 1]; ++t) x ^= es[cm.obs_col[t]];
-      if (x) obs[(obs_off ? obs_off[shot] : (long long)shot * obs_stride) + o] ^= 1;
     }
   }
 }
@@ -2253,10 +2269,13 @@ hipError_t gdg_launch_commit(const gdg_commit_dev& cm, int n_shots, const uint8_
                              long long obs_stride, const long long* det_off,
                              const long long* obs_off, int row0, hipStream_t st) {
   if (n_shots <= 0 || cm.n_rows + cm.n_obs == 0) return hipSuccess;
-  // n_win <= 65535 (a window's column limit): within the default LDS limit
-  const size_t lds = ((size_t)cm.n_win + 15) & ~(size_t)15;
-  hipLaunchKernelGGL(gdg_commit_kernel, dim3((unsigned)n_shots), dim3(256), lds, st, cm, n_shots,
-                     ehat, det, det_stride, obs, obs_stride, det_off, obs_off, row0);
+  // up to 8 shots per workgroup within 32 KiB of staged corrections (a
+  // window has at most 65535 columns: one shot then, within the default limit)
+  const size_t nw = ((size_t)cm.n_win + 15) & ~(size_t)15;
+  const int spw = (int)std::max<size_t>(1, std::min<size_t>(8, 32768 / nw));
+  const unsigned nb = (unsigned)((n_shots + spw - 1) / spw);
+  hipLaunchKernelGGL(gdg_commit_kernel, dim3(nb), dim3(256), (size_t)spw * nw, st, cm, n_shots,
+                     spw, ehat, det, det_stride, obs, obs_stride, det_off, obs_off, row0);
   return hipGetLastError();
 }
 
