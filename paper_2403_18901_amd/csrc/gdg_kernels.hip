@@ -616,7 +616,7 @@ __device__ __forceinline__ bool over_bound(const PathCtx<VPL>& P, int* thr) {
 // (a dead CN, or two different proposals for one VN; then the round is not
 // applied). Leaves P.sres recounted.
 template <int VPL>
-__device__ bool peel(PathCtx<VPL>& P) {
+__device__ __forceinline__ bool peel(PathCtx<VPL>& P) {
   for (;;) {
     bool dead, proposed;
     cn_recount(P, dead, proposed);
