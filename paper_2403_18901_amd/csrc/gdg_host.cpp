@@ -768,8 +768,8 @@ int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_sy
   return launch_jobs(&job, 1, win->waves, 0, tr, (hipStream_t)hip_stream);
 }
 
-// Persistent grid of the learned decode: two workgroups per CU on 256 CUs.
-constexpr int kLearnGrid = 512;
+// Persistent grid of the learned decode: three workgroups per CU on 256 CUs.
+constexpr int kLearnGrid = 768;
 
 size_t gdg_learned_work_bytes(const gdg_window* win) {
   if (!win) return 0;

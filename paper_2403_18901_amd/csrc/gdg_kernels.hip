@@ -1931,10 +1931,12 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
 // table; item i belongs to the job whose first item is the largest <= i. Jobs
 // may use windows of different codes (sizes): each job carries its own LDS
 // layout within the launch's allocation.
-// Register budget: three wavefronts per SIMD for the plain kernel with up to 7
-// VNs per lane (168 VGPRs; spills stay outside the BP loops), two otherwise.
+// Register budget: three wavefronts per SIMD with up to 7 VNs per lane (168
+// VGPRs; the plain kernel's spills stay outside the BP loops, the learned
+// kernel's reach the candidate scoring but the occupancy pays for them), two
+// otherwise.
 template <int VPL, bool kLearn>
-constexpr int kDecodeWavesPerSimd = (!kLearn && VPL <= 7) ? 3 : 2;
+constexpr int kDecodeWavesPerSimd = VPL <= 7 ? 3 : 2;
 
 template <int VPL, bool kLearn, bool kLow>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
