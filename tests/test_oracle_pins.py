@@ -348,3 +348,36 @@ def test_unit_column_prior_merge():
         for c in cols:                               # odd number of independent flips
             pe = pe * (1 - dem.priors[c]) + (1 - pe) * dem.priors[c]
         assert abs(ex["prior"][u] - pe) < 1e-15
+
+
+def test_decided_ones_bound_the_path_metric():
+    """The premise of the decoder's branch and bound over paths: a VN a path
+    decimates to 1 is 1 in that path's answer (decimation fixes it; Alg. 1 with
+    Fig. 2's guesses), so with positive priors the path's Eq. 5 metric is at
+    least the sum of the priors of its decisions to 1. Checked on every
+    converged path of the oracle's 16-path tree, replayed from its logs."""
+    dem = circuit_dem(get_code("72"), 6, 0.004)
+    prm = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=1, dmax_main=25,
+                   extra_steps=10)
+    e = sample_errors(dem.thresholds(), 80, seed=5)
+    det, _ = syndromes(dem, e)
+    w = O.OracleWindow(dem, 0, 3)
+    llr = w.export()["llr"]
+    assert (llr > 0).all()
+    syn = np.ascontiguousarray(det[:, w.row0:w.row0 + w.m])
+    out = w.decode(prm, syn, logs=True)
+    checked = 0
+    for s in range(syn.shape[0]):
+        if out["ends"][s, :, 1].max() == 0:
+            continue   # met the syndrome in the preprocessing: no paths
+        for p in range(out["dec"].shape[1]):
+            d = out["dec"][s, p]
+            steps = int((d[:, 0] >= 0).sum())
+            r = w.replay(prm, syn[s], out["sel"][s], p, d[:steps, 0], d[:steps, 1])
+            if r["end"] != 1:
+                continue
+            ones = [int(out["sel"][s][g]) for g, v in zip(d[:steps, 0], d[:steps, 1]) if v == 1]
+            assert all(r["e"][c] == 1 for c in ones), (s, p)
+            assert r["pm"] >= sum(llr[c] for c in ones) * (1 - 1e-12), (s, p)
+            checked += 1
+    assert checked > 0
