@@ -25,10 +25,10 @@ N_CU = 256
 def _bucket(w) -> int:
     """The kernel's register tiling for a window (VNs per lane)."""
     na = w.n_act
-    for b, cap in enumerate((384, 448, 512)):
+    for b, cap in enumerate((384, 448, 512, 896)):
         if na <= cap:
             return b
-    return 3
+    return 4
 
 
 class LaunchPlan:

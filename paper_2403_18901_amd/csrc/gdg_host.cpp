@@ -648,7 +648,7 @@ size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots) {
 
 namespace {
 
-int g_lds_set[4] = {65536, 65536, 65536, 65536};   // dynamic-LDS limit set per kernel bucket
+int g_lds_set[5] = {65536, 65536, 65536, 65536, 65536};   // dynamic-LDS limit set per kernel bucket
 
 int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
                 const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn = nullptr) {

@@ -2189,8 +2189,8 @@ __global__ void gdg_evaluate_kernel(int n_shots, int n_rows, int n_obs,
 // ------------------------------------------------------------------ launchers
 
 // Register tilings of the decode kernel: VNs per lane of each bucket.
-#define GDG_DECODE_TILINGS(X) X(6) X(7) X(8) X(16)
-constexpr int kBuckets = 4;
+#define GDG_DECODE_TILINGS(X) X(6) X(7) X(8) X(14) X(16)
+constexpr int kBuckets = 5;
 
 hipError_t gdg_launch_zero(int* p, int n, hipStream_t st) {
   hipLaunchKernelGGL(gdg_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
@@ -2231,7 +2231,8 @@ int gdg_kernel_bucket(int m, int n_act) {
   if (n_act <= 384) return 0;
   if (n_act <= 448) return 1;
   if (n_act <= 512) return 2;
-  if (n_act <= 1024) return 3;
+  if (n_act <= 896) return 3;
+  if (n_act <= 1024) return 4;
   return -1;
 }
 
