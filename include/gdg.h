@@ -138,6 +138,10 @@ size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots);
  *             step (NaN for decimated VNs)
  *  edge_iters [n_shots] int64: active edges summed over the BP iterations run
  *             (paths of Fig. 2's tree share their iterations until they split)
+ * When dec, ends or step_lsum is requested every path runs to its end; without
+ * them a path stops once the priors of its VNs fixed to 1 exceed a converged
+ * path's Eq. 5 metric (it cannot be the answer). The answer, its metric and
+ * the flags are the same either way; edge_iters can be lower without them.
  *  step_lsum  [n_shots][n_paths][log_cap][n_act] float: each VN's sum of its
  *             last four posteriors at the end of every step's BP run (the
  *             Alg. 1 key), NaN for decimated VNs and unused steps
@@ -200,7 +204,8 @@ int gdg_decode_jobs(const gdg_job* jobs, int32_t n_jobs, const gdg_launch_cfg* c
                     void* hip_stream);
 
 /* Least LDS bytes per workgroup the jobs need at `waves` wavefronts (negative on
- * error); a launch allocates up to the CU's share at the kernel's occupancy, and
+ * error); a launch allocates up to the CU's share at the kernel's occupancy (a
+ * larger share when it has fewer shots than that many workgroups per CU), and
  * each shot uses as many path wavefronts as fit in it. */
 int gdg_jobs_lds_bytes(const gdg_job* jobs, int32_t n_jobs, int32_t waves);
 
