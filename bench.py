@@ -426,6 +426,26 @@ def bench_learned(args):
                    "value_at_p": 0.002},
         "by_p": rows,
     }
+    # the proposer's network alone: BF16 matrix-core inference of 2^20 samples,
+    # algorithmic MACs (17x64 + 64x64 + 64 per sample) against the dense BF16
+    # peak (2.5 PFLOP/s = 1.25e15 MAC/s)
+    model = G.Model(params)
+    n = 1 << 20
+    x = torch.rand((n, G.MLP_IN), device="cuda")
+    model.infer(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        model.infer(x)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    macs = n * (G.MLP_IN * G.MLP_H + G.MLP_H * G.MLP_H + G.MLP_H)
+    out["mlp_infer"] = {"samples": n, "ms": ms, "mac_per_s": macs / (ms * 1e-3),
+                        "peak_mac_per_s": 1.25e15, "frac": macs / (ms * 1e-3) / 1.25e15}
     print(json.dumps(out))
 
 

@@ -162,18 +162,22 @@ __global__ void mlp_adam_kernel(int t, float lr, float b1, float b2, float eps,
   prm[p] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// Standalone BF16 inference of 16-sample tiles through mlp_score_tile.
+// Standalone BF16 inference of 16-sample tiles through mlp_score_tile; each
+// wavefront walks tiles with a grid stride, so the weights it loads (loop
+// invariant) stay in registers rather than being read again per tile.
 __global__ __launch_bounds__(64) void mlp_infer_kernel(gdg_model_dev md, int n,
                                                        const float* __restrict__ x,
                                                        float* __restrict__ z) {
   const int lane = threadIdx.x;
   const int c = lane & 15, q = lane >> 4;
-  const int s = blockIdx.x * 16 + c;
-  float f[4], deg = 0.0f;
-  for (int j = 0; j < 4; ++j) f[j] = s < n ? x[(long long)s * kIn + 4 * q + j] : 0.0f;
-  if (s < n) deg = x[(long long)s * kIn + 16];
-  const float out = mlp_score_tile(md, f, deg);
-  if (q == 0 && s < n) z[s] = out;
+  for (int t = blockIdx.x; t * 16 < n; t += gridDim.x) {
+    const int s = t * 16 + c;
+    float f[4], deg = 0.0f;
+    for (int j = 0; j < 4; ++j) f[j] = s < n ? x[(long long)s * kIn + 4 * q + j] : 0.0f;
+    if (s < n) deg = x[(long long)s * kIn + 16];
+    const float out = mlp_score_tile(md, f, deg);
+    if (q == 0 && s < n) z[s] = out;
+  }
 }
 
 }  // namespace
@@ -206,6 +210,10 @@ hipError_t gdg_launch_mlp_adam(int t, float lr, float b1, float b2, float eps, f
 
 hipError_t gdg_launch_mlp_infer(const gdg_model_dev& md, int n, const float* x, float* z,
                                 hipStream_t st) {
-  hipLaunchKernelGGL(mlp_infer_kernel, dim3((n + 15) / 16), dim3(64), 0, st, md, n, x, z);
+  // 24 wavefronts per CU on 256 CUs (as many as its registers allow), or one
+  // per tile if fewer
+  const int tiles = (n + 15) / 16;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3(tiles < 6144 ? tiles : 6144), dim3(64), 0, st, md, n,
+                     x, z);
   return hipGetLastError();
 }
