@@ -478,9 +478,22 @@ def cpu_baseline(dem, args, nwin):
     t = time.perf_counter()
     r = O.decode_shots(dem, 3, op, det, obs, n_threads=threads)
     dt = time.perf_counter() - t
+    # single-thread latency of one window decode (the first window, one shot
+    # per call, window built once)
+    w0 = O.OracleWindow(dem, 0, 3)
+    syn0 = np.ascontiguousarray(det[:, w0.row0:w0.row0 + w0.m])
+    lat = []
+    for i in range(min(200, n)):
+        t1 = time.perf_counter()
+        w0.decode(op, syn0[i:i + 1], n_threads=1)
+        lat.append((time.perf_counter() - t1) * 1e3)
     return {"value": n * nwin / dt, "unit": "windows/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} shots x {nwin} windows of the same workload (first {n} shots of "
-                      f"seed {args.seed}), {dt:.1f} s, {int(r['fail'].sum())} failures"}
+                      f"seed {args.seed}), {dt:.1f} s, {int(r['fail'].sum())} failures",
+            "window_ms_p50": float(np.percentile(lat, 50)),
+            "window_ms_p99": float(np.percentile(lat, 99)),
+            "latency_sample": f"first window of the first {len(lat)} shots, one thread, "
+                              "one shot per call"}
 
 
 if __name__ == "__main__":
