@@ -363,7 +363,8 @@ def bench_stream(args):
 def bench_learned(args):
     """Learned proposer (trained weights shipped with the package) against
     plain GDG on held-out [[144,12,12]] shots at p = 0.001, 0.002, 0.003:
-    windows/s, batch window latency, BP work and logical failures."""
+    windows/s, batch window latency, BP work (edge-iterations per window) and
+    logical failures, and the network's matrix-core throughput on its own."""
     import torch
     from gdg_inputs.bb import get_code
     from gdg_inputs.dem import circuit_dem
@@ -388,14 +389,22 @@ def bench_learned(args):
             t0 = time.perf_counter()
             wins = []
             fl_all = []
+            ei = torch.zeros((dec.n_windows, B), dtype=torch.int64, device="cuda")
             for k, w in enumerate(dec.windows):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()
                 if name == "plain":
-                    eh, pm, fl = w.decode(det, syn_offset=w.row0)
+                    eh = torch.empty((B, w.n), dtype=torch.uint8, device="cuda")
+                    pm = torch.empty(B, dtype=torch.float64, device="cuda")
+                    fl = torch.empty(B, dtype=torch.int32, device="cuda")
+                    tr = G.Trace(None, None, 0, None, None, G._ptr(ei[k]), None)
+                    G._check(G.lib().gdg_decode_batch(w.h, B, G._ptr(det, w.row0), det.shape[1],
+                                                       G._ptr(eh), G._ptr(pm), G._ptr(fl), None,
+                                                       0, G.C.byref(tr), G._stream()))
                 else:
-                    eh, pm, fl = G.decode_learned(w, det, w.row0, dec.cfg(), dec.model, dec.work)
+                    eh, pm, fl = G.decode_learned(w, det, w.row0, dec.cfg(ei[k]), dec.model,
+                                                  dec.work)
                 w.commit(eh, det, obs)
                 e1.record()
                 wins.append((e0, e1))
@@ -408,7 +417,8 @@ def bench_learned(args):
             row[name] = {"windows_per_s": B * dec.n_windows / dt, "failures": fail,
                          "P_L": fail / B, "batch_window_ms_p50": float(np.percentile(lat, 50)),
                          "batch_window_ms_p99": float(np.percentile(lat, 99)),
-                         "fallback_frac": fb}
+                         "fallback_frac": fb,
+                         "edge_iters_per_window": float(ei.sum().item()) / (B * dec.n_windows)}
         row["speedup"] = row["learned"]["windows_per_s"] / row["plain"]["windows_per_s"]
         rows[str(p)] = row
     head = rows["0.002"]
