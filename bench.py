@@ -48,7 +48,7 @@ def parse():
                     help="single-shot windows timed for the latency figures")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=["c2", "mixed", "stream", "learned"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c1", "mixed", "stream", "learned"], default="c2",
                     help="c2: [[144,12,12]] (the headline); mixed: five BB codes in shared "
                          "persistent launches with the autotuner; stream: the streaming "
                          "service over 256 [[144]] + 32 [[288]] blocks; learned: the "
@@ -75,16 +75,25 @@ def main():
         return bench_learned(args)
     import torch
     from gdg_inputs.bb import get_code
-    from gdg_inputs.dem import circuit_dem
+    from gdg_inputs.dem import circuit_dem, phenomenological_dem
     import paper_2403_18901_amd.gdg as G
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    code = get_code(args.code)
-    dem = circuit_dem(code, args.rounds, args.p)
-    low_error = 1 if args.p <= 0.002 else 0
-    prm = G.params(alpha=1.0, g=args.g, pre_iters=8, trunc_factor=2, low_error=low_error,
-                   dmax_main=25, extra_steps=10)
+    c1 = args.workload == "c1"
+    if c1:
+        # [[72,12,6]] phenomenological, p = q = 0.005, 6 noisy rounds: the main
+        # path only (plain BPGD, no preprocessing), alpha = 0.625
+        code = get_code("72")
+        dem = phenomenological_dem(code, 6, 0.005, 0.005)
+        low_error = 1
+        prm = G.params(alpha=0.625, g=0, pre_iters=0, low_error=1, dmax_main=25)
+    else:
+        code = get_code(args.code)
+        dem = circuit_dem(code, args.rounds, args.p)
+        low_error = 1 if args.p <= 0.002 else 0
+        prm = G.params(alpha=1.0, g=args.g, pre_iters=8, trunc_factor=2, low_error=low_error,
+                       dmax_main=25, extra_steps=10)
     dec = G.SlidingWindowDecoder(dem, prm, W=3)
     ddem = G.DeviceDem(dem)
     B = args.shots
@@ -184,18 +193,20 @@ def main():
 
     cpu = None
     if args.cpu_seconds > 0:
-        cpu = cpu_baseline(dem, args, nwin)
+        cpu = cpu_baseline(dem, args, nwin, c1)
 
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "decode_traffic.txt")
-    if os.path.exists(tpath):
+    if not c1 and os.path.exists(tpath):   # the summary covers the C2 workload
         with open(tpath) as f:
             t = json.load(f)
         if t.get("kernel_hash") == kernel_hash():
             traffic = t["bytes_per_shot"] * B
 
     out = {
-        "metric": "decoded windows/s and p99 window latency, [[144,12,12]] GDG at matched LER",
+        "metric": ("decoded windows/s and p99 window latency, [[72,12,6]] phenomenological "
+                   "BPGD (main path)" if c1 else
+                   "decoded windows/s and p99 window latency, [[144,12,12]] GDG at matched LER"),
         "value": value,
         "unit": "windows/s",
         "n_gpus": 1,
@@ -208,12 +219,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"GDG g={args.g} ({1 << args.g} paths), [[{code.n},12,12]] "
-                        f"circuit-level p={args.p}, {args.rounds} rounds, (3,1) windows "
-                        f"x {nwin} per shot, {B} shots per step, FP32 messages",
-            "code": code.name, "p": args.p, "rounds": args.rounds, "W": 3, "F": 1,
-            "shots_per_step": B, "windows_per_shot": nwin,
-            "low_error_mode": bool(low_error), "pre_iters": 8, "n_act": dec.windows[1].n_act,
+            "workload": (f"BPGD main path (alpha 0.625), [[72,12,6]] phenomenological "
+                         f"p=q=0.005, 6 rounds, (3,1) windows x {nwin} per shot, {B} shots "
+                         f"per step, FP32 messages" if c1 else
+                         f"GDG g={args.g} ({1 << args.g} paths), [[{code.n},12,12]] "
+                         f"circuit-level p={args.p}, {args.rounds} rounds, (3,1) windows "
+                         f"x {nwin} per shot, {B} shots per step, FP32 messages"),
+            "code": code.name, "p": 0.005 if c1 else args.p, "rounds": 6 if c1 else args.rounds,
+            "W": 3, "F": 1, "shots_per_step": B, "windows_per_shot": nwin,
+            "low_error_mode": bool(low_error), "pre_iters": 0 if c1 else 8,
+            "n_act": dec.windows[1].n_act,
             "waves_per_workgroup": dec.windows[1].info["waves"],
             "lds_bytes": dec.windows[1].info["lds_bytes"],
         },
@@ -467,13 +482,16 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(dem, args, nwin):
+def cpu_baseline(dem, args, nwin, c1=False):
     """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
     from gdg_inputs.philox import sample_errors, syndromes
     from oracle import oracle as O
     threads = len(os.sched_getaffinity(0))
-    op = O.params(alpha=1.0, g=args.g, pre_iters=8, trunc_factor=2,
-                  low_error=1 if args.p <= 0.002 else 0)
+    if c1:
+        op = O.params(alpha=0.625, g=0, pre_iters=0, low_error=1, dmax_main=25)
+    else:
+        op = O.params(alpha=1.0, g=args.g, pre_iters=8, trunc_factor=2,
+                      low_error=1 if args.p <= 0.002 else 0)
     # calibrate on a small sample (large enough that building the windows does
     # not dominate), then size the sample to the time budget
     n0 = max(16 * threads, 256)
