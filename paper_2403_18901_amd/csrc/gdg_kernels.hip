@@ -1609,10 +1609,13 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
           const bool on_main = learned && !lrn.tree ? !deviated : path_on_main(w, pid, split, D);
           unsigned long long kall = ~0ull, kneg = ~0ull;
           int n_agg = 0;
+          // the proposer picks this step's candidate; Alg. 1's keys are then
+          // unused, and in low-error mode (no Alg. 3) the pass is skipped
+          const bool use_mlp = kLearn && (learned || (record && D <= lrn.rec_steps));
 #pragma unroll
           for (int r = 0; r < VPL; ++r) {
             const int v = lane + kWave * r;
-            if (v < n_act && P.st(r) < 0 && P.vdg(r) >= 3) {
+            if (!(use_mlp && low_err) && v < n_act && P.st(r) < 0 && P.vdg(r) >= 3) {
               bool taken = false;
               if (!low_err) {
                 int nu = 0;
@@ -1633,7 +1636,7 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
             }
           }
           int gsel, fav, val;
-          if (kLearn && (learned || (record && D <= lrn.rec_steps))) {
+          if (use_mlp) {
             // the proposer's candidates: the first n_cand VNs in Alg. 1's order
             // key: all-<=0 class first, then L_sum, then index
             unsigned long long mine = ~0ull;   // lane l: candidate l % 16
