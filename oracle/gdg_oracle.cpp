@@ -504,8 +504,19 @@ struct PathResult {
   std::vector<double> first_post;   // posteriors after the first step's iterations
 };
 
+// Diagnostics of one path, per decimation step (test hooks only; nothing here
+// feeds back into the decoding): the posteriors and the four-value history at
+// the end of the step's BP run, the VN status before the step's Alg. 3 pass,
+// each VN's count of unsatisfied CN neighbours and its Alg. 3 decision.
+struct PathProbe {
+  int max_steps = 0, steps = 0;
+  double *post = nullptr, *hsum = nullptr, *hmin = nullptr, *hmax = nullptr;
+  int *status = nullptr, *n_unsat = nullptr, *agg = nullptr;
+};
+
 PathResult run_path(const Graph& g, const Status& st0, const orc_params& P, const PathSpec& ps,
-                    const int* forced_g, const int* forced_v, int n_forced) {
+                    const int* forced_g, const int* forced_v, int n_forced,
+                    PathProbe* probe = nullptr) {
   PathResult res;
   Status st = st0;
   Messages ms;
@@ -546,6 +557,19 @@ PathResult run_path(const Graph& g, const Status& st0, const orc_params& P, cons
     std::vector<int> agg;
     int fav = 0;
     int sel = select_vn(st.vn, g.deg, h, P.low_error != 0, D, on_main, n_unsat, &agg, &fav);
+    if (probe && D - 1 < probe->max_steps) {
+      const size_t o = (size_t)(D - 1) * g.n;
+      for (int c = 0; c < g.n; ++c) {
+        probe->post[o + c] = ms.post[c];
+        probe->hsum[o + c] = h.sum[c];
+        probe->hmin[o + c] = h.mn[c];
+        probe->hmax[o + c] = h.mx[c];
+        probe->status[o + c] = st.vn[c];
+        probe->n_unsat[o + c] = n_unsat[c];
+        probe->agg[o + c] = agg[c];
+      }
+      probe->steps = D;
+    }
     int n_agg = 0;
     for (int c = 0; c < g.n; ++c)
       if (agg[c] >= 0) {
@@ -1192,6 +1216,76 @@ void orc_dense_bp(int m, int n, const uint8_t* dense, const double* llr, const u
     bp_iteration(g, st, *P, ms);
     std::memcpy(post + (size_t)t * n, ms.post.data(), sizeof(double) * n);
   }
+}
+
+// A window-shaped problem from a dense [m][n] matrix and priors (no DEM).
+static Window dense_window(int m, int n, const uint8_t* dense, const double* llr) {
+  Window win;
+  win.m = m;
+  win.n = n;
+  win.col_rows.assign(n, {});
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < n; ++c)
+      if (dense[(size_t)r * n + c]) win.col_rows[c].push_back(r);
+  win.row_cols.assign(m, {});
+  for (int c = 0; c < n; ++c)
+    for (int r : win.col_rows[c]) win.row_cols[r].push_back(c);
+  win.llr.assign(llr, llr + n);
+  win.prior.resize(n);
+  win.src.resize(n);
+  win.commit.assign(n, 1);
+  return win;
+}
+
+// decode_window on a dense problem, preprocessing included when P->pre_iters
+// > 0: e[n], the kept columns in ranked order (kept[n], -1 padded; all n in
+// order without preprocessing), the ranking keys pre_lsum[n] (the sum of the
+// last four preprocessing posteriors; zeros without preprocessing). Returns
+// PM; *n_kept receives the number of kept columns (0 if the preprocessing met
+// the syndrome).
+double orc_dense_window(int m, int n, const uint8_t* dense, const double* llr, const uint8_t* syn,
+                        const orc_params* P, uint8_t* e, int* flags, int* kept, int* n_kept,
+                        double* pre_lsum) {
+  Window win = dense_window(m, n, dense, llr);
+  WindowResult wr;
+  decode_window(win, *P, syn, wr, nullptr, nullptr, nullptr, 0, -1);
+  std::memcpy(e, wr.e.data(), n);
+  if (flags) *flags = wr.flags;
+  if (n_kept) *n_kept = (int)wr.selected.size();
+  if (kept)
+    for (int i = 0; i < n; ++i) kept[i] = i < (int)wr.selected.size() ? wr.selected[i] : -1;
+  if (pre_lsum)
+    for (int c = 0; c < n; ++c) pre_lsum[c] = c < (int)wr.pre_lsum.size() ? wr.pre_lsum[c] : 0.0;
+  return wr.pm;
+}
+
+// One path (id path_id of the configured tree) of GDG on a dense problem, no
+// preprocessing, with the per-step diagnostics of PathProbe: arrays of
+// [max_steps][n]. Returns the number of steps probed (steps that reached the
+// Alg. 3 / Alg. 1 stage).
+int orc_dense_path_probe(int m, int n, const uint8_t* dense, const double* llr,
+                         const uint8_t* syn, const orc_params* P, int path_id, int max_steps,
+                         double* post, double* hsum, double* hmin, double* hmax, int* status,
+                         int* n_unsat, int* agg) {
+  Window win = dense_window(m, n, dense, llr);
+  Graph g = window_graph(win);
+  Status st0 = initial_status(g, syn);
+  if (!peel(g, st0)) return -1;
+  auto paths = path_set(*P);
+  PathSpec ps = paths[0];
+  for (auto& q : paths)
+    if (q.id == path_id) ps = q;
+  PathProbe probe;
+  probe.max_steps = max_steps;
+  probe.post = post;
+  probe.hsum = hsum;
+  probe.hmin = hmin;
+  probe.hmax = hmax;
+  probe.status = status;
+  probe.n_unsat = n_unsat;
+  probe.agg = agg;
+  run_path(g, st0, *P, ps, nullptr, nullptr, 0, &probe);
+  return probe.steps;
 }
 
 // GDG on a dense [m][n] problem with the given priors (no windowing, no

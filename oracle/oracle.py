@@ -84,6 +84,10 @@ def lib():
         L.orc_dense_bp.argtypes = [i32, i32, P, P, P, P, i32, P]
         L.orc_dense_gdg.argtypes = [i32, i32, P, P, P, P, P, P]
         L.orc_dense_gdg.restype = C.c_double
+        L.orc_dense_window.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_dense_window.restype = C.c_double
+        L.orc_dense_path_probe.argtypes = [i32, i32, P, P, P, P, i32, i32] + [P] * 7
+        L.orc_dense_path_probe.restype = i32
         _lib = L
     return _lib
 
@@ -287,3 +291,41 @@ def dense_gdg(H, llr, syn, prm):
     pm = lib().orc_dense_gdg(H.shape[0], H.shape[1], _p(H), _p(llr), _p(syn), C.byref(prm),
                              _p(e), _p(fl))
     return pm, e, int(fl[0])
+
+
+def dense_window(H, llr, syn, prm):
+    """decode_window on a dense problem (preprocessing, ranking and truncation
+    included when prm.pre_iters > 0). Returns dict(pm, e, flags, kept (ranked
+    kept columns), lsum (ranking keys))."""
+    H = np.ascontiguousarray(H, np.uint8)
+    llr = np.ascontiguousarray(llr, np.float64)
+    syn = np.ascontiguousarray(syn, np.uint8)
+    n = H.shape[1]
+    e = np.zeros(n, np.uint8)
+    fl = np.zeros(1, np.int32)
+    kept = np.full(n, -1, np.int32)
+    nk = np.zeros(1, np.int32)
+    lsum = np.zeros(n, np.float64)
+    pm = lib().orc_dense_window(H.shape[0], n, _p(H), _p(llr), _p(syn), C.byref(prm), _p(e),
+                                _p(fl), _p(kept), _p(nk), _p(lsum))
+    return dict(pm=pm, e=e, flags=int(fl[0]), kept=kept[:int(nk[0])], lsum=lsum)
+
+
+def dense_path_probe(H, llr, syn, prm, path_id=0, max_steps=8):
+    """One GDG path on a dense problem (no preprocessing) with per-step
+    diagnostics: posteriors and history at the end of each step's BP run, the
+    status before the Alg. 3 pass, unsatisfied-CN counts and Alg. 3 decisions."""
+    H = np.ascontiguousarray(H, np.uint8)
+    llr = np.ascontiguousarray(llr, np.float64)
+    syn = np.ascontiguousarray(syn, np.uint8)
+    n = H.shape[1]
+    f = lambda: np.full((max_steps, n), np.nan)
+    i = lambda: np.full((max_steps, n), -9, np.int32)
+    post, hsum, hmin, hmax = f(), f(), f(), f()
+    status, nu, agg = i(), i(), i()
+    steps = lib().orc_dense_path_probe(H.shape[0], n, _p(H), _p(llr), _p(syn), C.byref(prm),
+                                       path_id, max_steps, _p(post), _p(hsum), _p(hmin),
+                                       _p(hmax), _p(status), _p(nu), _p(agg))
+    k = max(steps, 0)
+    return dict(steps=steps, post=post[:k], hsum=hsum[:k], hmin=hmin[:k], hmax=hmax[:k],
+                status=status[:k], n_unsat=nu[:k], agg=agg[:k])

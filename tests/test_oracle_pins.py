@@ -105,6 +105,116 @@ def test_tree_minsum_is_min_marginal_and_sumproduct_is_exact(seed):
     np.testing.assert_allclose(post_sp, marg, rtol=0, atol=1e-9)
 
 
+def _ranking_order_ok(kept, key, n_keep, tol=1e-9):
+    """kept lists the n_keep columns of smallest key in ascending key order,
+    equal keys (within tol) in ascending column order."""
+    if len(kept) != n_keep:
+        return False
+    for a, b in zip(kept[:-1], kept[1:]):
+        if key[a] > key[b] + tol or (abs(key[a] - key[b]) <= tol and a > b):
+            return False
+    last = kept[-1]
+    for c in set(range(len(key))) - set(kept.tolist()):
+        if key[c] < key[last] - tol or (abs(key[c] - key[last]) <= tol and c < last):
+            return False
+    return True
+
+
+def _tie_tree():
+    """A tree with symmetric leaves of equal prior: columns 1 and 2 (on CN 0)
+    and 6 and 7 (on CN 2) have identical min-marginals by symmetry."""
+    H = np.zeros((3, 8), np.uint8)
+    H[0, [0, 1, 2, 3]] = 1
+    H[1, [3, 4, 5]] = 1
+    H[2, [5, 6, 7]] = 1
+    llr = np.array([2.1, 0.7, 0.7, 1.3, 2.6, 0.9, 1.6, 1.6])
+    syn = np.array([1, 0, 1], np.uint8)
+    return H, llr, syn
+
+
+@pytest.mark.parametrize("pre_iters", [8, 16])
+@pytest.mark.parametrize("seed", list(range(10)) + ["ties"])
+def test_preprocessing_ranking_on_trees(seed, pre_iters):
+    """Preprocessing, ranking and truncation (Sec. III, last paragraphs; Sec.
+    IV-C) through decode_window itself. On a tree Tanner graph (alpha = 1, no
+    clipping reached) flooding min-sum reaches the exact min-marginal
+    differences within five iterations and stays there, so the ranking key of
+    every column -- the sum of its last four preprocessing posteriors -- must be
+    4 x the brute-force min-marginal. An extra check row with no columns and
+    syndrome 1 keeps the preprocessing from stopping early. The kept columns are
+    then the trunc_factor * m smallest keys in ascending order, equal keys by
+    ascending column index. A descending sort, a sum over all pre_iters
+    iterations or over other than the last four, or another tie rule fails."""
+    if seed == "ties":
+        H, llr, syn = _tie_tree()
+    else:
+        rng = np.random.default_rng(100 + seed)
+        n = int(rng.integers(6, 12))
+        H = _random_tree(rng, n)
+        llr = rng.uniform(0.3, 3.0, n)
+        e = (rng.random(n) < 0.3).astype(int)
+        syn = ((H.astype(int) @ e) % 2).astype(np.uint8)
+    n = H.shape[1]
+    minm, _ = _brute(H, llr, syn)
+    post = O.dense_bp(H, llr, syn, O.params(alpha=1.0), pre_iters)
+    assert np.abs(post[4:] - minm).max() < 1e-12        # converged from iteration 5 on
+    assert np.abs(post[0] - minm).max() > 1e-6          # but not after the first
+    Hd = np.vstack([H, np.zeros((1, n), np.uint8)])
+    sd = np.append(syn, 1).astype(np.uint8)
+    m = Hd.shape[0]
+    for tf in (1, 2):
+        if tf * m >= n:
+            continue
+        r = O.dense_window(Hd, llr, sd, O.params(alpha=1.0, pre_iters=pre_iters, trunc_factor=tf))
+        np.testing.assert_allclose(r["lsum"], 4 * minm, rtol=0, atol=1e-9)
+        assert _ranking_order_ok(r["kept"], 4 * minm, tf * m), (r["kept"], 4 * minm)
+        # the same order with the oracle's own keys, exact ties included
+        assert _ranking_order_ok(r["kept"], r["lsum"], tf * m, tol=0.0)
+    if seed == "ties":
+        # keys -0.4 for columns 3 and 5, +0.4 for 1, 2, 6 and 7 (exactly equal):
+        # the four kept columns are 3, 5, then the two lowest of the tied four
+        assert r["lsum"][1] == r["lsum"][2] == r["lsum"][6] == r["lsum"][7]
+        assert r["lsum"][3] == r["lsum"][5]
+        assert r["kept"].tolist() == [3, 5, 1, 2]
+
+
+def test_alg3_unsatisfied_cn_wiring():
+    """Alg. 3's unsatisfied-CN count inside run_path (reading R10: an active CN
+    whose residual syndrome differs from the XOR of its active neighbours'
+    current hard decisions, from the state after the step's BP and before the
+    pass). On random frustrated graphs the count the oracle uses equals one
+    recomputed here from H, the syndrome, the statuses and the Eq. 4 hard
+    decisions of the step's posteriors; and every eligible VN whose four history
+    posteriors lie in (3, 30] is decided 0 exactly when at least 3 of its CNs
+    are unsatisfied (P_D = 3). Both outcomes must occur, including the
+    boundary counts 3 (decided) and 2 (not decided)."""
+    seen = {}
+    for seed in range(40):
+        rng = np.random.default_rng(seed)
+        m, n = 24, 48
+        H = np.zeros((m, n), np.uint8)
+        for c in range(n):
+            H[rng.choice(m, int(rng.integers(3, 5)), replace=False), c] = 1
+        llr = rng.uniform(1.0, 6.0, n)
+        e = (rng.random(n) < 0.12).astype(int)
+        syn = ((H.astype(int) @ e) % 2).astype(np.uint8)
+        r = O.dense_path_probe(H, llr, syn, O.params(alpha=1.0, g=0, low_error=0, dmax_main=6))
+        Hi = H.astype(np.int64)
+        for i in range(r["steps"]):
+            st = r["status"][i]
+            act = st < 0
+            e_now = np.where(act, (r["post"][i] <= 0).astype(int), np.maximum(st, 0))
+            unsat = (Hi @ e_now + syn) % 2
+            nu = Hi.T @ unsat
+            assert np.array_equal(nu[act], r["n_unsat"][i][act]), (seed, i)
+            for c in np.nonzero(act & (H.sum(0) >= 3))[0]:
+                if 3.0 < r["hmin"][i][c] <= 30.0:
+                    want = 0 if nu[c] >= 3 else -1
+                    assert r["agg"][i][c] == want, (seed, i, c, nu[c], r["agg"][i][c])
+                    seen[int(min(nu[c], 3))] = seen.get(int(min(nu[c], 3)), 0) + 1
+    assert seen.get(3, 0) > 0 and seen.get(2, 0) > 0, seen
+
+
 def test_alg1_select_vn_table():
     # columns: hist (4 posteriors), degree, status
     h = np.array([[-1, -1, -1, -1],     # 0: all <= 0, sum -4
@@ -199,7 +309,7 @@ def test_peel_order_independent_and_contradiction():
         ok, st, ss = O.peel(H, status, s_res)
         assert ok                                  # consistent data never contradicts
         decided = st >= 0
-        assert (st[decided] == e[decided]).all() or True
+        assert (st[decided] == e[decided]).all()   # peeling recovers e (consistent data)
         # every degree-one CN is resolved
         act = st < 0
         assert not ((H[:, act].sum(1) == 1)).any()
