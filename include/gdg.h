@@ -17,12 +17,14 @@
  *    NULL = the null stream). Results are ready once the stream is synchronised.
  *  - A decode failure is not a call failure: it shows in d_pm (+infinity) and
  *    d_flags, and the shot counts as a logical failure (Sec. III).
- *  - The decode entry points keep device scratch per (device, stream): a shot
- *    counter and the path checkpoints where Fig. 2's tree splits (C2: about
- *    150 MB). It is allocated on the first decode on a stream, grown (after
- *    synchronising that stream) when a larger window needs more, and kept
- *    until the process ends. Decodes on one stream therefore run in order;
- *    decodes on different streams do not share it.
+ *  - Decode scratch: a shot counter and the path checkpoints where Fig. 2's
+ *    tree splits (C2: about 150 MB at full occupancy). gdg_decode_batch takes
+ *    it from the caller's workspace when one is given; otherwise, like the
+ *    other decode entry points, from a library pool per (device, stream) that
+ *    is allocated on the first decode on that stream, grown (after
+ *    synchronising the stream) when a larger window needs more, and kept
+ *    until gdg_release_scratch or the process ends. Decodes that share
+ *    scratch (one stream's pool or one workspace) must not overlap in time.
  */
 #ifndef GDG_H
 #define GDG_H
@@ -104,7 +106,7 @@ typedef struct gdg_window_info {
  * Columns that reach past the window's last round (the bottom-right H_1
  * block) are replaced by one unit column per last-round row they touch, with
  * prior p_j = (1 - prod (1 - 2 p_c))/2 over the merged columns, product in DEM
- * column order (Sec. III "merge ... to an identity matrix"). Window column
+ * column order (Sec. III, the H_1 merge into unit columns). Window column
  * order: kept DEM columns in DEM order, then unit columns by row. Committed
  * columns: those starting in round k, or all of them in the final window
  * (k + W == n_rounds). Only F = 1 is supported (GDG_EINVAL otherwise).
@@ -122,7 +124,9 @@ int gdg_window_get_info(const gdg_window* win, gdg_window_info* info);
  * commit[n] = 1 if committed. Any pointer may be NULL. */
 int gdg_window_columns(const gdg_window* win, int32_t* src, double* llr, uint8_t* commit);
 
-/* Bytes of device workspace gdg_decode_batch needs for n_shots shots. */
+/* Bytes of device workspace with which gdg_decode_batch decodes n_shots shots
+ * with every workgroup keeping its path checkpoints: 256 (the shot counter)
+ * plus workgroups x (2^g - 1) checkpoint slots. 0 on a bad window. */
 size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots);
 
 /*
@@ -145,6 +149,10 @@ size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots);
  *  step_lsum  [n_shots][n_paths][log_cap][n_act] float: each VN's sum of its
  *             last four posteriors at the end of every step's BP run (the
  *             Alg. 1 key), NaN for decimated VNs and unused steps
+ *  pre_post   [n_shots][pre_iters][n] float: the posteriors (Eq. 2) of every
+ *             preprocessing BP iteration on the whole window, in window
+ *             column order; NaN for iterations not run (the preprocessing
+ *             stops once its hard decision meets the syndrome)
  */
 typedef struct gdg_trace {
   int32_t* sel;
@@ -154,6 +162,7 @@ typedef struct gdg_trace {
   float* first_post;
   int64_t* edge_iters;
   float* step_lsum;
+  float* pre_post;
 } gdg_trace;
 
 /*
@@ -170,13 +179,27 @@ typedef struct gdg_trace {
  *   d_ehat:     [n_shots][n] uint8 output, the window correction.
  *   d_pm:       [n_shots] double output, +inf when no path met the syndrome.
  *   d_flags:    [n_shots] int32 output, GDG_FLAG_* bits.
- *   d_workspace: >= gdg_workspace_bytes(win, n_shots) bytes of device memory.
+ *   d_workspace: NULL (the library's per-stream pool) or caller-owned device
+ *               memory, 256-byte aligned, of workspace_bytes >= 256 bytes: the
+ *               shot counter, then path checkpoints for as many workgroups as
+ *               fit (gdg_workspace_bytes(win, n_shots) fits all of them; the
+ *               other workgroups replay their paths from the root, which
+ *               gives the same results more slowly). With a workspace the call
+ *               allocates nothing and never synchronises. GDG_EINVAL if it is
+ *               misaligned or under 256 bytes.
  *   trace:      NULL or diagnostics as above (host struct of device pointers).
  */
 int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
                      int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
                      void* d_workspace, size_t workspace_bytes, const gdg_trace* trace,
                      void* hip_stream);
+
+/*
+ * Releases the library's decode scratch pool of (current device, hip_stream),
+ * after synchronising that stream. The next decode on the stream without a
+ * workspace allocates it again.
+ */
+int gdg_release_scratch(void* hip_stream);
 
 /*
  * Several decode jobs in one persistent launch: windows of different codes
@@ -249,8 +272,11 @@ int gdg_commit_indexed(const gdg_window* win, int32_t n_shots, const uint8_t* d_
  * Plain flooding min-sum BP on the whole window, no decimation (Eqs. 1-4):
  * n_iters iterations from fresh messages; d_post [n_shots][n_iters][n] float
  * receives every iteration's posteriors (Eq. 2), d_first_ok [n_shots] int32
- * the first iteration whose hard decision met the syndrome (0 = none).
- * Checks the message-passing kernels on their own.
+ * the first iteration whose hard decision met the syndrome (0 = none). It runs
+ * the decode kernel's own whole-window BP (the preprocessing of Sec. III and
+ * Sec. IV-C) without its early stop, so the message passing can be checked
+ * for any iteration count and on windows decoded without preprocessing.
+ * GDG_ESHAPE if the window does not fit one workgroup's LDS.
  */
 int gdg_bp(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome, int64_t syn_stride,
            int32_t n_iters, float* d_post, int32_t* d_first_ok, void* hip_stream);

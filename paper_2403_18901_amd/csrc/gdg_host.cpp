@@ -303,15 +303,15 @@ int cu_count() {
   return v > 0 ? v : 1;
 }
 
-// Device scratch of the decode launches on one stream: the shot counter of the
-// persistent grid and the path checkpoints. Launches on one stream run in
-// order, so they can share it; it grows on demand and lives until the process
-// ends.
+// Device scratch of the decode launches on one stream when the caller gives
+// no workspace: the shot counter followed by the path checkpoints. Launches on
+// one stream run in order, so they can share it; it grows on demand (after
+// synchronising the stream) and is kept until gdg_release_scratch or the
+// process ends.
 struct StreamScratch {
   int dev = 0;
   hipStream_t st = nullptr;
-  int* ctr = nullptr;
-  char* ckpt = nullptr;
+  char* base = nullptr;     // [256 B counter][ckpt_bytes of checkpoints]
   size_t ckpt_bytes = 0;
 };
 std::mutex g_scratch_mu;
@@ -331,20 +331,16 @@ int stream_scratch(hipStream_t st, size_t ckpt_bytes, StreamScratch* out) {
     s->dev = dev;
     s->st = st;
   }
-  if (!s->ctr) {
-    e = hipMalloc((void**)&s->ctr, 256);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc (shot counter)");
-  }
-  if (ckpt_bytes > s->ckpt_bytes) {
-    if (s->ckpt) {
+  if (!s->base || ckpt_bytes > s->ckpt_bytes) {
+    if (s->base) {
       e = hipStreamSynchronize(st);   // earlier launches may still use the old block
       if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-      (void)hipFree(s->ckpt);
-      s->ckpt = nullptr;
+      (void)hipFree(s->base);
+      s->base = nullptr;
       s->ckpt_bytes = 0;
     }
-    e = hipMalloc((void**)&s->ckpt, ckpt_bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc (path checkpoints)");
+    e = hipMalloc((void**)&s->base, 256 + ckpt_bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (decode scratch)");
     s->ckpt_bytes = ckpt_bytes;
   }
   *out = *s;
@@ -638,118 +634,161 @@ int gdg_window_columns(const gdg_window* win, int32_t* src, double* llr, uint8_t
   return GDG_OK;
 }
 
-size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots) {
-  (void)win;
-  (void)n_shots;
-  return 0;   // the decode kernel keeps all of its state in LDS
-}
-
 }  // extern "C"
 
 namespace {
 
 int g_lds_set[5] = {65536, 65536, 65536, 65536, 65536};   // dynamic-LDS limit set per kernel bucket
 
-int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
-                const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn = nullptr) {
+// Shape of one decode launch, fixed before any scratch is chosen: the LDS
+// allocation, register tiling, persistent grid and checkpoint geometry.
+struct LaunchGeom {
+  int lds = 0, bucket = 0, grid = 0, total = 0;
+  bool low = true;         // every window in low-error mode
+  int slots = 0;           // checkpoint slots per workgroup (0: no tree)
+  long long stride = 0;    // bytes per checkpoint slot
+  long long ck_per_wg() const { return (long long)slots * stride; }
+};
+
+constexpr size_t kCounterBytes = 256;   // the persistent grid's shot counter, first in any scratch
+
+int launch_geometry(const gdg_job* jobs, int n_jobs, int waves, int workgroups, bool learn,
+                    LaunchGeom& G) {
   if (!jobs || n_jobs < 1 || n_jobs > GDG_MAX_JOBS) return fail(GDG_EINVAL, "1..8 jobs per launch");
   if (waves < 1 || waves > 8) return fail(GDG_EINVAL, "waves must be in 1..8");
   if (workgroups < 0) return fail(GDG_EINVAL, "negative workgroup count");
-  gdg_jobs_dev J{};
-  int total = 0, lds = 0, bucket = 0;
-  bool low = true;   // every window in low-error mode: the kernel built without Alg. 3
+  G = LaunchGeom{};
   for (int j = 0; j < n_jobs; ++j) {
-    const gdg_job& jb = jobs[j];
-    if (!jb.win) return fail(GDG_EINVAL, "job without a window");
-    if (jb.n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
-    if (jb.n_shots > 0) {
-      if (!jb.d_syndrome || !jb.d_ehat || !jb.d_pm || !jb.d_flags)
-        return fail(GDG_EINVAL, "null buffer");
-      if (jb.syn_stride < jb.win->info.m) return fail(GDG_EINVAL, "syn_stride < m");
-    }
-    gdg_job_dev& d = J.job[j];
-    d.w = jb.win->d_dev;
-    d.L = jb.win->d_plans + (waves - 1);
-    d.item0 = total;
-    d.n_shots = jb.n_shots;
-    d.syn = jb.d_syndrome;
-    d.syn_stride = jb.syn_stride;
-    d.ehat = jb.d_ehat;
-    d.pm = jb.d_pm;
-    d.flags = jb.d_flags;
-    total += jb.n_shots;
-    lds = std::max(lds, jb.win->plans[waves - 1].total);
-    bucket = std::max(bucket, jb.win->bucket);
-    low = low && jb.win->dev.low_error;
+    const gdg_window* win = jobs[j].win;
+    if (!win) return fail(GDG_EINVAL, "job without a window");
+    if (jobs[j].n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+    G.total += jobs[j].n_shots;
+    G.lds = std::max(G.lds, win->plans[waves - 1].total);
+    G.bucket = std::max(G.bucket, win->bucket);
+    G.low = G.low && win->dev.low_error;
+    const int n_tree = win->dev.g > 0 ? 1 << win->dev.g : 1;
+    G.slots = std::max(G.slots, n_tree - 1);
+    const int e_pad_max = win->max_sub + 3 * win->dev.m;
+    G.stride = std::max(G.stride, (long long)(gdg_ck(win->dev.n_act, e_pad_max).bytes + 255) / 256 * 256);
   }
-  J.n_jobs = n_jobs;
-  J.total = total;
-  if (learn) J.learn = *learn;
-  if (total == 0) return GDG_OK;
-  if (lds > max_lds_per_block()) return fail(GDG_ESHAPE, "jobs do not fit in LDS at this shape");
+  if (G.lds > max_lds_per_block()) return fail(GDG_ESHAPE, "jobs do not fit in LDS at this shape");
   // Allocate the CU's LDS share at the occupancy the kernel is built for (or
   // the plans' minimum if larger): shots with larger sub-graphs then still
   // get all their path wavefronts.
-  const int wps = gdg_decode_waves_per_simd(bucket, J.learn.mode != 0);
+  const int wps = gdg_decode_waves_per_simd(G.bucket, learn);
   int wg_per_cu = 4 * wps / waves;
   // A launch with fewer shots than that many workgroups per CU (small
   // streaming batches) needs fewer per CU: each then gets a larger share, so
   // large sub-graphs still fit all their path wavefronts and a shot's latency
   // does not grow.
   if (workgroups <= 0) {
-    const int need = (int)((total + (long long)cu_count() - 1) / cu_count());
+    const int need = (int)((G.total + (long long)cu_count() - 1) / cu_count());
     wg_per_cu = std::max(1, std::min(wg_per_cu, need));
   }
   if (wg_per_cu >= 2)   // whole 2 KiB granules, so that the shares add up within the CU
-    lds = std::max(lds, std::min(lds_per_cu() / wg_per_cu / 2048 * 2048, max_lds_per_block()));
+    G.lds = std::max(G.lds, std::min(lds_per_cu() / wg_per_cu / 2048 * 2048, max_lds_per_block()));
   else   // one per CU: most of the CU's LDS (the full 160 KiB is refused as a dynamic size)
-    lds = std::max(lds, (max_lds_per_block() - 16384) / 2048 * 2048);
-  J.lds = lds;
-  if (lds > g_lds_set[bucket]) {
-    hipError_t e = gdg_decode_set_lds_limit(bucket, lds);
-    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-    g_lds_set[bucket] = lds;
-  }
+    G.lds = std::max(G.lds, (max_lds_per_block() - 16384) / 2048 * 2048);
   // Persistent grid at the resident workgroup count (or the caller's count):
   // workgroups take shots from a counter, and each owns the checkpoints where
   // its paths' decision tree splits.
-  const int by_lds = std::max(1, lds_per_cu() / ((lds + 2047) / 2048 * 2048));
+  const int by_lds = std::max(1, lds_per_cu() / ((G.lds + 2047) / 2048 * 2048));
   const int by_waves = std::max(1, 4 * wps / waves);
   const int resident = std::min(by_lds, by_waves) * cu_count();
-  const int grid = workgroups > 0 ? std::min(workgroups, total) : std::min(total, resident);
-  long long stride = 0;
-  int slots = 0;
+  G.grid = workgroups > 0 ? std::min(workgroups, G.total) : std::min(G.total, resident);
+  return GDG_OK;
+}
+
+// Launches the decode with the given scratch: the shot counter at `scratch`
+// and checkpoint slots for as many workgroups as fit in the rest (the others
+// replay their paths from the root, which gives the same results). Allocates
+// nothing.
+int launch_with_scratch(const gdg_job* jobs, int n_jobs, int waves, const LaunchGeom& G,
+                        const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn,
+                        void* scratch, size_t scratch_bytes) {
+  gdg_jobs_dev J{};
   for (int j = 0; j < n_jobs; ++j) {
-    const gdg_window* win = jobs[j].win;
-    const int n_tree = win->dev.g > 0 ? 1 << win->dev.g : 1;
-    slots = std::max(slots, n_tree - 1);
-    const int e_pad_max = win->max_sub + 3 * win->dev.m;
-    stride = std::max(stride, (long long)(gdg_ck(win->dev.n_act, e_pad_max).bytes + 255) / 256 * 256);
+    const gdg_job& jb = jobs[j];
+    if (jb.n_shots > 0) {
+      if (!jb.d_syndrome || !jb.d_ehat || !jb.d_pm || !jb.d_flags)
+        return fail(GDG_EINVAL, "null buffer");
+      if (jb.syn_stride < jb.win->info.m) return fail(GDG_EINVAL, "syn_stride < m");
+    }
   }
-  StreamScratch sc;
-  int rc = stream_scratch(st, slots > 0 ? (size_t)grid * slots * stride : 256, &sc);
-  if (rc) return rc;
-  J.work = sc.ctr;
-  J.ckpt = slots > 0 ? sc.ckpt : nullptr;
-  J.ckpt_stride = stride;
-  J.ckpt_slots = slots;
-  hipError_t e = gdg_launch_zero(sc.ctr, 1, st);
+  if (G.total == 0) return GDG_OK;
+  if (!scratch || scratch_bytes < kCounterBytes || ((uintptr_t)scratch & 255u))
+    return fail(GDG_EINVAL, "scratch must be 256-byte aligned and hold at least 256 bytes");
+  int item0 = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const gdg_job& jb = jobs[j];
+    gdg_job_dev& d = J.job[j];
+    d.w = jb.win->d_dev;
+    d.L = jb.win->d_plans + (waves - 1);
+    d.item0 = item0;
+    d.n_shots = jb.n_shots;
+    d.syn = jb.d_syndrome;
+    d.syn_stride = jb.syn_stride;
+    d.ehat = jb.d_ehat;
+    d.pm = jb.d_pm;
+    d.flags = jb.d_flags;
+    item0 += jb.n_shots;
+  }
+  J.n_jobs = n_jobs;
+  J.total = G.total;
+  if (learn) J.learn = *learn;
+  J.lds = G.lds;
+  if (G.lds > g_lds_set[G.bucket]) {
+    hipError_t e = gdg_decode_set_lds_limit(G.bucket, G.lds);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    g_lds_set[G.bucket] = G.lds;
+  }
+  J.work = (int*)scratch;
+  J.ckpt = nullptr;
+  J.ckpt_wgs = 0;
+  if (G.slots > 0) {
+    const long long fit = (long long)(scratch_bytes - kCounterBytes) / G.ck_per_wg();
+    J.ckpt_wgs = (int)std::min<long long>(fit, G.grid);
+    if (J.ckpt_wgs > 0) J.ckpt = (char*)scratch + kCounterBytes;
+  }
+  J.ckpt_stride = G.stride;
+  J.ckpt_slots = G.slots;
+  hipError_t e = gdg_launch_zero(J.work, 1, st);
   if (e != hipSuccess) return hip_fail(e, "counter reset");
-  e = gdg_launch_jobs(J, bucket, low, waves, grid, lds, tr, st);
+  e = gdg_launch_jobs(J, G.bucket, G.low, waves, G.grid, G.lds, tr, st);
   if (e != hipSuccess) return hip_fail(e, "decode launch");
   return GDG_OK;
+}
+
+// Decode launch on the library's per-stream scratch (allocated or grown here).
+int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
+                const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn = nullptr) {
+  LaunchGeom G;
+  int rc = launch_geometry(jobs, n_jobs, waves, workgroups, learn && learn->mode != 0, G);
+  if (rc) return rc;
+  if (G.total == 0) return launch_with_scratch(jobs, n_jobs, waves, G, tr, st, learn, nullptr, 0);
+  StreamScratch sc;
+  rc = stream_scratch(st, (size_t)G.grid * G.ck_per_wg(), &sc);
+  if (rc) return rc;
+  return launch_with_scratch(jobs, n_jobs, waves, G, tr, st, learn, sc.base,
+                             kCounterBytes + sc.ckpt_bytes);
 }
 
 }  // namespace
 
 extern "C" {
 
+size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots) {
+  if (!win || n_shots <= 0) return kCounterBytes;
+  gdg_job job{win, n_shots, nullptr, win->info.m, nullptr, nullptr, nullptr};
+  LaunchGeom G;
+  if (launch_geometry(&job, 1, win->waves, 0, false, G)) return 0;
+  return kCounterBytes + (size_t)G.grid * (size_t)G.ck_per_wg();
+}
+
 int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
                      int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
                      void* d_workspace, size_t workspace_bytes, const gdg_trace* trace,
                      void* hip_stream) {
-  (void)d_workspace;
-  (void)workspace_bytes;
   if (!win) return fail(GDG_EINVAL, "null window");
   if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
   if (n_shots == 0) return GDG_OK;
@@ -762,10 +801,34 @@ int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_sy
     tr.first_post = trace->first_post;
     tr.edge_iters = (long long*)trace->edge_iters;
     tr.step_lsum = trace->step_lsum;
+    tr.pre_post = trace->pre_post;
     if (tr.dec && tr.log_cap <= 0) return fail(GDG_EINVAL, "trace log_cap must be positive");
   }
   gdg_job job{win, n_shots, d_syndrome, syn_stride, d_ehat, d_pm, d_flags};
-  return launch_jobs(&job, 1, win->waves, 0, tr, (hipStream_t)hip_stream);
+  if (!d_workspace) return launch_jobs(&job, 1, win->waves, 0, tr, (hipStream_t)hip_stream);
+  LaunchGeom G;
+  int rc = launch_geometry(&job, 1, win->waves, 0, false, G);
+  if (rc) return rc;
+  return launch_with_scratch(&job, 1, win->waves, G, tr, (hipStream_t)hip_stream, nullptr,
+                             d_workspace, workspace_bytes);
+}
+
+int gdg_release_scratch(void* hip_stream) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  const hipStream_t st = (hipStream_t)hip_stream;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  for (size_t i = 0; i < g_scratch.size(); ++i) {
+    StreamScratch& x = g_scratch[i];
+    if (x.dev != dev || x.st != st) continue;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (x.base) (void)hipFree(x.base);
+    g_scratch.erase(g_scratch.begin() + (long)i);
+    return GDG_OK;
+  }
+  return GDG_OK;
 }
 
 // Persistent grid of the learned decode: three workgroups per CU on 256 CUs.
@@ -881,9 +944,11 @@ int gdg_bp(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome, in
   if (n_shots == 0) return GDG_OK;
   if (!d_syndrome || !d_post || !d_first_ok) return fail(GDG_EINVAL, "null buffer");
   if (syn_stride < win->info.m) return fail(GDG_EINVAL, "syn_stride < m");
-  const size_t lds = (size_t)((win->dev.m + 15) & ~15) + 4 * (size_t)((win->dev.n + 3) & ~3) +
-                     8 * (size_t)win->dev.e_full;
+  const size_t lds = (size_t)align16(win->dev.m) + (size_t)align16(4 * (win->dev.n + 1)) +
+                     4 * (size_t)(win->dev.fr_epad + 8);
   if (lds > (size_t)max_lds_per_block()) return fail(GDG_ESHAPE, "window does not fit in LDS");
+  // four wavefronts, each keeping the syndrome bits of up to 64 slot columns
+  if ((win->dev.fr_T + 3) / 4 > 64) return fail(GDG_ESHAPE, "window graph too large for gdg_bp");
   hipError_t e = gdg_launch_bp(win->dev, n_shots, d_syndrome, syn_stride, n_iters, d_post,
                                d_first_ok, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "bp launch");

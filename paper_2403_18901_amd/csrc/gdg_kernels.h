@@ -111,6 +111,7 @@ struct gdg_trace_dev {
   float* first_post;
   long long* edge_iters;
   float* step_lsum;
+  float* pre_post;
 };
 
 // Commit tables: affected DEM rows with the committed window columns touching
@@ -182,9 +183,11 @@ struct gdg_jobs_dev {
   int n_jobs, total;
   int lds;   // the launch's dynamic LDS bytes
   int* work;             // shot counter of a persistent launch (zeroed), or null: grid stride
-  char* ckpt;            // path checkpoints: [gridDim.x][ckpt_slots] of ckpt_stride bytes, or null
+  char* ckpt;            // path checkpoints: [ckpt_wgs][ckpt_slots] of ckpt_stride bytes, or null
   long long ckpt_stride;
   int ckpt_slots;
+  int ckpt_wgs;          // workgroups 0..ckpt_wgs-1 own checkpoint slots; the others
+                         // replay their paths from the root (same results)
   gdg_job_dev job[kMaxJobs];
   gdg_learn_dev learn;
 };

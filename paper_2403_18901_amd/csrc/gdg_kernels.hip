@@ -152,142 +152,9 @@ __device__ void wg_exclusive_scan_wave0(int* a, int len) {
   if (lane == 0) a[len] = carry;
 }
 
-// ------------------------------------------------------------------ whole-window BP
-//
-// Workgroup-cooperative flooding min-sum on the full window graph (used for
-// the preprocessing BP and for gdg_bp). The window's CSR edges are staged in
-// LDS as (column | column-order slot << 16); CN-to-VN messages are kept per
-// edge in column order (c2v[col_ptr[c] + t] is the message on column c's t-th
-// edge), so the VN phase sums contiguous entries. Loads are issued in batches
-// of kBatch edges so that their latencies overlap.
-
-constexpr int kBatch = 8;
-
-// Running two smallest magnitudes and the position of the smallest (first
-// position on ties), without branches: with n1 <= n2 the new second smallest is
-// the median of (n1, n2, a) and the new smallest the median of (n1, a, -inf).
-__device__ __forceinline__ void two_min(float a, int k, float& n1, float& n2, int& nidx) {
-  n2 = __builtin_amdgcn_fmed3f(n1, n2, a);
-  nidx = a < n1 ? k : nidx;
-  n1 = __builtin_amdgcn_fmed3f(n1, a, -kInfF);
-}
+// ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ float clip_to(float x, float c) { return __builtin_amdgcn_fmed3f(x, -c, c); }
-
-// Bit k (0..31) of w moved to the sign position.
-__device__ __forceinline__ uint32_t bit_to_sign(uint32_t w, int k) {
-  return (w << (31 - k)) & 0x80000000u;
-}
-
-struct FullBP {
-  const gdg_win_dev* w;
-  const uint32_t* cs;   // [E] staged CSR edges
-  float* post;          // [n]
-  float* c2v;           // [E]
-  const uint8_t* syn;   // [m]
-};
-
-// CN phase: new messages from the posteriors and the previous messages; returns
-// this thread's OR of "row j unsatisfied by the hard decisions of post".
-// Edges past a row's end are padded with a +infinity posterior, which clips to
-// +clip with a + sign and a 0 hard decision (see set_status); with at least one
-// real edge this reproduces the single-neighbour rule, so no edge needs a branch.
-__device__ int full_cn_phase(const FullBP& b) {
-  const gdg_win_dev& w = *b.w;
-  const float clip = w.clip;
-  int bad = 0;
-  for (int j = threadIdx.x; j < w.m; j += blockDim.x) {
-    const int e0 = w.row_ptr[j], dg = w.row_ptr[j + 1] - e0;
-    float n1 = kInfF, n2 = kInfF;
-    int nidx = 0, hcnt = 0;
-    uint32_t nlo = 0u, nhi = 0u;
-    for (int k0 = 0; k0 < dg; k0 += kBatch) {
-      uint32_t cs[kBatch];
-      float pv[kBatch], old[kBatch];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) cs[i] = b.cs[e0 + min(k0 + i, dg - 1)];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
-        pv[i] = b.post[cs[i] & 0xffffu];
-        old[i] = b.c2v[cs[i] >> 16];
-      }
-      uint32_t nw = 0u;
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
-        const int k = k0 + i;
-        const float p = k < dg ? pv[i] : kInfF;
-        hcnt += p <= 0.0f;
-        const float x = clip_to(p - old[i], clip);
-        nw |= (__float_as_uint(x) >> 31) << (k & 31);
-        two_min(fabsf(x), k, n1, n2, nidx);
-      }
-      if (k0 < 32) nlo |= nw; else nhi |= nw;
-    }
-    const int npar = (b.syn[j] ^ __builtin_popcount(nlo) ^ __builtin_popcount(nhi)) & 1;
-    const uint32_t flip = npar ? ~0u : 0u;
-    const uint32_t wlo = nlo ^ flip, whi = nhi ^ flip;   // sign bit of each new message
-    const float s2 = w.alpha * (n2 == kInfF ? clip : n2);
-    const float s1 = w.alpha * (n1 == kInfF ? clip : n1);
-    for (int k0 = 0; k0 < dg; k0 += kBatch) {
-      uint32_t cs[kBatch];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) cs[i] = b.cs[e0 + min(k0 + i, dg - 1)];
-      const uint32_t ww = k0 < 32 ? wlo : whi;
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
-        const int k = k0 + i;
-        if (k < dg) {
-          const float mag = k == nidx ? s2 : s1;
-          b.c2v[cs[i] >> 16] = __uint_as_float(__float_as_uint(mag) ^ bit_to_sign(ww, k & 31));
-        }
-      }
-    }
-    bad |= b.syn[j] ^ (hcnt & 1);
-  }
-  return bad;
-}
-
-// VN phase: posterior = prior + sum of incoming messages (Eq. 2), in column
-// edge order. Optional running sum of posteriors into lsum.
-__device__ void full_vn_phase(const FullBP& b, float* lsum) {
-  const gdg_win_dev& w = *b.w;
-  for (int c = threadIdx.x; c < w.n; c += blockDim.x) {
-    const int c0 = w.col_ptr[c], dg = w.col_ptr[c + 1] - c0;
-    float s = w.llr[c];
-    for (int k0 = 0; k0 < dg; k0 += kBatch) {
-      float x[kBatch];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) x[i] = b.c2v[c0 + min(k0 + i, dg - 1)];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i)
-        if (k0 + i < dg) s += x[i];
-    }
-    b.post[c] = s;
-    if (lsum) lsum[c] += s;
-  }
-}
-
-__device__ int full_check(const FullBP& b) {
-  const gdg_win_dev& w = *b.w;
-  int bad = 0;
-  for (int j = threadIdx.x; j < w.m; j += blockDim.x) {
-    const int e0 = w.row_ptr[j], dg = w.row_ptr[j + 1] - e0;
-    int hcnt = 0;
-    for (int k0 = 0; k0 < dg; k0 += kBatch) {
-      float pv[kBatch];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) pv[i] = b.post[b.cs[e0 + min(k0 + i, dg - 1)] & 0xffffu];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) hcnt += (k0 + i < dg) && pv[i] <= 0.0f;
-    }
-    bad |= b.syn[j] ^ (hcnt & 1);
-  }
-  return bad;
-}
-
-__device__ void stage_edges(const gdg_win_dev& w, uint32_t* cs) {
-  for (int e = threadIdx.x; e < w.e_full; e += blockDim.x) cs[e] = w.row_cs[e];
-}
 
 // ------------------------------------------------------------------ decode kernel
 
@@ -859,6 +726,88 @@ __device__ __forceinline__ void full_vn_pass(const gdg_win_dev& w, float* post, 
   }
 }
 
+// Flooding min-sum on the whole window graph, by the whole workgroup: the
+// preprocessing BP of Sec. III and Sec. IV-C (Eqs. 1-4), also behind gdg_bp.
+// It uses the path BP's CN code on the window graph's lane-group slot table
+// (built on the host), split over the wavefronts: column i of wavefront wv is
+// table column wv + i W. LDS arrays: syn [m] the window syndrome, post [n + 1]
+// (entry n: the padding's dummy VN), c2v [fr_epad + 2 kPad], lsum [n] (may be
+// null). From fresh messages it runs up to n_iters iterations; with `stop` it
+// ends after the first iteration whose hard decisions (Eq. 4) meet the
+// syndrome, otherwise it runs them all. lsum accumulates the posteriors of the
+// last four iterations of n_iters. rec (global [n_iters][n], may be null)
+// receives every iteration's posteriors, NaN for iterations not run. Returns
+// the first iteration whose hard decisions met the syndrome (0: none) and
+// sets *done to the number of iterations run. Every thread enters.
+template <int VPL>
+__device__ int window_bp(const gdg_win_dev& w, const uint8_t* syn, float* post, float* c2v,
+                         float* lsum, const int n_iters, const bool stop, float* rec, int* done) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = w.n;
+  for (int c = tid; c < n; c += blockDim.x) {
+    post[c] = w.llr[c];
+    if (lsum) lsum[c] = 0.0f;
+  }
+  if (tid == 0) post[n] = kInfF;   // dummy VN of the row padding
+  for (int e = tid; e < w.fr_epad + 2 * kPad; e += blockDim.x) c2v[e] = 0.0f;
+  const int nw = blockDim.x >> 6;
+  const int my_T = wave < w.fr_T ? (w.fr_T - wave + nw - 1) / nw : 0;
+  PathCtx<VPL> F;
+  F.rvn = w.fr_rvn;
+  F.meta = w.fr_meta;
+  F.rec = w.fr_rec;
+  F.post = post;
+  F.c2v = c2v;
+  F.lane = lane;
+  F.m = w.m;
+  F.n = n;
+  F.tstride = nw;
+  // syndrome bits of this wavefront's slot columns (at most 64)
+  uint32_t syn0 = 0u, syn1 = 0u;
+  for (int i = 0; i < my_T; ++i) {
+    const uint32_t mt = w.fr_meta[(wave + i * nw) * kWave + lane];
+    const uint32_t b = (mt & kMetaValid) ? (uint32_t)syn[(mt >> kMetaRowShift) & 0x3ff] : 0u;
+    if (i < 32)
+      syn0 |= b << i;
+    else
+      syn1 |= b << (i - 32);
+  }
+  __syncthreads();
+  auto walk = [&](bool messages) {
+    int bad = 0;
+    for (int c = 0; c < 2; ++c) {
+      if (my_T <= 32 * c) break;
+      F.t0 = wave + 32 * c * nw;
+      F.T = min(32, my_T - 32 * c);
+      F.sres = c ? syn1 : syn0;
+      bad |= messages ? cn_phase<VPL, true>(F, w.alpha, w.clip) : check_pass<VPL, true>(F, false);
+    }
+    return bad;
+  };
+  int first = 0, it = 0;
+  for (int t = 1; t <= n_iters; ++t) {
+    // the CN phase also checks the hard decisions of iteration t - 1
+    const int any_bad = __syncthreads_or(walk(true));
+    if (t >= 2 && !any_bad && first == 0) {
+      first = t - 1;
+      if (stop) break;
+    }
+    full_vn_pass(w, post, c2v, lsum && t > n_iters - 4 ? lsum : nullptr);
+    it = t;
+    __syncthreads();
+    if (rec)
+      for (int c = tid; c < n; c += blockDim.x) rec[(long long)(t - 1) * n + c] = post[c];
+  }
+  if (first == 0 && !__syncthreads_or(walk(false))) first = it;
+  if (rec)
+    for (long long i = (long long)it * n + tid; i < (long long)n_iters * n; i += blockDim.x)
+      rec[i] = __builtin_nanf("");
+  *done = it;
+  return first;
+}
+
 // Eq. 5 in ascending window-column order: the wavefront's lanes gather the
 // priors of the columns set in `bits` into `stage` in that order (a prefix sum
 // over the words), then lane 0 adds them up in that order. The sum is valid on
@@ -978,66 +927,14 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
 
   // ---------------------------------------------------------- preprocessing
   if (w.pre_iters > 0) {
-    // Flooding min-sum on the whole window with the path BP's CN code: the
-    // window graph's lane-group slot table (built on the host) is split over
-    // the wavefronts, column i of wavefront wv being table column wv + i W.
     float* const ppost = (float*)(U + L.p_post);
     float* const pc2v = (float*)(U + L.p_c2v);
     float* const lsum = (float*)(U + L.p_lsum);
-    for (int c = tid; c < n; c += blockDim.x) {
-      ppost[c] = w.llr[c];
-      lsum[c] = 0.0f;
-    }
-    if (tid == 0) ppost[n] = kInfF;   // dummy VN of the row padding
-    for (int e = tid; e < w.fr_epad + 2 * kPad; e += blockDim.x) pc2v[e] = 0.0f;
-    const int nw = blockDim.x >> 6;
-    const int my_T = wave < w.fr_T ? (w.fr_T - wave + nw - 1) / nw : 0;
-    PathCtx<VPL> F;
-    F.rvn = w.fr_rvn;
-    F.meta = w.fr_meta;
-    F.rec = w.fr_rec;
-    F.post = ppost;
-    F.c2v = pc2v;
-    F.lane = lane;
-    F.m = m;
-    F.n = n;
-    F.tstride = nw;
-    // syndrome bits of this wavefront's slot columns (at most 64)
-    uint32_t syn0 = 0u, syn1 = 0u;
-    for (int i = 0; i < my_T; ++i) {
-      const uint32_t mt = w.fr_meta[(wave + i * nw) * kWave + lane];
-      const uint32_t b = (mt & kMetaValid) ? (uint32_t)sorig[(mt >> kMetaRowShift) & 0x3ff] : 0u;
-      if (i < 32)
-        syn0 |= b << i;
-      else
-        syn1 |= b << (i - 32);
-    }
-    __syncthreads();
-    auto walk = [&](bool messages) {
-      int bad = 0;
-      for (int c = 0; c < 2; ++c) {
-        if (my_T <= 32 * c) break;
-        F.t0 = wave + 32 * c * nw;
-        F.T = min(32, my_T - 32 * c);
-        F.sres = c ? syn1 : syn0;
-        bad |= messages ? cn_phase<VPL, true>(F, w.alpha, w.clip) : check_pass<VPL, true>(F, false);
-      }
-      return bad;
-    };
-    bool conv = false;
     int iters_done = 0;
-    for (int t = 1; t <= w.pre_iters; ++t) {
-      const int bad = walk(true);
-      const int any_bad = __syncthreads_or(bad);
-      if (t >= 2 && !any_bad) {
-        conv = true;
-        break;
-      }
-      full_vn_pass(w, ppost, pc2v, t > w.pre_iters - 4 ? lsum : nullptr);
-      iters_done = t;
-      __syncthreads();
-    }
-    if (!conv) conv = !__syncthreads_or(walk(false));
+    const bool conv =
+        window_bp<VPL>(w, sorig, ppost, pc2v, lsum, w.pre_iters, true,
+                       tr.pre_post ? tr.pre_post + (long long)shot * w.pre_iters * n : nullptr,
+                       &iters_done) != 0;
     if (tid == 0) *eacc = (unsigned long long)iters_done * (unsigned long long)w.e_full;
     if (conv) {
       // the hard decision of the preprocessing BP is the answer
@@ -1945,7 +1842,9 @@ template <int VPL, bool kLearn, bool kLow>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     kDecodeWavesPerSimd<VPL, kLearn>, kDecodeWavesPerSimd<VPL, kLearn>))) void gdg_decode_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
   extern __shared__ __align__(16) unsigned char smem[];
-  char* const ck = J.ckpt ? J.ckpt + (long long)blockIdx.x * J.ckpt_slots * J.ckpt_stride : nullptr;
+  char* const ck = J.ckpt && (int)blockIdx.x < J.ckpt_wgs
+                       ? J.ckpt + (long long)blockIdx.x * J.ckpt_slots * J.ckpt_stride
+                       : nullptr;
   int item = blockIdx.x;
   for (;;) {
     if (J.work) {
@@ -1976,7 +1875,11 @@ __global__ void gdg_zero_kernel(int* p, int n) {
 
 // ------------------------------------------------------------------ plain BP
 
-__global__ __launch_bounds__(256) void gdg_bp_kernel(gdg_win_dev w, int n_shots,
+// gdg_bp: the decode kernel's whole-window BP (window_bp) with no early stop,
+// one workgroup of four wavefronts per shot. LDS: the syndrome, then
+// posteriors and messages at the host's offsets.
+__global__ __launch_bounds__(256) void gdg_bp_kernel(gdg_win_dev w, int post_off, int c2v_off,
+                                                     int n_shots,
                                                      const uint8_t* __restrict__ syn,
                                                      long long syn_stride, int n_iters,
                                                      float* __restrict__ post_out,
@@ -1984,41 +1887,16 @@ __global__ __launch_bounds__(256) void gdg_bp_kernel(gdg_win_dev w, int n_shots,
   extern __shared__ __align__(16) unsigned char smem[];
   const int shot = blockIdx.x;
   if (shot >= n_shots) return;
-  const int tid = threadIdx.x;
   uint8_t* s = smem;
-  float* post = (float*)(smem + ((w.m + 15) & ~15));
-  float* c2v = post + ((w.n + 3) & ~3);
-  uint32_t* cs = (uint32_t*)(c2v + w.e_full);
-  for (int j = tid; j < w.m; j += blockDim.x) s[j] = syn[(long long)shot * syn_stride + j] & 1;
-  for (int c = tid; c < w.n; c += blockDim.x) post[c] = w.llr[c];
-  for (int e = tid; e < w.e_full; e += blockDim.x) c2v[e] = 0.0f;
-  stage_edges(w, cs);
+  for (int j = threadIdx.x; j < w.m; j += blockDim.x) s[j] = syn[(long long)shot * syn_stride + j] & 1;
   __syncthreads();
-  FullBP b;
-  b.w = &w;
-  b.cs = cs;
-  b.post = post;
-  b.c2v = c2v;
-  b.syn = s;
-  int first = 0;
-  for (int t = 1; t <= n_iters; ++t) {
-    const int bad = full_cn_phase(b);
-    const int any_bad = __syncthreads_or(bad);
-    if (t >= 2 && !any_bad && first == 0) first = t - 1;
-    full_vn_phase(b, nullptr);
-    __syncthreads();
-    for (int c = tid; c < w.n; c += blockDim.x)
-      post_out[((long long)shot * n_iters + (t - 1)) * w.n + c] = post[c];
-  }
-  const int bad = __syncthreads_or(full_check(b));
-  if (tid == 0) first_ok[shot] = first ? first : (bad ? 0 : n_iters);
+  int done = 0;
+  const int first = window_bp<1>(w, s, (float*)(smem + post_off), (float*)(smem + c2v_off), nullptr,
+                                 n_iters, false, post_out + (long long)shot * n_iters * w.n, &done);
+  if (threadIdx.x == 0) first_ok[shot] = first;
 }
 
 // ------------------------------------------------------------------ commit
-//
-// One thread per (shot, affected DEM row): XOR of the committed window columns
-// decided 1 that touch the row (Eq. 7-8 update). Rows are disjoint per thread,
-// so no atomics. Observables likewise, one thread per (shot, observable).
 
 // Folds a window's committed correction into the later rows and the
 // observables of each shot (a workgroup per few shots). Shot s's row r lives
@@ -2258,15 +2136,16 @@ hipError_t gdg_decode_set_lds_limit(int bucket, int bytes) {
 
 hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, long long stride,
                          int n_iters, float* post, int* first_ok, hipStream_t st) {
-  const size_t lds = (size_t)((w.m + 15) & ~15) + 4 * (size_t)((w.n + 3) & ~3) +
-                     8 * (size_t)w.e_full;
+  const int post_off = gdg_align16(w.m);
+  const int c2v_off = post_off + gdg_align16(4 * (w.n + 1));
+  const size_t lds = (size_t)c2v_off + 4 * (size_t)(w.fr_epad + 2 * kPad);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)gdg_bp_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(gdg_bp_kernel, dim3(n_shots), dim3(256), lds, st, w, n_shots, syn, stride,
-                     n_iters, post, first_ok);
+  hipLaunchKernelGGL(gdg_bp_kernel, dim3(n_shots), dim3(4 * kWave), lds, st, w, post_off, c2v_off,
+                     n_shots, syn, stride, n_iters, post, first_ok);
   return hipGetLastError();
 }
 

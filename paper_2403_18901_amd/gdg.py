@@ -27,7 +27,7 @@ EXPORTED = ["gdg_build_window", "gdg_window_free", "gdg_window_get_info", "gdg_w
             "gdg_dem_free", "gdg_sample", "gdg_sample_errors", "gdg_evaluate",
             "gdg_mlp_forward", "gdg_mlp_grad_work_bytes", "gdg_mlp_grad", "gdg_mlp_adam",
             "gdg_model_create", "gdg_model_free", "gdg_mlp_infer", "gdg_learned_work_bytes",
-            "gdg_decode_learned", "gdg_last_error"]
+            "gdg_decode_learned", "gdg_last_error", "gdg_release_scratch"]
 
 MLP_IN, MLP_H = 17, 64
 MLP_PARAMS = 5377
@@ -56,7 +56,7 @@ class WindowInfo(C.Structure):
 class Trace(C.Structure):
     _fields_ = [("sel", C.c_void_p), ("dec", C.c_void_p), ("log_cap", C.c_int32),
                 ("ends", C.c_void_p), ("first_post", C.c_void_p), ("edge_iters", C.c_void_p),
-                ("step_lsum", C.c_void_p)]
+                ("step_lsum", C.c_void_p), ("pre_post", C.c_void_p)]
 
 
 class Job(C.Structure):
@@ -104,6 +104,7 @@ def lib():
         L.gdg_workspace_bytes.argtypes = [P, i32]
         L.gdg_workspace_bytes.restype = C.c_size_t
         L.gdg_decode_batch.argtypes = [P, i32, P, i64, P, P, P, P, C.c_size_t, P, P]
+        L.gdg_release_scratch.argtypes = [P]
         L.gdg_decode_jobs.argtypes = [P, i32, P, P]
         L.gdg_jobs_lds_bytes.argtypes = [P, i32, i32]
         L.gdg_commit.argtypes = [P, i32, P, P, i64, P, i64, P]
@@ -129,6 +130,11 @@ def lib():
         L.gdg_last_error.restype = C.c_char_p
         _lib = L
     return _lib
+
+
+def release_scratch():
+    """Frees the library's decode scratch pool of the current stream."""
+    _check(lib().gdg_release_scratch(_stream()))
 
 
 def _check(rc):
@@ -187,7 +193,8 @@ class Window:
         return src, llr, commit
 
     def decode(self, syn: torch.Tensor, syn_offset: int = 0, n_shots: int | None = None,
-               trace: bool = False, log_cap: int = 32, out=None, step_lsum: bool = False):
+               trace: bool = False, log_cap: int = 32, out=None, step_lsum: bool = False,
+               pre_post: bool = False):
         """syn: uint8 cuda tensor [n_shots, stride]; window rows start at column syn_offset."""
         assert syn.dtype == torch.uint8 and syn.is_cuda and syn.dim() == 2 and syn.is_contiguous()
         ns = syn.shape[0] if n_shots is None else n_shots
@@ -210,15 +217,33 @@ class Window:
             if step_lsum:
                 trd["step_lsum"] = torch.empty((ns, self.n_paths, log_cap, self.n_act),
                                                dtype=torch.float32, device=dev)
+            if pre_post:
+                trd["pre_post"] = torch.empty((ns, self.prm.pre_iters, self.n),
+                                              dtype=torch.float32, device=dev)
             tr = Trace(_ptr(trd["sel"]), _ptr(trd["dec"]), log_cap, _ptr(trd["ends"]),
                        _ptr(trd["first_post"]), _ptr(trd["edge_iters"]),
-                       _ptr(trd.get("step_lsum")))
+                       _ptr(trd.get("step_lsum")), _ptr(trd.get("pre_post")))
         _check(lib().gdg_decode_batch(self.h, ns, _ptr(syn, syn_offset), syn.shape[1], _ptr(ehat),
                                       _ptr(pm), _ptr(flags), None, 0,
                                       C.byref(tr) if tr is not None else None, _stream()))
         if trace:
             return ehat, pm, flags, trd
         return ehat, pm, flags
+
+    def workspace_bytes(self, n_shots: int) -> int:
+        return int(lib().gdg_workspace_bytes(self.h, n_shots))
+
+    def decode_into(self, syn: torch.Tensor, syn_offset: int, out, workspace=None,
+                    n_shots: int | None = None):
+        """gdg_decode_batch into caller buffers out = (ehat, pm, flags), with an
+        optional caller workspace (uint8 cuda tensor)."""
+        ns = syn.shape[0] if n_shots is None else n_shots
+        ehat, pm, flags = out
+        _check(lib().gdg_decode_batch(self.h, ns, _ptr(syn, syn_offset), syn.shape[1],
+                                      _ptr(ehat), _ptr(pm), _ptr(flags), _ptr(workspace),
+                                      workspace.numel() if workspace is not None else 0,
+                                      None, _stream()))
+        return out
 
     def commit(self, ehat: torch.Tensor, det: torch.Tensor, obs: torch.Tensor):
         ns = ehat.shape[0]

@@ -115,10 +115,25 @@ def _rel_ok(x, ref, tol=1e-4):
     return np.abs(x - ref) <= tol * np.maximum(np.abs(ref), 1.0)
 
 
+def _check_posteriors(post, ref, cmin, H):
+    """post, ref [iters][n]: within 1e-4 relative, or the sign-tie exception
+    (see test_bp_posteriors_within_1e4). Returns 'ok' or 'tie'."""
+    ok = _rel_ok(post, ref)
+    if ok.all():
+        return "ok"
+    t = int(np.argwhere(~ok.all(1))[0][0])
+    for v in np.nonzero(~ok[t])[0]:
+        rows = np.nonzero(H[:, v])[0]
+        assert (cmin[t][rows] <= 1e-3).any(), ("no sign tie", t, v)
+    return "tie"
+
+
 @gpu
-@pytest.mark.parametrize("model,k", [("phen", 1), ("phen", 4), ("circuit", 0), ("circuit", 5)])
+@pytest.mark.parametrize("model,k", [("phen", 1), ("phen", 4), ("circuit", 0), ("circuit", 5),
+                                     ("circuit", 10)])
 def test_bp_posteriors_within_1e4(model, k):
-    """Plain min-sum BP on the whole window: every iteration's posteriors
+    """Min-sum BP on the whole window (gdg_bp runs the decode kernel's own
+    preprocessing BP, without its early stop): every iteration's posteriors
     within 1e-4 relative of the FP64 oracle. The one allowed exception is a
     sign tie: a VN-to-CN message within 1e-3 of zero whose sign FP32 and FP64
     decide differently flips that CN's other outgoing messages; from the first
@@ -158,6 +173,54 @@ def test_bp_posteriors_within_1e4(model, k):
         n_ok += rfirst == first[s]
     assert n_tie <= max(2, det.shape[0] // 10)
     assert n_ok >= det.shape[0] - n_tie - 1
+
+
+@gpu
+@pytest.mark.parametrize("p,k", [(0.002, 0), (0.002, 5), (0.003, 5), (0.003, 10), (0.001, 3)])
+def test_decode_preprocessing_posteriors_within_1e4(p, k):
+    """The decode kernel's own preprocessing (Sec. III, Sec. IV-C), traced from
+    inside gdg_decode_batch: every one of its 8 iterations' posteriors within
+    1e-4 relative of the FP64 oracle (sign-tie exception as above), and it
+    stops after the same iteration as the oracle's early-stop rule."""
+    g = _g()
+    dem = c2_dem("144", 12, p)
+    cp = c2_params(p)
+    op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=cp["low_error"])
+    e = sample_errors(dem.thresholds(), 60, seed=31)
+    det, obs = syndromes(dem, e)
+    det = _residual_before(dem, op, det, obs, k)
+    w = g.Window(dem, k, 3, g.params(**cp))
+    ow = O.OracleWindow(dem, k, 3)
+    _, _, _, tr = w.decode(torch.from_numpy(det).cuda(), syn_offset=w.row0, trace=True,
+                           pre_post=True)
+    torch.cuda.synchronize()
+    pp = tr["pre_post"].cpu().numpy()
+    H = ow.export()["H"]
+    n_tie = n_stop = 0
+    for s in range(det.shape[0]):
+        syn = det[s, w.row0:w.row0 + w.m]
+        ref, rfirst, cmin = ow.bp(op, syn, 8, with_cn_min=True)
+        ran = int(np.isfinite(pp[s]).all(1).sum())
+        assert np.isnan(pp[s][ran:]).all()
+        verdict = _check_posteriors(pp[s][:ran], ref[:ran], cmin[:ran], H)
+        if verdict == "tie":
+            n_tie += 1
+            continue
+        # the oracle stops after the first iteration whose hard decision meets
+        # the syndrome, and so must the kernel -- unless the two hard decisions
+        # (Eq. 4) of an iteration up to then differ, which the tolerance allows
+        # only for posteriors within it of zero (reading R26's Eq. 4 tie)
+        want = rfirst if rfirst else 8
+        if ran != want:
+            t = min(ran, want) - 1
+            diff = (pp[s][t] <= 0) != (ref[t] <= 0)
+            assert diff.any() and (np.abs(ref[t][diff]) <= 1e-4).all(), (s, ran, rfirst)
+            n_tie += 1
+            continue
+        n_stop += ran < 8
+    assert n_tie <= max(2, det.shape[0] // 10)
+    if p >= 0.002:
+        assert n_stop > 0
 
 
 # ------------------------------------------------------------------ window decode
@@ -229,6 +292,23 @@ def _agg_tie(r, i, drift):
     return r["step_agg_margin"][i] <= drift + 1e-5 or _sign_tie(r, i, drift)
 
 
+# (step index, measured key drift, largest oracle key magnitude) of every step
+# compared in _check_decisions
+DRIFT_LOG = []
+
+
+def _drift_cap(i, scale):
+    """Largest FP32-vs-FP64 drift of the Alg. 1 keys allowed at step i (0-based):
+    2e-6 of the largest key magnitude at the first step, growing 16-fold per
+    six-iteration step. Measured on [[144,12,12]] windows at p = 0.001..0.003:
+    at most 3.4e-7 of the scale at the first step, then 10-16-fold growth per
+    step in paths that do not converge (loopy min-sum amplifies rounding). A
+    logic error moves keys by O(1) at the step where it acts, far outside the
+    early caps; past about five steps the two trajectories decorrelate and the
+    cap stops binding."""
+    return 2e-6 * max(1.0, scale) * 16.0 ** i
+
+
 def _check_decisions(ow, op, syn, ref, tr, s, n_act):
     gsel = tr["sel"][s]
     if gsel[0] >= 0 and not (ref["sel"][s][:n_act] == gsel).all():
@@ -254,7 +334,11 @@ def _check_decisions(ow, op, syn, ref, tr, s, n_act):
             a, b = tr["step_lsum"][s, p, i], r["step_lsum"][i]
             both = np.isfinite(a) & np.isfinite(b)
             if (np.isfinite(a) == np.isfinite(b)).all():
-                drift = max(drift, float(np.max(np.abs(a[both] - b[both]))) if both.any() else 0.0)
+                di = float(np.max(np.abs(a[both] - b[both]))) if both.any() else 0.0
+                drift = max(drift, di)
+                scale = float(np.max(np.abs(b[both]))) if both.any() else 0.0
+                DRIFT_LOG.append((i, di, scale))
+                assert drift <= _drift_cap(i, scale), ("drift", s, p, i, drift, scale)
             else:
                 # Either one side met the syndrome at this step and the other did
                 # not (the syndrome check turned on a posterior sign inside the
@@ -279,7 +363,11 @@ def _check_decisions(ow, op, syn, ref, tr, s, n_act):
                 # same VN, other value: the favoured value follows the sign of its key
                 assert boundary or _close(r["own_key"][i], 0.0, drift), ("value", s, p, i, drift)
             else:
-                assert boundary or _close(r["own_key"][i], r["forced_key"][i], 2 * drift), \
+                # with Alg. 3 on, a comparison inside the drift of its threshold
+                # changes the candidate set Alg. 1 chooses from
+                alg3_tie = op.low_error == 0 and r["step_agg_margin"][i] <= drift + 1e-5
+                assert boundary or alg3_tie or \
+                    _close(r["own_key"][i], r["forced_key"][i], 2 * drift), \
                     ("select", s, p, i, r["own_key"][i], r["forced_key"][i], drift)
 
 
@@ -304,17 +392,78 @@ def test_window_decode_c1(k):
 
 
 @gpu
-@pytest.mark.parametrize("p", [0.002, 0.003])
-@pytest.mark.parametrize("k", [0, 5, 9])
+@pytest.mark.parametrize("p", [0.001, 0.002, 0.003])
+@pytest.mark.parametrize("k", [0, 5, 9, 10])
 def test_window_decode_c2(p, k):
+    """[[144,12,12]] circuit-level windows at the paper's three noise rates,
+    the first, middle and last two windows (k = 10 commits everything)."""
     g = _g()
     dem = c2_dem("144", 12, p)
-    e = sample_errors(dem.thresholds(), 120, seed=7)
+    e = sample_errors(dem.thresholds(), 160, seed=7)
     det, obs = syndromes(dem, e)
     cp = c2_params(p)
     op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=cp["low_error"])
     det = _residual_before(dem, op, det, obs, k)
-    _compare_window(dem, k, g.params(**cp), op, det, require_exact=0.9)
+    _compare_window(dem, k, g.params(**cp), op, det, require_exact=0.98)
+
+
+@gpu
+@pytest.mark.parametrize("p,k", [(0.002, 0), (0.003, 5)])
+def test_window_decode_c2_22_paths(p, k):
+    """The paper's full tree for N <= 144 (Fig. 2): 16 tree paths plus side
+    paths splitting at depths 5..10, 22 paths, D_max = split + 10."""
+    g = _g()
+    dem = c2_dem("144", 12, p)
+    e = sample_errors(dem.thresholds(), 120, seed=17)
+    det, obs = syndromes(dem, e)
+    cp = dict(c2_params(p), side_max_depth=10)
+    op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=cp["low_error"],
+                  side_max_depth=10)
+    det = _residual_before(dem, op, det, obs, k)
+    w = g.Window(dem, k, 3, g.params(**cp))
+    assert w.n_paths == 22
+    _compare_window(dem, k, g.params(**cp), op, det, require_exact=0.98)
+
+
+@gpu
+@pytest.mark.parametrize("p,k", [(0.001, 0), (0.002, 0), (0.002, 10), (0.003, 5)])
+def test_full_launch_regime(p, k):
+    """The launch regime bench.py times: several thousand shots in one
+    persistent launch (three workgroups per CU sharing its LDS, workgroups
+    looping over the shot counter, large sub-graphs on fewer path wavefronts).
+    Its answers, metrics and flags must equal, bit for bit, the same shots
+    decoded in launches of at most 200 shots (one workgroup per CU, most of
+    its LDS each); a 300-shot subset is then compared with the oracle element
+    by element (_compare_window's bars), and the traced decode behind that
+    comparison must itself reproduce the full launch's answers."""
+    g = _g()
+    ns = 3200
+    dem = c2_dem("144", 12, p)
+    cp = c2_params(p)
+    op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=cp["low_error"])
+    e = sample_errors(dem.thresholds(), ns, seed=23)
+    det, obs = syndromes(dem, e)
+    det = _residual_before(dem, op, det, obs, k)
+    w = g.Window(dem, k, 3, g.params(**cp))
+    d = torch.from_numpy(det).cuda()
+    full = w.decode(d, syn_offset=w.row0)
+    chunks = [w.decode(d[i:i + 200].contiguous(), syn_offset=w.row0) for i in range(0, ns, 200)]
+    torch.cuda.synchronize()
+    for j in range(3):
+        part = torch.cat([c[j] for c in chunks])
+        if j == 1:
+            assert torch.equal(full[j].view(torch.int64), part.view(torch.int64))
+        else:
+            assert torch.equal(full[j], part), j
+    sub = np.arange(0, ns, ns // 300)[:300]
+    ds = np.ascontiguousarray(det[sub])
+    _compare_window(dem, k, g.params(**cp), op, ds, require_exact=0.98)
+    e_t, pm_t, fl_t, _ = w.decode(torch.from_numpy(ds).cuda(), syn_offset=w.row0, trace=True)
+    torch.cuda.synchronize()
+    idx = torch.from_numpy(sub).cuda()
+    assert torch.equal(e_t, full[0][idx])
+    assert torch.equal(pm_t.view(torch.int64), full[1][idx].view(torch.int64))
+    assert torch.equal(fl_t, full[2][idx])
 
 
 @gpu
@@ -379,15 +528,25 @@ def test_pipeline_c1_1000_shots():
 
 
 @gpu
-@pytest.mark.parametrize("p", [0.003])
-def test_pipeline_c2_ler_parity(p):
+@pytest.mark.parametrize("p,ns", [(0.003, 20000), (0.002, 50000)])
+def test_pipeline_c2_ler_parity(p, ns):
+    """Whole 12-round shots, 11 windows each, at the headline rate p = 0.002
+    (5e4 shots, about 25 failures expected) and at p = 0.003 (2e4 shots, Alg. 3
+    on): the GPU's failure count inside the oracle's 2-sigma Wilson interval on
+    the same shots, residual detectors exactly zero on every GPU success, and
+    the two agree shot by shot on at least 99.5 % of shots (measured 99.8 % at
+    p = 0.003: non-converging paths decorrelate between FP32 and FP64)."""
     dem = c2_dem("144", 12, p)
     cp = c2_params(p)
     op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=cp["low_error"])
-    gf, wf, resid, ref = _pipeline(dem, _g().params(**cp), op, 200, 99)
+    gf, wf, resid, ref = _pipeline(dem, _g().params(**cp), op, ns, 99)
     assert not resid[~gf].any()
-    lo, hi = wilson(int(ref["fail"].sum()), 200)
-    assert lo * 200 - 1e-9 <= gf.sum() <= hi * 200 + 1e-9
+    rf = ref["fail"].astype(bool)
+    lo, hi = wilson(int(rf.sum()), ns)
+    print(f"p={p}: GPU failures {int(gf.sum())}, oracle {int(rf.sum())} of {ns}")
+    assert rf.sum() >= 10
+    assert lo * ns - 1e-9 <= gf.sum() <= hi * ns + 1e-9
+    assert (gf == rf).mean() >= 0.995
 
 
 @gpu
