@@ -24,7 +24,8 @@
  *    is allocated on the first decode on that stream, grown (after
  *    synchronising the stream) when a larger window needs more, and kept
  *    until gdg_release_scratch or the process ends. Decodes that share
- *    scratch (one stream's pool or one workspace) must not overlap in time.
+ *    scratch (one stream's pool, one workspace, or the fixed array of
+ *    gdg_decode_batch_noalloc) must not overlap in time.
  */
 #ifndef GDG_H
 #define GDG_H
@@ -193,6 +194,22 @@ int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_sy
                      int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
                      void* d_workspace, size_t workspace_bytes, const gdg_trace* trace,
                      void* hip_stream);
+
+/*
+ * gdg_decode_batch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same decode, with its scratch in a fixed 64 MiB device array of the
+ * library that every GPU it runs on holds until the process ends. The array
+ * takes the shot counter (cleared by a fill kernel at every call) and the
+ * path checkpoints of as many workgroups as fit (C2: 341 of 768; the others
+ * replay their paths from the root, which gives identical results). Calls on
+ * one GPU share the array and must not overlap in time (they race). Outputs
+ * and errors as gdg_decode_batch, plus GDG_ESHAPE when one workgroup's
+ * checkpoints exceed the array. No traces.
+ */
+int gdg_decode_batch_noalloc(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                             int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
+                             void* hip_stream);
 
 /*
  * Releases the library's decode scratch pool of (current device, hip_stream),

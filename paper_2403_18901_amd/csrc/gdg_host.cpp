@@ -813,6 +813,28 @@ int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_sy
                              d_workspace, workspace_bytes);
 }
 
+int gdg_decode_batch_noalloc(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                             int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
+                             void* hip_stream) {
+  if (!win) return fail(GDG_EINVAL, "null window");
+  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+  if (n_shots == 0) return GDG_OK;
+  gdg_job job{win, n_shots, d_syndrome, syn_stride, d_ehat, d_pm, d_flags};
+  LaunchGeom G;
+  int rc = launch_geometry(&job, 1, win->waves, 0, false, G);
+  if (rc) return rc;
+  void* scratch = nullptr;
+  size_t bytes = 0;
+  hipError_t e = gdg_static_scratch(&scratch, &bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (static scratch)");
+  if (G.slots > 0 && (size_t)G.ck_per_wg() > bytes - kCounterBytes)
+    return fail(GDG_ESHAPE, "the window's path checkpoints for one workgroup exceed the fixed "
+                            "scratch of gdg_decode_batch_noalloc");
+  gdg_trace_dev tr{};
+  return launch_with_scratch(&job, 1, win->waves, G, tr, (hipStream_t)hip_stream, nullptr,
+                             scratch, bytes);
+}
+
 int gdg_release_scratch(void* hip_stream) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);

@@ -193,6 +193,9 @@ struct gdg_jobs_dev {
 };
 
 hipError_t gdg_launch_zero(int* p, int n, hipStream_t st);
+// The fixed device scratch of gdg_decode_batch_noalloc on the current device:
+// its address (looked up once per device) and size.
+hipError_t gdg_static_scratch(void** ptr, size_t* bytes);
 hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, bool low, int waves, int grid,
                            int lds, const gdg_trace_dev& tr, hipStream_t st);
 int gdg_kernel_bucket(int m, int n_act);

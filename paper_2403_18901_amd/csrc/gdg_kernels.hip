@@ -28,6 +28,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <vector>
+
 #include "gdg_kernels.h"
 
 namespace {
@@ -1868,6 +1871,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
+// Scratch of gdg_decode_batch_noalloc, for callers that cannot allocate:
+// the shot counter and as many workgroups' path checkpoints as fit. Each
+// device holds its own copy until the process ends; calls on one device share
+// it. Host code uses the address from hipGetSymbolAddress, never this name.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 __global__ void gdg_zero_kernel(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -2072,6 +2082,25 @@ __global__ void gdg_evaluate_kernel(int n_shots, int n_rows, int n_obs,
 // Register tilings of the decode kernel: VNs per lane of each bucket.
 #define GDG_DECODE_TILINGS(X) X(6) X(7) X(8) X(14) X(16)
 constexpr int kBuckets = 5;
+
+hipError_t gdg_static_scratch(void** ptr, size_t* bytes) {
+  static std::mutex mu;
+  static std::vector<void*> addr;   // per device, looked up once with that device current
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = kStaticScratchBytes;
+  return hipSuccess;
+}
 
 hipError_t gdg_launch_zero(int* p, int n, hipStream_t st) {
   hipLaunchKernelGGL(gdg_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);

@@ -27,7 +27,8 @@ EXPORTED = ["gdg_build_window", "gdg_window_free", "gdg_window_get_info", "gdg_w
             "gdg_dem_free", "gdg_sample", "gdg_sample_errors", "gdg_evaluate",
             "gdg_mlp_forward", "gdg_mlp_grad_work_bytes", "gdg_mlp_grad", "gdg_mlp_adam",
             "gdg_model_create", "gdg_model_free", "gdg_mlp_infer", "gdg_learned_work_bytes",
-            "gdg_decode_learned", "gdg_last_error", "gdg_release_scratch"]
+            "gdg_decode_learned", "gdg_last_error", "gdg_decode_batch_noalloc",
+            "gdg_release_scratch"]
 
 MLP_IN, MLP_H = 17, 64
 MLP_PARAMS = 5377
@@ -104,6 +105,7 @@ def lib():
         L.gdg_workspace_bytes.argtypes = [P, i32]
         L.gdg_workspace_bytes.restype = C.c_size_t
         L.gdg_decode_batch.argtypes = [P, i32, P, i64, P, P, P, P, C.c_size_t, P, P]
+        L.gdg_decode_batch_noalloc.argtypes = [P, i32, P, i64, P, P, P, P]
         L.gdg_release_scratch.argtypes = [P]
         L.gdg_decode_jobs.argtypes = [P, i32, P, P]
         L.gdg_jobs_lds_bytes.argtypes = [P, i32, i32]
@@ -234,15 +236,20 @@ class Window:
         return int(lib().gdg_workspace_bytes(self.h, n_shots))
 
     def decode_into(self, syn: torch.Tensor, syn_offset: int, out, workspace=None,
-                    n_shots: int | None = None):
+                    noalloc: bool = False, n_shots: int | None = None):
         """gdg_decode_batch into caller buffers out = (ehat, pm, flags), with an
-        optional caller workspace (uint8 cuda tensor)."""
+        optional caller workspace (uint8 cuda tensor), or
+        gdg_decode_batch_noalloc when noalloc is set."""
         ns = syn.shape[0] if n_shots is None else n_shots
         ehat, pm, flags = out
-        _check(lib().gdg_decode_batch(self.h, ns, _ptr(syn, syn_offset), syn.shape[1],
-                                      _ptr(ehat), _ptr(pm), _ptr(flags), _ptr(workspace),
-                                      workspace.numel() if workspace is not None else 0,
-                                      None, _stream()))
+        if noalloc:
+            _check(lib().gdg_decode_batch_noalloc(self.h, ns, _ptr(syn, syn_offset), syn.shape[1],
+                                                  _ptr(ehat), _ptr(pm), _ptr(flags), _stream()))
+        else:
+            _check(lib().gdg_decode_batch(self.h, ns, _ptr(syn, syn_offset), syn.shape[1],
+                                          _ptr(ehat), _ptr(pm), _ptr(flags), _ptr(workspace),
+                                          workspace.numel() if workspace is not None else 0,
+                                          None, _stream()))
         return out
 
     def commit(self, ehat: torch.Tensor, det: torch.Tensor, obs: torch.Tensor):
