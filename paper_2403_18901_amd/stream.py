@@ -3,18 +3,23 @@
 Many logical blocks produce syndrome rounds over time; each block is decoded
 window by window (Sec. III, Eq. 6-8): window k of an experiment becomes
 decodable once its W rounds have arrived and window k - 1 has been committed.
-The service batches every decodable window of every block into one persistent
-multi-job launch per tick (one job per code and window shape: first, middle,
-last window of an experiment; a time-uniform DEM gives all middle windows one
-graph), commits each window into its block's device-resident detector record
-and observable accumulator, and evaluates experiments that finished (Eq. 8-9).
+The service batches every decodable window -- the next window of every
+admitted experiment of every block, windows of one experiment strictly in
+order -- into persistent multi-job launches per tick (one job per code and
+window shape: first, middle, last window of an experiment; a time-uniform DEM
+gives all middle windows one graph), commits each window into its
+experiment's device-resident detector record and observable accumulator, and
+evaluates experiments that finished (Eq. 8-9).
 
 Time is virtual: rounds arrive as a Poisson process per block in simulated
 time, and each tick advances the clock by the measured device time of its
 launches (HIP events), so latencies are queueing plus decode time on the GPU,
-without the host's scheduling overhead (reported separately). Admission: an
-experiment that starts while every device slot of its code is taken (the
-memory budget) is rejected.
+without the host's scheduling overhead (reported separately). Admission is by
+device memory: a byte budget (by default a share of the free device memory
+that hipMemGetInfo reports) is divided into experiment slots of each code --
+its detector record and observable accumulator plus the per-window batch
+buffers of one in-flight window -- and an experiment that starts while every
+slot of its code is taken is rejected.
 
 StreamScheduler is the host bookkeeping (numpy only); StreamingService drives
 the library's kernels through the C ABI.
@@ -32,9 +37,12 @@ class StreamScheduler:
 
     Block b's rounds arrive as a Poisson process of `rate` rounds per second;
     an experiment is n_rounds consecutive rounds; its window k (0 <= k < K,
-    K = n_rounds - W + 1) needs rounds k .. k + W - 1. A block decodes its
-    experiments in order, one window at a time. An experiment is admitted at
-    its first round if one of the n_slots device slots is free, else rejected.
+    K = n_rounds - W + 1) needs rounds k .. k + W - 1 and the commit of window
+    k - 1 of the same experiment (Sec. III). Experiments are independent
+    decoding problems, so the admitted experiments of a block (and of all
+    blocks) have their next windows decoded concurrently. An experiment is
+    admitted at its first round if one of the n_slots device slots is free,
+    else rejected.
     """
 
     def __init__(self, n_blocks, n_rounds, W, rate, n_slots, seed=0):
@@ -48,7 +56,6 @@ class StreamScheduler:
         self.free = list(range(n_slots - 1, -1, -1))
         # arrival time of the first round of each block's next experiment
         self.t_first = self.rng.exponential(1.0 / self.rate, size=n_blocks)
-        self.pending = [[] for _ in range(n_blocks)]   # admitted experiments, oldest first
         self.slot_block = np.full(n_slots, -1, np.int64)
         self.slot_k = np.zeros(n_slots, np.int64)
         self.slot_times = np.zeros((n_slots, n_rounds))
@@ -79,46 +86,51 @@ class StreamScheduler:
         return s[order], np.concatenate(blocks)[order], np.concatenate(times)[order]
 
     def advance_to(self, now):
-        """Process arrivals up to `now`; returns (slots, experiment ids) newly
-        admitted, ids consecutive."""
+        """Process arrivals up to `now`: experiments are admitted in start
+        order while slots are free, the rest rejected. Returns (slots,
+        experiment ids) newly admitted, ids consecutive."""
         s, b, t = self._generate(now)
         self.n_exp_started += s.size
-        new_slots, new_ids = [], []
-        for i in range(s.size):
-            if not self.free:
-                self.n_rejected += 1
-                continue
-            slot = self.free.pop()
-            blk = int(b[i])
-            self.slot_block[slot] = blk
-            self.slot_k[slot] = 0
-            self.slot_times[slot] = t[i]
-            self.slot_exp[slot] = self.next_exp_id
-            new_ids.append(self.next_exp_id)
-            self.next_exp_id += 1
-            self.pending[blk].append(slot)
-            new_slots.append(slot)
-            self.n_admitted += 1
-        return np.array(new_slots, np.int64), np.array(new_ids, np.int64)
+        n = min(s.size, len(self.free))
+        slots = np.array([self.free.pop() for _ in range(n)], np.int64)
+        ids = np.arange(self.next_exp_id, self.next_exp_id + n, dtype=np.int64)
+        self.slot_block[slots] = b[:n]
+        self.slot_k[slots] = 0
+        self.slot_times[slots] = t[:n]
+        self.slot_exp[slots] = ids
+        self.next_exp_id += n
+        self.n_admitted += n
+        self.n_rejected += s.size - n
+        return slots, ids
 
-    def heads(self):
-        """Slot of each block's oldest admitted experiment (or none)."""
-        return np.array([p[0] for p in self.pending if p], np.int64)
+    @property
+    def pending(self):
+        """Admitted, unfinished experiments of each block (slots, oldest first)."""
+        out = [[] for _ in range(self.nb)]
+        act = self.active()
+        for slot in act[np.argsort(self.slot_exp[act], kind="stable")]:
+            out[int(self.slot_block[slot])].append(int(slot))
+        return out
+
+    def active(self):
+        """Slots of every admitted experiment not yet finished."""
+        return np.nonzero(self.slot_block >= 0)[0].astype(np.int64)
 
     def avail_time(self, slots):
         k = self.slot_k[slots]
         return self.slot_times[slots, k + self.W - 1]
 
     def ready(self, now):
-        """Slots whose next window is decodable at `now` (one per block at most)."""
-        h = self.heads()
+        """Slots whose next window is decodable at `now` (one window per
+        experiment: its previous window is committed)."""
+        h = self.active()
         if h.size == 0:
             return h
         return h[self.avail_time(h) <= now]
 
     def next_event(self):
-        """Earliest time a head window becomes decodable (inf if none is waiting)."""
-        h = self.heads()
+        """Earliest time a next window becomes decodable (inf if none is waiting)."""
+        h = self.active()
         if h.size == 0:
             return np.inf
         return float(self.avail_time(h).min())
@@ -131,31 +143,29 @@ class StreamScheduler:
         """Windows of `slots` are committed; returns the slots whose experiment ended."""
         self.slot_k[slots] += 1
         done = slots[self.slot_k[slots] >= self.K]
-        for slot in done:
-            blk = int(self.slot_block[slot])
-            assert self.pending[blk] and self.pending[blk][0] == slot
-            self.pending[blk].pop(0)
-            self.slot_block[slot] = -1
-            self.free.append(int(slot))
+        self.slot_block[done] = -1
+        self.free.extend(int(x) for x in done)
         return done
 
     def backlog(self, now):
         """Windows whose rounds have arrived but that are not yet committed."""
-        n = 0
-        for slot in range(self.n_slots):
-            if self.slot_block[slot] < 0:
-                continue
-            arrived = int(np.searchsorted(self.slot_times[slot], now, side="right"))
-            n += max(0, min(self.K, arrived - self.W + 1) - int(self.slot_k[slot]))
-        return n
+        act = self.active()
+        if act.size == 0:
+            return 0
+        arrived = (self.slot_times[act] <= now).sum(axis=1)
+        ready = np.minimum(self.K, arrived - self.W + 1) - self.slot_k[act]
+        return int(np.maximum(ready, 0).sum())
 
 
 class _Code:
-    def __init__(self, dem, n_blocks, prm, W, rate, n_slots, seed, stream_id, device):
-        import torch
+    """One code's windows (first, middle, last shapes), device sampler and,
+    once sized, its experiment slots: the scheduler and the device-resident
+    detector records and observable accumulators."""
+
+    def __init__(self, dem, n_blocks, prm, W, rate, seed, stream_id, device):
         self.dem = dem
-        self.sched = StreamScheduler(n_blocks, dem.n_rounds, W, rate, n_slots, seed)
-        self.K = self.sched.K
+        self.n_blocks, self.W, self.rate = n_blocks, W, rate
+        self.K = dem.n_rounds - W + 1
         self.w = dem.w
         self.n_rows, self.n_obs = dem.n_rows, max(dem.n_obs, 1)
         self.win = {0: G.Window(dem, 0, W, prm)}
@@ -165,13 +175,25 @@ class _Code:
             self.win[self.K - 1] = G.Window(dem, self.K - 1, W, prm)
         self.m = self.win[0].m
         self.ddem = G.DeviceDem(dem)
-        self.det = torch.zeros((n_slots, self.n_rows), dtype=torch.uint8, device=device)
-        self.obs = torch.zeros((n_slots, self.n_obs), dtype=torch.uint8, device=device)
         self.stream_id = stream_id
         self.seed = seed
         self.device = device
         self.fails = []     # (experiment id, failed)
         self.obs_out = {}   # experiment id -> observable accumulator after the last commit
+
+    def slot_bytes(self):
+        """Device bytes of one experiment slot: its detector record and
+        observable accumulator, plus the batch buffers of one in-flight window
+        (window syndrome, correction, path metric, flags, three offsets)."""
+        n = max(w.n for w in self.win.values())
+        return self.n_rows + self.n_obs + self.m + n + 8 + 4 + 3 * 8
+
+    def alloc(self, n_slots):
+        import torch
+        self.sched = StreamScheduler(self.n_blocks, self.dem.n_rounds, self.W, self.rate, n_slots,
+                                     self.seed)
+        self.det = torch.zeros((n_slots, self.n_rows), dtype=torch.uint8, device=self.device)
+        self.obs = torch.zeros((n_slots, self.n_obs), dtype=torch.uint8, device=self.device)
 
     def shape_of(self, k):
         if k == 0:
@@ -185,17 +207,35 @@ class StreamingService:
     """Continuous batching of the decodable windows of many blocks.
 
     codes: list of (dem, n_blocks). rate: rounds per second per block.
-    n_slots: device slots (concurrent experiments) per code, the memory budget.
+    mem_budget: device bytes for experiment slots (None: a quarter of the free
+    device memory reported by hipMemGetInfo, at most 1 GiB), shared by the
+    codes in proportion to n_blocks x slot_bytes. n_slots: a fixed slot count
+    per code instead (tests).
     """
 
     def __init__(self, codes, prm, W=3, rate=1e6, n_slots=None, seed=0, plan=None,
-                 device="cuda"):
-        self.codes = []
-        for i, (dem, nb) in enumerate(codes):
-            ns = n_slots if n_slots is not None else 2 * nb
-            self.codes.append(_Code(dem, nb, prm, W, rate, ns, seed + 7919 * i, i, device))
-        self.plan = plan or B.LaunchPlan(waves=4, wg_per_cu=0, split=False)
+                 device="cuda", mem_budget=None):
+        import torch
+        self.codes = [_Code(dem, nb, prm, W, rate, seed + 7919 * i, i, device)
+                      for i, (dem, nb) in enumerate(codes)]
+        per = [c.slot_bytes() for c in self.codes]
+        if n_slots is None:
+            if mem_budget is None:
+                free, _ = torch.cuda.mem_get_info()   # hipMemGetInfo
+                mem_budget = min(free // 4, 1 << 30)
+            demand = sum(c.n_blocks * b for c, b in zip(self.codes, per))
+        self.mem_budget = mem_budget
+        self.slot_bytes = per
+        for c, b in zip(self.codes, per):
+            if n_slots is not None:
+                c.alloc(n_slots)
+            else:
+                c.alloc(max(1, int(mem_budget * (c.n_blocks * b / demand) // b)))
+        # one persistent launch per register tiling: windows of a small code do
+        # not run in a larger code's tiling and LDS share
+        self.plan = plan or B.LaunchPlan(waves=4, wg_per_cu=0, split=True)
         self.device = device
+        self.streams = [torch.cuda.Stream(device=device) for _ in self.codes]
         self.now = 0.0
         self.latencies = []
         self.n_windows = 0
@@ -223,8 +263,9 @@ class StreamingService:
         G.copy_rows(tmp_obs, src * c.n_obs, c.n_obs, c.obs, dst * c.n_obs)
 
     def tick(self):
-        """One batch: every decodable head window of every block. Returns the
-        number of windows decoded (0: nothing was ready at the current time)."""
+        """One batch: the next window of every admitted experiment whose rounds
+        have arrived. Returns the number of windows decoded (0: nothing was
+        ready at the current time)."""
         import torch
         t_host = time.perf_counter()
         for c in self.codes:
@@ -235,7 +276,7 @@ class StreamingService:
             if r.size == 0:
                 continue
             k = c.sched.slot_k[r]
-            shapes = np.array([c.shape_of(int(x)) for x in k])
+            shapes = np.where(k == 0, 0, np.where(k == c.K - 1, c.K - 1, 1))
             for sh in np.unique(shapes):
                 groups.append((c, int(sh), r[shapes == sh]))
         if not groups:
@@ -243,27 +284,43 @@ class StreamingService:
             return 0
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        jobs, commits = [], []
-        e0.record()
-        for c, sh, slots in groups:
-            win = c.win[sh]
-            k = c.sched.slot_k[slots]
-            off = torch.from_numpy(slots * c.n_rows + k * c.w).to(self.device)
-            n = slots.size
-            syn = torch.empty((n, win.m), dtype=torch.uint8, device=self.device)
-            G.copy_rows(c.det, off, win.m, syn)
-            outs = (torch.empty((n, win.n), dtype=torch.uint8, device=self.device),
-                    torch.empty(n, dtype=torch.float64, device=self.device),
-                    torch.empty(n, dtype=torch.int32, device=self.device))
-            jobs.append((win, syn, 0, outs))
-            obs_off = torch.from_numpy(slots * c.n_obs).to(self.device)
-            commits.append((c, win, outs[0], off, obs_off, slots))
-        jobs.sort(key=lambda j: -(j[0].n_paths * j[0].n_act * j[1].shape[0]))
-        for i in range(0, len(jobs), G.MAX_JOBS):
-            self.plan.run(jobs[i:i + G.MAX_JOBS])
-        for c, win, ehat, off, obs_off, slots in commits:
-            win.commit_indexed(ehat, c.det, off, c.obs, obs_off)
-        e1.record()
+        main = torch.cuda.current_stream()
+        e0.record(main)
+        commits = []
+        # each code's gathers, decode launches and commits on a stream of its
+        # own: codes are independent, so their launches overlap (one code's
+        # launch drains while the other's runs)
+        for c in self.codes:
+            mine = [(sh, slots) for cc, sh, slots in groups if cc is c]
+            if not mine:
+                continue
+            st = self.streams[c.stream_id]
+            st.wait_event(e0)
+            with torch.cuda.stream(st):
+                jobs, cm = [], []
+                for sh, slots in mine:
+                    win = c.win[sh]
+                    k = c.sched.slot_k[slots]
+                    off = torch.from_numpy(slots * c.n_rows + k * c.w).to(self.device)
+                    n = slots.size
+                    syn = torch.empty((n, win.m), dtype=torch.uint8, device=self.device)
+                    G.copy_rows(c.det, off, win.m, syn)
+                    outs = (torch.empty((n, win.n), dtype=torch.uint8, device=self.device),
+                            torch.empty(n, dtype=torch.float64, device=self.device),
+                            torch.empty(n, dtype=torch.int32, device=self.device))
+                    jobs.append((win, syn, 0, outs))
+                    obs_off = torch.from_numpy(slots * c.n_obs).to(self.device)
+                    cm.append((c, win, outs[0], off, obs_off, slots))
+                jobs.sort(key=lambda j: -(j[0].n_paths * j[0].n_act * j[1].shape[0]))
+                for i in range(0, len(jobs), G.MAX_JOBS):
+                    self.plan.run(jobs[i:i + G.MAX_JOBS])
+                for cc, win, ehat, off, obs_off, slots in cm:
+                    win.commit_indexed(ehat, cc.det, off, cc.obs, obs_off)
+                done = torch.cuda.Event()
+                done.record(st)
+            main.wait_event(done)
+            commits.extend(cm)
+        e1.record(main)
         e1.synchronize()
         dt = e0.elapsed_time(e1) * 1e-3
         self.device_s += dt
@@ -324,6 +381,9 @@ class StreamingService:
                            "max": float(lat.max() * 1e3) if lat.size else None},
             "backlog_windows": int(backlog),
             "backlog_growth_per_s": backlog / span,
+            "mem_budget_bytes": int(self.mem_budget) if self.mem_budget is not None else None,
+            "slots": [int(c.sched.n_slots) for c in self.codes],
+            "slot_bytes": [int(b) for b in self.slot_bytes],
             "experiments_started": int(sum(c.sched.n_exp_started for c in self.codes)),
             "admitted": int(sum(c.sched.n_admitted for c in self.codes)),
             "rejected": int(sum(c.sched.n_rejected for c in self.codes)),

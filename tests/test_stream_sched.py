@@ -27,9 +27,10 @@ def test_admission_cap_and_rejections():
     assert sum(len(p) for p in s.pending) == 3
 
 
-def test_windows_in_order_per_block():
-    """A block's window k is ready only when its round k+W-1 has arrived, one
-    window per block at a time, and the slot frees after K windows."""
+def test_windows_in_order_per_experiment():
+    """An experiment's window k is ready only when its round k+W-1 has arrived
+    and window k-1 is committed, one window per experiment at a time, and the
+    slot frees after K windows."""
     s = StreamScheduler(1, 6, 3, rate=100.0, n_slots=2, seed=0)
     now = 0.0
     s.advance_to(now)
@@ -70,3 +71,21 @@ def test_fake_service_drains_every_admitted_experiment():
         done += s.complete(r).size
     assert done == s.n_admitted and min(lat) >= 0.0
     assert s.backlog(now) == 0
+
+
+def test_experiments_of_a_block_decode_concurrently():
+    """A block's later experiments do not wait for its earlier ones: once
+    their rounds have arrived, the next windows of all of them are ready in the
+    same tick (each experiment still one window at a time, in order)."""
+    s = StreamScheduler(1, 6, 3, rate=1e5, n_slots=8, seed=2)
+    s.advance_to(1e-3)                        # about 16 experiments started, 8 admitted
+    assert s.n_admitted == 8 and s.n_rejected > 0
+    r = s.ready(1.0)
+    assert r.size == 8                        # every admitted experiment has window 0 ready
+    s.complete(r)
+    assert (s.slot_k[r] == 1).all()
+    r2 = s.ready(1.0)
+    assert sorted(r2.tolist()) == sorted(r.tolist())
+    for _ in range(s.K - 1):
+        s.complete(s.ready(1.0))
+    assert s.active().size == 0 and len(s.free) == 8 and not any(s.pending)
