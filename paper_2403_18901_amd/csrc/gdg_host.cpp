@@ -165,7 +165,9 @@ gdg_lds plan_lds(const gdg_win_dev& w, int max_sub_edges, int col_slots, int tco
     };
     L.p_post = ptake(4 * (n + 1));   // + the padding's dummy VN
     // the ranking's radix-select scratch reuses the message array
-    const int rank_bytes = 4 * (256 + 4) + 8 * na;
+    int sort_p = 1;   // the kept keys, padded to a power of two for the sort
+    while (sort_p < na) sort_p <<= 1;
+    const int rank_bytes = 4 * (256 + 4) + 8 * sort_p;
     const int c2v_bytes = std::max(std::max(4 * (w.fr_epad + 8), 8 * L.sort_n), rank_bytes);
     L.p_c2v = ptake(c2v_bytes);
     L.p_keys = L.p_c2v;   // the sort keys reuse the message array

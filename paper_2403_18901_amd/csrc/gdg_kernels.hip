@@ -155,6 +155,25 @@ __device__ void wg_exclusive_scan_wave0(int* a, int len) {
   if (lane == 0) a[len] = carry;
 }
 
+// Ascending bitonic sort (Batcher) of P 64-bit keys in LDS by the whole
+// workgroup, P a power of two; each stage compares and exchanges P / 2
+// disjoint pairs, then synchronises.
+__device__ void wg_bitonic_sort(unsigned long long* a, int P) {
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P / 2; i += blockDim.x) {
+        const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));   // bit j of lo clear
+        const unsigned long long x = a[lo], y = a[lo + j];
+        if ((x > y) == ((lo & k) == 0)) {
+          a[lo] = y;
+          a[lo + j] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ float clip_to(float x, float c) { return __builtin_amdgcn_fmed3f(x, -c, c); }
@@ -581,16 +600,33 @@ __device__ __forceinline__ int cn_slot(PathCtx<VPL>& P, const Slot& c, int t, fl
   return (int)(srow ^ a.hp);   // bit 31: the row is unsatisfied
 }
 
+// Gather of a slot's four posteriors (hard decisions in the sign bits).
+template <int VPL>
+__device__ __forceinline__ void gather_post(const PathCtx<VPL>& P, Slot& s) {
+  s.g.x = __float_as_uint(at_byte(P.post, s.vo.x & 0xffffu));
+  s.g.y = __float_as_uint(at_byte(P.post, s.vo.x >> 16));
+  s.g.z = __float_as_uint(at_byte(P.post, s.vo.y & 0xffffu));
+  s.g.w = __float_as_uint(at_byte(P.post, s.vo.y >> 16));
+}
+
+// Syndrome check of one slot: bit 0 set if its row is unsatisfied by the
+// gathered hard decisions; optionally records the row's flag for Alg. 3.
+template <int VPL>
+__device__ __forceinline__ int check_slot(const PathCtx<VPL>& P, const Slot& s, int t,
+                                          bool write_unsat) {
+  const uint32_t mt = s.mt;
+  uint32_t hp = xor3(s.g.x, s.g.y, s.g.z) ^ s.g.w;
+  hp_group(hp, (mt >> kMetaLogKShift) & 7);
+  const int hx = (int)(((P.sres >> t) & 1u) ^ (hp >> 31));
+  if (write_unsat && (mt & kMetaLead) && (mt & kMetaValid))
+    P.unsat[(mt >> kMetaRowShift) & 0x3ff] = (uint8_t)hx;
+  return hx;
+}
+
 template <int VPL, bool REC = false>
 __device__ __forceinline__ int cn_phase(PathCtx<VPL>& P, float alpha, float clip) {
   return slot_walk<VPL, true, REC>(
-      P,
-      [&](Slot& s) {
-        s.g.x = __float_as_uint(at_byte(P.post, s.vo.x & 0xffffu));
-        s.g.y = __float_as_uint(at_byte(P.post, s.vo.x >> 16));
-        s.g.z = __float_as_uint(at_byte(P.post, s.vo.y & 0xffffu));
-        s.g.w = __float_as_uint(at_byte(P.post, s.vo.y >> 16));
-      },
+      P, [&](Slot& s) { gather_post(P, s); },
       [&](const Slot& s, int t) { return cn_slot(P, s, t, alpha, clip); });
 }
 
@@ -599,22 +635,8 @@ __device__ __forceinline__ int cn_phase(PathCtx<VPL>& P, float alpha, float clip
 template <int VPL, bool REC = false>
 __device__ __forceinline__ int check_pass(PathCtx<VPL>& P, bool write_unsat) {
   return slot_walk<VPL, false, REC>(
-      P,
-      [&](Slot& s) {
-        s.g.x = __float_as_uint(at_byte(P.post, s.vo.x & 0xffffu));
-        s.g.y = __float_as_uint(at_byte(P.post, s.vo.x >> 16));
-        s.g.z = __float_as_uint(at_byte(P.post, s.vo.y & 0xffffu));
-        s.g.w = __float_as_uint(at_byte(P.post, s.vo.y >> 16));
-      },
-      [&](const Slot& s, int t) {
-        const uint32_t mt = s.mt;
-        uint32_t hp = xor3(s.g.x, s.g.y, s.g.z) ^ s.g.w;
-        hp_group(hp, (mt >> kMetaLogKShift) & 7);
-        const int hx = (int)(((P.sres >> t) & 1u) ^ (hp >> 31));
-        if (write_unsat && (mt & kMetaLead) && (mt & kMetaValid))
-          P.unsat[(mt >> kMetaRowShift) & 0x3ff] = (uint8_t)hx;
-        return hx;
-      });
+      P, [&](Slot& s) { gather_post(P, s); },
+      [&](const Slot& s, int t) { return check_slot(P, s, t, write_unsat); });
 }
 
 // VN phase: posteriors of the owned active VNs (Eq. 2), summed in column slot
@@ -690,36 +712,37 @@ __device__ __forceinline__ int vn_phase(PathCtx<VPL>& P, bool hist, float* ring_
 __device__ __forceinline__ void full_vn_pass(const gdg_win_dev& w, float* post, const float* c2v,
                                              float* lsum) {
   const int n = w.n, bs = blockDim.x;
-  for (int v0 = threadIdx.x; v0 < n; v0 += 4 * bs) {
-    uint4 rc[4];
+  constexpr int kV = 4;   // VNs per thread and round: their record loads in flight together
+  for (int v0 = threadIdx.x; v0 < n; v0 += kV * bs) {
+    uint4 rc[kV];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) rc[j] = w.fr_vrec[min(v0 + j * bs, n - 1)];
-    float g[4][5];
+    for (int j = 0; j < kV; ++j) rc[j] = w.fr_vrec[min(v0 + j * bs, n - 1)];
+    float g[kV][5];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kV; ++j) {
       g[j][0] = at_byte(c2v, rc[j].x & 0xffffu);
       g[j][1] = at_byte(c2v, rc[j].x >> 16);
       g[j][2] = at_byte(c2v, rc[j].y & 0xffffu);
       g[j][3] = at_byte(c2v, rc[j].y >> 16);
       g[j][4] = at_byte(c2v, rc[j].z & 0xffffu);
     }
-    float t[4];
+    float t[kV];
     bool deep = false;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kV; ++j) {
       t[j] = ((((-__uint_as_float(rc[j].w) - g[j][0]) - g[j][1]) - g[j][2]) - g[j][3]) - g[j][4];
       deep |= (rc[j].z >> 16) > 5;
     }
     if (wave_any(deep)) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < kV; ++j) {
         const int v = min(v0 + j * bs, n - 1);
         const int dg = rc[j].z >> 16;
         for (int k = 5; k < dg; ++k) t[j] -= at_byte(c2v, w.fr_cidx[w.fr_cptr[v] + k]);
       }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kV; ++j) {
       const int v = v0 + j * bs;
       if (v >= n) continue;
       const float x = __uint_as_float(__float_as_uint(t[j]) ^ 0x80000000u);
@@ -743,7 +766,8 @@ __device__ __forceinline__ void full_vn_pass(const gdg_win_dev& w, float* post, 
 // the first iteration whose hard decisions met the syndrome (0: none) and
 // sets *done to the number of iterations run. Every thread enters.
 template <int VPL>
-__device__ int window_bp(const gdg_win_dev& w, const uint8_t* syn, float* post, float* c2v,
+__device__ __forceinline__ int window_bp(const gdg_win_dev& w, const uint8_t* syn, float* post,
+                                         float* c2v,
                          float* lsum, const int n_iters, const bool stop, float* rec, int* done) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -878,7 +902,7 @@ __device__ __forceinline__ void ck_save(uint4* dst, const void* src, int bytes, 
 // kLow: every window of the launch is in low-error mode (Alg. 3 off), which
 // frees the registers only Alg. 3 reads.
 template <int VPL, bool kLearn, bool kLow>
-__device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int shot,
+__device__ __attribute__((noinline)) void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int shot,
                             const uint8_t* __restrict__ syn, const long long syn_stride,
                             uint8_t* __restrict__ ehat, double* __restrict__ pm_out,
                             int* __restrict__ flags_out, const gdg_trace_dev& tr,
@@ -983,11 +1007,11 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
     // radix select over the key's 32 + 16 bits (up to six 8-bit passes; it
     // stops once the bucket holding the n_act-th smallest key is kept whole)
     // finds a threshold K; the kept keys (<= K) are gathered in any order and
-    // each one's position is the count of smaller kept keys.
+    // sorted.
     __syncthreads();
     int* hist = (int*)(U + L.p_keys);                 // [256]
     int* ctl = hist + 256;                            // [0], [1] key prefix, [2] still needed, [3] count
-    unsigned long long* ck = (unsigned long long*)(ctl + 4);   // [n_act]
+    unsigned long long* ck = (unsigned long long*)(ctl + 4);   // [n_act rounded up to a power of two]
     const int bs = blockDim.x;
     if (tid == 0) {
       ctl[0] = 0;
@@ -1033,6 +1057,12 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       if (ctl[2] == 0) break;
     }
     const unsigned long long kthr = ((unsigned long long)(uint32_t)ctl[0] << 32) | (uint32_t)ctl[1];
+    // the n_act kept keys (exactly those <= the threshold: keys are distinct)
+    // in any order, padded with the largest key to a power of two, then
+    // sorted ascending
+    int sort_p = 1;
+    while (sort_p < n_act) sort_p <<= 1;
+    for (int i = n_act + tid; i < sort_p; i += bs) ck[i] = ~0ull;
     for (int c = tid; c < n; c += bs) {
       const unsigned long long k = ((unsigned long long)ord_f32(lsum[c]) << 16) | (unsigned)c;
       if (k <= kthr) {
@@ -1041,17 +1071,8 @@ __device__ void decode_shot(const gdg_win_dev& wref, const gdg_lds& L, const int
       }
     }
     __syncthreads();
-    for (int i = tid; i < n_act; i += bs) {
-      const unsigned long long ki = ck[i];
-      int r = 0;
-      int j = 0;
-      for (; j + 1 < n_act; j += 2) {
-        const ulonglong2 kj = *(const ulonglong2*)(ck + j);
-        r += (kj.x < ki) + (kj.y < ki);
-      }
-      if (j < n_act) r += ck[j] < ki;
-      sel[r] = (int16_t)(ki & 0xffffu);
-    }
+    wg_bitonic_sort(ck, sort_p);
+    for (int i = tid; i < n_act; i += bs) sel[i] = (int16_t)(ck[i] & 0xffffu);
   } else {
     for (int v = tid; v < n_act; v += blockDim.x) sel[v] = (int16_t)v;
   }
