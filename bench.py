@@ -278,7 +278,9 @@ def bench_mixed(args):
     low = 1 if args.p <= 0.002 else 0
     prm = G.params(alpha=1.0, g=args.g, pre_iters=8, trunc_factor=2, low_error=low)
     dems = [circuit_dem(get_code(k), CODE_D[k], args.p) for k in keys]
-    md = Bt.MixedDecoder(dems, [prm] * len(dems))
+    # [[288,12,18]] with the paper's N = 288 settings (Sec. IV-C), the others g = args.g
+    prms = [prm if k != "288" else G.paper_params(288, args.p) for k in keys]
+    md = Bt.MixedDecoder(dems, prms)
     ddems = [G.DeviceDem(d) for d in dems]
 
     def batch(i):

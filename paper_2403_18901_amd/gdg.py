@@ -86,6 +86,23 @@ def params(alpha=1.0, clip=50.0, iters_per_step=6, pre_iters=0, trunc_factor=2, 
                   extra_steps, side_max_depth, low_error)
 
 
+def paper_params(n_qubits: int, p: float, **over) -> Params:
+    """The decoder settings the paper uses for an N-qubit BB code under
+    circuit-level noise (Sec. IV-C, Fig. 2): for N <= 144 a depth-4 guessing
+    tree with side paths splitting up to depth 10 (22 paths), main D_max 25,
+    10 steps after a split, 8 preprocessing iterations; for N = 288 a depth-5
+    tree, side paths up to depth 20 (47 paths), main D_max 40, 20 steps after
+    a split, 16 preprocessing iterations. Low-error mode (no Alg. 3) for
+    p <= 0.002 (Sec. IV-A). Keyword arguments override fields."""
+    if n_qubits >= 288:
+        d = dict(g=5, side_max_depth=20, dmax_main=40, extra_steps=20, pre_iters=16)
+    else:
+        d = dict(g=4, side_max_depth=10, dmax_main=25, extra_steps=10, pre_iters=8)
+    d.update(alpha=1.0, trunc_factor=2, low_error=int(p <= 0.002))
+    d.update(over)
+    return params(**d)
+
+
 _lib = None
 
 

@@ -83,6 +83,33 @@ def test_window_decode_other_codes(key):
     _compare_window(dem, 1, _prm(G, p), _oprm(p), det, require_exact=0.9)
 
 
+def _paper(G, key, p):
+    """The paper's settings for the code (Sec. IV-C), GPU and oracle."""
+    prm = G.paper_params(get_code(key).n, p)
+    op = O.params(alpha=1.0, g=prm.g, pre_iters=prm.pre_iters, trunc_factor=2,
+                  low_error=prm.low_error, dmax_main=prm.dmax_main,
+                  extra_steps=prm.extra_steps, side_max_depth=prm.side_max_depth)
+    return prm, op
+
+
+@gpu
+@pytest.mark.parametrize("p,k", [(0.002, 1), (0.003, 1)])
+def test_window_decode_288_paper_params(p, k):
+    """[[288,12,18]] windows with the paper's N = 288 settings: depth-5 tree,
+    side paths to depth 20 (47 paths), main D_max 40, 20 steps after a split,
+    16 preprocessing iterations -- against the oracle with the same settings
+    (same bars as the [[144,12,12]] windows)."""
+    G, _ = _mods()
+    dem = circuit_dem(get_code("288"), 4, p)
+    prm, op = _paper(G, "288", p)
+    e = sample_errors(dem.thresholds(), 24, seed=13)
+    det, obs = syndromes(dem, e)
+    det = _residual_before(dem, op, det, obs, k)
+    w = G.Window(dem, k, 3, prm)
+    assert w.n_paths == 47
+    _compare_window(dem, k, prm, op, det, log_cap=48, require_exact=0.9)
+
+
 @gpu
 def test_autotune_picks_a_measured_plan():
     G, B = _mods()
@@ -116,19 +143,23 @@ def test_mixed_pipeline_ler_parity():
     for i, key in enumerate(keys):
         rounds = min(CODE_D[key], 6)
         dem = circuit_dem(get_code(key), rounds, p)
-        ns = 120 if key != "288" else 40
+        ns = 120 if key != "288" else 2400
         det, obs = syndromes(dem, sample_errors(dem.thresholds(), ns, seed=100 + i))
         dems.append(dem)
         raw.append((det, obs))
         dets.append(torch.from_numpy(det).cuda())
         obss.append(torch.from_numpy(obs).cuda())
-    md = B.MixedDecoder(dems, [_prm(G, p)] * len(dems))
+    # [[288,12,18]] with the paper's N = 288 settings, the others with g = 4
+    prms = [_prm(G, p) if key != "288" else _paper(G, key, p)[0] for key in keys]
+    oprms = [_oprm(p) if key != "288" else _paper(G, key, p)[1] for key in keys]
+    md = B.MixedDecoder(dems, prms)
     md.plan = B.LaunchPlan(waves=4, wg_per_cu=2, split=False)
     fails = md.decode(dets, obss)
     torch.cuda.synchronize()
-    for key, dem, (det, obs), f, d in zip(keys, dems, raw, fails, dets):
+    for key, dem, (det, obs), f, d, op in zip(keys, dems, raw, fails, dets, oprms):
         gf = f.cpu().numpy().astype(bool)
         assert not d.cpu().numpy()[~gf].any()
-        ref = O.decode_shots(dem, 3, _oprm(p), det, obs)
+        ref = O.decode_shots(dem, 3, op, det, obs)
         lo, hi = wilson(int(ref["fail"].sum()), len(gf))
+        print(f"{key}: GPU failures {int(gf.sum())}, oracle {int(ref['fail'].sum())} of {len(gf)}")
         assert lo * len(gf) - 1e-9 <= gf.sum() <= hi * len(gf) + 1e-9, key
