@@ -4,12 +4,15 @@ per-column priors and the logical observable matrix L.
 Input generation only (it stands in for the circuit simulator the paper used);
 none of the decoder's arithmetic lives here.
 
-Two models:
+Models:
 
 * ``phenomenological_dem`` -- i.i.d. data flips before every noisy round plus
   i.i.d. measurement flips, then one perfect round. Detectors are XORs of the
   same check in consecutive rounds (Sec. II-B); a data flip triggers one round,
   a measurement flip two consecutive rounds (the degree-two VNs of Sec. II-B).
+* ``data_noise_dem``, ``single_shot_dem`` -- one noiseless / one noisy
+  syndrome measurement of a BB code's H_X under i.i.d. data flips (the
+  appendices on data-qubit noise and single-shot syndrome noise).
 * ``circuit_dem`` -- a depth-8 BB syndrome-extraction circuit of our own design
   (the paper's circuit comes from another work and is not reproduced), Z-basis
   memory with R noisy rounds and a final noiseless round computed from a data
@@ -130,6 +133,48 @@ def phenomenological_dem(code: BBCode, noisy_rounds: int, p: float, q: float,
                          pri, w, noisy_rounds + 1, lg.shape[0],
                          dict(model="phenomenological", p=p, q=q,
                               noisy_rounds=noisy_rounds, logicals=lg))
+
+
+# ------------------------------------------------------------ one-round models
+
+def data_noise_dem(code: BBCode, p_d: float) -> DEM:
+    """Appendix A: X-type data-qubit noise only, each data qubit flipped with
+    probability p_d (the classical BSC(p_d)), one noiseless syndrome
+    measurement: one detector round with H = H_X and the logical operators as
+    observables."""
+    h = code.hx
+    lg = logical_operators(code.hx, code.hz)
+    w, n = h.shape
+    cols = [np.nonzero(h[:, i])[0] for i in range(n)]
+    obs = [np.nonzero(lg[:, i])[0] for i in range(n)]
+    return _from_columns(f"{code.name} data noise p_d={p_d}", cols, obs, [p_d] * n, w, 1,
+                         lg.shape[0], dict(model="data_noise", p_d=p_d, logicals=lg))
+
+
+def single_shot_dem(code: BBCode, p_d: float, p_s: float) -> DEM:
+    """Appendix B: data flips BSC(p_d) and one noisy syndrome measurement whose
+    bits flip with probability p_s. The decoding matrix is [H_X | I]: one
+    virtual column per check for its syndrome flip. A correction is right when
+    its data part has the same syndrome as the data error and no logical effect
+    (Appendix B), so the observables are the logical operators on the data
+    columns followed by H_X itself on the data columns (the virtual columns
+    touch no observable)."""
+    h = code.hx
+    lg = logical_operators(code.hx, code.hz)
+    w, n = h.shape
+    k = lg.shape[0]
+    cols, obs, pri = [], [], []
+    for i in range(n):
+        rows = np.nonzero(h[:, i])[0]
+        cols.append(rows)
+        obs.append(np.concatenate([np.nonzero(lg[:, i])[0], k + rows]))
+        pri.append(p_d)
+    for j in range(w):
+        cols.append(np.array([j]))
+        obs.append(np.zeros(0, dtype=np.int64))
+        pri.append(p_s)
+    return _from_columns(f"{code.name} single shot p_d={p_d} p_s={p_s}", cols, obs, pri, w, 1,
+                         k + w, dict(model="single_shot", p_d=p_d, p_s=p_s, logicals=lg))
 
 
 # ------------------------------------------------------------ circuit level

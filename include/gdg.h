@@ -88,7 +88,7 @@ typedef struct gdg_window gdg_window;
 
 /* Summary of a built window. */
 typedef struct gdg_window_info {
-  int32_t k, W, m, n;       /* window index, rounds, rows, columns (incl. merged unit columns) */
+  int32_t k, W, m, n;       /* window index, rounds in it, rows, columns (incl. merged unit columns) */
   int32_t row0;             /* first DEM row of the window */
   int32_t n_act;            /* columns GDG runs on after truncation */
   int32_t n_paths;          /* decision paths per shot */
@@ -102,15 +102,19 @@ typedef struct gdg_window_info {
 } gdg_window_info;
 
 /*
- * Build window k of a (W,F) sliding window over `dem` (Sec. III, Eq. 6): the
- * detector rows of rounds k..k+W-1 and the fault columns starting in them.
+ * Build window k of a (W,F) sliding window over `dem` (Sec. III, Eq. 6; App. E
+ * for F > 1): the detector rows of rounds kF..kF+W-1 and the fault columns
+ * starting in them. The last window is the first with kF + W >= n_rounds; it
+ * covers the remaining rounds (fewer than W when the schedule does not end
+ * evenly) and commits every column.
  * Columns that reach past the window's last round (the bottom-right H_1
  * block) are replaced by one unit column per last-round row they touch, with
  * prior p_j = (1 - prod (1 - 2 p_c))/2 over the merged columns, product in DEM
  * column order (Sec. III, the H_1 merge into unit columns). Window column
  * order: kept DEM columns in DEM order, then unit columns by row. Committed
- * columns: those starting in round k, or all of them in the final window
- * (k + W == n_rounds). Only F = 1 is supported (GDG_EINVAL otherwise).
+ * columns: those starting in rounds kF..kF+F-1 (no later window contains
+ * them), or all of them in the last window. GDG_EINVAL unless 1 <= F <= W and
+ * kF < n_rounds; GDG_ESHAPE for windows of more than 512 rows.
  * Uploads the window graph to the current device; *out is owned by the caller
  * and released with gdg_window_free. The window is immutable afterwards and
  * may be used from several streams at once.
@@ -274,7 +278,7 @@ int gdg_commit(const gdg_window* win, int32_t n_shots, const uint8_t* d_ehat,
  *   on the device, e.g. block base + k*w to gather window k's syndrome).
  *
  * gdg_commit_indexed is gdg_commit with per-shot offsets: shot i's DEM row r
- * of the window (row0 <= r, r - row0 < 2w) is d_detectors[d_det_off[i] + r - row0]
+ * of the window (row0 <= r, r - row0 < (F+1)w) is d_detectors[d_det_off[i] + r - row0]
  * and observable o is d_obs[d_obs_off[i] + o]; d_det_off / d_obs_off are [n]
  * int64 on the device. Offsets are the caller's: they must stay inside the
  * buffers. Both calls are asynchronous on hip_stream; errors as gdg_commit.

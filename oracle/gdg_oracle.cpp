@@ -43,8 +43,12 @@ struct Dem {
 
 // ------------------------------------------------------------------ window
 //
-// Window k of a (W,1) sliding window (Sec. III, Eq. 6, Fig. 1): the detector
-// rows of rounds k..k+W-1 and the fault columns that start in those rounds.
+// Window k of a (W,F) sliding window (Sec. III, Eq. 6, Fig. 1; App. E for
+// F > 1): the detector rows of rounds kF..kF+W-1 and the fault columns that
+// start in those rounds. The last window is the first with kF + W >= the
+// number of rounds; it covers the remaining rounds (possibly fewer than W) and
+// commits every column (reading: the paper does not say how the schedule
+// ends when the rounds are not a multiple of F).
 // A column that reaches past the window (it starts in the last window round and
 // also triggers the next round: the bottom-right H_1 block) is not kept;
 // instead every last-round row touched by such columns gets one unit column
@@ -52,7 +56,8 @@ struct Dem {
 // priors are recalculated) is the probability that an odd number of the merged
 // columns fire: p_j = (1 - prod_c (1 - 2 p_c)) / 2, product in DEM column order.
 // Column order: kept DEM columns in DEM order, then unit columns in row order.
-// Committed columns: those starting in round k; in the last window, all.
+// Committed columns: those starting in rounds kF..kF+F-1 (the columns no later
+// window contains, Sec. III); in the last window, all.
 
 struct Window {
   int k = 0, W = 0, row0 = 0, m = 0, n = 0;
@@ -67,27 +72,29 @@ struct Window {
 int col_first_round(const Dem& d, int c) { return d.h_idx[d.h_ptr[c]] / d.w; }
 int col_last_round(const Dem& d, int c) { return d.h_idx[d.h_ptr[c + 1] - 1] / d.w; }
 
-bool build_window(const Dem& d, int k, int W, Window& win) {
-  if (W < 1 || k < 0 || k + W > d.n_rounds) return false;
+bool build_window(const Dem& d, int k, int W, int F, Window& win) {
+  if (W < 1 || F < 1 || F > W || k < 0 || k * F >= d.n_rounds) return false;
+  const int r0 = k * F;
+  const int Wk = std::min(W, d.n_rounds - r0);
   win = Window();
   win.k = k;
-  win.W = W;
-  win.row0 = k * d.w;
-  win.m = W * d.w;
-  win.last = (k + W == d.n_rounds);
-  const int last_round = k + W - 1;
+  win.W = Wk;
+  win.row0 = r0 * d.w;
+  win.m = Wk * d.w;
+  win.last = (r0 + W >= d.n_rounds);
+  const int last_round = r0 + Wk - 1;
   std::vector<int> spill_cols;
   for (int c = 0; c < d.n_cols; ++c) {
     int f = col_first_round(d, c), l = col_last_round(d, c);
     if (l - f > 1) return false;   // no fault spans more than two rounds (Sec. II-B)
-    if (f < k || f > last_round) continue;
+    if (f < r0 || f > last_round) continue;
     if (l > last_round) {
       spill_cols.push_back(c);
       continue;
     }
     win.src.push_back(c);
     win.prior.push_back(d.prior[c]);
-    win.commit.push_back(win.last || f == k);
+    win.commit.push_back(win.last || f < r0 + F);
     std::vector<int> rows;
     for (int e = d.h_ptr[c]; e < d.h_ptr[c + 1]; ++e) rows.push_back(d.h_idx[e] - win.row0);
     win.col_rows.push_back(rows);
@@ -781,13 +788,13 @@ struct OrcWindow {
 
 extern "C" {
 
-// Build window k of a (W,1) sliding window over a DEM given in CSC form.
+// Build window k of a (W,F) sliding window over a DEM given in CSC form.
 void* orc_window_new(int n_rows, int n_cols, int n_obs, int w, int n_rounds, const int* h_ptr,
                      const int* h_idx, const int* l_ptr, const int* l_idx, const double* prior,
-                     int k, int W) {
+                     int k, int W, int F) {
   OrcWindow* ow = new OrcWindow();
   ow->dem = make_dem(n_rows, n_cols, n_obs, w, n_rounds, h_ptr, h_idx, l_ptr, l_idx, prior);
-  if (!build_window(ow->dem, k, W, ow->win)) {
+  if (!build_window(ow->dem, k, W, F, ow->win)) {
     delete ow;
     return nullptr;
   }
@@ -1072,8 +1079,9 @@ int orc_window_replay(void* h, const orc_params* P, const uint8_t* syn, const in
   return steps * 8 + end;
 }
 
-// Full sliding-window decode of n_shots shots: det[s][n_rows] is copied,
-// windows k = 0 .. n_rounds-W are decoded and committed in order. Outputs the
+// Full (W,F) sliding-window decode of n_shots shots: det[s][n_rows] is copied,
+// windows k = 0 .. K-1 (K = 1 + ceil((n_rounds - W) / F)) are decoded and
+// committed in order. Outputs the
 // residual detectors (det_out), the observable accumulator XOR the true
 // observables (obs_out, so a logical error shows as a nonzero entry),
 // fail[s] = 1 unless all residual detectors are 0 (Eq. 8) and obs_out is 0
@@ -1086,14 +1094,14 @@ int orc_decode_shots(int n_rows, int n_cols, int n_obs, int w, int n_rounds, con
                      int W, const orc_params* P, int n_shots, const uint8_t* det,
                      const uint8_t* obs, uint8_t* det_out, uint8_t* obs_out, uint8_t* fail,
                      int* win_flags, uint8_t* e_out, long long* edge_iters, int n_threads,
-                     int max_windows) {
+                     int max_windows, int F) {
   Dem d = make_dem(n_rows, n_cols, n_obs, w, n_rounds, h_ptr, h_idx, l_ptr, l_idx, prior);
-  int nwin = n_rounds - W + 1;
-  if (nwin < 1) return -1;
+  if (W < 1 || F < 1 || F > W) return -1;
+  const int nwin = n_rounds <= W ? 1 : 1 + (n_rounds - W + F - 1) / F;
   const int run_windows = (max_windows >= 0 && max_windows < nwin) ? max_windows : nwin;
   std::vector<Window> wins(nwin);
   for (int k = 0; k < nwin; ++k)
-    if (!build_window(d, k, W, wins[k])) return -2;
+    if (!build_window(d, k, W, F, wins[k])) return -2;
   std::atomic<int> next(0);
   std::atomic<long long> ei(0);
   auto work = [&]() {

@@ -59,7 +59,7 @@ def lib():
         P = C.c_void_p
         i32 = C.c_int
         L.orc_window_new.restype = P
-        L.orc_window_new.argtypes = [i32] * 5 + [P] * 5 + [i32, i32]
+        L.orc_window_new.argtypes = [i32] * 5 + [P] * 5 + [i32, i32, i32]
         L.orc_window_free.argtypes = [P]
         L.orc_window_dims.argtypes = [P, P]
         L.orc_window_export.argtypes = [P] * 6
@@ -69,7 +69,7 @@ def lib():
                                         i32, i32]
         L.orc_window_replay.argtypes = [P, P, P, P, i32, P, P, i32] + [P] * 11 + [i32, P, P, P, P, P, P]
         L.orc_window_replay.restype = i32
-        L.orc_decode_shots.argtypes = [i32] * 5 + [P] * 5 + [i32, P, i32] + [P] * 8 + [i32, i32]
+        L.orc_decode_shots.argtypes = [i32] * 5 + [P] * 5 + [i32, P, i32] + [P] * 8 + [i32] * 3
         L.orc_decode_shots.restype = i32
         L.orc_select_vn.argtypes = [i32, P, P, P, P, i32, i32, i32, P, P]
         L.orc_select_vn.restype = i32
@@ -107,13 +107,18 @@ def default_threads():
     return max(1, len(os.sched_getaffinity(0)))
 
 
-class OracleWindow:
-    """Window k of a (W,1) sliding window, built by the oracle."""
+def n_windows(n_rounds, W, F=1):
+    """Windows of a (W,F) sliding window over n_rounds detector rounds."""
+    return 1 if n_rounds <= W else 1 + (n_rounds - W + F - 1) // F
 
-    def __init__(self, dem, k, W=3):
+
+class OracleWindow:
+    """Window k of a (W,F) sliding window, built by the oracle."""
+
+    def __init__(self, dem, k, W=3, F=1):
         self._keep = _dem_args(dem)
         self.h = lib().orc_window_new(dem.n_rows, dem.n_cols, dem.n_obs, dem.w, dem.n_rounds,
-                                      *[_p(a) for a in self._keep], k, W)
+                                      *[_p(a) for a in self._keep], k, W, F)
         if not self.h:
             raise ValueError("window build failed")
         dims = np.zeros(4, np.int32)
@@ -211,13 +216,13 @@ class OracleWindow:
                     first_post=first_post)
 
 
-def decode_shots(dem, W, prm, det, obs, n_threads=None, max_windows=-1):
-    """Sliding-window decode of whole shots; returns dict(fail, det_out, obs_out,
-    win_flags, e (committed correction over DEM columns), edge_iters)."""
+def decode_shots(dem, W, prm, det, obs, n_threads=None, max_windows=-1, F=1):
+    """(W,F) sliding-window decode of whole shots; returns dict(fail, det_out,
+    obs_out, win_flags, e (committed correction over DEM columns), edge_iters)."""
     det = np.ascontiguousarray(det, np.uint8)
     obs = np.ascontiguousarray(obs, np.uint8)
     ns = det.shape[0]
-    nwin = dem.n_rounds - W + 1
+    nwin = n_windows(dem.n_rounds, W, F)
     keep = _dem_args(dem)
     det_out = np.zeros_like(det)
     obs_out = np.zeros_like(obs)
@@ -228,7 +233,7 @@ def decode_shots(dem, W, prm, det, obs, n_threads=None, max_windows=-1):
     r = lib().orc_decode_shots(dem.n_rows, dem.n_cols, dem.n_obs, dem.w, dem.n_rounds,
                                *[_p(a) for a in keep], W, C.byref(prm), ns, _p(det), _p(obs),
                                _p(det_out), _p(obs_out), _p(fail), _p(wf), _p(e_out), _p(ei),
-                               n_threads or default_threads(), max_windows)
+                               n_threads or default_threads(), max_windows, F)
     if r < 0:
         raise ValueError(f"orc_decode_shots failed: {r}")
     return dict(fail=fail, det_out=det_out, obs_out=obs_out, win_flags=wf, e=e_out,

@@ -370,8 +370,8 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   *out = nullptr;
   int rc = validate_dem(dem);
   if (rc) return rc;
-  if (F != 1) return fail(GDG_EINVAL, "only F = 1 windows are supported");
-  if (W < 1 || k < 0 || k + W > dem->n_rounds) return fail(GDG_EINVAL, "window out of range");
+  if (W < 1 || F < 1 || F > W) return fail(GDG_EINVAL, "need 1 <= F <= W");
+  if (k < 0 || (long long)k * F >= dem->n_rounds) return fail(GDG_EINVAL, "window out of range");
   if (prm->iters_per_step < 4) return fail(GDG_EINVAL, "iters_per_step must be >= 4");
   if (prm->g < 0 || prm->g > 5) return fail(GDG_EINVAL, "g must be in 0..5");
   if (prm->dmax_main < 1 || prm->extra_steps < 0 || prm->pre_iters < 0 || prm->trunc_factor < 1)
@@ -379,8 +379,10 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   if (!(prm->clip > 0.0f) || !(prm->alpha > 0.0f)) return fail(GDG_EINVAL, "bad alpha/clip");
 
   const int w = dem->w;
-  const int row0 = k * w, m = W * w, last_round = k + W - 1;
-  const bool last = (k + W == dem->n_rounds);
+  const int r0 = k * F;                              // first round of the window
+  const int Wk = std::min(W, dem->n_rounds - r0);    // rounds in it (the last may have fewer)
+  const int row0 = r0 * w, m = Wk * w, last_round = r0 + Wk - 1;
+  const bool last = (r0 + W >= dem->n_rounds);
   std::unique_ptr<gdg_window> win(new gdg_window());
   win->prm = *prm;
   // window columns: DEM columns starting inside, not reaching past; then unit columns
@@ -391,7 +393,7 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   for (int c = 0; c < dem->n_cols; ++c) {
     const int a = dem->h_ptr[c], b = dem->h_ptr[c + 1];
     const int fr = dem->h_idx[a] / w, lr = dem->h_idx[b - 1] / w;
-    if (fr < k || fr > last_round) continue;
+    if (fr < r0 || fr > last_round) continue;
     if (lr > last_round) {
       for (int e = a; e < b; ++e) {
         const int r = dem->h_idx[e];
@@ -406,7 +408,7 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
     col_rows.push_back(rows);
     prior.push_back(dem->priors[c]);
     win->src.push_back(c);
-    win->commit.push_back((uint8_t)(last || fr == k));
+    win->commit.push_back((uint8_t)(last || fr < r0 + F));
   }
   for (int r = 0; r < m; ++r) {
     if (!touched[r]) continue;
@@ -601,7 +603,7 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
 
   gdg_window_info& I = win->info;
   I.k = k;
-  I.W = W;
+  I.W = Wk;
   I.m = m;
   I.n = n;
   I.row0 = row0;

@@ -182,13 +182,18 @@ class _HostDem:
         self.s = Dem(dem.n_rows, dem.n_cols, dem.n_obs, dem.w, dem.n_rounds, *p)
 
 
-class Window:
-    """One window of a (W,1) sliding window, built and held by the library."""
+def n_windows(n_rounds: int, W: int, F: int = 1) -> int:
+    """Windows of a (W,F) sliding window over n_rounds detector rounds."""
+    return 1 if n_rounds <= W else 1 + (n_rounds - W + F - 1) // F
 
-    def __init__(self, dem, k: int, W: int, prm: Params):
+
+class Window:
+    """One window of a (W,F) sliding window, built and held by the library."""
+
+    def __init__(self, dem, k: int, W: int, prm: Params, F: int = 1):
         hd = _HostDem(dem)
         h = C.c_void_p()
-        _check(lib().gdg_build_window(C.byref(hd.s), k, W, 1, C.byref(prm), C.byref(h)))
+        _check(lib().gdg_build_window(C.byref(hd.s), k, W, F, C.byref(prm), C.byref(h)))
         self.h = h
         self.prm = prm
         info = WindowInfo()
@@ -362,16 +367,15 @@ def evaluate(det: torch.Tensor, obs: torch.Tensor, out=None) -> torch.Tensor:
 
 
 class SlidingWindowDecoder:
-    """(W,1) sliding-window GDG over a DEM: window k is decoded on the current
-    residual detectors and committed before window k+1 (Sec. III)."""
+    """(W,F) sliding-window GDG over a DEM: window k is decoded on the current
+    residual detectors and committed before window k+1 (Sec. III; F > 1 in
+    App. E)."""
 
-    def __init__(self, dem, prm: Params, W: int = 3):
+    def __init__(self, dem, prm: Params, W: int = 3, F: int = 1):
         self.dem = dem
-        self.W = W
-        self.n_windows = dem.n_rounds - W + 1
-        if self.n_windows < 1:
-            raise ValueError("fewer detector rounds than the window size")
-        self.windows = [Window(dem, k, W, prm) for k in range(self.n_windows)]
+        self.W, self.F = W, F
+        self.n_windows = n_windows(dem.n_rounds, W, F)
+        self.windows = [Window(dem, k, W, prm, F) for k in range(self.n_windows)]
 
     def decode(self, det: torch.Tensor, obs: torch.Tensor, trace: bool = False):
         """Decodes in place: det becomes the residual detector record and obs the

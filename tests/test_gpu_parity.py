@@ -225,7 +225,7 @@ def test_decode_preprocessing_posteriors_within_1e4(p, k):
 
 # ------------------------------------------------------------------ window decode
 
-def _compare_window(dem, k, gp, op, det, log_cap=32, require_exact=0.97):
+def _compare_window(dem, k, gp, op, det, log_cap=32, require_exact=0.97, W=3, F=1):
     """Runs one window on both sides on the same syndromes.
 
     * Syndrome consistency is exact: every answer the GPU reports as satisfying
@@ -246,8 +246,9 @@ def _compare_window(dem, k, gp, op, det, log_cap=32, require_exact=0.97):
       tie-break, peeling or branch value) does not fit inside it.
     """
     g = _g()
-    w = g.Window(dem, k, 3, gp)
-    ow = O.OracleWindow(dem, k, 3)
+    w = g.Window(dem, k, W, gp, F)
+    ow = O.OracleWindow(dem, k, W, F)
+    assert (w.m, w.n, w.row0) == (ow.m, ow.n, ow.row0)
     syn = np.ascontiguousarray(det[:, w.row0:w.row0 + w.m])
     ehat, pm, fl, tr = w.decode(torch.from_numpy(det).cuda(), syn_offset=w.row0, trace=True,
                                 log_cap=log_cap, step_lsum=True)
@@ -371,12 +372,12 @@ def _check_decisions(ow, op, syn, ref, tr, s, n_act):
                     ("select", s, p, i, r["own_key"][i], r["forced_key"][i], drift)
 
 
-def _residual_before(dem, op, det, obs, k):
+def _residual_before(dem, op, det, obs, k, W=3, F=1):
     """The detector record window k sees: the oracle decodes and commits windows
     0..k-1 (both sides then decode window k on the same syndromes)."""
     if k == 0:
         return det
-    return O.decode_shots(dem, 3, op, det, obs, max_windows=k)["det_out"]
+    return O.decode_shots(dem, W, op, det, obs, max_windows=k, F=F)["det_out"]
 
 
 @gpu
@@ -501,16 +502,16 @@ def test_window_first_step_posteriors():
 
 # ------------------------------------------------------------------ whole shots
 
-def _pipeline(dem, gp, op, n_shots, seed):
+def _pipeline(dem, gp, op, n_shots, seed, W=3, F=1):
     g = _g()
     e = sample_errors(dem.thresholds(), n_shots, seed=seed)
     det, obs = syndromes(dem, e)
-    dec = g.SlidingWindowDecoder(dem, gp, W=3)
+    dec = g.SlidingWindowDecoder(dem, gp, W=W, F=F)
     d = torch.from_numpy(det).cuda()
     o = torch.from_numpy(obs).cuda()
     fail, wf = dec.decode(d, o)
     torch.cuda.synchronize()
-    ref = O.decode_shots(dem, 3, op, det, obs)
+    ref = O.decode_shots(dem, W, op, det, obs, F=F)
     return fail.cpu().numpy().astype(bool), wf.cpu().numpy(), d.cpu().numpy(), ref
 
 
@@ -585,3 +586,76 @@ def test_path_bound_changes_no_answer(p, k):
     ref_ei = tr["edge_iters"]
     assert bool((ei <= ref_ei).all())
     assert int(ei.sum()) < int(ref_ei.sum())
+
+
+# ------------------------------------------------------------ other window shapes and models
+
+@gpu
+@pytest.mark.parametrize("W,F,k", [(4, 1, 0), (4, 1, 4), (5, 2, 0), (5, 2, 2), (5, 2, 4)])
+def test_window_decode_wf(W, F, k):
+    """(4,1) and (5,2) sliding windows (App. E) of [[144,12,12]] at p = 0.003
+    with the paper's tree, against the oracle (k = 4 of (5,2) is the last
+    window, which commits everything)."""
+    g = _g()
+    p = 0.003
+    dem = c2_dem("144", 12, p)
+    cp = dict(c2_params(p), side_max_depth=10)
+    op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0, side_max_depth=10)
+    e = sample_errors(dem.thresholds(), 80, seed=19)
+    det, obs = syndromes(dem, e)
+    det = _residual_before(dem, op, det, obs, k, W, F)
+    _compare_window(dem, k, g.params(**cp), op, det, require_exact=0.97, W=W, F=F)
+
+
+@gpu
+@pytest.mark.parametrize("W,F", [(4, 1), (5, 2)])
+def test_pipeline_wf_ler_parity(W, F):
+    """Whole [[144,12,12]] shots (12 rounds) with (4,1) and (5,2) windows at
+    p = 0.003: failures inside the oracle's 2-sigma interval, residuals zero on
+    every GPU success."""
+    p = 0.003
+    dem = c2_dem("144", 12, p)
+    cp = dict(c2_params(p), side_max_depth=10)
+    op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0, side_max_depth=10)
+    ns = 4000
+    gf, wf, resid, ref = _pipeline(dem, _g().params(**cp), op, ns, 61, W=W, F=F)
+    assert wf.shape[1] == O.n_windows(dem.n_rounds, W, F)
+    assert not resid[~gf].any()
+    rf = ref["fail"].astype(bool)
+    lo, hi = wilson(int(rf.sum()), ns)
+    print(f"({W},{F}): GPU failures {int(gf.sum())}, oracle {int(rf.sum())} of {ns}")
+    assert lo * ns - 1e-9 <= gf.sum() <= hi * ns + 1e-9
+
+
+def _app_params(key, p, g=None):
+    """GDG on one-round problems (App. A, App. B): alpha = 0.625, the paper's
+    tree for the code size, no preprocessing or truncation, no Alg. 3."""
+    gg = g or _g()
+    prm = gg.paper_params(get_code(key).n, p, alpha=0.625, pre_iters=0, low_error=1)
+    op = O.params(alpha=0.625, g=prm.g, pre_iters=0, low_error=1, dmax_main=prm.dmax_main,
+                  extra_steps=prm.extra_steps, side_max_depth=prm.side_max_depth)
+    return prm, op
+
+
+@gpu
+@pytest.mark.parametrize("model,key", [("data", "144"), ("data", "288"), ("single", "288")])
+def test_one_round_models(model, key):
+    """Data-qubit noise (App. A, H_X under BSC(p_d)) and single-shot syndrome
+    noise (App. B, [H_X | I]) decoded as one window of one round: answers and
+    decisions against the oracle, then the logical error count inside the
+    oracle's 2-sigma interval on 2000 shots."""
+    from gdg_inputs.dem import data_noise_dem, single_shot_dem
+    g = _g()
+    code = get_code(key)
+    dem = data_noise_dem(code, 0.05) if model == "data" else single_shot_dem(code, 0.04, 0.002)
+    prm, op = _app_params(key, 0.05)
+    e = sample_errors(dem.thresholds(), 60, seed=29)
+    det, obs = syndromes(dem, e)
+    _compare_window(dem, 0, prm, op, det, log_cap=48, require_exact=0.95, W=1, F=1)
+    ns = 2000
+    gf, wf, resid, ref = _pipeline(dem, prm, op, ns, 37, W=1, F=1)
+    assert not resid[~gf].any()
+    rf = ref["fail"].astype(bool)
+    lo, hi = wilson(int(rf.sum()), ns)
+    print(f"{model} {key}: GPU failures {int(gf.sum())}, oracle {int(rf.sum())} of {ns}")
+    assert lo * ns - 1e-9 <= gf.sum() <= hi * ns + 1e-9

@@ -491,3 +491,84 @@ def test_decided_ones_bound_the_path_metric():
             assert r["pm"] >= sum(llr[c] for c in ones) * (1 - 1e-12), (s, p)
             checked += 1
     assert checked > 0
+
+
+@pytest.mark.parametrize("W,F", [(3, 1), (4, 1), (5, 2), (4, 3)])
+def test_wf_windows_commit_every_column_once(W, F):
+    """(W,F) sliding windows (Sec. III; App. E): window k holds rounds
+    kF..kF+W-1, the last window is the first reaching the final round; every
+    DEM column is committed by exactly one window, a window commits only
+    columns no later window contains, and a column spilling past a non-last
+    window's last round is replaced by unit columns there."""
+    dem = circuit_dem(get_code("72"), 6, 0.003)
+    K = O.n_windows(dem.n_rounds, W, F)
+    assert (K - 2) * F + W < dem.n_rounds <= (K - 1) * F + W
+    fr, lr = dem.first_round(), dem.last_round()
+    count = np.zeros(dem.n_cols, int)
+    later = [set() for _ in range(K)]
+    exps = []
+    for k in range(K):
+        w = O.OracleWindow(dem, k, W, F)
+        ex = w.export()
+        exps.append(ex)
+        r0 = k * F
+        assert w.row0 == r0 * dem.w and w.m == min(W, dem.n_rounds - r0) * dem.w
+        src = ex["src"]
+        real = src >= 0
+        for c in src[real & (ex["commit"] == 1)]:
+            count[c] += 1
+        last_round = r0 + w.m // dem.w - 1
+        inside = np.nonzero((fr >= r0) & (fr <= last_round) & (lr <= last_round))[0]
+        assert sorted(src[real].tolist()) == inside.tolist()
+        for j in range(k):
+            later[j] |= set(src[real].tolist())
+    assert (count == 1).all()
+    for k in range(K):
+        src, com = exps[k]["src"], exps[k]["commit"]
+        committed = set(src[(src >= 0) & (com == 1)].tolist())
+        assert not committed & later[k]
+
+
+def test_wf_commit_composes_to_eq8():
+    """(5,2) windows on whole circuit-level shots: the residual detectors and
+    observable accumulators the oracle reports equal H e + det and L e + obs
+    recomputed here (Eq. 8, Eq. 9)."""
+    dem = circuit_dem(get_code("72"), 6, 0.004)
+    prm = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
+    e = sample_errors(dem.thresholds(), 120, seed=13)
+    det, obs = syndromes(dem, e)
+    r = O.decode_shots(dem, 5, prm, det, obs, F=2)
+    H = dem.dense_h().astype(np.int64)
+    L = dem.dense_l().astype(np.int64)
+    resid = (det.astype(np.int64) + r["e"].astype(np.int64) @ H.T) % 2
+    assert np.array_equal(resid, r["det_out"])
+    lres = (obs.astype(np.int64) + r["e"].astype(np.int64) @ L.T) % 2
+    assert np.array_equal(lres, r["obs_out"])
+    assert r["fail"].sum() < 120
+    assert r["win_flags"].shape[1] == O.n_windows(dem.n_rounds, 5, 2)
+
+
+def test_one_round_models_structure_and_decoding():
+    """App. A and App. B problems: H is H_X (data noise) or [H_X | I] (single
+    shot); the single-shot observables are the logical operators and H_X on
+    the data columns. A single syndrome-bit flip is explained by its virtual
+    column (a weight-one syndrome needs many data flips), a single data flip by
+    its data column, and in both cases the correction counts as a success."""
+    from gdg_inputs.dem import data_noise_dem, single_shot_dem
+    code = get_code("72")
+    dd = data_noise_dem(code, 0.03)
+    assert np.array_equal(dd.dense_h(), code.hx) and dd.n_rounds == 1
+    lg = logical_operators(code.hx, code.hz)
+    assert np.array_equal(dd.dense_l(), lg)
+    ss = single_shot_dem(code, 0.03, 0.001)
+    m, n = code.hx.shape
+    assert np.array_equal(ss.dense_h(), np.hstack([code.hx, np.eye(m, dtype=np.uint8)]))
+    Lss = ss.dense_l()
+    assert np.array_equal(Lss[:, :n], np.vstack([lg, code.hx])) and not Lss[:, n:].any()
+    prm = O.params(alpha=0.625, g=4, low_error=1)
+    for col in (n + 5, 17):
+        e = np.zeros((1, ss.n_cols), np.uint8)
+        e[0, col] = 1
+        det, obs = syndromes(ss, e)
+        r = O.decode_shots(ss, 1, prm, det, obs)
+        assert r["fail"][0] == 0 and r["e"][0, col] == 1 and r["e"][0].sum() == 1
