@@ -749,6 +749,174 @@ void decode_window(const Window& win, const orc_params& P, const uint8_t* syn, W
   }
 }
 
+// A window-shaped problem from a dense [m][n] matrix and priors (no DEM).
+Window dense_window(int m, int n, const uint8_t* dense, const double* llr) {
+  Window win;
+  win.m = m;
+  win.n = n;
+  win.col_rows.assign(n, {});
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < n; ++c)
+      if (dense[(size_t)r * n + c]) win.col_rows[c].push_back(r);
+  win.row_cols.assign(m, {});
+  for (int c = 0; c < n; ++c)
+    for (int r : win.col_rows[c]) win.row_cols[r].push_back(c);
+  win.llr.assign(llr, llr + n);
+  win.prior.resize(n);
+  win.src.resize(n);
+  win.commit.assign(n, 1);
+  return win;
+}
+
+// ------------------------------------------------------------------ BP+OSD
+//
+// BP+OSD-CS (Sec. II-A, the OSD paragraph; Sec. III): flooding min-sum BP on
+// the whole window, up to n_iters iterations from fresh messages, stopping at
+// the first iteration whose hard decision meets the syndrome (that decision is
+// then the answer). Otherwise the columns are ranked by their last posterior
+// LLR, ascending -- the most likely to be flipped first -- ties by column index,
+// and the first n_keep ranked columns are kept (n_keep <= 0: all of them;
+// Sec. III's shortening keeps 2w'). Gauss-Jordan elimination over GF(2)
+// visits the kept columns in rank order and makes a column a pivot when it has
+// a 1 in a row that is not a pivot row yet (the lowest such row); the pivots
+// form the information set S. OSD-0 solves H_S e_S = s with every other column
+// at zero. The combination sweep (cs) also tries every single non-pivot kept
+// column and every pair among the first lambda non-pivot columns in rank
+// order, each with e_S solving the rest of the syndrome. The candidate of
+// least cost wins; ties go to the earlier candidate in the order OSD-0, single
+// columns in rank order, pairs (a, b) with a ranked before b in lexicographic
+// order. Readings (the paper and its OSD sources leave them open): the cost is
+// the Eq. 5 sum of prior LLRs, added up as the swept columns first, then the
+// information-set columns in the order they became pivots; the pivot row is
+// the lowest eligible row. If the syndrome is not in the span of the kept
+// columns the answer is the BP hard decision and no path metric.
+
+struct OsdResult {
+  std::vector<uint8_t> e;
+  double pm = kInf;
+  int flags = 0;
+  std::vector<int> order;
+  int bp_iters = 0;
+};
+
+OsdResult osd_window(const Window& win, const orc_params& P, const uint8_t* syn, int n_iters,
+                     bool cs, int lambda, int n_keep, const int* forced_order) {
+  OsdResult R;
+  R.e.assign(win.n, 0);
+  Graph g = window_graph(win);
+  Status st = initial_status(g, syn);
+  Messages ms;
+  init_messages(g, P, ms);
+  bool ok = false;
+  int t = 0;
+  for (t = 1; t <= n_iters; ++t) {
+    bp_iteration(g, st, P, ms);
+    if (syndrome_ok(g, st, ms, nullptr)) {
+      ok = true;
+      break;
+    }
+  }
+  R.bp_iters = ok ? t : n_iters;
+  std::vector<uint8_t> hard(win.n);
+  for (int c = 0; c < win.n; ++c) hard[c] = ms.post[c] <= 0.0 ? 1 : 0;
+  if (ok) {
+    R.e = hard;
+    R.pm = path_metric(win, R.e, syn);
+    R.flags = 1;
+    return R;
+  }
+  std::vector<int> order(win.n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return ms.post[a] < ms.post[b]; });
+  if (forced_order) order.assign(forced_order, forced_order + win.n);
+  R.order = order;
+  const int m = win.m;
+  const int nk = n_keep > 0 ? std::min(n_keep, win.n) : win.n;
+  // kept columns (rank order) as dense 0/1 vectors over the rows, and the syndrome
+  std::vector<std::vector<uint8_t>> col(nk, std::vector<uint8_t>(m, 0));
+  for (int i = 0; i < nk; ++i)
+    for (int r : win.col_rows[order[i]]) col[i][r] = 1;
+  std::vector<uint8_t> sv(m);
+  for (int r = 0; r < m; ++r) sv[r] = syn[r] & 1;
+  std::vector<char> row_used(m, 0), is_piv(nk, 0);
+  std::vector<int> pcol, prow;   // pivots in the order they were found
+  for (int i = 0; i < nk; ++i) {
+    int r = -1;
+    for (int rr = 0; rr < m; ++rr)
+      if (!row_used[rr] && col[i][rr]) {
+        r = rr;
+        break;
+      }
+    if (r < 0) continue;
+    std::vector<int> others;
+    for (int rr = 0; rr < m; ++rr)
+      if (rr != r && col[i][rr]) others.push_back(rr);
+    // row rr += row r for every other row rr with a 1 in column i
+    for (int j = 0; j < nk; ++j)
+      if (col[j][r])
+        for (int rr : others) col[j][rr] ^= 1;
+    if (sv[r])
+      for (int rr : others) sv[rr] ^= 1;
+    row_used[r] = 1;
+    is_piv[i] = 1;
+    pcol.push_back(i);
+    prow.push_back(r);
+  }
+  for (int r = 0; r < m; ++r)
+    if (!row_used[r] && sv[r]) {   // the syndrome is not in the span of the kept columns
+      R.e = hard;
+      return R;
+    }
+  std::vector<int> free_cols;
+  for (int i = 0; i < nk; ++i)
+    if (!is_piv[i]) free_cols.push_back(i);
+  // candidate t (kept-column indices): cost and solution
+  auto evaluate = [&](const std::vector<int>& tt, std::vector<uint8_t>* e_out) {
+    std::vector<uint8_t> u = sv;
+    double cost = 0.0;
+    for (int j : tt) {
+      cost += win.llr[order[j]];
+      for (int r = 0; r < m; ++r) u[r] ^= col[j][r];
+    }
+    for (size_t q = 0; q < pcol.size(); ++q)
+      if (u[prow[q]]) cost += win.llr[order[pcol[q]]];
+    if (e_out) {
+      e_out->assign(win.n, 0);
+      for (int j : tt) (*e_out)[order[j]] = 1;
+      for (size_t q = 0; q < pcol.size(); ++q)
+        if (u[prow[q]]) (*e_out)[order[pcol[q]]] = 1;
+    }
+    return cost;
+  };
+  std::vector<int> best_t;
+  double best = evaluate(best_t, nullptr);
+  if (cs) {
+    for (int j : free_cols) {
+      std::vector<int> tt{j};
+      const double c = evaluate(tt, nullptr);
+      if (c < best) {
+        best = c;
+        best_t = tt;
+      }
+    }
+    const int L = std::min<int>(lambda, (int)free_cols.size());
+    for (int a = 0; a < L; ++a)
+      for (int b = a + 1; b < L; ++b) {
+        std::vector<int> tt{free_cols[a], free_cols[b]};
+        const double c = evaluate(tt, nullptr);
+        if (c < best) {
+          best = c;
+          best_t = tt;
+        }
+      }
+  }
+  evaluate(best_t, &R.e);
+  R.pm = path_metric(win, R.e, syn);
+  R.flags = std::isfinite(R.pm) ? 1 : 0;
+  return R;
+}
+
 // Commit (Eq. 7-8, Sec. III): the committed columns decided 1 are applied to the
 // detector record (this updates the next window's syndrome, s_2' = s_2 + H_2 e_1)
 // and to the observable accumulator (Eq. 9's L e).
@@ -908,6 +1076,49 @@ void orc_window_decode(void* h, const orc_params* P, int n_shots, const uint8_t*
   for (int i = 1; i < nt; ++i) th.emplace_back(work);
   work();
   for (auto& t : th) t.join();
+}
+
+// BP+OSD(-CS) on n_shots window syndromes syn[s][m] (see osd_window): e[s][n],
+// pm[s], flags[s] (1: satisfied), bp_iters[s] (iterations run), order[s][n] the
+// column ranking used (-1 when BP met the syndrome; may be null). forced_order
+// [s][n] (may be null) replaces the oracle's own ranking (replay of another
+// implementation's ranking).
+void orc_window_osd(void* h, const orc_params* P, int n_shots, const uint8_t* syn, int n_iters,
+                    int cs, int lambda, int n_keep, const int* forced_order, uint8_t* e, double* pm,
+                    int* flags, int* order, int* bp_iters, int n_threads) {
+  const Window& w = ((OrcWindow*)h)->win;
+  std::atomic<int> next(0);
+  auto work = [&]() {
+    for (;;) {
+      const int s = next.fetch_add(1);
+      if (s >= n_shots) break;
+      OsdResult R = osd_window(w, *P, syn + (size_t)s * w.m, n_iters, cs != 0, lambda, n_keep,
+                               forced_order ? forced_order + (size_t)s * w.n : nullptr);
+      std::memcpy(e + (size_t)s * w.n, R.e.data(), w.n);
+      pm[s] = R.pm;
+      flags[s] = R.flags;
+      if (bp_iters) bp_iters[s] = R.bp_iters;
+      if (order)
+        for (int c = 0; c < w.n; ++c)
+          order[(size_t)s * w.n + c] = R.order.empty() ? -1 : R.order[c];
+    }
+  };
+  int nt = std::max(1, n_threads);
+  std::vector<std::thread> th;
+  for (int i = 1; i < nt; ++i) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
+}
+
+// BP+OSD(-CS) on a dense [m][n] problem with priors llr (see osd_window).
+double orc_dense_osd(int m, int n, const uint8_t* dense, const double* llr, const uint8_t* syn,
+                     const orc_params* P, int n_iters, int cs, int lambda, int n_keep,
+                     uint8_t* e, int* flags) {
+  Window win = dense_window(m, n, dense, llr);
+  OsdResult R = osd_window(win, *P, syn, n_iters, cs != 0, lambda, n_keep, nullptr);
+  std::memcpy(e, R.e.data(), n);
+  if (flags) *flags = R.flags;
+  return R.pm;
 }
 
 // Replay one path of one shot with the given kept-column set and decision
@@ -1226,24 +1437,6 @@ void orc_dense_bp(int m, int n, const uint8_t* dense, const double* llr, const u
   }
 }
 
-// A window-shaped problem from a dense [m][n] matrix and priors (no DEM).
-static Window dense_window(int m, int n, const uint8_t* dense, const double* llr) {
-  Window win;
-  win.m = m;
-  win.n = n;
-  win.col_rows.assign(n, {});
-  for (int r = 0; r < m; ++r)
-    for (int c = 0; c < n; ++c)
-      if (dense[(size_t)r * n + c]) win.col_rows[c].push_back(r);
-  win.row_cols.assign(m, {});
-  for (int c = 0; c < n; ++c)
-    for (int r : win.col_rows[c]) win.row_cols[r].push_back(c);
-  win.llr.assign(llr, llr + n);
-  win.prior.resize(n);
-  win.src.resize(n);
-  win.commit.assign(n, 1);
-  return win;
-}
 
 // decode_window on a dense problem, preprocessing included when P->pre_iters
 // > 0: e[n], the kept columns in ranked order (kept[n], -1 padded; all n in

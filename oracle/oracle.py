@@ -84,6 +84,9 @@ def lib():
         L.orc_dense_bp.argtypes = [i32, i32, P, P, P, P, i32, P]
         L.orc_dense_gdg.argtypes = [i32, i32, P, P, P, P, P, P]
         L.orc_dense_gdg.restype = C.c_double
+        L.orc_window_osd.argtypes = [P, P, i32, P, i32, i32, i32, i32, P, P, P, P, P, P, i32]
+        L.orc_dense_osd.argtypes = [i32, i32, P, P, P, P, i32, i32, i32, i32, P, P]
+        L.orc_dense_osd.restype = C.c_double
         L.orc_dense_window.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P]
         L.orc_dense_window.restype = C.c_double
         L.orc_dense_path_probe.argtypes = [i32, i32, P, P, P, P, i32, i32] + [P] * 7
@@ -177,6 +180,24 @@ class OracleWindow:
         if logs:
             out.update(sel=sel, dec=dec, ends=ends, first_post=post)
         return out
+
+    def osd(self, prm, syn, n_iters=200, cs=True, lam=10, n_keep=0, forced_order=None,
+            n_threads=None):
+        """BP + OSD-CS(lam) (or OSD-0 with cs=False) on window syndromes; n_keep
+        > 0 keeps only the first n_keep ranked columns. Returns dict(e, pm,
+        flags, order (-1 rows where BP met the syndrome), bp_iters)."""
+        syn = np.ascontiguousarray(syn, np.uint8).reshape(-1, self.m)
+        ns = syn.shape[0]
+        e = np.zeros((ns, self.n), np.uint8)
+        pm = np.zeros(ns, np.float64)
+        fl = np.zeros(ns, np.int32)
+        order = np.zeros((ns, self.n), np.int32)
+        it = np.zeros(ns, np.int32)
+        fo = None if forced_order is None else np.ascontiguousarray(forced_order, np.int32)
+        lib().orc_window_osd(self.h, C.byref(prm), ns, _p(syn), n_iters, int(cs), lam, n_keep,
+                             _p(fo), _p(e), _p(pm), _p(fl), _p(order), _p(it),
+                             n_threads or default_threads())
+        return dict(e=e, pm=pm, flags=fl, order=order, bp_iters=it)
 
     def replay(self, prm, syn, forced_sel, path_id, forced_g, forced_v, max_steps=64):
         syn = np.ascontiguousarray(syn, np.uint8)
@@ -334,3 +355,15 @@ def dense_path_probe(H, llr, syn, prm, path_id=0, max_steps=8):
     k = max(steps, 0)
     return dict(steps=steps, post=post[:k], hsum=hsum[:k], hmin=hmin[:k], hmax=hmax[:k],
                 status=status[:k], n_unsat=nu[:k], agg=agg[:k])
+
+
+def dense_osd(H, llr, syn, prm, n_iters=0, cs=True, lam=10, n_keep=0):
+    """BP + OSD-CS on a dense problem (n_iters = 0: OSD on the priors)."""
+    H = np.ascontiguousarray(H, np.uint8)
+    llr = np.ascontiguousarray(llr, np.float64)
+    syn = np.ascontiguousarray(syn, np.uint8)
+    e = np.zeros(H.shape[1], np.uint8)
+    fl = np.zeros(1, np.int32)
+    pm = lib().orc_dense_osd(H.shape[0], H.shape[1], _p(H), _p(llr), _p(syn), C.byref(prm),
+                             n_iters, int(cs), lam, n_keep, _p(e), _p(fl))
+    return pm, e, int(fl[0])

@@ -572,3 +572,82 @@ def test_one_round_models_structure_and_decoding():
         det, obs = syndromes(ss, e)
         r = O.decode_shots(ss, 1, prm, det, obs)
         assert r["fail"][0] == 0 and r["e"][0, col] == 1 and r["e"][0].sum() == 1
+
+
+def _gf2_rank(M):
+    M = (np.array(M, np.uint8) & 1).copy()
+    r = 0
+    rows, cols = M.shape
+    for c in range(cols):
+        piv = [i for i in range(r, rows) if M[i, c]]
+        if not piv:
+            continue
+        M[[r, piv[0]]] = M[[piv[0], r]]
+        for i in range(rows):
+            if i != r and M[i, c]:
+                M[i] ^= M[r]
+        r += 1
+    return r
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_osd_structure_and_exact_ml_on_small_problems(seed):
+    """BP+OSD (Sec. II-A): with no BP iterations the ranking is the priors,
+    ascending, ties by column. OSD-0's answer meets the syndrome and lies on
+    the information set -- the first columns of that order that raise the GF(2)
+    rank, found here by rank increments. With two non-pivot columns and
+    lambda >= 2 the combination sweep tries every solution of H e = s, so its
+    answer has the brute-force least Eq. 5 cost."""
+    rng = np.random.default_rng(200 + seed)
+    m, n = 7, 9
+    while True:
+        H = (rng.random((m, n)) < 0.4).astype(np.uint8)
+        if _gf2_rank(H) == m:
+            break
+    llr = np.round(rng.uniform(0.5, 4.0, n), 1)          # ties among priors happen
+    e0 = (rng.random(n) < 0.3).astype(np.uint8)
+    syn = ((H.astype(int) @ e0) % 2).astype(np.uint8)
+    prm = O.params(alpha=1.0)
+    order = sorted(range(n), key=lambda c: (llr[c], c))
+    S, cur = [], np.zeros((0, m), np.uint8)
+    for c in order:
+        nxt = np.vstack([cur, H[:, c][None, :]])
+        if _gf2_rank(nxt) > len(S):
+            S.append(c)
+            cur = nxt
+    pm0, e_0, fl0 = O.dense_osd(H, llr, syn, prm, n_iters=0, cs=False)
+    assert fl0 == 1 and not (((H.astype(int) @ e_0) % 2) ^ syn).any()
+    assert set(np.nonzero(e_0)[0]) <= set(S)
+    assert abs(pm0 - float(llr @ e_0)) < 1e-12
+    best = np.inf
+    for bits in itertools.product([0, 1], repeat=n):
+        e = np.array(bits)
+        if not (((H.astype(int) @ e) % 2) ^ syn).any():
+            best = min(best, float(llr @ e))
+    pmc, e_c, flc = O.dense_osd(H, llr, syn, prm, n_iters=0, cs=True, lam=2)
+    assert flc == 1 and not (((H.astype(int) @ e_c) % 2) ^ syn).any()
+    assert abs(pmc - best) < 1e-9 and pmc <= pm0 + 1e-12
+
+
+def test_osd_keeps_bp_answer_and_solves_windows():
+    """When BP meets the syndrome, BP+OSD returns its hard decision; on
+    circuit-level windows where it does not, OSD-CS10 on the whole window and
+    on the first 2m ranked columns (Sec. III's shortening) both return answers
+    that meet the window syndrome exactly."""
+    dem = circuit_dem(get_code("72"), 6, 0.006)
+    w = O.OracleWindow(dem, 1, 3)
+    e = sample_errors(dem.thresholds(), 40, seed=17)
+    det, obs = syndromes(dem, e)
+    syn = np.ascontiguousarray(det[:, w.row0:w.row0 + w.m])
+    H = w.export()["H"].astype(np.int64)
+    prm = O.params(alpha=1.0)
+    for n_keep in (0, 2 * w.m):
+        r = w.osd(prm, syn, n_iters=30, cs=True, lam=10, n_keep=n_keep)
+        osd_used = r["order"][:, 0] >= 0
+        assert osd_used.any() and (~osd_used).any()
+        for s in range(syn.shape[0]):
+            if r["flags"][s] & 1:
+                assert not ((H @ r["e"][s] + syn[s]) % 2).any()
+        assert (r["flags"][~osd_used] & 1).all()
+        assert (r["bp_iters"][osd_used] == 30).all()
+        assert (r["flags"] & 1).mean() >= 0.95
