@@ -303,6 +303,33 @@ int gdg_bp(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome, in
            int32_t n_iters, float* d_post, int32_t* d_first_ok, void* hip_stream);
 
 /*
+ * BP+OSD on the window (the comparator of Sec. II-A's OSD paragraph and Sec.
+ * III; App. E decodes last windows with it): flooding min-sum BP on the whole
+ * window, at most bp_iters iterations, stopping once its hard decision meets
+ * the syndrome (that decision is then the answer). Otherwise the columns are
+ * ranked by posterior LLR ascending (ties: column index) and the first n_keep
+ * kept (n_keep <= 0: all; Sec. III's shortening keeps 2m); Gauss-Jordan
+ * elimination over GF(2) in rank order picks the information set (each pivot
+ * at its lowest row not yet a pivot row). OSD-0 solves the syndrome on it; with
+ * cs != 0 the combination sweep of order lambda also tries every single
+ * non-pivot kept column and every pair among the first lambda of them (OSD-CS,
+ * Sec. II-A). The least Eq. 5 cost wins (summed as the swept columns, then the
+ * information-set columns by ascending pivot row), ties to the earlier
+ * candidate (OSD-0, singles in rank order, pairs lexicographically).
+ *   d_ehat [n_shots][n] uint8, d_pm [n_shots] (Eq. 5 in window-column order;
+ *   +inf if the syndrome is outside the span of the kept columns: the answer is
+ *   then BP's hard decision), d_flags [n_shots] (GDG_FLAG_SATISFIED or 0).
+ *   d_order [n_shots][n] int32 or NULL: the ranking used (-1 where BP met the
+ *   syndrome). d_bp_iters [n_shots] or NULL: BP iterations run.
+ * One workgroup per shot. GDG_ESHAPE for windows of more than 512 rows or 4096
+ * columns, or whose bit-columns do not fit in LDS (keep fewer columns).
+ */
+int gdg_decode_osd(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                   int64_t syn_stride, int32_t bp_iters, int32_t cs, int32_t lambda,
+                   int32_t n_keep, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
+                   int32_t* d_order, int32_t* d_bp_iters, void* hip_stream);
+
+/*
  * Device copy of a DEM for sampling and evaluation. gdg_dem_upload copies the
  * CSC arrays, a CSR copy of H and uint32 sampling thresholds floor(p 2^32).
  */

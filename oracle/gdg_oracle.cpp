@@ -787,9 +787,9 @@ Window dense_window(int m, int n, const uint8_t* dense, const double* llr) {
 // columns in rank order, pairs (a, b) with a ranked before b in lexicographic
 // order. Readings (the paper and its OSD sources leave them open): the cost is
 // the Eq. 5 sum of prior LLRs, added up as the swept columns first, then the
-// information-set columns in the order they became pivots; the pivot row is
-// the lowest eligible row. If the syndrome is not in the span of the kept
-// columns the answer is the BP hard decision and no path metric.
+// information-set columns in ascending order of their pivot rows; the pivot
+// row is the lowest eligible row. If the syndrome is not in the span of the
+// kept columns the answer is the BP hard decision and no path metric.
 
 struct OsdResult {
   std::vector<uint8_t> e;
@@ -841,6 +841,7 @@ OsdResult osd_window(const Window& win, const orc_params& P, const uint8_t* syn,
   for (int r = 0; r < m; ++r) sv[r] = syn[r] & 1;
   std::vector<char> row_used(m, 0), is_piv(nk, 0);
   std::vector<int> pcol, prow;   // pivots in the order they were found
+  std::vector<int> pcol_of_row(m, -1);
   for (int i = 0; i < nk; ++i) {
     int r = -1;
     for (int rr = 0; rr < m; ++rr)
@@ -862,6 +863,7 @@ OsdResult osd_window(const Window& win, const orc_params& P, const uint8_t* syn,
     is_piv[i] = 1;
     pcol.push_back(i);
     prow.push_back(r);
+    pcol_of_row[r] = i;
   }
   for (int r = 0; r < m; ++r)
     if (!row_used[r] && sv[r]) {   // the syndrome is not in the span of the kept columns
@@ -879,8 +881,8 @@ OsdResult osd_window(const Window& win, const orc_params& P, const uint8_t* syn,
       cost += win.llr[order[j]];
       for (int r = 0; r < m; ++r) u[r] ^= col[j][r];
     }
-    for (size_t q = 0; q < pcol.size(); ++q)
-      if (u[prow[q]]) cost += win.llr[order[pcol[q]]];
+    for (int r = 0; r < m; ++r)
+      if (row_used[r] && u[r]) cost += win.llr[order[pcol_of_row[r]]];
     if (e_out) {
       e_out->assign(win.n, 0);
       for (int j : tt) (*e_out)[order[j]] = 1;
@@ -1292,7 +1294,10 @@ int orc_window_replay(void* h, const orc_params* P, const uint8_t* syn, const in
 
 // Full (W,F) sliding-window decode of n_shots shots: det[s][n_rows] is copied,
 // windows k = 0 .. K-1 (K = 1 + ceil((n_rounds - W) / F)) are decoded and
-// committed in order. Outputs the
+// committed in order. With osd_iters > 0 the last window (every window when
+// osd_all is set) is decoded by BP (that many iterations) + OSD-CS(osd_lambda)
+// on its first osd_keep ranked columns (<= 0: all) instead of GDG: the window
+// BP+OSD comparator of Sec. III, and the last-window variant of App. E. Outputs the
 // residual detectors (det_out), the observable accumulator XOR the true
 // observables (obs_out, so a logical error shows as a nonzero entry),
 // fail[s] = 1 unless all residual detectors are 0 (Eq. 8) and obs_out is 0
@@ -1305,7 +1310,8 @@ int orc_decode_shots(int n_rows, int n_cols, int n_obs, int w, int n_rounds, con
                      int W, const orc_params* P, int n_shots, const uint8_t* det,
                      const uint8_t* obs, uint8_t* det_out, uint8_t* obs_out, uint8_t* fail,
                      int* win_flags, uint8_t* e_out, long long* edge_iters, int n_threads,
-                     int max_windows, int F) {
+                     int max_windows, int F, int osd_iters, int osd_lambda, int osd_keep,
+                     int osd_all) {
   Dem d = make_dem(n_rows, n_cols, n_obs, w, n_rounds, h_ptr, h_idx, l_ptr, l_idx, prior);
   if (W < 1 || F < 1 || F > W) return -1;
   const int nwin = n_rounds <= W ? 1 : 1 + (n_rounds - W + F - 1) / F;
@@ -1324,7 +1330,15 @@ int orc_decode_shots(int n_rows, int n_cols, int n_obs, int w, int n_rounds, con
       for (int k = 0; k < run_windows; ++k) {
         const Window& wn = wins[k];
         WindowResult wr;
-        decode_window(wn, *P, dd.data() + wn.row0, wr, nullptr, nullptr, nullptr, 0, -1);
+        if (osd_iters > 0 && (osd_all || wn.last)) {
+          // BP+OSD-CS instead of GDG on this window (Sec. III, App. E)
+          OsdResult R = osd_window(wn, *P, dd.data() + wn.row0, osd_iters, true, osd_lambda,
+                                   osd_keep, nullptr);
+          wr.e = R.e;
+          wr.flags = R.flags;
+        } else {
+          decode_window(wn, *P, dd.data() + wn.row0, wr, nullptr, nullptr, nullptr, 0, -1);
+        }
         ei += wr.stats.edge_iters;
         if (win_flags) win_flags[(size_t)s * nwin + k] = wr.flags;
         commit_window(d, wn, wr.e.data(), dd.data(), oo.data());

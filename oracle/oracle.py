@@ -69,7 +69,7 @@ def lib():
                                         i32, i32]
         L.orc_window_replay.argtypes = [P, P, P, P, i32, P, P, i32] + [P] * 11 + [i32, P, P, P, P, P, P]
         L.orc_window_replay.restype = i32
-        L.orc_decode_shots.argtypes = [i32] * 5 + [P] * 5 + [i32, P, i32] + [P] * 8 + [i32] * 3
+        L.orc_decode_shots.argtypes = [i32] * 5 + [P] * 5 + [i32, P, i32] + [P] * 8 + [i32] * 7
         L.orc_decode_shots.restype = i32
         L.orc_select_vn.argtypes = [i32, P, P, P, P, i32, i32, i32, P, P]
         L.orc_select_vn.restype = i32
@@ -237,9 +237,12 @@ class OracleWindow:
                     first_post=first_post)
 
 
-def decode_shots(dem, W, prm, det, obs, n_threads=None, max_windows=-1, F=1):
+def decode_shots(dem, W, prm, det, obs, n_threads=None, max_windows=-1, F=1, osd=None,
+                 osd_on="last"):
     """(W,F) sliding-window decode of whole shots; returns dict(fail, det_out,
-    obs_out, win_flags, e (committed correction over DEM columns), edge_iters)."""
+    obs_out, win_flags, e (committed correction over DEM columns), edge_iters).
+    osd = (bp_iters, lambda, n_keep) decodes the last window (osd_on="all":
+    every window) by BP + OSD-CS instead of GDG."""
     det = np.ascontiguousarray(det, np.uint8)
     obs = np.ascontiguousarray(obs, np.uint8)
     ns = det.shape[0]
@@ -254,7 +257,8 @@ def decode_shots(dem, W, prm, det, obs, n_threads=None, max_windows=-1, F=1):
     r = lib().orc_decode_shots(dem.n_rows, dem.n_cols, dem.n_obs, dem.w, dem.n_rounds,
                                *[_p(a) for a in keep], W, C.byref(prm), ns, _p(det), _p(obs),
                                _p(det_out), _p(obs_out), _p(fail), _p(wf), _p(e_out), _p(ei),
-                               n_threads or default_threads(), max_windows, F)
+                               n_threads or default_threads(), max_windows, F,
+                               *(osd if osd else (0, 0, 0)), int(osd_on == "all"))
     if r < 0:
         raise ValueError(f"orc_decode_shots failed: {r}")
     return dict(fail=fail, det_out=det_out, obs_out=obs_out, win_flags=wf, e=e_out,

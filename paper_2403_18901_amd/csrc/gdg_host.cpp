@@ -981,6 +981,58 @@ int gdg_bp(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome, in
   return GDG_OK;
 }
 
+int gdg_decode_osd(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                   int64_t syn_stride, int32_t bp_iters, int32_t cs, int32_t lambda,
+                   int32_t n_keep, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
+                   int32_t* d_order, int32_t* d_bp_iters, void* hip_stream) {
+  if (!win) return fail(GDG_EINVAL, "null window");
+  if (n_shots < 0 || bp_iters < 1 || lambda < 0) return fail(GDG_EINVAL, "bad sizes");
+  if (n_shots == 0) return GDG_OK;
+  if (!d_syndrome || !d_ehat || !d_pm || !d_flags) return fail(GDG_EINVAL, "null buffer");
+  if (syn_stride < win->info.m) return fail(GDG_EINVAL, "syn_stride < m");
+  const gdg_win_dev& w = win->dev;
+  if (w.m > 512) return fail(GDG_ESHAPE, "BP+OSD supports windows of up to 512 rows");
+  if ((w.fr_T + 3) / 4 > 64) return fail(GDG_ESHAPE, "window graph too large for the window BP");
+  gdg_osd_lds L{};
+  L.nk = n_keep > 0 ? std::min<int>(n_keep, w.n) : w.n;
+  L.mw = (w.m + 31) / 32;
+  L.sort_p = 1;
+  while (L.sort_p < w.n) L.sort_p <<= 1;
+  if (L.sort_p > 4096) return fail(GDG_ESHAPE, "BP+OSD supports windows of up to 4096 columns");
+  L.obits_words = (w.n + 31) / 32 + 1;
+  int off = 0;
+  auto take = [&](int bytes) {
+    const int o = off;
+    off = align16(off + bytes);
+    return o;
+  };
+  L.syn = take(w.m);
+  L.order = take(2 * w.n);
+  L.rank_of = take(2 * w.n);
+  L.obits = take(4 * L.obits_words);
+  L.sv = take(4 * L.mw);
+  L.pcol = take(2 * w.m);
+  L.llrp = 0;
+  L.isp = take(L.nk);
+  L.freec = take(2 * L.nk);
+  L.misc = take(8 * 4);
+  L.A = off;
+  L.post = L.A;
+  L.c2v = L.A + align16(4 * (w.n + 1));
+  L.keys = L.A;
+  L.mat = L.A;
+  const int a_bytes = std::max(std::max(L.c2v - L.A + 4 * (w.fr_epad + 8), 8 * L.sort_p),
+                               4 * L.mw * L.nk);
+  L.total = L.A + align16(a_bytes);
+  if (L.total > max_lds_per_block())
+    return fail(GDG_ESHAPE, "BP+OSD on this window does not fit in LDS (keep fewer columns)");
+  hipError_t e = gdg_launch_osd(w, L, n_shots, d_syndrome, syn_stride, bp_iters, cs ? 1 : 0,
+                                lambda, d_ehat, d_pm, d_flags, d_order, d_bp_iters,
+                                (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "osd launch");
+  return GDG_OK;
+}
+
 int gdg_dem_upload(const gdg_dem* dem, gdg_dem_dev** out) {
   if (!out) return fail(GDG_EINVAL, "null argument");
   *out = nullptr;

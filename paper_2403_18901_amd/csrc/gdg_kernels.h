@@ -192,6 +192,18 @@ struct gdg_jobs_dev {
   gdg_learn_dev learn;
 };
 
+// LDS plan of the BP+OSD kernel (byte offsets): fixed arrays, then one region
+// reused by the window BP (posteriors, messages), the ranking sort keys and
+// the GF(2) bit-columns of the kept columns.
+struct gdg_osd_lds {
+  int syn, order, rank_of, obits, sv, pcol, llrp, isp, freec, misc;   // fixed
+  int A, post, c2v, keys, mat, sort_p, mw, nk, obits_words, total;
+};
+hipError_t gdg_launch_osd(const gdg_win_dev& w, const gdg_osd_lds& L, int n_shots,
+                          const uint8_t* syn, long long syn_stride, int n_iters, int cs,
+                          int lambda, uint8_t* ehat, double* pm, int* flags, int* order,
+                          int* iters, hipStream_t st);
+
 hipError_t gdg_launch_zero(int* p, int n, hipStream_t st);
 // The fixed device scratch of gdg_decode_batch_noalloc on the current device:
 // its address (looked up once per device) and size.

@@ -1927,6 +1927,287 @@ __global__ __launch_bounds__(256) void gdg_bp_kernel(gdg_win_dev w, int post_off
   if (threadIdx.x == 0) first_ok[shot] = first;
 }
 
+// ------------------------------------------------------------------ BP + OSD
+//
+// The window comparator of Sec. II-A (the OSD paragraph) and Sec. III: one
+// workgroup per shot. The decode kernel's whole-window BP runs up to n_iters
+// iterations and stops once its hard decision meets the syndrome (that is the
+// answer). Otherwise the columns are ranked by posterior, ascending, ties by
+// column (a bitonic sort of 48-bit keys); the first nk ranked columns become
+// bit-columns over the rows; Gauss-Jordan elimination visits them in rank
+// order and makes a column a pivot at its lowest row that is not a pivot row
+// yet, adding that row to every other row where the column has a 1 (in column
+// form: every column with a 1 at the pivot row gets the pivot column's other
+// bits flipped). OSD-0 takes the information set's solution; the combination
+// sweep also tries each single non-pivot column and each pair among the first
+// lambda non-pivot columns. Costs are Eq. 5 sums in double: swept columns,
+// then information-set columns by ascending pivot row. The least cost wins,
+// ties to the earlier candidate (OSD-0, singles in rank order, pairs in
+// lexicographic order).
+constexpr int kOsdMaxWords = 16;   // rows <= 512
+
+__global__ __launch_bounds__(256) void gdg_osd_kernel(gdg_win_dev w, gdg_osd_lds L, int n_shots,
+                                                      const uint8_t* __restrict__ syn,
+                                                      long long syn_stride, int n_iters, int cs,
+                                                      int lambda, uint8_t* __restrict__ ehat,
+                                                      double* __restrict__ pm_out,
+                                                      int* __restrict__ flags_out,
+                                                      int* __restrict__ order_out,
+                                                      int* __restrict__ iters_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int shot = blockIdx.x;
+  if (shot >= n_shots) return;
+  const int tid = threadIdx.x, bs = blockDim.x, lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = w.m, n = w.n, nk = L.nk, MW = L.mw;
+  uint8_t* s = smem + L.syn;
+  uint16_t* order = (uint16_t*)(smem + L.order);
+  uint16_t* rank_of = (uint16_t*)(smem + L.rank_of);
+  uint32_t* obits = (uint32_t*)(smem + L.obits);
+  uint32_t* sv = (uint32_t*)(smem + L.sv);
+  int16_t* pcol = (int16_t*)(smem + L.pcol);      // [m] pivot (rank) column of each row, -1
+  uint8_t* isp = smem + L.isp;                    // [nk] 1 = pivot column
+  uint16_t* freec = (uint16_t*)(smem + L.freec);  // [nk] non-pivot kept columns in rank order
+  unsigned long long* misc = (unsigned long long*)(smem + L.misc);   // [0] best cost, [1] best candidate
+  float* post = (float*)(smem + L.post);
+  float* c2v = (float*)(smem + L.c2v);
+  unsigned long long* keys = (unsigned long long*)(smem + L.keys);
+  uint32_t* mat = (uint32_t*)(smem + L.mat);
+  double* stage = (double*)(smem + L.A);
+
+  for (int j = tid; j < m; j += bs) s[j] = syn[(long long)shot * syn_stride + j] & 1;
+  __syncthreads();
+  int done = 0;
+  const int first = window_bp<1>(w, s, post, c2v, nullptr, n_iters, true, nullptr, &done);
+  if (tid == 0 && iters_out) iters_out[shot] = done;
+  // the BP hard decision (the answer when BP converged or the syndrome is out of reach)
+  for (int i = tid; i < L.obits_words; i += bs) obits[i] = 0u;
+  __syncthreads();
+  for (int base = wave * kWave; base < n; base += bs) {
+    const int c = base + lane;
+    const unsigned long long bal = __ballot(c < n && post[c] <= 0.0f);
+    if (lane == 0) {
+      obits[base >> 5] = (uint32_t)bal;
+      obits[(base >> 5) + 1] = (uint32_t)(bal >> 32);
+    }
+  }
+  __syncthreads();
+  auto finish = [&](bool satisfied) {
+    // Eq. 5 in ascending window-column order (wave 0), and the answer bytes
+    __syncthreads();
+    if (wave == 0) {
+      const double pm = eq5_sum(obits, L.obits_words, w.llr64, stage, lane);
+      if (lane == 0) {
+        pm_out[shot] = satisfied ? pm : __builtin_inf();
+        flags_out[shot] = satisfied ? 1 : 0;
+      }
+    }
+    for (int c = tid; c < n; c += bs)
+      ehat[(long long)shot * n + c] = (uint8_t)((obits[c >> 5] >> (c & 31)) & 1u);
+  };
+  if (first) {
+    if (order_out)
+      for (int c = tid; c < n; c += bs) order_out[(long long)shot * n + c] = -1;
+    finish(true);
+    return;
+  }
+
+  // ranking: keys ord(posterior) << 16 | column, sorted ascending (the keys
+  // overwrite the posteriors: read first)
+  constexpr int kKeysPerThread = 16;   // sort sizes up to 4096 with 256 threads
+  const int P2 = L.sort_p;
+  unsigned long long kr[kKeysPerThread];
+#pragma unroll
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const int i = tid + q * bs;
+    kr[q] = i < n ? (((unsigned long long)ord_f32(post[i]) << 16) | (unsigned)i) : ~0ull;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const int i = tid + q * bs;
+    if (i < P2) keys[i] = kr[q];
+  }
+  __syncthreads();
+  wg_bitonic_sort(keys, P2);
+  for (int i = tid; i < n; i += bs) {
+    const int c = (int)(keys[i] & 0xffffu);
+    order[i] = (uint16_t)c;
+    rank_of[c] = (uint16_t)i;
+    if (order_out) order_out[(long long)shot * n + i] = c;
+  }
+  __syncthreads();
+
+  // bit-columns of the kept columns (rank order) and the syndrome
+  for (int i = tid; i < nk * MW; i += bs) mat[i] = 0u;
+  for (int r = tid; r < m; r += bs) pcol[r] = -1;
+  for (int i = tid; i < nk; i += bs) isp[i] = 0;
+  if (tid < MW) {
+    uint32_t x = 0u;
+    for (int b = 0; b < 32 && 32 * tid + b < m; ++b) x |= (uint32_t)s[32 * tid + b] << b;
+    sv[tid] = x;
+  }
+  __syncthreads();
+  for (int r = tid; r < m; r += bs)
+    for (int e = w.row_ptr[r]; e < w.row_ptr[r + 1]; ++e) {
+      const int i = rank_of[w.row_col[e]];
+      if (i < nk) atomicOr(&mat[i * MW + (r >> 5)], 1u << (r & 31));
+    }
+  __syncthreads();
+
+  // Gauss-Jordan in rank order
+  uint32_t used[kOsdMaxWords];
+#pragma unroll
+  for (int q = 0; q < kOsdMaxWords; ++q) used[q] = 0u;
+  int np = 0;
+  for (int i = 0; i < nk && np < m; ++i) {
+    int r = -1;
+#pragma unroll
+    for (int q = 0; q < kOsdMaxWords; ++q) {
+      if (q >= MW) break;
+      const uint32_t x = mat[i * MW + q] & ~used[q];
+      if (x && r < 0) r = 32 * q + __builtin_ctz(x);
+    }
+    r = __builtin_amdgcn_readfirstlane(r);
+    if (r < 0) continue;
+    uint32_t oth[kOsdMaxWords];
+#pragma unroll
+    for (int q = 0; q < kOsdMaxWords; ++q) oth[q] = q < MW ? mat[i * MW + q] : 0u;
+    const int rw = r >> 5;
+    const uint32_t rb = 1u << (r & 31);
+#pragma unroll
+    for (int q = 0; q < kOsdMaxWords; ++q)
+      if (q == rw) oth[q] &= ~rb;
+    __syncthreads();   // every thread has read column i
+    for (int j = tid; j < nk; j += bs) {
+      uint32_t* cj = mat + j * MW;
+      if (cj[rw] & rb) {
+#pragma unroll
+        for (int q = 0; q < kOsdMaxWords; ++q)
+          if (q < MW) cj[q] ^= oth[q];
+      }
+    }
+    if (tid == 0) {
+      if (sv[rw] & rb) {
+#pragma unroll
+        for (int q = 0; q < kOsdMaxWords; ++q)
+          if (q < MW) sv[q] ^= oth[q];
+      }
+      pcol[r] = (int16_t)i;
+      isp[i] = 1;
+    }
+#pragma unroll
+    for (int q = 0; q < kOsdMaxWords; ++q)
+      if (q == rw) used[q] |= rb;
+    ++np;
+    __syncthreads();
+  }
+  // the syndrome must lie in the span of the kept columns
+  bool out_of_span = false;
+#pragma unroll
+  for (int q = 0; q < kOsdMaxWords; ++q)
+    if (q < MW && (sv[q] & ~used[q])) out_of_span = true;
+  if (out_of_span) {
+    finish(false);
+    return;
+  }
+  // non-pivot kept columns in rank order (wave 0, ballots)
+  if (wave == 0) {
+    int cnt = 0;
+    for (int base = 0; base < nk; base += kWave) {
+      const int i = base + lane;
+      const bool f = i < nk && !isp[i];
+      const unsigned long long bal = __ballot(f);
+      if (f) freec[cnt + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = (uint16_t)i;
+      cnt += __builtin_popcountll(bal);
+    }
+    if (lane == 0) {
+      misc[0] = ~0ull;
+      misc[1] = ~0ull;
+      misc[2] = (unsigned long long)cnt;
+    }
+  }
+  __syncthreads();
+  const int n_free = (int)misc[2];
+  const int L2 = cs ? min(lambda, n_free) : 0;
+  const int n_cand = 1 + (cs ? n_free : 0) + L2 * (L2 - 1) / 2;
+  auto cand_cols = [&](int cand, int& j1, int& j2) {
+    j1 = -1;
+    j2 = -1;
+    if (cand == 0) return;
+    if (cand <= n_free) {
+      j1 = freec[cand - 1];
+      return;
+    }
+    int k = cand - 1 - n_free;   // pair index, lexicographic over a < b < L2
+    int a = 0;
+    while (k >= L2 - 1 - a) {
+      k -= L2 - 1 - a;
+      ++a;
+    }
+    j1 = freec[a];
+    j2 = freec[a + 1 + k];
+  };
+  auto solution = [&](int j1, int j2, uint32_t (&u)[kOsdMaxWords]) {
+#pragma unroll
+    for (int q = 0; q < kOsdMaxWords; ++q) {
+      uint32_t x = q < MW ? sv[q] : 0u;
+      if (q < MW && j1 >= 0) x ^= mat[j1 * MW + q];
+      if (q < MW && j2 >= 0) x ^= mat[j2 * MW + q];
+      u[q] = x & used[q];
+    }
+  };
+  unsigned long long my_cost = ~0ull, my_cand = ~0ull;
+  for (int cand = tid; cand < n_cand; cand += bs) {
+    int j1, j2;
+    cand_cols(cand, j1, j2);
+    uint32_t u[kOsdMaxWords];
+    solution(j1, j2, u);
+    double cost = 0.0;
+    if (j1 >= 0) cost += w.llr64[order[j1]];
+    if (j2 >= 0) cost += w.llr64[order[j2]];
+#pragma unroll
+    for (int q = 0; q < kOsdMaxWords; ++q) {
+      uint32_t x = u[q];
+      while (x) {
+        const int r = 32 * q + __builtin_ctz(x);
+        x &= x - 1u;
+        cost += w.llr64[order[pcol[r]]];
+      }
+    }
+    const unsigned long long cb = (unsigned long long)__double_as_longlong(cost);
+    if (cb < my_cost || (cb == my_cost && (unsigned long long)cand < my_cand)) {
+      my_cost = cb;
+      my_cand = (unsigned long long)cand;
+    }
+  }
+  atomicMin(&misc[0], my_cost);
+  __syncthreads();
+  if (my_cost == misc[0]) atomicMin(&misc[1], my_cand);
+  __syncthreads();
+  // the winner's answer bits (one thread), then its Eq. 5 metric
+  if (tid == 0) {
+    for (int i = 0; i < L.obits_words; ++i) obits[i] = 0u;
+    int j1, j2;
+    cand_cols((int)misc[1], j1, j2);
+    uint32_t u[kOsdMaxWords];
+    solution(j1, j2, u);
+    auto set = [&](int c) { obits[c >> 5] |= 1u << (c & 31); };
+    if (j1 >= 0) set(order[j1]);
+    if (j2 >= 0) set(order[j2]);
+#pragma unroll
+    for (int q = 0; q < kOsdMaxWords; ++q) {
+      uint32_t x = u[q];
+      while (x) {
+        const int r = 32 * q + __builtin_ctz(x);
+        x &= x - 1u;
+        set(order[pcol[r]]);
+      }
+    }
+  }
+  finish(true);
+}
+
 // ------------------------------------------------------------------ commit
 
 // Folds a window's committed correction into the later rows and the
@@ -2196,6 +2477,20 @@ hipError_t gdg_launch_bp(const gdg_win_dev& w, int n_shots, const uint8_t* syn, 
   }
   hipLaunchKernelGGL(gdg_bp_kernel, dim3(n_shots), dim3(4 * kWave), lds, st, w, post_off, c2v_off,
                      n_shots, syn, stride, n_iters, post, first_ok);
+  return hipGetLastError();
+}
+
+hipError_t gdg_launch_osd(const gdg_win_dev& w, const gdg_osd_lds& L, int n_shots,
+                          const uint8_t* syn, long long syn_stride, int n_iters, int cs,
+                          int lambda, uint8_t* ehat, double* pm, int* flags, int* order,
+                          int* iters, hipStream_t st) {
+  if (L.total > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)gdg_osd_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(gdg_osd_kernel, dim3(n_shots), dim3(4 * kWave), L.total, st, w, L, n_shots,
+                     syn, syn_stride, n_iters, cs, lambda, ehat, pm, flags, order, iters);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ EXPORTED = ["gdg_build_window", "gdg_window_free", "gdg_window_get_info", "gdg_w
             "gdg_mlp_forward", "gdg_mlp_grad_work_bytes", "gdg_mlp_grad", "gdg_mlp_adam",
             "gdg_model_create", "gdg_model_free", "gdg_mlp_infer", "gdg_learned_work_bytes",
             "gdg_decode_learned", "gdg_last_error", "gdg_decode_batch_noalloc",
-            "gdg_release_scratch"]
+            "gdg_release_scratch", "gdg_decode_osd"]
 
 MLP_IN, MLP_H = 17, 64
 MLP_PARAMS = 5377
@@ -124,6 +124,7 @@ def lib():
         L.gdg_decode_batch.argtypes = [P, i32, P, i64, P, P, P, P, C.c_size_t, P, P]
         L.gdg_decode_batch_noalloc.argtypes = [P, i32, P, i64, P, P, P, P]
         L.gdg_release_scratch.argtypes = [P]
+        L.gdg_decode_osd.argtypes = [P, i32, P, i64, i32, i32, i32, i32, P, P, P, P, P, P]
         L.gdg_decode_jobs.argtypes = [P, i32, P, P]
         L.gdg_jobs_lds_bytes.argtypes = [P, i32, i32]
         L.gdg_commit.argtypes = [P, i32, P, P, i64, P, i64, P]
@@ -274,6 +275,30 @@ class Window:
                                           None, _stream()))
         return out
 
+    def decode_osd(self, syn: torch.Tensor, syn_offset: int = 0, bp_iters: int = 200,
+                   cs: bool = True, lam: int = 10, n_keep: int = 0, trace: bool = False,
+                   out=None):
+        """BP + OSD-CS(lam) (OSD-0 with cs=False) on the window (gdg_decode_osd);
+        n_keep > 0 keeps the first n_keep ranked columns. Returns (ehat, pm,
+        flags) and, with trace, (order, bp_iters) too."""
+        ns = syn.shape[0]
+        dev = syn.device
+        if out is None:
+            out = (torch.empty((ns, self.n), dtype=torch.uint8, device=dev),
+                   torch.empty(ns, dtype=torch.float64, device=dev),
+                   torch.empty(ns, dtype=torch.int32, device=dev))
+        ehat, pm, flags = out
+        order = it = None
+        if trace:
+            order = torch.empty((ns, self.n), dtype=torch.int32, device=dev)
+            it = torch.empty(ns, dtype=torch.int32, device=dev)
+        _check(lib().gdg_decode_osd(self.h, ns, _ptr(syn, syn_offset), syn.shape[1], bp_iters,
+                                    int(cs), lam, n_keep, _ptr(ehat), _ptr(pm), _ptr(flags),
+                                    _ptr(order), _ptr(it), _stream()))
+        if trace:
+            return ehat, pm, flags, order, it
+        return ehat, pm, flags
+
     def commit(self, ehat: torch.Tensor, det: torch.Tensor, obs: torch.Tensor):
         ns = ehat.shape[0]
         _check(lib().gdg_commit(self.h, ns, _ptr(ehat), _ptr(det), det.shape[1], _ptr(obs),
@@ -371,9 +396,16 @@ class SlidingWindowDecoder:
     residual detectors and committed before window k+1 (Sec. III; F > 1 in
     App. E)."""
 
-    def __init__(self, dem, prm: Params, W: int = 3, F: int = 1):
+    def __init__(self, dem, prm: Params, W: int = 3, F: int = 1, osd=None,
+                 osd_on: str = "last"):
+        """osd = (bp_iters, lambda, n_keep): the last window (osd_on="all":
+        every window) is decoded by BP + OSD-CS instead of GDG (Sec. III's
+        window comparator; App. E's last-window variant)."""
+        if osd_on not in ("last", "all"):
+            raise ValueError("osd_on is 'last' or 'all'")
         self.dem = dem
         self.W, self.F = W, F
+        self.osd, self.osd_on = osd, osd_on
         self.n_windows = n_windows(dem.n_rounds, W, F)
         self.windows = [Window(dem, k, W, prm, F) for k in range(self.n_windows)]
 
@@ -385,10 +417,15 @@ class SlidingWindowDecoder:
         wflags = torch.empty((ns, self.n_windows), dtype=torch.int32, device=det.device)
         traces = []
         for k, w in enumerate(self.windows):
-            res = w.decode(det, syn_offset=w.row0, trace=trace)
+            if self.osd and (self.osd_on == "all" or k == self.n_windows - 1):
+                it, lam, keep = self.osd
+                res = w.decode_osd(det, syn_offset=w.row0, bp_iters=it, cs=True, lam=lam,
+                                   n_keep=keep)
+            else:
+                res = w.decode(det, syn_offset=w.row0, trace=trace)
             ehat, pm, fl = res[:3]
             if trace:
-                traces.append(res[3])
+                traces.append(res[3] if len(res) > 3 else None)
             wflags[:, k] = fl
             w.commit(ehat, det, obs)
         fail = evaluate(det, obs)

@@ -79,6 +79,10 @@ def test_stream_admission_rejects_over_budget():
     svc = S.StreamingService(codes, prm, rate=1e5, seed=5, mem_budget=budget)
     assert svc.codes[0].sched.n_slots == 4
     rep = svc.run(duration=0.01)
+    # the virtual clock advances by measured device time, and a first launch
+    # can take longer than the whole span: go on until experiments finish
+    while rep["experiments_done"] < 8 and svc.now < 1.0:
+        rep = svc.run(duration=svc.now + 0.01)
     assert rep["rejected"] > 0
     assert rep["admitted"] + rep["rejected"] == rep["experiments_started"]
     c = svc.codes[0]

@@ -651,3 +651,27 @@ def test_osd_keeps_bp_answer_and_solves_windows():
         assert (r["flags"][~osd_used] & 1).all()
         assert (r["bp_iters"][osd_used] == 30).all()
         assert (r["flags"] & 1).mean() >= 0.95
+
+
+def test_window_osd_pipeline_solves_every_window():
+    """Sec. III's window comparator: the H1 block of each window before the
+    last is merged into an identity, so its matrix has full row rank and
+    BP+OSD on all kept columns solves it; once those are solved the last
+    window's syndrome lies in its span too. So with OSD on every window each
+    window flag says satisfied and the residual detectors end at zero. With
+    OSD on the last window only (App. E), the earlier windows decode exactly as
+    without it, and on shots whose GDG windows were all satisfied the last one
+    is solved and its rows end clear."""
+    dem = circuit_dem(get_code("72"), 6, 0.004)
+    det, obs = syndromes(dem, sample_errors(dem.thresholds(), 24, seed=31))
+    prm = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
+    every = O.decode_shots(dem, 3, prm, det, obs, osd=(60, 10, 0), osd_on="all")
+    assert (every["win_flags"] & 1).all()
+    assert not every["det_out"].any()
+    base = O.decode_shots(dem, 3, prm, det, obs)
+    last = O.decode_shots(dem, 3, prm, det, obs, osd=(60, 10, 0))
+    assert np.array_equal(last["win_flags"][:, :-1], base["win_flags"][:, :-1])
+    assert (base["win_flags"] & 1).all()   # so the last window's syndrome is in its span
+    assert (last["win_flags"][:, -1] & 1).all()
+    K = O.n_windows(dem.n_rounds, 3, 1)
+    assert not last["det_out"][:, O.OracleWindow(dem, K - 1, 3).row0:].any()
