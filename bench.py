@@ -9,9 +9,9 @@ DEM before the timed region; every step decodes a fresh batch.
 
 Prints one JSON line: the metric, windows/s over the timed steps, window
 latencies, the logical error rate, the decode kernel's LDS roofline (16 B per
-edge-iteration against 78.6 TB/s, with the HBM traffic per launch from the
-rocprofv3 summary when it matches the kernel source) and the FP64 oracle's
-rate on the host cores.
+edge-iteration against 157.3 TB/s, with the HBM traffic per launch from the
+rocprofv3 summary when it matches the kernel source), the LDS rates the probe
+kernels reach, and the FP64 oracle's rate on the host cores.
 """
 from __future__ import annotations
 
@@ -27,7 +27,9 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 
-LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+# 256 CUs x 256 B/clk x 2.4 GHz = 157286 GB/s of LDS reads: the LDS probe's 16 KiB
+# b64/b128 reads reach 129.5 TB/s, above what 128 B/clk per CU (78.6 TB/s) allows
+LDS_PEAK_GBS = 256 * 256 * 2.4
 BYTES_PER_EDGE_ITER = 16         # one FP32 message written and read each way
 
 
@@ -46,6 +48,8 @@ def parse():
                     help="budget for the oracle CPU baseline (0 = skip)")
     ap.add_argument("--latency-windows", type=int, default=110,
                     help="single-shot windows timed for the latency figures")
+    ap.add_argument("--lds-probe", type=int, default=1,
+                    help="also measure the LDS bandwidth with the probe kernels (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     ap.add_argument("--workload", choices=["c2", "c1", "mixed", "stream", "learned"], default="c2",
@@ -187,6 +191,8 @@ def main():
                 e1.synchronize()
                 lat.append(e0.elapsed_time(e1))
 
+    probe = lds_probe(dev) if args.lds_probe else None
+
     if args.copy_probe:
         # plain copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters
         src = torch.empty(256 * 1024 * 1024, dtype=torch.uint8, device=dev)
@@ -257,6 +263,7 @@ def main():
             "edge_iters_per_launch": edge_iters / launches,
         },
         "cpu_baseline": cpu,
+        "lds_probe_gbs": probe,
     }
     print(json.dumps(out))
 
@@ -484,6 +491,40 @@ def bench_learned(args):
     out["mlp_infer"] = {"samples": n, "ms": ms, "mac_per_s": macs / (ms * 1e-3),
                         "peak_mac_per_s": 1.25e15, "frac": macs / (ms * 1e-3) / 1.25e15}
     print(json.dumps(out))
+
+
+def lds_probe(dev):
+    """LDS GB/s of the probe kernels (4, 8, 16-byte reads on 32 and 16 KiB per
+    workgroup; 4-byte writes), each timed with HIP events on the stream it is
+    launched on, best of three after a first launch."""
+    import ctypes as C
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_2403_18901_amd", "libgdg_probe.so"))
+    lib.lds_probe_launch.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    lib.lds_probe_bytes.argtypes = [C.c_int, C.c_int, C.c_int]
+    lib.lds_probe_bytes.restype = C.c_double
+    n_blocks, reps = 256 * 20, 256
+    sink = torch.empty(n_blocks * 256, dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream()
+    out = {}
+    for mode, name in ((0, "read_b32"), (1, "read_b64"), (2, "read_b128"), (3, "write_b32"),
+                       (4, "read_b32_16k"), (5, "read_b64_16k"), (6, "read_b128_16k")):
+        best = None
+        for _ in range(4):   # the first launch also loads the code object
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            rc = lib.lds_probe_launch(mode, n_blocks, reps, C.c_void_p(sink.data_ptr()),
+                                      C.c_void_p(st.cuda_stream))
+            e1.record(st)
+            e1.synchronize()
+            if rc != 0:
+                raise RuntimeError("LDS probe launch failed")
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        nbytes = lib.lds_probe_bytes(mode, n_blocks, reps)
+        out[name] = nbytes / (best * 1e-3) / 1e9
+    return out
 
 
 def kernel_hash():

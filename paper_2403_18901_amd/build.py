@@ -16,16 +16,26 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + SOURCES + ["-o", tmp]
+# the LDS bandwidth probe behind the decode kernel's roofline peak (its own library)
+PROBE_LIB = os.path.join(HERE, "libgdg_probe.so")
+PROBE_SOURCES = [os.path.join(HERE, "csrc", "lds_probe.hip")]
+
+
+def _hipcc(sources, out, verbose):
+    tmp = out + ".tmp"
+    cmd = [HIPCC] + FLAGS + sources + ["-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libgdg_hip.so")
+        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
     if verbose:
         sys.stderr.write(r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(SOURCES, LIB, verbose)
+    _hipcc(PROBE_SOURCES, PROBE_LIB, verbose)
     return LIB
 
 
