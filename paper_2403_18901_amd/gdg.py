@@ -103,6 +103,18 @@ def paper_params(n_qubits: int, p: float, **over) -> Params:
     return params(**d)
 
 
+def appendix_params(**over) -> Params:
+    """The GDG settings of the one-round problems (App. A data-qubit noise,
+    App. B single-shot syndrome noise): low-error mode, main D_max 40, side
+    paths splitting up to depth 20, a depth-5 guessing tree, 30 more steps
+    after a split, scaling 0.625, and no preprocessing or truncation (the
+    window is the whole one-round matrix). Keyword arguments override fields."""
+    d = dict(g=5, side_max_depth=20, dmax_main=40, extra_steps=30, alpha=0.625, pre_iters=0,
+             low_error=1)
+    d.update(over)
+    return params(**d)
+
+
 _lib = None
 
 

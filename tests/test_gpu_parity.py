@@ -627,11 +627,12 @@ def test_pipeline_wf_ler_parity(W, F):
     assert lo * ns - 1e-9 <= gf.sum() <= hi * ns + 1e-9
 
 
-def _app_params(key, p, g=None):
-    """GDG on one-round problems (App. A, App. B): alpha = 0.625, the paper's
-    tree for the code size, no preprocessing or truncation, no Alg. 3."""
+def _app_params(g=None):
+    """GDG on one-round problems (App. A, App. B): low-error mode, main D_max
+    40, side paths to depth 20, depth-5 tree, 30 steps after a split, alpha
+    0.625, no preprocessing or truncation."""
     gg = g or _g()
-    prm = gg.paper_params(get_code(key).n, p, alpha=0.625, pre_iters=0, low_error=1)
+    prm = gg.appendix_params()
     op = O.params(alpha=0.625, g=prm.g, pre_iters=0, low_error=1, dmax_main=prm.dmax_main,
                   extra_steps=prm.extra_steps, side_max_depth=prm.side_max_depth)
     return prm, op
@@ -648,10 +649,11 @@ def test_one_round_models(model, key):
     g = _g()
     code = get_code(key)
     dem = data_noise_dem(code, 0.05) if model == "data" else single_shot_dem(code, 0.04, 0.002)
-    prm, op = _app_params(key, 0.05)
+    prm, op = _app_params()
     e = sample_errors(dem.thresholds(), 60, seed=29)
     det, obs = syndromes(dem, e)
-    _compare_window(dem, 0, prm, op, det, log_cap=48, require_exact=0.95, W=1, F=1)
+    # side paths split up to depth 20 and run 30 more steps: logs of up to 50
+    _compare_window(dem, 0, prm, op, det, log_cap=56, require_exact=0.95, W=1, F=1)
     ns = 2000
     gf, wf, resid, ref = _pipeline(dem, prm, op, ns, 37, W=1, F=1)
     assert not resid[~gf].any()
