@@ -99,6 +99,8 @@ typedef struct gdg_window_info {
   int32_t lds_bytes;        /* least LDS per workgroup of the decode kernel (a launch
                                allocates up to its CU share at full occupancy) */
   int32_t waves;            /* wavefronts per workgroup of the decode kernel */
+  int32_t n_msg;            /* message slots of the preprocessing BP: the per-shot
+                               length of gdg_decode_batch_warm's buffers */
 } gdg_window_info;
 
 /*
@@ -221,6 +223,54 @@ int gdg_decode_batch_noalloc(const gdg_window* win, int32_t n_shots, const uint8
  * workspace allocates it again.
  */
 int gdg_release_scratch(void* hip_stream);
+
+/*
+ * Cross-window message reuse (Sec. V, where the paper leaves it as future
+ * work; readings below). gdg_link_windows prepares `next` to start its
+ * preprocessing BP from messages `prev` hands over: for every edge of next's
+ * window graph it finds the edge of prev between the same detector row and
+ * the same DEM column (unit columns of merged faults have none). Both windows
+ * must come from the same DEM; next must have preprocessing (pre_iters > 0).
+ * Call it before decoding with next, not while a decode with next runs; a
+ * second call replaces the link. GDG_EINVAL for a null window or a window
+ * without preprocessing.
+ */
+int gdg_link_windows(gdg_window* next, const gdg_window* prev);
+
+/*
+ * The message slot of every edge of the window graph in the warm-start
+ * buffers: slot[e] for edge e of the row-major window CSR (rows in window
+ * order, columns ascending; gdg_window_info.n_edges entries), values below
+ * gdg_window_info.n_msg. Host array owned by the caller.
+ */
+int gdg_window_edge_slots(const gdg_window* win, int32_t* slot);
+
+/*
+ * gdg_decode_batch with a warm start (Sec. V's message reuse). Reading: the
+ * window's preprocessing BP -- the one BP that covers the whole window graph,
+ * and the whole decoder for shots it already solves -- starts its CN-to-VN
+ * messages on edges the previous window also had from the previous window's
+ * handed-over messages, zero elsewhere, followed by one VN update (Eqs. 2-3)
+ * that forms the first posteriors and VN-to-CN messages; it then runs as in
+ * gdg_decode_batch. The messages a window hands over are one CN update (Eq. 1)
+ * of its preprocessing BP's final VN-to-CN messages, whether or not that BP met
+ * the syndrome. The decision paths restart from fresh messages on the
+ * truncated graph as without warm start.
+ *   d_warm_in:  NULL (cold start) or [n_shots][warm_in_stride] float, the
+ *               previous window's d_warm_out for the same shots; the window
+ *               must be linked (gdg_link_windows) and warm_in_stride at least
+ *               the previous window's n_msg.
+ *   d_warm_out: NULL or [n_shots][warm_out_stride] float output, this window's
+ *               handed-over messages in its slot order (gdg_window_edge_slots),
+ *               warm_out_stride >= n_msg. It may not alias d_warm_in.
+ * Other arguments and errors as gdg_decode_batch; GDG_EINVAL also for warm
+ * buffers on a window without preprocessing, or strides below those bounds.
+ */
+int gdg_decode_batch_warm(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                          int64_t syn_stride, const float* d_warm_in, int64_t warm_in_stride,
+                          float* d_warm_out, int64_t warm_out_stride, uint8_t* d_ehat,
+                          double* d_pm, int32_t* d_flags, void* d_workspace,
+                          size_t workspace_bytes, const gdg_trace* trace, void* hip_stream);
 
 /*
  * Several decode jobs in one persistent launch: windows of different codes

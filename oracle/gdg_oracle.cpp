@@ -293,8 +293,8 @@ int sgn(double x) { return x < 0.0 ? -1 : 1; }   // sign(0) = +1 (irrelevant, se
 // single active neighbour has an empty min; it sends +clip (reading: peeling
 // keeps BP from ever seeing one). sign(0) = +1: a zero magnitude zeroes every
 // other outgoing message anyway.
-long long bp_iteration(const Graph& g, const Status& st, const orc_params& P, Messages& ms,
-                       double* cn_min_abs = nullptr) {
+long long cn_update(const Graph& g, const Status& st, const orc_params& P, Messages& ms,
+                    double* cn_min_abs) {
   long long active_edges = 0;
   if (cn_min_abs)
     for (int r = 0; r < g.m; ++r) {
@@ -334,6 +334,12 @@ long long bp_iteration(const Graph& g, const Status& st, const orc_params& P, Me
       ms.c2v[e0 + a] = P.alpha * (st.s[r] ? -1.0 : 1.0) * sign * mn;
     }
   }
+  return active_edges;
+}
+
+// The VN half of an iteration: posteriors (Eq. 2) and clipped extrinsic
+// messages (Eq. 3) of every active VN from the current CN-to-VN messages.
+void vn_update(const Graph& g, const Status& st, const orc_params& P, Messages& ms) {
   for (int c = 0; c < g.n; ++c) {
     if (st.vn[c] >= 0) continue;
     double sum = g.llr[c];
@@ -344,6 +350,12 @@ long long bp_iteration(const Graph& g, const Status& st, const orc_params& P, Me
       ms.v2c[e] = P.sum_product ? x : std::min(P.clip, std::max(-P.clip, x));
     }
   }
+}
+
+long long bp_iteration(const Graph& g, const Status& st, const orc_params& P, Messages& ms,
+                       double* cn_min_abs = nullptr) {
+  const long long active_edges = cn_update(g, st, P, ms, cn_min_abs);
+  vn_update(g, st, P, ms);
   return active_edges;
 }
 
@@ -647,9 +659,17 @@ Graph window_graph(const Window& win) {
 // syndrome is met), rank columns by the sum of the last four posteriors
 // ascending (ties: lower column index first), keep the first trunc_factor * m.
 // GDG then runs on the kept columns, in ranked order, with fresh messages.
+//
+// Warm start (Sec. V's message reuse; readings in the header of warm_map):
+// with warm_in (one value per edge of the window graph, NaN where the edge
+// has no counterpart in the previous window) the preprocessing BP starts from
+// those CN-to-VN messages instead of zeros, followed by one VN update (so its
+// first VN-to-CN messages carry them); with warm_out the messages handed to
+// the next window are one CN update of the BP's final VN-to-CN messages.
 void decode_window(const Window& win, const orc_params& P, const uint8_t* syn, WindowResult& out,
                    const int* forced_sel, const int* forced_g, const int* forced_v,
-                   int n_forced, int forced_path) {
+                   int n_forced, int forced_path, const std::vector<double>* warm_in = nullptr,
+                   std::vector<double>* warm_out = nullptr) {
   out = WindowResult();
   out.e.assign(win.n, 0);
   Graph full = window_graph(win);
@@ -660,6 +680,11 @@ void decode_window(const Window& win, const orc_params& P, const uint8_t* syn, W
     Status st = initial_status(full, syn);
     Messages ms;
     init_messages(full, P, ms);
+    if (warm_in) {
+      for (size_t e = 0; e < ms.c2v.size(); ++e)
+        if (!std::isnan((*warm_in)[e])) ms.c2v[e] = (*warm_in)[e];
+      vn_update(full, st, P, ms);
+    }
     std::vector<double> lsum(win.n, 0.0);
     bool ok = false;
     int t;
@@ -674,6 +699,10 @@ void decode_window(const Window& win, const orc_params& P, const uint8_t* syn, W
       }
     }
     out.pre_lsum = lsum;
+    if (warm_out) {
+      cn_update(full, st, P, ms, nullptr);
+      *warm_out = ms.c2v;
+    }
     if (ok) {
       for (int c = 0; c < win.n; ++c) out.e[c] = ms.post[c] <= 0.0 ? 1 : 0;
       out.pm = path_metric(win, out.e, syn);
@@ -747,6 +776,38 @@ void decode_window(const Window& win, const orc_params& P, const uint8_t* syn, W
     if (n_contra == (int)paths.size()) out.flags |= 2;
     if (n_exh > 0) out.flags |= 4;
   }
+}
+
+// Edges shared by consecutive windows, for the warm start (Sec. V's message
+// reuse, which the paper leaves as future work). Reading: an edge of `next`
+// (row-major, columns ascending within a row) continues the edge of `prev`
+// between the same detector row and the same DEM column; unit columns of
+// merged faults, and rows or columns `prev` lacks, continue nothing (-1).
+std::vector<int> warm_map(const Window& prev, const Window& next) {
+  std::vector<int> pcol_of_src;
+  int max_src = 0;
+  for (int c : prev.src) max_src = std::max(max_src, c + 1);
+  for (int c : next.src) max_src = std::max(max_src, c + 1);
+  pcol_of_src.assign(max_src, -1);
+  for (int c = 0; c < prev.n; ++c)
+    if (prev.src[c] >= 0) pcol_of_src[prev.src[c]] = c;
+  std::vector<int> prow_ptr(prev.m + 1, 0);
+  for (int r = 0; r < prev.m; ++r) prow_ptr[r + 1] = prow_ptr[r] + (int)prev.row_cols[r].size();
+  std::vector<int> map;
+  for (int r = 0; r < next.m; ++r) {
+    const int rp = r + next.row0 - prev.row0;
+    for (int c : next.row_cols[r]) {
+      int q = -1;
+      const int sc = next.src[c];
+      if (sc >= 0 && rp >= 0 && rp < prev.m && pcol_of_src[sc] >= 0) {
+        const auto& rc = prev.row_cols[rp];
+        auto it = std::lower_bound(rc.begin(), rc.end(), pcol_of_src[sc]);
+        if (it != rc.end() && *it == pcol_of_src[sc]) q = prow_ptr[rp] + (int)(it - rc.begin());
+      }
+      map.push_back(q);
+    }
+  }
+  return map;
 }
 
 // A window-shaped problem from a dense [m][n] matrix and priors (no DEM).
@@ -1006,12 +1067,17 @@ void orc_window_export(void* h, uint8_t* dense, int* src, double* prior, double*
 // incoming |VN-to-CN message| of each CN at iteration t. Returns the first
 // iteration (1-based) whose hard decision met the syndrome, or 0.
 int orc_window_bp(void* h, const orc_params* P, const uint8_t* syn, int n_iters, double* post,
-                  double* cn_min) {
+                  double* cn_min, const double* warm_in) {
   const Window& w = ((OrcWindow*)h)->win;
   Graph g = window_graph(w);
   Status st = initial_status(g, syn);
   Messages ms;
   init_messages(g, *P, ms);
+  if (warm_in) {   // warm start as in decode_window
+    for (size_t e = 0; e < ms.c2v.size(); ++e)
+      if (!std::isnan(warm_in[e])) ms.c2v[e] = warm_in[e];
+    vn_update(g, st, *P, ms);
+  }
   int first_ok = 0;
   for (int t = 0; t < n_iters; ++t) {
     bp_iteration(g, st, *P, ms, cn_min ? cn_min + (size_t)t * w.m : nullptr);
@@ -1030,15 +1096,26 @@ int orc_window_bp(void* h, const orc_params* P, const uint8_t* syn, int n_iters,
 void orc_window_decode(void* h, const orc_params* P, int n_shots, const uint8_t* syn,
                        uint8_t* e, double* pm, int* flags, orc_stats* stats, int* sel,
                        int sel_cap, int* dec, int n_paths_cap, int log_cap, int* ends,
-                       double* first_post, int n_post_cap, int n_threads) {
+                       double* first_post, int n_post_cap, int n_threads,
+                       const double* warm_in, double* warm_out, double* pre_lsum) {
   const Window& w = ((OrcWindow*)h)->win;
+  size_t ne = 0;
+  for (int r = 0; r < w.m; ++r) ne += w.row_cols[r].size();
   std::atomic<int> next(0);
   auto work = [&]() {
     for (;;) {
       int s = next.fetch_add(1);
       if (s >= n_shots) break;
       WindowResult wr;
-      decode_window(w, *P, syn + (size_t)s * w.m, wr, nullptr, nullptr, nullptr, 0, -1);
+      std::vector<double> wi, wo;
+      if (warm_in) wi.assign(warm_in + s * ne, warm_in + (s + 1) * ne);
+      decode_window(w, *P, syn + (size_t)s * w.m, wr, nullptr, nullptr, nullptr, 0, -1,
+                    warm_in ? &wi : nullptr, warm_out ? &wo : nullptr);
+      if (warm_out)
+        for (size_t i = 0; i < ne; ++i) warm_out[s * ne + i] = i < wo.size() ? wo[i] : std::nan("");
+      if (pre_lsum)   // the preprocessing's ranking keys (NaN without preprocessing)
+        for (int c = 0; c < w.n; ++c)
+          pre_lsum[(size_t)s * w.n + c] = c < (int)wr.pre_lsum.size() ? wr.pre_lsum[c] : std::nan("");
       std::memcpy(e + (size_t)s * w.n, wr.e.data(), w.n);
       pm[s] = wr.pm;
       flags[s] = wr.flags;
@@ -1110,6 +1187,14 @@ void orc_window_osd(void* h, const orc_params* P, int n_shots, const uint8_t* sy
   for (int i = 1; i < nt; ++i) th.emplace_back(work);
   work();
   for (auto& t : th) t.join();
+}
+
+// The warm-start edge map from window `hp` to window `hn` (warm_map); map
+// holds one entry per edge of hn. Returns the number of edges.
+int orc_warm_map(void* hp, void* hn, int* map) {
+  std::vector<int> mp = warm_map(((OrcWindow*)hp)->win, ((OrcWindow*)hn)->win);
+  if (map) std::memcpy(map, mp.data(), mp.size() * sizeof(int));
+  return (int)mp.size();
 }
 
 // BP+OSD(-CS) on a dense [m][n] problem with priors llr (see osd_window).
@@ -1311,7 +1396,7 @@ int orc_decode_shots(int n_rows, int n_cols, int n_obs, int w, int n_rounds, con
                      const uint8_t* obs, uint8_t* det_out, uint8_t* obs_out, uint8_t* fail,
                      int* win_flags, uint8_t* e_out, long long* edge_iters, int n_threads,
                      int max_windows, int F, int osd_iters, int osd_lambda, int osd_keep,
-                     int osd_all) {
+                     int osd_all, int warm) {
   Dem d = make_dem(n_rows, n_cols, n_obs, w, n_rounds, h_ptr, h_idx, l_ptr, l_idx, prior);
   if (W < 1 || F < 1 || F > W) return -1;
   const int nwin = n_rounds <= W ? 1 : 1 + (n_rounds - W + F - 1) / F;
@@ -1319,6 +1404,10 @@ int orc_decode_shots(int n_rows, int n_cols, int n_obs, int w, int n_rounds, con
   std::vector<Window> wins(nwin);
   for (int k = 0; k < nwin; ++k)
     if (!build_window(d, k, W, F, wins[k])) return -2;
+  const bool use_warm = warm && P->pre_iters > 0;
+  std::vector<std::vector<int>> wmaps(nwin);
+  if (use_warm)
+    for (int k = 1; k < nwin; ++k) wmaps[k] = warm_map(wins[k - 1], wins[k]);
   std::atomic<int> next(0);
   std::atomic<long long> ei(0);
   auto work = [&]() {
@@ -1327,6 +1416,7 @@ int orc_decode_shots(int n_rows, int n_cols, int n_obs, int w, int n_rounds, con
       if (s >= n_shots) break;
       std::vector<uint8_t> dd(det + (size_t)s * n_rows, det + (size_t)(s + 1) * n_rows);
       std::vector<uint8_t> oo(n_obs, 0);
+      std::vector<double> carry;   // messages the previous window handed over
       for (int k = 0; k < run_windows; ++k) {
         const Window& wn = wins[k];
         WindowResult wr;
@@ -1336,6 +1426,18 @@ int orc_decode_shots(int n_rows, int n_cols, int n_obs, int w, int n_rounds, con
                                    osd_keep, nullptr);
           wr.e = R.e;
           wr.flags = R.flags;
+          carry.clear();
+        } else if (use_warm) {
+          std::vector<double> win_in;
+          if (!carry.empty()) {
+            win_in.resize(wmaps[k].size());
+            for (size_t e = 0; e < win_in.size(); ++e)
+              win_in[e] = wmaps[k][e] >= 0 ? carry[wmaps[k][e]] : std::nan("");
+          }
+          std::vector<double> win_out;
+          decode_window(wn, *P, dd.data() + wn.row0, wr, nullptr, nullptr, nullptr, 0, -1,
+                        carry.empty() ? nullptr : &win_in, &win_out);
+          carry.swap(win_out);
         } else {
           decode_window(wn, *P, dd.data() + wn.row0, wr, nullptr, nullptr, nullptr, 0, -1);
         }
@@ -1460,10 +1562,17 @@ void orc_dense_bp(int m, int n, const uint8_t* dense, const double* llr, const u
 // the syndrome).
 double orc_dense_window(int m, int n, const uint8_t* dense, const double* llr, const uint8_t* syn,
                         const orc_params* P, uint8_t* e, int* flags, int* kept, int* n_kept,
-                        double* pre_lsum) {
+                        double* pre_lsum, const double* warm_in, double* warm_out) {
   Window win = dense_window(m, n, dense, llr);
   WindowResult wr;
-  decode_window(win, *P, syn, wr, nullptr, nullptr, nullptr, 0, -1);
+  size_t ne = 0;
+  for (int c = 0; c < n; ++c) ne += win.col_rows[c].size();
+  std::vector<double> wi, wo;
+  if (warm_in) wi.assign(warm_in, warm_in + ne);
+  decode_window(win, *P, syn, wr, nullptr, nullptr, nullptr, 0, -1, warm_in ? &wi : nullptr,
+                warm_out ? &wo : nullptr);
+  if (warm_out)
+    for (size_t i = 0; i < ne; ++i) warm_out[i] = i < wo.size() ? wo[i] : std::nan("");
   std::memcpy(e, wr.e.data(), n);
   if (flags) *flags = wr.flags;
   if (n_kept) *n_kept = (int)wr.selected.size();

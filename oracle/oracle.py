@@ -63,13 +63,15 @@ def lib():
         L.orc_window_free.argtypes = [P]
         L.orc_window_dims.argtypes = [P, P]
         L.orc_window_export.argtypes = [P] * 6
-        L.orc_window_bp.argtypes = [P, P, P, i32, P, P]
+        L.orc_window_bp.argtypes = [P, P, P, i32, P, P, P]
         L.orc_window_bp.restype = i32
         L.orc_window_decode.argtypes = [P, P, i32, P, P, P, P, P, P, i32, P, i32, i32, P, P,
-                                        i32, i32]
+                                        i32, i32, P, P, P]
+        L.orc_warm_map.argtypes = [P, P, P]
+        L.orc_warm_map.restype = i32
         L.orc_window_replay.argtypes = [P, P, P, P, i32, P, P, i32] + [P] * 11 + [i32, P, P, P, P, P, P]
         L.orc_window_replay.restype = i32
-        L.orc_decode_shots.argtypes = [i32] * 5 + [P] * 5 + [i32, P, i32] + [P] * 8 + [i32] * 7
+        L.orc_decode_shots.argtypes = [i32] * 5 + [P] * 5 + [i32, P, i32] + [P] * 8 + [i32] * 8
         L.orc_decode_shots.restype = i32
         L.orc_select_vn.argtypes = [i32, P, P, P, P, i32, i32, i32, P, P]
         L.orc_select_vn.restype = i32
@@ -87,7 +89,7 @@ def lib():
         L.orc_window_osd.argtypes = [P, P, i32, P, i32, i32, i32, i32, P, P, P, P, P, P, i32]
         L.orc_dense_osd.argtypes = [i32, i32, P, P, P, P, i32, i32, i32, i32, P, P]
         L.orc_dense_osd.restype = C.c_double
-        L.orc_dense_window.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_dense_window.argtypes = [i32, i32, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_dense_window.restype = C.c_double
         L.orc_dense_path_probe.argtypes = [i32, i32, P, P, P, P, i32, i32] + [P] * 7
         L.orc_dense_path_probe.restype = i32
@@ -144,18 +146,30 @@ class OracleWindow:
         lib().orc_window_export(self.h, _p(dense), _p(src), _p(prior), _p(llr), _p(commit))
         return dict(H=dense, src=src, prior=prior, llr=llr, commit=commit)
 
-    def bp(self, prm, syn, n_iters, with_cn_min=False):
+    def bp(self, prm, syn, n_iters, with_cn_min=False, warm_in=None):
+        """Flooding BP on the whole window, every iteration's posteriors; warm_in
+        (per edge, NaN: none) starts it as the warm-started preprocessing."""
         syn = np.ascontiguousarray(syn, np.uint8)
         post = np.zeros((n_iters, self.n), np.float64)
         cmin = np.zeros((n_iters, self.m), np.float64) if with_cn_min else None
-        first = lib().orc_window_bp(self.h, C.byref(prm), _p(syn), n_iters, _p(post), _p(cmin))
+        wi = None if warm_in is None else np.ascontiguousarray(warm_in, np.float64)
+        first = lib().orc_window_bp(self.h, C.byref(prm), _p(syn), n_iters, _p(post), _p(cmin),
+                                    _p(wi))
         if with_cn_min:
             return post, first, cmin
         return post, first
 
-    def decode(self, prm, syn, n_threads=None, logs=False, log_cap=32):
+    def decode(self, prm, syn, n_threads=None, logs=False, log_cap=32, warm_in=None,
+               warm_out=False):
+        """Window decode; warm_in [n_shots][edges] (row-major window edges, NaN
+        for edges the previous window lacks) starts the preprocessing BP from
+        those CN-to-VN messages, warm_out=True returns the messages this window
+        hands over (key "warm_out")."""
         syn = np.ascontiguousarray(syn, np.uint8).reshape(-1, self.m)
         ns = syn.shape[0]
+        ne = self.n_edges if (warm_in is not None or warm_out) else 0
+        wi = None if warm_in is None else np.ascontiguousarray(warm_in, np.float64).reshape(ns, ne)
+        wo = np.zeros((ns, ne), np.float64) if warm_out else None
         e = np.zeros((ns, self.n), np.uint8)
         pm = np.zeros(ns, np.float64)
         flags = np.zeros(ns, np.int32)
@@ -168,18 +182,30 @@ class OracleWindow:
             dec = np.zeros((ns, npaths, log_cap, 3), np.int32)
             ends = np.zeros((ns, npaths, 2), np.int32)
             post = np.zeros((ns, self.n), np.float64)
+        lsum = np.zeros((ns, self.n), np.float64) if logs else None
         lib().orc_window_decode(self.h, C.byref(prm), ns, _p(syn), _p(e), _p(pm), _p(flags),
                                 C.cast(stats, C.c_void_p), _p(sel), sel_cap if logs else 0,
                                 _p(dec), npaths if logs else 0, log_cap, _p(ends), _p(post),
-                                self.n if logs else 0, n_threads or default_threads())
+                                self.n if logs else 0, n_threads or default_threads(), _p(wi),
+                                _p(wo), _p(lsum))
         out = dict(e=e, pm=pm, flags=flags,
                    edge_iters=np.array([s.edge_iters for s in stats], np.int64),
                    bp_iters=np.array([s.bp_iters for s in stats], np.int64),
                    converged_path=np.array([s.converged_path for s in stats], np.int32),
-                   steps_main=np.array([s.steps_main for s in stats], np.int32))
+                   steps_main=np.array([s.steps_main for s in stats], np.int32),
+                   pre_converged=np.array([s.pre_converged for s in stats], np.int32))
         if logs:
-            out.update(sel=sel, dec=dec, ends=ends, first_post=post)
+            out.update(sel=sel, dec=dec, ends=ends, first_post=post, lsum=lsum)
+        if warm_out:
+            out["warm_out"] = wo
         return out
+
+    def warm_map(self, prev):
+        """For each edge of this window, the edge of window `prev` it continues
+        (same detector row and DEM column) or -1."""
+        mp = np.zeros(self.n_edges, np.int32)
+        lib().orc_warm_map(prev.h, self.h, _p(mp))
+        return mp
 
     def osd(self, prm, syn, n_iters=200, cs=True, lam=10, n_keep=0, forced_order=None,
             n_threads=None):
@@ -238,11 +264,12 @@ class OracleWindow:
 
 
 def decode_shots(dem, W, prm, det, obs, n_threads=None, max_windows=-1, F=1, osd=None,
-                 osd_on="last"):
+                 osd_on="last", warm=False):
     """(W,F) sliding-window decode of whole shots; returns dict(fail, det_out,
     obs_out, win_flags, e (committed correction over DEM columns), edge_iters).
     osd = (bp_iters, lambda, n_keep) decodes the last window (osd_on="all":
-    every window) by BP + OSD-CS instead of GDG."""
+    every window) by BP + OSD-CS instead of GDG. warm: each window's
+    preprocessing BP starts from the messages the previous window hands over."""
     det = np.ascontiguousarray(det, np.uint8)
     obs = np.ascontiguousarray(obs, np.uint8)
     ns = det.shape[0]
@@ -258,7 +285,7 @@ def decode_shots(dem, W, prm, det, obs, n_threads=None, max_windows=-1, F=1, osd
                                *[_p(a) for a in keep], W, C.byref(prm), ns, _p(det), _p(obs),
                                _p(det_out), _p(obs_out), _p(fail), _p(wf), _p(e_out), _p(ei),
                                n_threads or default_threads(), max_windows, F,
-                               *(osd if osd else (0, 0, 0)), int(osd_on == "all"))
+                               *(osd if osd else (0, 0, 0)), int(osd_on == "all"), int(warm))
     if r < 0:
         raise ValueError(f"orc_decode_shots failed: {r}")
     return dict(fail=fail, det_out=det_out, obs_out=obs_out, win_flags=wf, e=e_out,
@@ -323,22 +350,30 @@ def dense_gdg(H, llr, syn, prm):
     return pm, e, int(fl[0])
 
 
-def dense_window(H, llr, syn, prm):
+def dense_window(H, llr, syn, prm, warm_in=None, warm_out=False):
     """decode_window on a dense problem (preprocessing, ranking and truncation
     included when prm.pre_iters > 0). Returns dict(pm, e, flags, kept (ranked
-    kept columns), lsum (ranking keys))."""
+    kept columns), lsum (ranking keys)). warm_in: CN-to-VN messages per edge
+    (row-major, NaN: none) the preprocessing BP starts from; warm_out=True adds
+    the messages the window hands over ("warm_out")."""
     H = np.ascontiguousarray(H, np.uint8)
     llr = np.ascontiguousarray(llr, np.float64)
     syn = np.ascontiguousarray(syn, np.uint8)
     n = H.shape[1]
+    ne = int(H.sum())
     e = np.zeros(n, np.uint8)
     fl = np.zeros(1, np.int32)
     kept = np.full(n, -1, np.int32)
     nk = np.zeros(1, np.int32)
     lsum = np.zeros(n, np.float64)
+    wi = None if warm_in is None else np.ascontiguousarray(warm_in, np.float64)
+    wo = np.zeros(ne, np.float64) if warm_out else None
     pm = lib().orc_dense_window(H.shape[0], n, _p(H), _p(llr), _p(syn), C.byref(prm), _p(e),
-                                _p(fl), _p(kept), _p(nk), _p(lsum))
-    return dict(pm=pm, e=e, flags=int(fl[0]), kept=kept[:int(nk[0])], lsum=lsum)
+                                _p(fl), _p(kept), _p(nk), _p(lsum), _p(wi), _p(wo))
+    out = dict(pm=pm, e=e, flags=int(fl[0]), kept=kept[:int(nk[0])], lsum=lsum)
+    if warm_out:
+        out["warm_out"] = wo
+    return out
 
 
 def dense_path_probe(H, llr, syn, prm, path_id=0, max_steps=8):

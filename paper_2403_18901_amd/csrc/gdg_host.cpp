@@ -11,6 +11,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <unordered_map>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -92,6 +93,10 @@ struct gdg_window {
   int max_sub = 0;
   int bucket = 0;
   gdg_win_dev* d_dev = nullptr;   // device copy of dev
+  // host copies for linking windows (warm start): the window CSR and each
+  // CSR edge's message slot in the preprocessing layout
+  std::vector<int> h_row_ptr, epos;
+  std::vector<uint16_t> h_row_col;
   gdg_lds* d_plans = nullptr;     // device LDS plans for 1..8 wavefronts (index waves-1)
   gdg_lds plans[8]{};
   std::vector<void*> allocs;
@@ -218,6 +223,7 @@ struct FullLayout {
   std::vector<uint32_t> meta;
   std::vector<uint16_t> rvn, cidx;
   std::vector<int> cptr;
+  std::vector<int> epos;   // message slot of each CSR edge
   int T = 0, epad = 0;
 };
 
@@ -251,12 +257,14 @@ bool full_layout(int m, int n, const std::vector<int>& row_ptr, const std::vecto
   // idle lanes point at the dummy batch; 3 idle columns per wavefront (up to 8)
   // past the end take the loads the CN walk issues ahead of its last slots
   F.meta.assign((size_t)(F.T + 3 * 8) * 64, (uint32_t)(epad + 4));
+  F.epos.assign(row_ptr[m], 0);
   int g = 0;
   for (int pj = 0; pj < m; ++pj) {
     const int j = order[pj];
     int pos = start[pj];
     for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e, ++pos) {
       const int c = row_col[e];
+      F.epos[e] = pos;
       F.rvn[pos] = (uint16_t)(4 * c);
       F.cidx[F.cptr[c] + row_kcol[e]] = (uint16_t)(4 * pos);
     }
@@ -505,6 +513,9 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
       return fail(GDG_ESHAPE, "window too large for the preprocessing layout");
     D.fr_T = F.T;
     D.fr_epad = F.epad;
+    win->epos = F.epos;
+    win->h_row_ptr = row_ptr;
+    win->h_row_col = row_col;
     if ((rc = win->put(F.meta, &D.fr_meta))) return rc;
     {
       std::vector<uint32_t> rec(4 * F.meta.size());
@@ -615,6 +626,7 @@ int gdg_build_window(const gdg_dem* dem, int32_t k, int32_t W, int32_t F, const 
   I.last = last ? 1 : 0;
   I.lds_bytes = L.total;
   I.waves = waves;
+  I.n_msg = D.fr_epad;
   *out = win.release();
   return GDG_OK;
 }
@@ -624,6 +636,47 @@ void gdg_window_free(gdg_window* win) { delete win; }
 int gdg_window_get_info(const gdg_window* win, gdg_window_info* info) {
   if (!win || !info) return fail(GDG_EINVAL, "null argument");
   *info = win->info;
+  return GDG_OK;
+}
+
+int gdg_link_windows(gdg_window* next, const gdg_window* prev) {
+  if (!next || !prev) return fail(GDG_EINVAL, "null window");
+  if (next->dev.pre_iters <= 0)
+    return fail(GDG_EINVAL, "the window has no preprocessing BP to warm-start");
+  // previous window: DEM column -> window column
+  std::unordered_map<int, int> pcol;
+  for (int c = 0; c < prev->info.n; ++c)
+    if (prev->src[c] >= 0) pcol[prev->src[c]] = c;
+  std::vector<int> map(std::max(1, next->dev.fr_epad), -1);
+  const int shift = next->info.row0 - prev->info.row0;
+  for (int j = 0; j < next->info.m; ++j) {
+    const int jp = j + shift;   // the same detector row in the previous window
+    if (jp < 0 || jp >= prev->info.m) continue;
+    const uint16_t* pb = prev->h_row_col.data() + prev->h_row_ptr[jp];
+    const uint16_t* pe = prev->h_row_col.data() + prev->h_row_ptr[jp + 1];
+    for (int e = next->h_row_ptr[j]; e < next->h_row_ptr[j + 1]; ++e) {
+      const int sc = next->src[next->h_row_col[e]];
+      if (sc < 0) continue;   // a unit column of merged faults
+      auto it = pcol.find(sc);
+      if (it == pcol.end()) continue;
+      const uint16_t* f = std::lower_bound(pb, pe, (uint16_t)it->second);
+      if (f == pe || *f != it->second) continue;
+      map[next->epos[e]] = prev->epos[prev->h_row_ptr[jp] + (int)(f - pb)];
+    }
+  }
+  const int* d = nullptr;
+  int rc = next->put(map, &d);
+  if (rc) return rc;
+  next->dev.warm_map = d;
+  next->dev.warm_prev_slots = prev->dev.fr_epad;
+  hipError_t e = hipMemcpy(next->d_dev, &next->dev, sizeof(gdg_win_dev), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  return GDG_OK;
+}
+
+int gdg_window_edge_slots(const gdg_window* win, int32_t* slot) {
+  if (!win || !slot) return fail(GDG_EINVAL, "null argument");
+  for (size_t e = 0; e < win->epos.size(); ++e) slot[e] = win->epos[e];
   return GDG_OK;
 }
 
@@ -707,9 +760,16 @@ int launch_geometry(const gdg_job* jobs, int n_jobs, int waves, int workgroups, 
 // and checkpoint slots for as many workgroups as fit in the rest (the others
 // replay their paths from the root, which gives the same results). Allocates
 // nothing.
+// Warm-start buffers of one job (gdg_decode_batch_warm).
+struct WarmIO {
+  const float* in = nullptr;
+  float* out = nullptr;
+  long long in_stride = 0, out_stride = 0;
+};
+
 int launch_with_scratch(const gdg_job* jobs, int n_jobs, int waves, const LaunchGeom& G,
                         const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn,
-                        void* scratch, size_t scratch_bytes) {
+                        void* scratch, size_t scratch_bytes, const WarmIO* warm = nullptr) {
   gdg_jobs_dev J{};
   for (int j = 0; j < n_jobs; ++j) {
     const gdg_job& jb = jobs[j];
@@ -739,6 +799,13 @@ int launch_with_scratch(const gdg_job* jobs, int n_jobs, int waves, const Launch
   }
   J.n_jobs = n_jobs;
   J.total = G.total;
+  if (warm) {
+    if (n_jobs != 1) return fail(GDG_EINVAL, "a warm start takes a one-job launch");
+    J.warm_in = warm->in;
+    J.warm_out = warm->out;
+    J.warm_in_stride = warm->in_stride;
+    J.warm_out_stride = warm->out_stride;
+  }
   if (learn) J.learn = *learn;
   J.lds = G.lds;
   if (G.lds > g_lds_set[G.bucket]) {
@@ -765,16 +832,18 @@ int launch_with_scratch(const gdg_job* jobs, int n_jobs, int waves, const Launch
 
 // Decode launch on the library's per-stream scratch (allocated or grown here).
 int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
-                const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn = nullptr) {
+                const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn = nullptr,
+                const WarmIO* warm = nullptr) {
   LaunchGeom G;
   int rc = launch_geometry(jobs, n_jobs, waves, workgroups, learn && learn->mode != 0, G);
   if (rc) return rc;
-  if (G.total == 0) return launch_with_scratch(jobs, n_jobs, waves, G, tr, st, learn, nullptr, 0);
+  if (G.total == 0)
+    return launch_with_scratch(jobs, n_jobs, waves, G, tr, st, learn, nullptr, 0, warm);
   StreamScratch sc;
   rc = stream_scratch(st, (size_t)G.grid * G.ck_per_wg(), &sc);
   if (rc) return rc;
   return launch_with_scratch(jobs, n_jobs, waves, G, tr, st, learn, sc.base,
-                             kCounterBytes + sc.ckpt_bytes);
+                             kCounterBytes + sc.ckpt_bytes, warm);
 }
 
 }  // namespace
@@ -789,13 +858,14 @@ size_t gdg_workspace_bytes(const gdg_window* win, int32_t n_shots) {
   return kCounterBytes + (size_t)G.grid * (size_t)G.ck_per_wg();
 }
 
-int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
-                     int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
-                     void* d_workspace, size_t workspace_bytes, const gdg_trace* trace,
-                     void* hip_stream) {
-  if (!win) return fail(GDG_EINVAL, "null window");
-  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
-  if (n_shots == 0) return GDG_OK;
+}  // extern "C"
+
+namespace {
+
+int decode_batch_impl(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                      int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
+                      void* d_workspace, size_t workspace_bytes, const gdg_trace* trace,
+                      void* hip_stream, const WarmIO* warm) {
   gdg_trace_dev tr{};
   if (trace) {
     tr.sel = trace->sel;
@@ -809,12 +879,53 @@ int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_sy
     if (tr.dec && tr.log_cap <= 0) return fail(GDG_EINVAL, "trace log_cap must be positive");
   }
   gdg_job job{win, n_shots, d_syndrome, syn_stride, d_ehat, d_pm, d_flags};
-  if (!d_workspace) return launch_jobs(&job, 1, win->waves, 0, tr, (hipStream_t)hip_stream);
+  if (!d_workspace)
+    return launch_jobs(&job, 1, win->waves, 0, tr, (hipStream_t)hip_stream, nullptr, warm);
   LaunchGeom G;
   int rc = launch_geometry(&job, 1, win->waves, 0, false, G);
   if (rc) return rc;
   return launch_with_scratch(&job, 1, win->waves, G, tr, (hipStream_t)hip_stream, nullptr,
-                             d_workspace, workspace_bytes);
+                             d_workspace, workspace_bytes, warm);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gdg_decode_batch(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                     int64_t syn_stride, uint8_t* d_ehat, double* d_pm, int32_t* d_flags,
+                     void* d_workspace, size_t workspace_bytes, const gdg_trace* trace,
+                     void* hip_stream) {
+  if (!win) return fail(GDG_EINVAL, "null window");
+  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+  if (n_shots == 0) return GDG_OK;
+  return decode_batch_impl(win, n_shots, d_syndrome, syn_stride, d_ehat, d_pm, d_flags,
+                           d_workspace, workspace_bytes, trace, hip_stream, nullptr);
+}
+
+int gdg_decode_batch_warm(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,
+                          int64_t syn_stride, const float* d_warm_in, int64_t warm_in_stride,
+                          float* d_warm_out, int64_t warm_out_stride, uint8_t* d_ehat,
+                          double* d_pm, int32_t* d_flags, void* d_workspace,
+                          size_t workspace_bytes, const gdg_trace* trace, void* hip_stream) {
+  if (!win) return fail(GDG_EINVAL, "null window");
+  if (n_shots < 0) return fail(GDG_EINVAL, "negative n_shots");
+  if (n_shots == 0) return GDG_OK;
+  if ((d_warm_in || d_warm_out) && win->dev.pre_iters <= 0)
+    return fail(GDG_EINVAL, "the window has no preprocessing BP to warm-start");
+  if (d_warm_in && !win->dev.warm_map)
+    return fail(GDG_EINVAL, "warm input for a window that gdg_link_windows has not linked");
+  if (d_warm_in && warm_in_stride < win->dev.warm_prev_slots)
+    return fail(GDG_EINVAL, "warm_in_stride below the previous window's message slots");
+  if (d_warm_out && warm_out_stride < win->dev.fr_epad)
+    return fail(GDG_EINVAL, "warm_out_stride below the window's message slots");
+  WarmIO w;
+  w.in = d_warm_in;
+  w.out = d_warm_out;
+  w.in_stride = warm_in_stride;
+  w.out_stride = warm_out_stride;
+  return decode_batch_impl(win, n_shots, d_syndrome, syn_stride, d_ehat, d_pm, d_flags,
+                           d_workspace, workspace_bytes, trace, hip_stream, &w);
 }
 
 int gdg_decode_batch_noalloc(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,

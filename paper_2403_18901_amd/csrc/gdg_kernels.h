@@ -43,6 +43,11 @@ struct gdg_win_dev {
   // offsets of its first four column slots (u16 each), the fifth's (the zero
   // message below degree five) | degree << 16, the prior's float bits
   const uint4* fr_vrec;     // [n]
+  // warm start from the previous window (Sec. V): for each padded CSR edge,
+  // the message slot of the same edge in the previous window, or -1; null
+  // until the window is linked
+  const int* warm_map;      // [fr_epad]
+  int warm_prev_slots;      // fr_epad of the linked previous window
 };
 
 // Byte offsets of the decode kernel's dynamic LDS regions. A header lives for
@@ -190,6 +195,11 @@ struct gdg_jobs_dev {
                          // replay their paths from the root (same results)
   gdg_job_dev job[kMaxJobs];
   gdg_learn_dev learn;
+  // optional warm start of a one-job launch: the previous window's handed-over
+  // CN-to-VN messages per shot (its slot order) and this window's; may be null
+  const float* warm_in;
+  float* warm_out;
+  long long warm_in_stride, warm_out_stride;
 };
 
 // LDS plan of the BP+OSD kernel (byte offsets): fixed arrays, then one region

@@ -765,10 +765,19 @@ __device__ __forceinline__ void full_vn_pass(const gdg_win_dev& w, float* post, 
 // receives every iteration's posteriors, NaN for iterations not run. Returns
 // the first iteration whose hard decisions met the syndrome (0: none) and
 // sets *done to the number of iterations run. Every thread enters.
+// Warm start (Sec. V's message reuse): with `warm` (the previous window's
+// handed-over messages, indexed through w.warm_map) the CN-to-VN messages of
+// edges the previous window also had start from those values instead of
+// zero, and one VN pass forms the first posteriors and VN-to-CN messages from
+// them. With `hand_over` the BP ends on a CN update of its final VN-to-CN
+// messages, the messages the next window starts from: a BP that stops early
+// has already made it (the CN walk that found the syndrome met), otherwise
+// the closing check walk makes it.
 template <int VPL>
 __device__ __forceinline__ int window_bp(const gdg_win_dev& w, const uint8_t* syn, float* post,
                                          float* c2v,
-                         float* lsum, const int n_iters, const bool stop, float* rec, int* done) {
+                         float* lsum, const int n_iters, const bool stop, float* rec, int* done,
+                         const float* warm = nullptr, const bool hand_over = false) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -778,7 +787,14 @@ __device__ __forceinline__ int window_bp(const gdg_win_dev& w, const uint8_t* sy
     if (lsum) lsum[c] = 0.0f;
   }
   if (tid == 0) post[n] = kInfF;   // dummy VN of the row padding
-  for (int e = tid; e < w.fr_epad + 2 * kPad; e += blockDim.x) c2v[e] = 0.0f;
+  for (int e = tid; e < w.fr_epad + 2 * kPad; e += blockDim.x) {
+    float x = 0.0f;
+    if (warm && e < w.fr_epad) {
+      const int q = w.warm_map[e];
+      if (q >= 0) x = warm[q];
+    }
+    c2v[e] = x;
+  }
   const int nw = blockDim.x >> 6;
   const int my_T = wave < w.fr_T ? (w.fr_T - wave + nw - 1) / nw : 0;
   PathCtx<VPL> F;
@@ -814,20 +830,24 @@ __device__ __forceinline__ int window_bp(const gdg_win_dev& w, const uint8_t* sy
     return bad;
   };
   int first = 0, it = 0;
-  for (int t = 1; t <= n_iters; ++t) {
-    // the CN phase also checks the hard decisions of iteration t - 1
-    const int any_bad = __syncthreads_or(walk(true));
-    if (t >= 2 && !any_bad && first == 0) {
-      first = t - 1;
-      if (stop) break;
+  // a warm start begins with a VN pass over the carried messages (t = 0)
+  for (int t = warm ? 0 : 1; t <= n_iters; ++t) {
+    if (t > 0) {
+      // the CN phase also checks the hard decisions of iteration t - 1
+      const int any_bad = __syncthreads_or(walk(true));
+      if (t >= 2 && !any_bad && first == 0) {
+        first = t - 1;
+        if (stop) break;
+      }
     }
-    full_vn_pass(w, post, c2v, lsum && t > n_iters - 4 ? lsum : nullptr);
-    it = t;
+    full_vn_pass(w, post, c2v, lsum && t > 0 && t > n_iters - 4 ? lsum : nullptr);
     __syncthreads();
+    if (t == 0) continue;
+    it = t;
     if (rec)
       for (int c = tid; c < n; c += blockDim.x) rec[(long long)(t - 1) * n + c] = post[c];
   }
-  if (first == 0 && !__syncthreads_or(walk(false))) first = it;
+  if (first == 0 && !__syncthreads_or(walk(hand_over))) first = it;
   if (rec)
     for (long long i = (long long)it * n + tid; i < (long long)n_iters * n; i += blockDim.x)
       rec[i] = __builtin_nanf("");
@@ -907,7 +927,8 @@ __device__ __attribute__((noinline)) void decode_shot(const gdg_win_dev& wref, c
                             uint8_t* __restrict__ ehat, double* __restrict__ pm_out,
                             int* __restrict__ flags_out, const gdg_trace_dev& tr,
                             const gdg_learn_dev& lrn, unsigned char* smem, const int lds_alloc,
-                            char* const ck, const long long ck_stride) {
+                            char* const ck, const long long ck_stride,
+                            const float* __restrict__ warm_in, float* __restrict__ warm_out) {
   const gdg_win_dev w = wref;   // uniform: kept in scalar registers, not re-read
   const bool low_err = kLow || w.low_error;
   const int tid = threadIdx.x;
@@ -961,8 +982,13 @@ __device__ __attribute__((noinline)) void decode_shot(const gdg_win_dev& wref, c
     const bool conv =
         window_bp<VPL>(w, sorig, ppost, pc2v, lsum, w.pre_iters, true,
                        tr.pre_post ? tr.pre_post + (long long)shot * w.pre_iters * n : nullptr,
-                       &iters_done) != 0;
+                       &iters_done, warm_in, warm_out != nullptr) != 0;
     if (tid == 0) *eacc = (unsigned long long)iters_done * (unsigned long long)w.e_full;
+    if (warm_out) {
+      // the messages the next window starts from (before the array is reused)
+      for (int e = tid; e < w.fr_epad; e += blockDim.x) warm_out[e] = pc2v[e];
+      __syncthreads();
+    }
     if (conv) {
       // the hard decision of the preprocessing BP is the answer
       for (int base = wave * kWave; base < n; base += blockDim.x) {
@@ -1885,8 +1911,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int t = 1; t < kMaxJobs; ++t)
       if (t < J.n_jobs && item >= J.job[t].item0) jb = J.job[t];
-    decode_shot<VPL, kLearn, kLow>(*jb.w, *jb.L, item - jb.item0, jb.syn, jb.syn_stride, jb.ehat,
-                                   jb.pm, jb.flags, tr, J.learn, smem, J.lds, ck, J.ckpt_stride);
+    const long long shot = item - jb.item0;
+    decode_shot<VPL, kLearn, kLow>(*jb.w, *jb.L, (int)shot, jb.syn, jb.syn_stride, jb.ehat, jb.pm,
+                                   jb.flags, tr, J.learn, smem, J.lds, ck, J.ckpt_stride,
+                                   J.warm_in ? J.warm_in + shot * J.warm_in_stride : nullptr,
+                                   J.warm_out ? J.warm_out + shot * J.warm_out_stride : nullptr);
     __syncthreads();
     if (!J.work) item += gridDim.x;
   }

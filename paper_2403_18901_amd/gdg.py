@@ -28,7 +28,8 @@ EXPORTED = ["gdg_build_window", "gdg_window_free", "gdg_window_get_info", "gdg_w
             "gdg_mlp_forward", "gdg_mlp_grad_work_bytes", "gdg_mlp_grad", "gdg_mlp_adam",
             "gdg_model_create", "gdg_model_free", "gdg_mlp_infer", "gdg_learned_work_bytes",
             "gdg_decode_learned", "gdg_last_error", "gdg_decode_batch_noalloc",
-            "gdg_release_scratch", "gdg_decode_osd"]
+            "gdg_release_scratch", "gdg_decode_osd", "gdg_link_windows", "gdg_window_edge_slots",
+            "gdg_decode_batch_warm"]
 
 MLP_IN, MLP_H = 17, 64
 MLP_PARAMS = 5377
@@ -51,7 +52,7 @@ class Params(C.Structure):
 class WindowInfo(C.Structure):
     _fields_ = [(f, C.c_int32) for f in ("k", "W", "m", "n", "row0", "n_act", "n_paths", "n_edges",
                                          "max_sub_edges", "n_commit", "last", "lds_bytes",
-                                         "waves")]
+                                         "waves", "n_msg")]
 
 
 class Trace(C.Structure):
@@ -137,6 +138,10 @@ def lib():
         L.gdg_decode_batch_noalloc.argtypes = [P, i32, P, i64, P, P, P, P]
         L.gdg_release_scratch.argtypes = [P]
         L.gdg_decode_osd.argtypes = [P, i32, P, i64, i32, i32, i32, i32, P, P, P, P, P, P]
+        L.gdg_link_windows.argtypes = [P, P]
+        L.gdg_window_edge_slots.argtypes = [P, P]
+        L.gdg_decode_batch_warm.argtypes = [P, i32, P, i64, P, i64, P, i64, P, P, P, P,
+                                            C.c_size_t, P, P]
         L.gdg_decode_jobs.argtypes = [P, i32, P, P]
         L.gdg_jobs_lds_bytes.argtypes = [P, i32, i32]
         L.gdg_commit.argtypes = [P, i32, P, P, i64, P, i64, P]
@@ -214,6 +219,20 @@ class Window:
         self.info = {f: getattr(info, f) for f, _ in WindowInfo._fields_}
         self.m, self.n, self.row0 = info.m, info.n, info.row0
         self.n_act, self.n_paths = info.n_act, info.n_paths
+        self.n_msg, self.n_edges = info.n_msg, info.n_edges
+        self.linked = None
+
+    def link(self, prev: "Window"):
+        """gdg_link_windows: this window's preprocessing BP may start from the
+        messages `prev` hands over (warm start)."""
+        _check(lib().gdg_link_windows(self.h, prev.h))
+        self.linked = prev   # keeps prev's graph alive while linked
+
+    def edge_slots(self):
+        """Message slot of every window edge (row-major CSR) in the warm buffers."""
+        slot = np.zeros(self.n_edges, np.int32)
+        _check(lib().gdg_window_edge_slots(self.h, slot.ctypes.data_as(C.c_void_p)))
+        return slot
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -231,8 +250,11 @@ class Window:
 
     def decode(self, syn: torch.Tensor, syn_offset: int = 0, n_shots: int | None = None,
                trace: bool = False, log_cap: int = 32, out=None, step_lsum: bool = False,
-               pre_post: bool = False):
-        """syn: uint8 cuda tensor [n_shots, stride]; window rows start at column syn_offset."""
+               pre_post: bool = False, warm_in: torch.Tensor | None = None,
+               warm_out: torch.Tensor | None = None):
+        """syn: uint8 cuda tensor [n_shots, stride]; window rows start at column syn_offset.
+        warm_in / warm_out: float32 cuda tensors [n_shots, >= n_msg] of handed-over
+        messages (gdg_decode_batch_warm); warm_in needs link()."""
         assert syn.dtype == torch.uint8 and syn.is_cuda and syn.dim() == 2 and syn.is_contiguous()
         ns = syn.shape[0] if n_shots is None else n_shots
         dev = syn.device
@@ -260,9 +282,19 @@ class Window:
             tr = Trace(_ptr(trd["sel"]), _ptr(trd["dec"]), log_cap, _ptr(trd["ends"]),
                        _ptr(trd["first_post"]), _ptr(trd["edge_iters"]),
                        _ptr(trd.get("step_lsum")), _ptr(trd.get("pre_post")))
-        _check(lib().gdg_decode_batch(self.h, ns, _ptr(syn, syn_offset), syn.shape[1], _ptr(ehat),
-                                      _ptr(pm), _ptr(flags), None, 0,
-                                      C.byref(tr) if tr is not None else None, _stream()))
+        if warm_in is not None or warm_out is not None:
+            for t in (warm_in, warm_out):
+                assert t is None or (t.dtype == torch.float32 and t.is_cuda and t.dim() == 2
+                                     and t.is_contiguous() and t.shape[0] >= ns)
+            _check(lib().gdg_decode_batch_warm(
+                self.h, ns, _ptr(syn, syn_offset), syn.shape[1], _ptr(warm_in),
+                warm_in.shape[1] if warm_in is not None else 0, _ptr(warm_out),
+                warm_out.shape[1] if warm_out is not None else 0, _ptr(ehat), _ptr(pm),
+                _ptr(flags), None, 0, C.byref(tr) if tr is not None else None, _stream()))
+        else:
+            _check(lib().gdg_decode_batch(self.h, ns, _ptr(syn, syn_offset), syn.shape[1],
+                                          _ptr(ehat), _ptr(pm), _ptr(flags), None, 0,
+                                          C.byref(tr) if tr is not None else None, _stream()))
         if trace:
             return ehat, pm, flags, trd
         return ehat, pm, flags
@@ -409,10 +441,12 @@ class SlidingWindowDecoder:
     App. E)."""
 
     def __init__(self, dem, prm: Params, W: int = 3, F: int = 1, osd=None,
-                 osd_on: str = "last"):
+                 osd_on: str = "last", warm: bool = False):
         """osd = (bp_iters, lambda, n_keep): the last window (osd_on="all":
         every window) is decoded by BP + OSD-CS instead of GDG (Sec. III's
-        window comparator; App. E's last-window variant)."""
+        window comparator; App. E's last-window variant). warm: each window's
+        preprocessing BP starts from the messages the previous one hands over
+        (Sec. V's message reuse, gdg_decode_batch_warm)."""
         if osd_on not in ("last", "all"):
             raise ValueError("osd_on is 'last' or 'all'")
         self.dem = dem
@@ -420,6 +454,10 @@ class SlidingWindowDecoder:
         self.osd, self.osd_on = osd, osd_on
         self.n_windows = n_windows(dem.n_rounds, W, F)
         self.windows = [Window(dem, k, W, prm, F) for k in range(self.n_windows)]
+        self.warm = warm and prm.pre_iters > 0
+        if self.warm:
+            for k in range(1, self.n_windows):
+                self.windows[k].link(self.windows[k - 1])
 
     def decode(self, det: torch.Tensor, obs: torch.Tensor, trace: bool = False):
         """Decodes in place: det becomes the residual detector record and obs the
@@ -428,11 +466,23 @@ class SlidingWindowDecoder:
         ns = det.shape[0]
         wflags = torch.empty((ns, self.n_windows), dtype=torch.int32, device=det.device)
         traces = []
+        bufs = [None, None]
+        if self.warm:
+            slots = max(w.n_msg for w in self.windows)
+            bufs = [torch.empty((ns, slots), dtype=torch.float32, device=det.device)
+                    for _ in range(2)]
+        carried = False
         for k, w in enumerate(self.windows):
             if self.osd and (self.osd_on == "all" or k == self.n_windows - 1):
                 it, lam, keep = self.osd
                 res = w.decode_osd(det, syn_offset=w.row0, bp_iters=it, cs=True, lam=lam,
                                    n_keep=keep)
+                carried = False
+            elif self.warm:
+                res = w.decode(det, syn_offset=w.row0, trace=trace,
+                               warm_in=bufs[(k + 1) % 2] if carried else None,
+                               warm_out=bufs[k % 2] if k + 1 < self.n_windows else None)
+                carried = True
             else:
                 res = w.decode(det, syn_offset=w.row0, trace=trace)
             ehat, pm, fl = res[:3]

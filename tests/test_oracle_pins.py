@@ -675,3 +675,64 @@ def test_window_osd_pipeline_solves_every_window():
     assert (last["win_flags"][:, -1] & 1).all()
     K = O.n_windows(dem.n_rounds, 3, 1)
     assert not last["det_out"][:, O.OracleWindow(dem, K - 1, 3).row0:].any()
+
+
+def test_warm_start_hand_example():
+    """Warm start (reading of Sec. V's message reuse) on a hand-computed
+    example: the carried CN-to-VN message enters through one VN update before
+    the first iteration (it changes VN2's posterior through VN1's extrinsic
+    message), and the hand-over is one CN update of the final VN-to-CN
+    messages (not the last CN messages themselves, which are [-3, -2, 4, -2])."""
+    warm, cold = _read_cases("warm_start_2cn_3vn.txt")
+    prm = O.params(alpha=1.0, pre_iters=4, trunc_factor=2)
+    for case, wi in ((warm, warm.get("warm_in")), (cold, None)):
+        r = O.dense_window(case["H"], case["llr"], case["syn"].astype(np.uint8), prm,
+                           warm_in=wi, warm_out=True)
+        np.testing.assert_allclose(r["lsum"], case["lsum"], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(r["warm_out"], case["warm_out"], rtol=0, atol=1e-15)
+        assert r["e"].tolist() == case["ehat"].astype(int).tolist()
+        assert r["pm"] == case["pm"][0] and r["flags"] & 1
+
+
+def test_warm_zero_messages_equal_cold_start():
+    """Carried messages that are all zero leave the window decode exactly as
+    the cold start (the VN update then forms the priors' messages)."""
+    dem = circuit_dem(get_code("72"), 6, 0.004)
+    det, obs = syndromes(dem, sample_errors(dem.thresholds(), 40, seed=43))
+    w = O.OracleWindow(dem, 2, 3)
+    prm = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
+    syn = np.ascontiguousarray(det[:, w.row0:w.row0 + w.m])
+    cold = w.decode(prm, syn, warm_out=True)
+    zero = w.decode(prm, syn, warm_in=np.zeros((syn.shape[0], w.n_edges)), warm_out=True)
+    for k in ("e", "flags", "edge_iters"):
+        assert np.array_equal(cold[k], zero[k]), k
+    assert np.array_equal(cold["pm"], zero["pm"])
+    assert np.array_equal(cold["warm_out"], zero["warm_out"])
+
+
+def test_warm_map_joins_the_same_row_and_column():
+    """The edge map between consecutive windows (1..4 of (3,1), and (5,2)):
+    every mapped pair is the same detector row and DEM column, and every edge
+    of the next window whose DEM column and row the previous window also has
+    is mapped (brute force over the dense window matrices); unit columns
+    never are."""
+    dem = circuit_dem(get_code("72"), 8, 0.003)
+    for W, F, ks in ((3, 1, (1, 2, 5)), (5, 2, (1, 2))):
+        for k in ks:
+            a, b = O.OracleWindow(dem, k - 1, W, F), O.OracleWindow(dem, k, W, F)
+            ea, eb = a.export(), b.export()
+            mp = b.warm_map(a)
+            ra, ca = np.nonzero(ea["H"])      # row-major edge order
+            rb, cb = np.nonzero(eb["H"])
+            assert len(mp) == len(rb)
+            key_a = {(a.row0 + r, ea["src"][c]): i for i, (r, c) in enumerate(zip(ra, ca))
+                     if ea["src"][c] >= 0}
+            n_mapped = 0
+            for i, (r, c) in enumerate(zip(rb, cb)):
+                want = key_a.get((b.row0 + r, eb["src"][c])) if eb["src"][c] >= 0 else None
+                if want is None:
+                    assert mp[i] == -1, (W, F, k, i)
+                else:
+                    assert mp[i] == want, (W, F, k, i)
+                    n_mapped += 1
+            assert n_mapped > 0
