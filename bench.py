@@ -63,6 +63,9 @@ def parse():
                     help="virtual seconds of the saturated streaming run")
     ap.add_argument("--stream-s", type=float, default=0.6,
                     help="virtual seconds of the 80%%-load streaming run")
+    ap.add_argument("--stream-chain", type=int, default=-1,
+                    help="windows of one experiment per tick: -1 one per tick with separate "
+                         "launches and commits, 0 all decodable (chained launch), n at most n")
     ap.add_argument("--stream-mem-mib", type=float, default=0.0,
                     help="device memory budget of the streaming service's experiment "
                          "slots in MiB (0: a quarter of the free memory, at most 1 GiB)")
@@ -394,8 +397,8 @@ def bench_stream(args):
     """Streaming service: 256 [[144,12,12]] blocks (12 noisy rounds) and 32
     [[288,12,18]] blocks (18), circuit-level p, Poisson round arrivals. First at
     one round per microsecond per block (far above capacity: reports the
-    sustained rate, backlog growth and admission rejections), then at 80% of
-    the capacity measured there (reports p50/p99 window latency)."""
+    sustained rate, backlog growth and admission rejections), then at 80%, 50%
+    and 10% of the capacity measured there (reports p50/p99 window latency)."""
     import torch
     from gdg_inputs.bb import get_code
     from gdg_inputs.dem import circuit_dem
@@ -408,17 +411,18 @@ def bench_stream(args):
     wins_per_round = sum(nb * (d.n_rounds - 2) / d.n_rounds for d, nb in dems)
     t = time.perf_counter()
     budget = int(args.stream_mem_mib * 2**20) if args.stream_mem_mib > 0 else None
+    chain = dict(chain=args.stream_chain >= 0, chain_max=max(args.stream_chain, 0))
     sat = S.StreamingService(dems, prm, rate=1e6, n_slots=None, seed=args.seed,
-                             mem_budget=budget)
+                             mem_budget=budget, **chain)
     rep_sat = sat.run(duration=args.stream_sat_s)
     wall_sat = time.perf_counter() - t
     cap = rep_sat["windows_per_s"]
     loads = {}
-    for frac in (0.8, 0.5):
+    for frac in (0.8, 0.5, 0.1):
         rate = frac * cap / wins_per_round
         t = time.perf_counter()
         svc = S.StreamingService(dems, prm, rate=rate, n_slots=None, seed=args.seed + 1,
-                                 mem_budget=budget)
+                                 mem_budget=budget, **chain)
         rep = svc.run(duration=args.stream_s)
         loads[frac] = dict(rep, rate_rounds_per_s_per_block=rate, wall_s=time.perf_counter() - t)
     rep80, wall80, rate80 = loads[0.8], loads[0.8]["wall_s"], loads[0.8]["rate_rounds_per_s_per_block"]
@@ -432,10 +436,11 @@ def bench_stream(args):
         "config": {"workload": f"256 x [[144,12,12]] (12 rounds) + 32 x [[288,12,18]] (18 rounds), "
                                f"circuit-level p={args.p}, g={args.g}, Poisson round arrivals, "
                                "virtual time advanced by measured device time",
-                   "blocks": 288},
+                   "blocks": 288, "chain": args.stream_chain},
         "saturated_1_round_per_us": dict(rep_sat, wall_s=wall_sat),
         "load_80pct": rep80,
         "load_50pct": loads[0.5],
+        "load_10pct": loads[0.1],
     }
     print(json.dumps(out))
 

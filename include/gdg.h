@@ -225,6 +225,36 @@ int gdg_decode_batch_noalloc(const gdg_window* win, int32_t n_shots, const uint8
 int gdg_release_scratch(void* hip_stream);
 
 /*
+ * Chained window decoding for streaming (Sec. III: window k + 1 needs the
+ * commit of window k): one launch takes n_items experiments, each a shot's
+ * detector record, and decodes and commits windows k_begin[i] .. k_end[i]-1 of
+ * item i in order inside the same workgroup, so an experiment whose rounds
+ * have all arrived needs one launch, not one per window. Each window is
+ * decoded as gdg_decode_batch decodes it, straight from the record, and
+ * committed as gdg_commit_indexed commits it.
+ *   first, middle, last: the window objects of k = 0, of k = 1 (standing for
+ *               every middle window of a time-uniform DEM; NULL if n_windows
+ *               <= 2) and of k = n_windows - 1 (may equal first when
+ *               n_windows = 1); built from one DEM with the same parameters.
+ *   d_k_begin, d_k_end: [n_items] int32 window ranges (clamped to 0..n_windows).
+ *   d_det:      detector records; item i's DEM row r at d_det[d_det_off[i] + r]
+ *               (int64 offsets); updated in place by every commit.
+ *   d_obs:      observable accumulators at d_obs[d_obs_off[i] + o]; XORed by
+ *               every commit.
+ *   d_ehat:     [n_items][ehat_stride] scratch for one window's correction,
+ *               ehat_stride >= the largest window's n.
+ *   d_pm, d_flags: [n_items][n_windows] outputs for each window decoded.
+ * Items must not share records. Errors: GDG_EINVAL for missing windows or
+ * buffers, windows out of order or of different launch shapes, unequal
+ * window steps, or a small ehat_stride.
+ */
+int gdg_decode_chain(const gdg_window* first, const gdg_window* middle, const gdg_window* last,
+                     int32_t n_windows, int32_t n_items, const int32_t* d_k_begin,
+                     const int32_t* d_k_end, uint8_t* d_det, const int64_t* d_det_off,
+                     uint8_t* d_obs, const int64_t* d_obs_off, uint8_t* d_ehat,
+                     int64_t ehat_stride, double* d_pm, int32_t* d_flags, void* hip_stream);
+
+/*
  * Cross-window message reuse (Sec. V, where the paper leaves it as future
  * work; readings below). gdg_link_windows prepares `next` to start its
  * preprocessing BP from messages `prev` hands over: for every edge of next's

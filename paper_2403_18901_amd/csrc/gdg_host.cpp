@@ -756,10 +756,6 @@ int launch_geometry(const gdg_job* jobs, int n_jobs, int waves, int workgroups, 
   return GDG_OK;
 }
 
-// Launches the decode with the given scratch: the shot counter at `scratch`
-// and checkpoint slots for as many workgroups as fit in the rest (the others
-// replay their paths from the root, which gives the same results). Allocates
-// nothing.
 // Warm-start buffers of one job (gdg_decode_batch_warm).
 struct WarmIO {
   const float* in = nullptr;
@@ -767,9 +763,14 @@ struct WarmIO {
   long long in_stride = 0, out_stride = 0;
 };
 
+// Launches the decode with the given scratch: the shot counter at `scratch`
+// and checkpoint slots for as many workgroups as fit in the rest (the others
+// replay their paths from the root, which gives the same results). Allocates
+// nothing. With `chain` the items are the experiments of a chained launch.
 int launch_with_scratch(const gdg_job* jobs, int n_jobs, int waves, const LaunchGeom& G,
                         const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn,
-                        void* scratch, size_t scratch_bytes, const WarmIO* warm = nullptr) {
+                        void* scratch, size_t scratch_bytes, const WarmIO* warm = nullptr,
+                        const gdg_chain_dev* chain = nullptr) {
   gdg_jobs_dev J{};
   for (int j = 0; j < n_jobs; ++j) {
     const gdg_job& jb = jobs[j];
@@ -799,6 +800,10 @@ int launch_with_scratch(const gdg_job* jobs, int n_jobs, int waves, const Launch
   }
   J.n_jobs = n_jobs;
   J.total = G.total;
+  if (chain) {
+    J.chained = 1;
+    J.chain = *chain;
+  }
   if (warm) {
     if (n_jobs != 1) return fail(GDG_EINVAL, "a warm start takes a one-job launch");
     J.warm_in = warm->in;
@@ -833,17 +838,17 @@ int launch_with_scratch(const gdg_job* jobs, int n_jobs, int waves, const Launch
 // Decode launch on the library's per-stream scratch (allocated or grown here).
 int launch_jobs(const gdg_job* jobs, int n_jobs, int waves, int workgroups,
                 const gdg_trace_dev& tr, hipStream_t st, const gdg_learn_dev* learn = nullptr,
-                const WarmIO* warm = nullptr) {
+                const WarmIO* warm = nullptr, const gdg_chain_dev* chain = nullptr) {
   LaunchGeom G;
   int rc = launch_geometry(jobs, n_jobs, waves, workgroups, learn && learn->mode != 0, G);
   if (rc) return rc;
   if (G.total == 0)
-    return launch_with_scratch(jobs, n_jobs, waves, G, tr, st, learn, nullptr, 0, warm);
+    return launch_with_scratch(jobs, n_jobs, waves, G, tr, st, learn, nullptr, 0, warm, chain);
   StreamScratch sc;
   rc = stream_scratch(st, (size_t)G.grid * G.ck_per_wg(), &sc);
   if (rc) return rc;
   return launch_with_scratch(jobs, n_jobs, waves, G, tr, st, learn, sc.base,
-                             kCounterBytes + sc.ckpt_bytes, warm);
+                             kCounterBytes + sc.ckpt_bytes, warm, chain);
 }
 
 }  // namespace
@@ -926,6 +931,62 @@ int gdg_decode_batch_warm(const gdg_window* win, int32_t n_shots, const uint8_t*
   w.out_stride = warm_out_stride;
   return decode_batch_impl(win, n_shots, d_syndrome, syn_stride, d_ehat, d_pm, d_flags,
                            d_workspace, workspace_bytes, trace, hip_stream, &w);
+}
+
+int gdg_decode_chain(const gdg_window* first, const gdg_window* middle, const gdg_window* last,
+                     int32_t n_windows, int32_t n_items, const int32_t* d_k_begin,
+                     const int32_t* d_k_end, uint8_t* d_det, const int64_t* d_det_off,
+                     uint8_t* d_obs, const int64_t* d_obs_off, uint8_t* d_ehat,
+                     int64_t ehat_stride, double* d_pm, int32_t* d_flags, void* hip_stream) {
+  if (!first) return fail(GDG_EINVAL, "null first window");
+  if (n_windows < 1 || n_items < 0) return fail(GDG_EINVAL, "bad sizes");
+  if (n_items == 0) return GDG_OK;
+  if (n_windows > 2 && !middle) return fail(GDG_EINVAL, "a middle window is needed");
+  if (n_windows >= 2 && !last) return fail(GDG_EINVAL, "a last window is needed");
+  if (n_windows == 1) last = first;
+  if (!middle) middle = first;
+  if (first->info.k != 0 || last->info.k != n_windows - 1 || !last->info.last ||
+      (n_windows > 2 && middle->info.k != 1))
+    return fail(GDG_EINVAL, "windows must be k = 0, k = 1 and the last, k = n_windows - 1");
+  if (!d_k_begin || !d_k_end || !d_det || !d_det_off || !d_obs || !d_obs_off || !d_ehat ||
+      !d_pm || !d_flags)
+    return fail(GDG_EINVAL, "null buffer");
+  const gdg_window* ws[3] = {first, middle, last};
+  int n_max = 0;
+  for (const gdg_window* w : ws) {
+    n_max = std::max(n_max, w->info.n);
+    if (w->waves != first->waves) return fail(GDG_EINVAL, "windows of different launch shapes");
+  }
+  if (ehat_stride < n_max) return fail(GDG_EINVAL, "ehat_stride below the largest window");
+  const int row_step = n_windows >= 2 ? last->info.row0 / (n_windows - 1) : 0;
+  if (n_windows > 2 && middle->info.row0 != row_step)
+    return fail(GDG_EINVAL, "windows do not advance by equal steps");
+  gdg_chain_dev C{};
+  for (int i = 0; i < 3; ++i) {
+    C.w[i] = ws[i]->d_dev;
+    C.L[i] = ws[i]->d_plans + (first->waves - 1);
+    C.cm[i] = ws[i]->cm;
+    C.row0[i] = ws[i]->info.row0;
+  }
+  C.K = n_windows;
+  C.row_step = row_step;
+  C.ehat_stride = ehat_stride;
+  C.det = d_det;
+  C.obs = d_obs;
+  C.det_off = (const long long*)d_det_off;
+  C.obs_off = (const long long*)d_obs_off;
+  C.k_begin = d_k_begin;
+  C.k_end = d_k_end;
+  C.ehat = d_ehat;
+  C.pm = d_pm;
+  C.flags = d_flags;
+  // one job per shape for the launch geometry (LDS, register tiling,
+  // checkpoints); the first carries the item count, the buffers are unused
+  gdg_job jobs[3];
+  for (int i = 0; i < 3; ++i)
+    jobs[i] = gdg_job{ws[i], i == 0 ? n_items : 0, d_det, first->info.m, d_ehat, d_pm, d_flags};
+  gdg_trace_dev tr{};
+  return launch_jobs(jobs, 3, first->waves, 0, tr, (hipStream_t)hip_stream, nullptr, nullptr, &C);
 }
 
 int gdg_decode_batch_noalloc(const gdg_window* win, int32_t n_shots, const uint8_t* d_syndrome,

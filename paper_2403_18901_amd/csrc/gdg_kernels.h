@@ -184,6 +184,27 @@ __host__ __device__ inline gdg_ck_layout gdg_ck(int n_act, int e_pad) {
   return c;
 }
 
+// A chained launch (streaming): each item is one experiment whose windows
+// k_begin..k_end-1 are decoded and committed in order by one workgroup, the
+// commit of window k feeding the syndrome of window k+1 in device memory.
+struct gdg_chain_dev {
+  const gdg_win_dev* w[3];   // window graphs: first, middle, last (device copies)
+  const gdg_lds* L[3];       // their LDS plans at the launch's wavefronts
+  gdg_commit_dev cm[3];      // their commit tables
+  int row0[3];               // first DEM row of each shape's window object
+  int K, row_step;           // windows per experiment; rows between windows
+  long long ehat_stride;     // per-item correction scratch
+  uint8_t* det;              // detector records; item i's at det + det_off[i]
+  uint8_t* obs;              // observable accumulators at obs + obs_off[i]
+  const long long* det_off;
+  const long long* obs_off;
+  const int* k_begin;
+  const int* k_end;
+  uint8_t* ehat;             // [items][ehat_stride]
+  double* pm;                // [items][K]: each decoded window's path metric
+  int* flags;                // [items][K]: and flags
+};
+
 struct gdg_jobs_dev {
   int n_jobs, total;
   int lds;   // the launch's dynamic LDS bytes
@@ -200,6 +221,8 @@ struct gdg_jobs_dev {
   const float* warm_in;
   float* warm_out;
   long long warm_in_stride, warm_out_stride;
+  int chained;               // 1: items are experiments of `chain`
+  gdg_chain_dev chain;
 };
 
 // LDS plan of the BP+OSD kernel (byte offsets): fixed arrays, then one region

@@ -1877,6 +1877,62 @@ __device__ __attribute__((noinline)) void decode_shot(const gdg_win_dev& wref, c
     ehat[(long long)shot * n + c] = (uint8_t)((obits[c >> 5] >> (c & 31)) & 1u);
 }
 
+// Commit of one shot's window correction (Eqs. 7-9) by the whole workgroup:
+// every DEM row the committed columns touch flips where their XOR is 1, and
+// likewise every observable. det_rel[row] is the shot's detector of DEM row
+// `row` (the record shifted by the window object's own first row).
+__device__ __forceinline__ void commit_shot(const gdg_commit_dev& cm, const uint8_t* ehat,
+                                            uint8_t* det_rel, uint8_t* obs) {
+  for (int r = threadIdx.x; r < cm.n_rows + cm.n_obs; r += blockDim.x) {
+    const bool is_row = r < cm.n_rows;
+    const int o = r - cm.n_rows;
+    const int t0 = is_row ? cm.row_ptr[r] : cm.obs_ptr[o];
+    const int t1 = is_row ? cm.row_ptr[r + 1] : cm.obs_ptr[o + 1];
+    const int* cols = is_row ? cm.row_col : cm.obs_col;
+    uint32_t x = 0u;
+    for (int t = t0; t < t1; ++t) x ^= ehat[cols[t]] & 1u;
+    if (!x) continue;
+    if (is_row)
+      det_rel[cm.row_global[r]] ^= 1;
+    else
+      obs[o] ^= 1;
+  }
+}
+
+// One experiment of a chained launch: its windows k_begin..k_end-1 in order,
+// each decoded straight from the experiment's detector record and committed
+// into it (and its observables) before the next window reads its syndrome.
+template <int VPL, bool kLow>
+__device__ __forceinline__ void decode_chain_item(
+    const gdg_chain_dev& C, const int item, const gdg_trace_dev& tr, const gdg_learn_dev& lrn,
+    unsigned char* smem, const int lds_alloc, char* const ck, const long long ck_stride) {
+  const int kb = max(0, C.k_begin[item]);
+  const int ke = min(C.K, C.k_end[item]);
+  uint8_t* eh = C.ehat + (long long)item * C.ehat_stride;
+  uint8_t* obs = C.obs + C.obs_off[item];
+  for (int k = kb; k < ke; ++k) {
+    // the window shape with static indices only (no dynamic indexing of the
+    // kernel argument, which would copy it to private memory)
+    const bool first = k == 0, last = k == C.K - 1;
+    const gdg_win_dev* wp = first ? C.w[0] : (last ? C.w[2] : C.w[1]);
+    const gdg_lds* lp = first ? C.L[0] : (last ? C.L[2] : C.L[1]);
+    const int row0 = first ? C.row0[0] : (last ? C.row0[2] : C.row0[1]);
+    const long long base = C.det_off[item] + (long long)k * C.row_step;
+    decode_shot<VPL, false, kLow>(*wp, *lp, 0, C.det + base, 0, eh,
+                                  C.pm + (long long)item * C.K + k,
+                                  C.flags + (long long)item * C.K + k, tr, lrn, smem, lds_alloc,
+                                  ck, ck_stride, nullptr, nullptr);
+    __syncthreads();
+    if (first)
+      commit_shot(C.cm[0], eh, C.det + base - row0, obs);
+    else if (last)
+      commit_shot(C.cm[2], eh, C.det + base - row0, obs);
+    else
+      commit_shot(C.cm[1], eh, C.det + base - row0, obs);
+    __syncthreads();
+  }
+}
+
 // Persistent decode: workgroup b takes items b, b + gridDim.x, ... of the job
 // table; item i belongs to the job whose first item is the largest <= i. Jobs
 // may use windows of different codes (sizes): each job carries its own LDS
@@ -1906,6 +1962,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
       __syncthreads();
     }
     if (item >= J.total) break;
+    if constexpr (!kLearn) {
+      if (J.chained) {
+        decode_chain_item<VPL, kLow>(J.chain, item, tr, J.learn, smem, J.lds, ck, J.ckpt_stride);
+        __syncthreads();
+        if (!J.work) item += gridDim.x;
+        continue;
+      }
+    }
     // pick the job with static indices only (no dynamic indexing of kernel arguments)
     gdg_job_dev jb = J.job[0];
 #pragma unroll

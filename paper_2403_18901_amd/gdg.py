@@ -29,7 +29,7 @@ EXPORTED = ["gdg_build_window", "gdg_window_free", "gdg_window_get_info", "gdg_w
             "gdg_model_create", "gdg_model_free", "gdg_mlp_infer", "gdg_learned_work_bytes",
             "gdg_decode_learned", "gdg_last_error", "gdg_decode_batch_noalloc",
             "gdg_release_scratch", "gdg_decode_osd", "gdg_link_windows", "gdg_window_edge_slots",
-            "gdg_decode_batch_warm"]
+            "gdg_decode_batch_warm", "gdg_decode_chain"]
 
 MLP_IN, MLP_H = 17, 64
 MLP_PARAMS = 5377
@@ -139,6 +139,7 @@ def lib():
         L.gdg_release_scratch.argtypes = [P]
         L.gdg_decode_osd.argtypes = [P, i32, P, i64, i32, i32, i32, i32, P, P, P, P, P, P]
         L.gdg_link_windows.argtypes = [P, P]
+        L.gdg_decode_chain.argtypes = [P, P, P, i32, i32, P, P, P, P, P, P, P, i64, P, P, P]
         L.gdg_window_edge_slots.argtypes = [P, P]
         L.gdg_decode_batch_warm.argtypes = [P, i32, P, i64, P, i64, P, i64, P, P, P, P,
                                             C.c_size_t, P, P]
@@ -415,6 +416,24 @@ class DeviceDem:
         _check(lib().gdg_sample(self.h, n_shots, seed, stream, shot0, _ptr(det), _ptr(obs),
                                 _stream()))
         return det, obs
+
+
+def decode_chain(first: Window, middle, last, n_windows: int, k_begin: torch.Tensor,
+                 k_end: torch.Tensor, det: torch.Tensor, det_off: torch.Tensor,
+                 obs: torch.Tensor, obs_off: torch.Tensor, ehat: torch.Tensor, pm: torch.Tensor,
+                 flags: torch.Tensor):
+    """gdg_decode_chain: item i decodes and commits windows k_begin[i] ..
+    k_end[i]-1 of the record at flat element offset det_off[i] of det (and the
+    observables at obs_off[i] of obs) in one launch. k_begin/k_end int32,
+    offsets int64, ehat uint8 [items, >= largest n], pm float64 and flags int32
+    [items, n_windows]."""
+    n = k_begin.shape[0]
+    assert ehat.dim() == 2 and ehat.shape[0] >= n and pm.shape[1] == n_windows
+    _check(lib().gdg_decode_chain(first.h, middle.h if middle is not None else None,
+                                  last.h if last is not None else None, n_windows, n,
+                                  _ptr(k_begin), _ptr(k_end), _ptr(det), _ptr(det_off), _ptr(obs),
+                                  _ptr(obs_off), _ptr(ehat), ehat.shape[1], _ptr(pm), _ptr(flags),
+                                  _stream()))
 
 
 def copy_rows(src: torch.Tensor, src_off: torch.Tensor, m: int, dst: torch.Tensor,

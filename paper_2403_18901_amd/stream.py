@@ -3,13 +3,15 @@
 Many logical blocks produce syndrome rounds over time; each block is decoded
 window by window (Sec. III, Eq. 6-8): window k of an experiment becomes
 decodable once its W rounds have arrived and window k - 1 has been committed.
-The service batches every decodable window -- the next window of every
-admitted experiment of every block, windows of one experiment strictly in
-order -- into persistent multi-job launches per tick (one job per code and
-window shape: first, middle, last window of an experiment; a time-uniform DEM
-gives all middle windows one graph), commits each window into its
-experiment's device-resident detector record and observable accumulator, and
-evaluates experiments that finished (Eq. 8-9).
+The service batches every decodable window of every admitted experiment of
+every block into one chained launch per code and tick: each experiment's
+workgroup decodes all its windows whose rounds have arrived, strictly in
+order, committing each into the experiment's device-resident detector record
+and observable accumulator before the next reads its syndrome
+(gdg_decode_chain; first, middle and last window shapes, a time-uniform DEM
+giving all middle windows one graph). Finished experiments are evaluated
+(Eq. 8-9). With chain=False a tick instead takes the next window of each
+experiment only, in persistent multi-job launches followed by a commit.
 
 Time is virtual: rounds arrive as a Poisson process per block in simulated
 time, and each tick advances the clock by the measured device time of its
@@ -139,9 +141,16 @@ class StreamScheduler:
         """Arrival time of the next experiment start of any block."""
         return float(self.t_first.min())
 
-    def complete(self, slots):
-        """Windows of `slots` are committed; returns the slots whose experiment ended."""
-        self.slot_k[slots] += 1
+    def chain_end(self, slots, now):
+        """One past the last window of each slot whose rounds have all arrived
+        at `now` (windows slot_k .. chain_end - 1 can be decoded in order)."""
+        arrived = (self.slot_times[slots] <= now).sum(axis=1)
+        return np.minimum(self.K, arrived - self.W + 1)
+
+    def complete(self, slots, counts=1):
+        """`counts` more windows of `slots` are committed; returns the slots
+        whose experiment ended."""
+        self.slot_k[slots] += counts
         done = slots[self.slot_k[slots] >= self.K]
         self.slot_block[done] = -1
         self.free.extend(int(x) for x in done)
@@ -181,11 +190,15 @@ class _Code:
         self.fails = []     # (experiment id, failed)
         self.obs_out = {}   # experiment id -> observable accumulator after the last commit
 
-    def slot_bytes(self):
+    def slot_bytes(self, chain=True):
         """Device bytes of one experiment slot: its detector record and
-        observable accumulator, plus the batch buffers of one in-flight window
-        (window syndrome, correction, path metric, flags, three offsets)."""
+        observable accumulator, plus its batch buffers in a tick (chained:
+        correction scratch, every window's path metric and flags, two offsets
+        and the window range; otherwise one window's syndrome, correction,
+        path metric, flags and three offsets)."""
         n = max(w.n for w in self.win.values())
+        if chain:
+            return self.n_rows + self.n_obs + n + 12 * self.K + 2 * 8 + 2 * 4
         return self.n_rows + self.n_obs + self.m + n + 8 + 4 + 3 * 8
 
     def alloc(self, n_slots):
@@ -214,11 +227,15 @@ class StreamingService:
     """
 
     def __init__(self, codes, prm, W=3, rate=1e6, n_slots=None, seed=0, plan=None,
-                 device="cuda", mem_budget=None):
+                 device="cuda", mem_budget=None, chain=True, chain_max=0):
+        """chain_max: at most this many windows of one experiment per tick in
+        the chained launch (0: every decodable one)."""
         import torch
+        self.chain = chain
+        self.chain_max = chain_max
         self.codes = [_Code(dem, nb, prm, W, rate, seed + 7919 * i, i, device)
                       for i, (dem, nb) in enumerate(codes)]
-        per = [c.slot_bytes() for c in self.codes]
+        per = [c.slot_bytes(chain) for c in self.codes]
         if n_slots is None:
             if mem_budget is None:
                 free, _ = torch.cuda.mem_get_info()   # hipMemGetInfo
@@ -263,9 +280,11 @@ class StreamingService:
         G.copy_rows(tmp_obs, src * c.n_obs, c.n_obs, c.obs, dst * c.n_obs)
 
     def tick(self):
-        """One batch: the next window of every admitted experiment whose rounds
-        have arrived. Returns the number of windows decoded (0: nothing was
-        ready at the current time)."""
+        """One batch: every decodable window of every admitted experiment
+        (chained), or the next one of each (chain=False). Returns the number
+        of windows decoded (0: nothing was ready at the current time)."""
+        if self.chain:
+            return self._tick_chain()
         import torch
         t_host = time.perf_counter()
         for c in self.codes:
@@ -332,6 +351,69 @@ class StreamingService:
             done = c.sched.complete(slots)
             if done.size:
                 self._evaluate(c, done)
+        self.batch_sizes.append(nw)
+        self.n_windows += nw
+        self.n_ticks += 1
+        self.now = done_t
+        self.host_s += time.perf_counter() - t_host - dt
+        return nw
+
+    def _tick_chain(self):
+        import torch
+        t_host = time.perf_counter()
+        for c in self.codes:
+            self._admit(c, self.now)
+        work = []   # (code, slots, first window, end)
+        for c in self.codes:
+            r = c.sched.ready(self.now)
+            if r.size:
+                kb = c.sched.slot_k[r].copy()
+                ke = c.sched.chain_end(r, self.now)
+                if self.chain_max > 0:
+                    ke = np.minimum(ke, kb + self.chain_max)
+                work.append((c, r, kb, ke))
+        if not work:
+            self.host_s += time.perf_counter() - t_host
+            return 0
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        main = torch.cuda.current_stream()
+        e0.record(main)
+        # each code's chained launch on a stream of its own (codes are
+        # independent: one code's launch drains while the other's runs)
+        for c, slots, kb, ke in work:
+            st = self.streams[c.stream_id]
+            st.wait_event(e0)
+            with torch.cuda.stream(st):
+                dev = self.device
+                n = slots.size
+                nmax = max(w.n for w in c.win.values())
+                G.decode_chain(c.win[0], c.win.get(1), c.win.get(c.K - 1), c.K,
+                               torch.from_numpy(kb.astype(np.int32)).to(dev),
+                               torch.from_numpy(ke.astype(np.int32)).to(dev), c.det,
+                               torch.from_numpy(slots * c.n_rows).to(dev), c.obs,
+                               torch.from_numpy(slots * c.n_obs).to(dev),
+                               torch.empty((n, nmax), dtype=torch.uint8, device=dev),
+                               torch.empty((n, c.K), dtype=torch.float64, device=dev),
+                               torch.empty((n, c.K), dtype=torch.int32, device=dev))
+                done = torch.cuda.Event()
+                done.record(st)
+            main.wait_event(done)
+        e1.record(main)
+        e1.synchronize()
+        dt = e0.elapsed_time(e1) * 1e-3
+        self.device_s += dt
+        done_t = self.now + dt
+        nw = 0
+        for c, slots, kb, ke in work:
+            cnt = ke - kb
+            rows = np.repeat(np.arange(slots.size), cnt)
+            ks = np.concatenate([np.arange(a, b) for a, b in zip(kb, ke)])
+            self.latencies.append(done_t - c.sched.slot_times[slots[rows], ks + c.W - 1])
+            nw += int(cnt.sum())
+            finished = c.sched.complete(slots, cnt)
+            if finished.size:
+                self._evaluate(c, finished)
         self.batch_sizes.append(nw)
         self.n_windows += nw
         self.n_ticks += 1

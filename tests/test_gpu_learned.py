@@ -201,7 +201,9 @@ def test_trained_proposer_picks_errors_more_often_than_alg1():
 def test_trained_proposer_saves_work_at_matched_ler():
     """[[144,12,12]], p = 0.002, held-out shots: the learned decoder spends
     fewer BP edge updates than plain GDG, and its failure count lies inside
-    plain GDG's 2-sigma Wilson interval."""
+    plain GDG's 2-sigma Wilson interval. Plain GDG's work is counted with a
+    trace that records only edge updates, so its path bound stays on (traces
+    of decisions or path ends turn it off)."""
     from test_gpu_parity import wilson
     G = _G()
     LRN, params = _trained()
@@ -213,9 +215,16 @@ def test_trained_proposer_saves_work_at_matched_ler():
     plain = G.SlidingWindowDecoder(dem, prm)
     det, obs = det0.clone(), obs0.clone()
     work_plain = 0
+    edges = torch.empty(n, dtype=torch.int64, device="cuda")
     for w in plain.windows:
-        e, pm, fl, tr = w.decode(det, syn_offset=w.row0, trace=True, log_cap=1)
-        work_plain += int(tr["edge_iters"].sum().item())
+        e = torch.empty((n, w.n), dtype=torch.uint8, device="cuda")
+        pm = torch.empty(n, dtype=torch.float64, device="cuda")
+        fl = torch.empty(n, dtype=torch.int32, device="cuda")
+        tr = G.Trace(None, None, 0, None, None, G._ptr(edges), None, None)
+        G._check(G.lib().gdg_decode_batch(w.h, n, G._ptr(det, w.row0), det.shape[1], G._ptr(e),
+                                           G._ptr(pm), G._ptr(fl), None, 0, G.C.byref(tr),
+                                           G._stream()))
+        work_plain += int(edges.sum().item())
         w.commit(e, det, obs)
     f_plain = int(G.evaluate(det, obs).sum().item())
     dec = LRN.LearnedSlidingWindowDecoder(dem, prm, params)

@@ -90,3 +90,44 @@ def test_stream_admission_rejects_over_budget():
     f_off, o_off = _offline(G, c, prm, ids)
     for e, f in c.fails:
         assert f == f_off[e] and np.array_equal(c.obs_out[e], o_off[e])
+
+
+@gpu
+@pytest.mark.parametrize("p", [0.002, 0.003])
+def test_chain_decode_matches_window_by_window(p):
+    """gdg_decode_chain: experiments decoded in one launch per range of
+    windows -- all of them, or split in two launches at a window chosen per
+    experiment -- leave the detector records, observable accumulators and
+    window flags exactly as the window-by-window decoder (one window object per
+    k, a launch and a commit per window) leaves them."""
+    G, _ = _mods()
+    prm = G.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=int(p <= 0.002))
+    dem = circuit_dem(get_code("144"), 12, p)
+    ns = 400
+    det, obs = syndromes(dem, sample_errors(dem.thresholds(), ns, seed=81))
+    dec = G.SlidingWindowDecoder(dem, prm)
+    K = dec.n_windows
+    d_ref, o_ref = torch.from_numpy(det).cuda(), torch.from_numpy(obs).cuda()
+    print(f"chain p={p} shots={ns}", flush=True)
+    fail, wflags = dec.decode(d_ref, o_ref)
+    first, mid, last = G.Window(dem, 0, 3, prm), G.Window(dem, 1, 3, prm), G.Window(dem, K - 1, 3, prm)
+    n_max = max(first.n, mid.n, last.n)
+    rng = np.random.default_rng(5)
+    for split in (np.full(ns, K), rng.integers(0, K + 1, ns)):
+        d = torch.from_numpy(det).cuda().reshape(-1)
+        o = torch.from_numpy(obs).cuda().reshape(-1)
+        doff = torch.arange(ns, dtype=torch.int64, device="cuda") * dem.n_rows
+        ooff = torch.arange(ns, dtype=torch.int64, device="cuda") * dem.n_obs
+        eh = torch.empty((ns, n_max), dtype=torch.uint8, device="cuda")
+        pm = torch.full((ns, K), -1.0, dtype=torch.float64, device="cuda")
+        fl = torch.full((ns, K), -1, dtype=torch.int32, device="cuda")
+        sp = torch.from_numpy(split.astype(np.int32)).cuda()
+        zero = torch.zeros(ns, dtype=torch.int32, device="cuda")
+        full = torch.full((ns,), K, dtype=torch.int32, device="cuda")
+        G.decode_chain(first, mid, last, K, zero, sp, d, doff, o, ooff, eh, pm, fl)
+        G.decode_chain(first, mid, last, K, sp, full, d, doff, o, ooff, eh, pm, fl)
+        torch.cuda.synchronize()
+        assert torch.equal(d.reshape(ns, -1), d_ref)
+        assert torch.equal(o.reshape(ns, -1), o_ref)
+        assert torch.equal(fl, wflags)
+        assert bool((pm >= 0).all())

@@ -89,3 +89,21 @@ def test_experiments_of_a_block_decode_concurrently():
     for _ in range(s.K - 1):
         s.complete(s.ready(1.0))
     assert s.active().size == 0 and len(s.free) == 8 and not any(s.pending)
+
+
+def test_chain_end_counts_the_windows_whose_rounds_arrived():
+    """Window k of an experiment needs rounds k .. k + W - 1: at a time when
+    r rounds have arrived, windows slot_k .. r - W are decodable in order
+    (capped at K), and completing several at once advances the slot by that
+    many and frees it at the end."""
+    s = StreamScheduler(n_blocks=1, n_rounds=7, W=3, rate=1e3, n_slots=2, seed=3)
+    slots, _ = s.advance_to(s.t_first[0])
+    t = s.slot_times[slots[0]]
+    assert s.chain_end(slots, t[1]).tolist() == [0]     # two rounds: nothing yet
+    assert s.chain_end(slots, t[2]).tolist() == [1]
+    assert s.chain_end(slots, t[5]).tolist() == [4]
+    assert s.chain_end(slots, t[6] + 1.0).tolist() == [5]   # K = 5
+    done = s.complete(slots, np.array([3]))
+    assert done.size == 0 and s.slot_k[slots[0]] == 3
+    done = s.complete(slots, np.array([2]))
+    assert done.tolist() == slots.tolist() and slots[0] in s.free
