@@ -227,9 +227,10 @@ class StreamingService:
     """
 
     def __init__(self, codes, prm, W=3, rate=1e6, n_slots=None, seed=0, plan=None,
-                 device="cuda", mem_budget=None, chain=True, chain_max=0):
-        """chain_max: at most this many windows of one experiment per tick in
-        the chained launch (0: every decodable one)."""
+                 device="cuda", mem_budget=None, chain=False, chain_max=0):
+        """chain: decode through chained launches (gdg_decode_chain), at most
+        chain_max windows of one experiment per tick (0: every decodable one);
+        otherwise the next window of each experiment per tick."""
         import torch
         self.chain = chain
         self.chain_max = chain_max
