@@ -800,10 +800,7 @@ int launch_with_scratch(const gdg_job* jobs, int n_jobs, int waves, const Launch
   }
   J.n_jobs = n_jobs;
   J.total = G.total;
-  if (chain) {
-    J.chained = 1;
-    J.chain = *chain;
-  }
+  if (chain) J.chain = *chain;
   if (warm) {
     if (n_jobs != 1) return fail(GDG_EINVAL, "a warm start takes a one-job launch");
     J.warm_in = warm->in;
@@ -830,7 +827,8 @@ int launch_with_scratch(const gdg_job* jobs, int n_jobs, int waves, const Launch
   J.ckpt_slots = G.slots;
   hipError_t e = gdg_launch_zero(J.work, 1, st);
   if (e != hipSuccess) return hip_fail(e, "counter reset");
-  e = gdg_launch_jobs(J, G.bucket, G.low, waves, G.grid, G.lds, tr, st);
+  e = chain ? gdg_launch_chain(J, G.bucket, G.low, waves, G.grid, G.lds, st)
+            : gdg_launch_jobs(J, G.bucket, G.low, waves, G.grid, G.lds, tr, st);
   if (e != hipSuccess) return hip_fail(e, "decode launch");
   return GDG_OK;
 }

@@ -221,8 +221,7 @@ struct gdg_jobs_dev {
   const float* warm_in;
   float* warm_out;
   long long warm_in_stride, warm_out_stride;
-  int chained;               // 1: items are experiments of `chain`
-  gdg_chain_dev chain;
+  gdg_chain_dev chain;       // the chained launch's experiments (gdg_chain_kernel)
 };
 
 // LDS plan of the BP+OSD kernel (byte offsets): fixed arrays, then one region
@@ -241,6 +240,8 @@ hipError_t gdg_launch_zero(int* p, int n, hipStream_t st);
 // The fixed device scratch of gdg_decode_batch_noalloc on the current device:
 // its address (looked up once per device) and size.
 hipError_t gdg_static_scratch(void** ptr, size_t* bytes);
+hipError_t gdg_launch_chain(const gdg_jobs_dev& J, int bucket, bool low, int waves, int grid,
+                            int lds, hipStream_t st);
 hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, bool low, int waves, int grid,
                            int lds, const gdg_trace_dev& tr, hipStream_t st);
 int gdg_kernel_bucket(int m, int n_act);

@@ -1962,14 +1962,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
       __syncthreads();
     }
     if (item >= J.total) break;
-    if constexpr (!kLearn) {
-      if (J.chained) {
-        decode_chain_item<VPL, kLow>(J.chain, item, tr, J.learn, smem, J.lds, ck, J.ckpt_stride);
-        __syncthreads();
-        if (!J.work) item += gridDim.x;
-        continue;
-      }
-    }
     // pick the job with static indices only (no dynamic indexing of kernel arguments)
     gdg_job_dev jb = J.job[0];
 #pragma unroll
@@ -1980,6 +1972,32 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
                                    jb.flags, tr, J.learn, smem, J.lds, ck, J.ckpt_stride,
                                    J.warm_in ? J.warm_in + shot * J.warm_in_stride : nullptr,
                                    J.warm_out ? J.warm_out + shot * J.warm_out_stride : nullptr);
+    __syncthreads();
+    if (!J.work) item += gridDim.x;
+  }
+}
+
+// The chained launch (gdg_decode_chain): the decode kernel's persistent loop
+// over experiments instead of shots, each item one experiment's run of
+// windows (decode_chain_item). A kernel of its own, so that the plain decode
+// kernel keeps its registers and stack.
+template <int VPL, bool kLow>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
+    kDecodeWavesPerSimd<VPL, false>, kDecodeWavesPerSimd<VPL, false>))) void gdg_chain_kernel(gdg_jobs_dev J, gdg_trace_dev tr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  char* const ck = J.ckpt && (int)blockIdx.x < J.ckpt_wgs
+                       ? J.ckpt + (long long)blockIdx.x * J.ckpt_slots * J.ckpt_stride
+                       : nullptr;
+  int item = blockIdx.x;
+  for (;;) {
+    if (J.work) {
+      if (threadIdx.x == 0) *(int*)smem = atomicAdd(J.work, 1);
+      __syncthreads();
+      item = *(volatile int*)smem;
+      __syncthreads();
+    }
+    if (item >= J.total) break;
+    decode_chain_item<VPL, kLow>(J.chain, item, tr, J.learn, smem, J.lds, ck, J.ckpt_stride);
     __syncthreads();
     if (!J.work) item += gridDim.x;
   }
@@ -2516,6 +2534,31 @@ hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, bool low, int wave
     else                                                                                   \
       hipLaunchKernelGGL((gdg_decode_kernel<V, false, false>), g, block, lds, st, J, tr);  \
     return hipGetLastError();                                                              \
+  }
+  GDG_DECODE_TILINGS(GDG_LAUNCH)
+#undef GDG_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t gdg_launch_chain(const gdg_jobs_dev& J, int bucket, bool low, int waves, int grid,
+                            int lds, hipStream_t st) {
+  dim3 g(grid), block(waves * kWave);
+  gdg_trace_dev tr{};
+  int b = 0;
+#define GDG_LAUNCH(V)                                                                    \
+  if (b++ == bucket) {                                                                   \
+    const void* f = low ? (const void*)gdg_chain_kernel<V, true>                         \
+                        : (const void*)gdg_chain_kernel<V, false>;                       \
+    if (lds > 65536) {                                                                   \
+      const hipError_t e =                                                               \
+          hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);       \
+      if (e != hipSuccess) return e;                                                     \
+    }                                                                                    \
+    if (low)                                                                             \
+      hipLaunchKernelGGL((gdg_chain_kernel<V, true>), g, block, lds, st, J, tr);         \
+    else                                                                                 \
+      hipLaunchKernelGGL((gdg_chain_kernel<V, false>), g, block, lds, st, J, tr);        \
+    return hipGetLastError();                                                            \
   }
   GDG_DECODE_TILINGS(GDG_LAUNCH)
 #undef GDG_LAUNCH

@@ -57,6 +57,7 @@ def _valid_ranking(post, order):
     ("144", 6, 0.004, 1, 0),
     ("144", 6, 0.004, 1, -2),
     ("144", 6, 0.003, 0, -2),
+    ("288", 4, 0.004, 1, -2),
 ])
 def test_osd_window_replays_bit_exact(key, rounds, p, k, n_keep):
     G = _gdg()
