@@ -306,6 +306,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved_gbs / LDS_PEAK_GBS,
             "traffic": traffic,
+            # the counted HBM bytes as a rate, against HBM's 8 TB/s
+            "traffic_gbs": traffic / mean_dec_s / 1e9 if traffic else None,
+            "traffic_frac_hbm": traffic / mean_dec_s / 8e12 if traffic else None,
             "kernel": "gdg_decode_kernel",
             "mean_launch_ms": mean_dec_s * 1e3,
             "edge_iters_per_launch": edge_iters / launches,
