@@ -679,3 +679,37 @@ def test_one_round_models(model, key):
     lo, hi = wilson(int(rf.sum()), ns)
     print(f"{model} {key}: GPU failures {int(gf.sum())}, oracle {int(rf.sum())} of {ns}")
     assert lo * ns - 1e-9 <= gf.sum() <= hi * ns + 1e-9
+
+
+@gpu
+def test_decode_edge_cases():
+    """Empty and degenerate inputs of gdg_decode_batch: no shots is a no-op; an
+    all-zero syndrome gives the empty answer with metric 0 (the preprocessing
+    meets it at once); a lone shot, and a batch one larger than the resident
+    grid, decode exactly as inside a larger batch; a row stride below the
+    window's rows is refused."""
+    g = _g()
+    p = 0.003
+    dem = c2_dem("144", 12, p)
+    w = g.Window(dem, 5, 3, g.params(**c2_params(p)))
+    e = sample_errors(dem.thresholds(), 1600, seed=83)
+    det, _ = syndromes(dem, e)
+    d = torch.from_numpy(det).cuda()
+    ref = w.decode(d, syn_offset=w.row0)
+    torch.cuda.synchronize()
+    out = w.decode(d[:0].contiguous(), syn_offset=w.row0)
+    assert out[0].shape[0] == 0
+    z = torch.zeros((3, dem.n_rows), dtype=torch.uint8, device="cuda")
+    e0, pm0, fl0 = w.decode(z, syn_offset=w.row0)
+    torch.cuda.synchronize()
+    assert not e0.any() and (pm0 == 0).all() and (fl0 == 1).all()
+    for lo, hi in ((7, 8), (0, 769), (100, 1600)):
+        part = w.decode(d[lo:hi].contiguous(), syn_offset=w.row0)
+        torch.cuda.synchronize()
+        assert torch.equal(part[0], ref[0][lo:hi]), (lo, hi)
+        assert torch.equal(part[1].view(torch.int64), ref[1][lo:hi].view(torch.int64)), (lo, hi)
+        assert torch.equal(part[2], ref[2][lo:hi]), (lo, hi)
+    eh, pm, fl = (torch.empty_like(t) for t in ref)
+    rc = g.lib().gdg_decode_batch(w.h, 4, g._ptr(d), w.m - 1, g._ptr(eh), g._ptr(pm), g._ptr(fl),
+                                  None, 0, None, g._stream())
+    assert rc == -22
