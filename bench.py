@@ -252,6 +252,20 @@ def main():
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(dem, args, nwin, c1)
 
+    # LDS accesses the counters saw per edge-iteration (wavefront LDS
+    # instructions, at most 64 lanes x 4 B each): the roofline counted from
+    # the hardware side, an upper bound on the LDS bytes moved
+    lds_counted = None
+    lpath = os.path.join(ROOT, "profiles", "decode_lds.txt")
+    if not c1 and os.path.exists(lpath):
+        with open(lpath) as f:
+            t = json.load(f)
+        if t.get("kernel_hash") == kernel_hash():
+            bpe = t["lds_instr_per_edge_iter"] * t["bytes_per_lds_instr_max"]
+            gbs = bpe * edge_iters / launches / mean_dec_s / 1e9
+            lds_counted = {"bytes_per_edge_iter_max": bpe, "gbs_max": gbs,
+                           "frac_max": gbs / LDS_PEAK_GBS}
+
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "decode_traffic.txt")
     if not c1 and os.path.exists(tpath):   # the summary covers the C2 workload
@@ -309,6 +323,7 @@ def main():
             # the counted HBM bytes as a rate, against HBM's 8 TB/s
             "traffic_gbs": traffic / mean_dec_s / 1e9 if traffic else None,
             "traffic_frac_hbm": traffic / mean_dec_s / 8e12 if traffic else None,
+            "lds_counted": lds_counted,
             "kernel": "gdg_decode_kernel",
             "mean_launch_ms": mean_dec_s * 1e3,
             "edge_iters_per_launch": edge_iters / launches,
