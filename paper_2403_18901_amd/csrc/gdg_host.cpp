@@ -882,12 +882,18 @@ int decode_batch_impl(const gdg_window* win, int32_t n_shots, const uint8_t* d_s
     if (tr.dec && tr.log_cap <= 0) return fail(GDG_EINVAL, "trace log_cap must be positive");
   }
   gdg_job job{win, n_shots, d_syndrome, syn_stride, d_ehat, d_pm, d_flags};
+  // A batch of at most one shot per CU is latency-bound: each shot's workgroup
+  // gets eight wavefronts (its sixteen paths in two rounds instead of four)
+  // when the eight-wavefront plan fits; the answers do not depend on it.
+  const int waves = (n_shots <= cu_count() && win->plans[7].total <= max_lds_per_block())
+                        ? 8
+                        : win->waves;
   if (!d_workspace)
-    return launch_jobs(&job, 1, win->waves, 0, tr, (hipStream_t)hip_stream, nullptr, warm);
+    return launch_jobs(&job, 1, waves, 0, tr, (hipStream_t)hip_stream, nullptr, warm);
   LaunchGeom G;
-  int rc = launch_geometry(&job, 1, win->waves, 0, false, G);
+  int rc = launch_geometry(&job, 1, waves, 0, false, G);
   if (rc) return rc;
-  return launch_with_scratch(&job, 1, win->waves, G, tr, (hipStream_t)hip_stream, nullptr,
+  return launch_with_scratch(&job, 1, waves, G, tr, (hipStream_t)hip_stream, nullptr,
                              d_workspace, workspace_bytes, warm);
 }
 
