@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--stream-chain", type=int, default=-1,
                     help="windows of one experiment per tick: -1 one per tick with separate "
                          "launches and commits, 0 all decodable (chained launch), n at most n")
+    ap.add_argument("--stream-decouple", type=int, default=1,
+                    help="1: each code runs its own ticks on its own stream and clock")
     ap.add_argument("--stream-waves", type=int, default=4,
                     help="wavefronts per workgroup of the streaming launches")
     ap.add_argument("--stream-mem-mib", type=float, default=0.0,
@@ -433,7 +435,8 @@ def bench_stream(args):
     budget = int(args.stream_mem_mib * 2**20) if args.stream_mem_mib > 0 else None
     import paper_2403_18901_amd.batched as BT
     chain = dict(chain=args.stream_chain >= 0, chain_max=max(args.stream_chain, 0),
-                 plan=BT.LaunchPlan(waves=args.stream_waves, wg_per_cu=0, split=True))
+                 plan=BT.LaunchPlan(waves=args.stream_waves, wg_per_cu=0, split=True),
+                 decouple=bool(args.stream_decouple))
     sat = S.StreamingService(dems, prm, rate=1e6, n_slots=None, seed=args.seed,
                              mem_budget=budget, **chain)
     rep_sat = sat.run(duration=args.stream_sat_s)
@@ -458,7 +461,8 @@ def bench_stream(args):
         "config": {"workload": f"256 x [[144,12,12]] (12 rounds) + 32 x [[288,12,18]] (18 rounds), "
                                f"circuit-level p={args.p}, g={args.g}, Poisson round arrivals, "
                                "virtual time advanced by measured device time",
-                   "blocks": 288, "chain": args.stream_chain, "waves": args.stream_waves},
+                   "blocks": 288, "chain": args.stream_chain, "waves": args.stream_waves,
+                   "decouple": bool(args.stream_decouple)},
         "saturated_1_round_per_us": dict(rep_sat, wall_s=wall_sat),
         "load_80pct": rep80,
         "load_50pct": loads[0.5],

@@ -227,13 +227,18 @@ class StreamingService:
     """
 
     def __init__(self, codes, prm, W=3, rate=1e6, n_slots=None, seed=0, plan=None,
-                 device="cuda", mem_budget=None, chain=False, chain_max=0):
+                 device="cuda", mem_budget=None, chain=False, chain_max=0, decouple=False):
         """chain: decode through chained launches (gdg_decode_chain), at most
         chain_max windows of one experiment per tick (0: every decodable one);
-        otherwise the next window of each experiment per tick."""
+        otherwise the next window of each experiment per tick. decouple: each
+        code runs its own ticks on its own stream and clock, so one code's
+        slow windows do not hold back the other's next tick."""
         import torch
+        if chain and decouple:
+            raise ValueError("decoupled ticks take the separate-launch policy")
         self.chain = chain
         self.chain_max = chain_max
+        self.decouple = decouple
         self.codes = [_Code(dem, nb, prm, W, rate, seed + 7919 * i, i, device)
                       for i, (dem, nb) in enumerate(codes)]
         per = [c.slot_bytes(chain) for c in self.codes]
@@ -256,6 +261,7 @@ class StreamingService:
         self.streams = [torch.cuda.Stream(device=device) for _ in self.codes]
         self.now = 0.0
         self.latencies = []
+        self.lat_code = []
         self.n_windows = 0
         self.n_ticks = 0
         self.device_s = 0.0
@@ -348,6 +354,7 @@ class StreamingService:
         nw = 0
         for c, win, ehat, off, obs_off, slots in commits:
             self.latencies.append(done_t - c.sched.avail_time(slots))
+            self.lat_code.append(np.full(slots.size, c.stream_id))
             nw += slots.size
             done = c.sched.complete(slots)
             if done.size:
@@ -411,6 +418,7 @@ class StreamingService:
             rows = np.repeat(np.arange(slots.size), cnt)
             ks = np.concatenate([np.arange(a, b) for a, b in zip(kb, ke)])
             self.latencies.append(done_t - c.sched.slot_times[slots[rows], ks + c.W - 1])
+            self.lat_code.append(np.full(rows.size, c.stream_id))
             nw += int(cnt.sum())
             finished = c.sched.complete(slots, cnt)
             if finished.size:
@@ -437,8 +445,112 @@ class StreamingService:
         for i, e in enumerate(ids.tolist()):
             c.obs_out[e] = o[i].copy()
 
+    def _launch_code(self, c, now):
+        """Decoupled ticks: admits and launches code c's decodable windows at
+        its own clock `now`, everything on its stream. Returns the in-flight
+        record, or None when nothing is ready."""
+        import torch
+        t_host = time.perf_counter()
+        st = self.streams[c.stream_id]
+        with torch.cuda.stream(st):
+            self._admit(c, now)
+            r = c.sched.ready(now)
+            if r.size == 0:
+                self.host_s += time.perf_counter() - t_host
+                return None
+            k_all = c.sched.slot_k[r]
+            shapes = np.where(k_all == 0, 0, np.where(k_all == c.K - 1, c.K - 1, 1))
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            jobs, cm = [], []
+            for sh in np.unique(shapes):
+                slots = r[shapes == sh]
+                win = c.win[int(sh)]
+                k = c.sched.slot_k[slots]
+                off = torch.from_numpy(slots * c.n_rows + k * c.w).to(self.device)
+                n = slots.size
+                syn = torch.empty((n, win.m), dtype=torch.uint8, device=self.device)
+                G.copy_rows(c.det, off, win.m, syn)
+                outs = (torch.empty((n, win.n), dtype=torch.uint8, device=self.device),
+                        torch.empty(n, dtype=torch.float64, device=self.device),
+                        torch.empty(n, dtype=torch.int32, device=self.device))
+                jobs.append((win, syn, 0, outs))
+                cm.append((win, outs[0], off, torch.from_numpy(slots * c.n_obs).to(self.device),
+                           slots))
+            jobs.sort(key=lambda j: -(j[0].n_paths * j[0].n_act * j[1].shape[0]))
+            for i in range(0, len(jobs), G.MAX_JOBS):
+                self.plan.run(jobs[i:i + G.MAX_JOBS])
+            for win, ehat, off, obs_off, slots in cm:
+                win.commit_indexed(ehat, c.det, off, c.obs, obs_off)
+            e1.record(st)
+        self.host_s += time.perf_counter() - t_host
+        return dict(c=c, e0=e0, e1=e1, start=now, cm=cm, keep=jobs)
+
+    def _finish_code(self, rec, clocks, duration):
+        """A decoupled tick completed: its code's clock advances by the tick's
+        device time. Ticks started past `duration` only keep the device
+        shared until every code has reached it; they are not counted."""
+        c = rec["c"]
+        dt = rec["e0"].elapsed_time(rec["e1"]) * 1e-3
+        done_t = rec["start"] + dt
+        count = rec["start"] < duration
+        nw = 0
+        for win, ehat, off, obs_off, slots in rec["cm"]:
+            if count:
+                self.latencies.append(done_t - c.sched.avail_time(slots))
+                self.lat_code.append(np.full(slots.size, c.stream_id))
+            nw += slots.size
+            done = c.sched.complete(slots)
+            if done.size:
+                self._evaluate(c, done)
+        if count:
+            self.device_s += dt
+            self.batch_sizes.append(nw)
+            self.n_windows += nw
+            self.n_ticks += 1
+        clocks[c.stream_id] = done_t
+
+    def _run_decoupled(self, duration, max_ticks=None):
+        """Each code ticks on its own stream and clock (the launches of the
+        codes overlap on the device, so each tick's measured time includes the
+        sharing). Every code keeps the device busy until all clocks have
+        passed `duration`; windows of ticks started before it are counted."""
+        clocks = [self.now] * len(self.codes)
+        inflight = {}
+        while max_ticks is None or self.n_ticks < max_ticks:
+            if all(t >= duration for t in clocks) and not inflight:
+                break
+            for c in self.codes:
+                i = c.stream_id
+                if i in inflight or all(t >= duration for t in clocks):
+                    continue
+                rec = self._launch_code(c, clocks[i])
+                if rec is not None:
+                    inflight[i] = rec
+                    continue
+                # idle: jump this code's clock to its next arrival
+                nxt = min(c.sched.next_event(), c.sched.next_start())
+                clocks[i] = max(clocks[i], min(nxt, duration) if clocks[i] < duration else nxt)
+            if not inflight:
+                continue
+            done = None
+            while done is None:   # the first launch in flight to complete
+                for i, rec in inflight.items():
+                    if rec["e1"].query():
+                        done = i
+                        break
+            self._finish_code(inflight.pop(done), clocks, duration)
+        for rec in inflight.values():
+            rec["e1"].synchronize()
+            self._finish_code(rec, clocks, duration)
+        self.now = duration
+        return self.report(duration)
+
     def run(self, duration, max_ticks=None):
         """Runs until the virtual clock passes `duration` seconds."""
+        if self.decouple:
+            return self._run_decoupled(duration, max_ticks)
         while self.now < duration and (max_ticks is None or self.n_ticks < max_ticks):
             if self.tick() == 0:
                 # idle: jump to the next arrival that can make a window ready
@@ -451,6 +563,14 @@ class StreamingService:
 
     def report(self, duration):
         lat = np.concatenate(self.latencies) if self.latencies else np.zeros(0)
+        code = np.concatenate(self.lat_code) if self.lat_code else np.zeros(0, np.int64)
+        by_code = {}
+        for c in self.codes:
+            x = lat[code == c.stream_id]
+            by_code[c.dem.name.split()[0]] = {
+                "windows": int(x.size),
+                "p50": float(np.percentile(x, 50) * 1e3) if x.size else None,
+                "p99": float(np.percentile(x, 99) * 1e3) if x.size else None}
         span = max(self.now, 1e-12)
         offered = sum(c.sched.nb * c.sched.rate * c.K / c.sched.nR for c in self.codes)
         backlog = sum(c.sched.backlog(self.now) for c in self.codes)
@@ -462,6 +582,7 @@ class StreamingService:
             "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
                            "p99": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
                            "max": float(lat.max() * 1e3) if lat.size else None},
+            "latency_ms_by_code": by_code,
             "backlog_windows": int(backlog),
             "backlog_growth_per_s": backlog / span,
             "mem_budget_bytes": int(self.mem_budget) if self.mem_budget is not None else None,

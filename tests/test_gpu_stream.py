@@ -40,7 +40,8 @@ def _oracle(c, op, ids):
 
 
 @gpu
-@pytest.mark.parametrize("chain", [(False, 0), (True, 0), (True, 2)])
+@pytest.mark.parametrize("chain", [(False, 0, False), (True, 0, False), (True, 2, False),
+                                   (False, 0, True)])
 def test_stream_matches_offline_decoder_and_oracle(chain):
     G, S = _mods()
     p = 0.003
@@ -48,7 +49,7 @@ def test_stream_matches_offline_decoder_and_oracle(chain):
     op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
     codes = [(circuit_dem(get_code("72"), 6, p), 6), (circuit_dem(get_code("144"), 4, p), 3)]
     svc = S.StreamingService(codes, prm, rate=2000.0, n_slots=64, seed=11, chain=chain[0],
-                             chain_max=chain[1])
+                             chain_max=chain[1], decouple=chain[2])
     rep = svc.run(duration=0.15)
     assert rep["rejected"] == 0 and rep["windows"] > 0
     assert max(svc.batch_sizes) > 9      # later experiments of a block decode concurrently
