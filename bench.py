@@ -371,7 +371,7 @@ def bench_mixed(args):
     plan, timings = md.tune(dets, reps=2)
     tune_s = time.perf_counter() - t
     n_windows = sum(d.n_windows for d in md.decoders) * B
-    batches = [batch(i + 1) for i in range(args.warmup + 2 * args.steps)]
+    batches = [batch(i + 1) for i in range(args.warmup + 3 * args.steps)]
     outs = md.alloc(batches[0][0])
     torch.cuda.synchronize()
     for i in range(args.warmup):
@@ -391,6 +391,18 @@ def bench_mixed(args):
             dec.decode(dets[c], obss[c])
     torch.cuda.synchronize()
     seq_s = time.perf_counter() - t0
+    # alternative: each code's whole window sequence on a stream of its own
+    # (default launch shape), the codes running concurrently
+    streams = [torch.cuda.Stream(device=dev) for _ in keys]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup + 2 * args.steps, args.warmup + 3 * args.steps):
+        dets, obss = batches[i]
+        for c, dec in enumerate(md.decoders):
+            with torch.cuda.stream(streams[c]):
+                dec.decode(dets[c], obss[c])
+    torch.cuda.synchronize()
+    streams_s = time.perf_counter() - t0
     per_code = {}
     for c, k in enumerate(keys):
         nf = int(sum(int(f[c].sum().item()) for f in fails))
@@ -409,6 +421,7 @@ def bench_mixed(args):
                    "plan": repr(plan), "autotune_s": tune_s,
                    "autotune_ms": {str(k): v for k, v in timings.items()}},
         "sequential_windows_per_s": n_windows * args.steps / seq_s,
+        "per_code_streams_windows_per_s": n_windows * args.steps / streams_s,
         "speedup_vs_sequential": seq_s / mixed_s,
         "per_code": per_code,
     }
