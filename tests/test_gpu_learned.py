@@ -236,3 +236,28 @@ def test_trained_proposer_saves_work_at_matched_ler():
     lo, hi = wilson(f_plain, n)
     assert work_learn < 0.8 * work_plain, (work_learn, work_plain)
     assert lo * n - 1e-9 <= f_learn <= hi * n + 1e-9, (f_learn, f_plain)
+
+
+@gpu
+def test_learned_with_metric_fallback_matches_plain_ler_at_p003():
+    """[[144,12,12]] at p = 0.003 (Alg. 3 on), held-out shots: with the plain
+    16-path tree also run whenever the best learned path metric exceeds 60,
+    the learned decoder's failures lie inside plain GDG's 2-sigma Wilson
+    interval (without it they do not: the proposer's converged answers are
+    worse more often at this rate)."""
+    from test_gpu_parity import wilson
+    G = _G()
+    LRN, params = _trained()
+    p = 0.003
+    dem = circuit_dem(get_code("144"), 12, p)
+    prm = G.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
+    n = 20000
+    det0, obs0 = G.DeviceDem(dem).sample(n, seed=9191, stream=6)
+    f_plain, _ = G.SlidingWindowDecoder(dem, prm).decode(det0.clone(), obs0.clone())
+    dec = LRN.LearnedSlidingWindowDecoder(dem, prm, params, pm_fallback=60.0)
+    f_learn, _ = dec.decode(det0.clone(), obs0.clone())
+    fp, fl = int(f_plain.sum().item()), int(f_learn.sum().item())
+    lo, hi = wilson(fp, n)
+    print(f"p=0.003: plain {fp}, learned with metric fallback {fl} of {n}")
+    assert fp >= 50
+    assert lo * n - 1e-9 <= fl <= hi * n + 1e-9, (fl, fp)
