@@ -269,6 +269,13 @@ def main():
             gbs = bpe * edge_iters / launches / mean_dec_s / 1e9
             lds_counted = {"bytes_per_edge_iter_max": bpe, "gbs_max": gbs,
                            "frac_max": gbs / LDS_PEAK_GBS}
+            if "valu_instr_per_edge_iter" in t:
+                # VALU issue: a wavefront instruction holds a 16-lane SIMD for
+                # four clocks; 1024 SIMDs at 2.4 GHz
+                ipe = t["valu_instr_per_edge_iter"]
+                rate = ipe * edge_iters / launches / mean_dec_s
+                lds_counted["valu_instr_per_edge_iter"] = ipe
+                lds_counted["valu_issue_frac"] = rate * 4 / (1024 * 2.4e9)
 
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "decode_traffic.txt")
