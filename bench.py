@@ -68,8 +68,9 @@ def parse():
                          "launches and commits, 0 all decodable (chained launch), n at most n")
     ap.add_argument("--stream-decouple", type=int, default=1,
                     help="1: each code runs its own ticks on its own stream and clock")
-    ap.add_argument("--stream-waves", type=int, default=4,
-                    help="wavefronts per workgroup of the streaming launches")
+    ap.add_argument("--stream-waves", default="4,8",
+                    help="wavefronts per workgroup of the streaming launches: one count, "
+                         "or one per code ([[144]],[[288]]), e.g. 4,8")
     ap.add_argument("--stream-mem-mib", type=float, default=0.0,
                     help="device memory budget of the streaming service's experiment "
                          "slots in MiB (0: a quarter of the free memory, at most 1 GiB)")
@@ -454,8 +455,13 @@ def bench_stream(args):
     t = time.perf_counter()
     budget = int(args.stream_mem_mib * 2**20) if args.stream_mem_mib > 0 else None
     import paper_2403_18901_amd.batched as BT
+    waves = [int(x) for x in str(args.stream_waves).split(",")]
+    if len(waves) == 1:
+        waves = waves * len(dems)
+    if len(waves) != len(dems) or any(w not in (2, 4, 8) for w in waves):
+        raise SystemExit("--stream-waves: 2, 4 or 8, once or once per code")
     chain = dict(chain=args.stream_chain >= 0, chain_max=max(args.stream_chain, 0),
-                 plan=BT.LaunchPlan(waves=args.stream_waves, wg_per_cu=0, split=True),
+                 plan=[BT.LaunchPlan(waves=w, wg_per_cu=0, split=True) for w in waves],
                  decouple=bool(args.stream_decouple))
     sat = S.StreamingService(dems, prm, rate=1e6, n_slots=None, seed=args.seed,
                              mem_budget=budget, **chain)
@@ -481,7 +487,7 @@ def bench_stream(args):
         "config": {"workload": f"256 x [[144,12,12]] (12 rounds) + 32 x [[288,12,18]] (18 rounds), "
                                f"circuit-level p={args.p}, g={args.g}, Poisson round arrivals, "
                                "virtual time advanced by measured device time",
-                   "blocks": 288, "chain": args.stream_chain, "waves": args.stream_waves,
+                   "blocks": 288, "chain": args.stream_chain, "waves": waves,
                    "decouple": bool(args.stream_decouple)},
         "saturated_1_round_per_us": dict(rep_sat, wall_s=wall_sat),
         "load_80pct": rep80,

@@ -255,8 +255,12 @@ class StreamingService:
             else:
                 c.alloc(max(1, int(mem_budget * (c.n_blocks * b / demand) // b)))
         # one persistent launch per register tiling: windows of a small code do
-        # not run in a larger code's tiling and LDS share
-        self.plan = plan or B.LaunchPlan(waves=4, wg_per_cu=0, split=True)
+        # not run in a larger code's tiling and LDS share; `plan` is one
+        # LaunchPlan for every code or a list of them, one per code
+        plan = plan or B.LaunchPlan(waves=4, wg_per_cu=0, split=True)
+        self.plans = list(plan) if isinstance(plan, (list, tuple)) else [plan] * len(self.codes)
+        if len(self.plans) != len(self.codes):
+            raise ValueError("one launch plan per code")
         self.device = device
         self.streams = [torch.cuda.Stream(device=device) for _ in self.codes]
         self.now = 0.0
@@ -339,7 +343,7 @@ class StreamingService:
                     cm.append((c, win, outs[0], off, obs_off, slots))
                 jobs.sort(key=lambda j: -(j[0].n_paths * j[0].n_act * j[1].shape[0]))
                 for i in range(0, len(jobs), G.MAX_JOBS):
-                    self.plan.run(jobs[i:i + G.MAX_JOBS])
+                    self.plans[c.stream_id].run(jobs[i:i + G.MAX_JOBS])
                 for cc, win, ehat, off, obs_off, slots in cm:
                     win.commit_indexed(ehat, cc.det, off, cc.obs, obs_off)
                 done = torch.cuda.Event()
@@ -480,7 +484,7 @@ class StreamingService:
                            slots))
             jobs.sort(key=lambda j: -(j[0].n_paths * j[0].n_act * j[1].shape[0]))
             for i in range(0, len(jobs), G.MAX_JOBS):
-                self.plan.run(jobs[i:i + G.MAX_JOBS])
+                self.plans[c.stream_id].run(jobs[i:i + G.MAX_JOBS])
             for win, ehat, off, obs_off, slots in cm:
                 win.commit_indexed(ehat, c.det, off, c.obs, obs_off)
             e1.record(st)

@@ -41,18 +41,25 @@ def _oracle(c, op, ids):
 
 @gpu
 @pytest.mark.parametrize("chain", [(False, 0, False), (True, 0, False), (True, 2, False),
-                                   (False, 0, True)])
+                                   (False, 0, True), (False, 0, True, (8, 4))])
 def test_stream_matches_offline_decoder_and_oracle(chain):
+    """(chained, windows per tick, decoupled ticks[, wavefronts per shot of each code])"""
     G, S = _mods()
+    import paper_2403_18901_amd.batched as B
     p = 0.003
     prm = G.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
     op = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=0)
     codes = [(circuit_dem(get_code("72"), 6, p), 6), (circuit_dem(get_code("144"), 4, p), 3)]
+    plan = ([B.LaunchPlan(waves=w, wg_per_cu=0, split=True) for w in chain[3]]
+            if len(chain) > 3 else None)
     svc = S.StreamingService(codes, prm, rate=2000.0, n_slots=64, seed=11, chain=chain[0],
-                             chain_max=chain[1], decouple=chain[2])
+                             chain_max=chain[1], decouple=chain[2], plan=plan)
     rep = svc.run(duration=0.15)
     assert rep["rejected"] == 0 and rep["windows"] > 0
-    assert max(svc.batch_sizes) > 9      # later experiments of a block decode concurrently
+    # later experiments of a block decode concurrently: a tick holds more
+    # windows than there are blocks (a decoupled tick holds one code's only)
+    blocks = [nb for _, nb in codes]
+    assert max(svc.batch_sizes) > (max(blocks) if chain[2] else sum(blocks))
     for c in svc.codes:
         assert len(c.fails) >= 30
         ids = np.array([e for e, _ in c.fails])
