@@ -1879,9 +1879,12 @@ __device__ __attribute__((noinline)) void decode_shot(const gdg_win_dev& wref, c
 
 // Commit of one shot's window correction (Eqs. 7-9) by the whole workgroup:
 // every DEM row the committed columns touch flips where their XOR is 1, and
-// likewise every observable. det_rel[row] is the shot's detector of DEM row
-// `row` (the record shifted by the window object's own first row).
-__device__ __forceinline__ void commit_shot(const gdg_commit_dev& cm, const uint8_t* ehat,
+// likewise every observable. The correction is read from its window bitmask,
+// which the decode leaves in LDS (ebits); a row's column indices are loaded
+// four at a time so that their global loads overlap. det_rel[row] is the
+// shot's detector of DEM row `row` (the record shifted by the window object's
+// own first row).
+__device__ __forceinline__ void commit_shot(const gdg_commit_dev& cm, const uint32_t* ebits,
                                             uint8_t* det_rel, uint8_t* obs) {
   for (int r = threadIdx.x; r < cm.n_rows + cm.n_obs; r += blockDim.x) {
     const bool is_row = r < cm.n_rows;
@@ -1890,7 +1893,14 @@ __device__ __forceinline__ void commit_shot(const gdg_commit_dev& cm, const uint
     const int t1 = is_row ? cm.row_ptr[r + 1] : cm.obs_ptr[o + 1];
     const int* cols = is_row ? cm.row_col : cm.obs_col;
     uint32_t x = 0u;
-    for (int t = t0; t < t1; ++t) x ^= ehat[cols[t]] & 1u;
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+      const int c0 = cols[t], c1 = cols[t + 1], c2 = cols[t + 2], c3 = cols[t + 3];
+      x ^= (ebits[c0 >> 5] >> (c0 & 31)) ^ (ebits[c1 >> 5] >> (c1 & 31)) ^
+           (ebits[c2 >> 5] >> (c2 & 31)) ^ (ebits[c3 >> 5] >> (c3 & 31));
+    }
+    for (; t < t1; ++t) x ^= ebits[cols[t] >> 5] >> (cols[t] & 31);
+    x &= 1u;
     if (!x) continue;
     if (is_row)
       det_rel[cm.row_global[r]] ^= 1;
@@ -1923,12 +1933,13 @@ __device__ __forceinline__ void decode_chain_item(
                                   C.flags + (long long)item * C.K + k, tr, lrn, smem, lds_alloc,
                                   ck, ck_stride, nullptr, nullptr);
     __syncthreads();
+    const uint32_t* ebits = (const uint32_t*)(smem + lp->obits);
     if (first)
-      commit_shot(C.cm[0], eh, C.det + base - row0, obs);
+      commit_shot(C.cm[0], ebits, C.det + base - row0, obs);
     else if (last)
-      commit_shot(C.cm[2], eh, C.det + base - row0, obs);
+      commit_shot(C.cm[2], ebits, C.det + base - row0, obs);
     else
-      commit_shot(C.cm[1], eh, C.det + base - row0, obs);
+      commit_shot(C.cm[1], ebits, C.det + base - row0, obs);
     __syncthreads();
   }
 }
@@ -2331,24 +2342,29 @@ __global__ __launch_bounds__(256) void gdg_commit_kernel(
     uint8_t* __restrict__ det, long long det_stride, uint8_t* __restrict__ obs,
     long long obs_stride, const long long* __restrict__ det_off,
     const long long* __restrict__ obs_off, int row0) {
-  // spw shots per workgroup: their correction bytes are staged in LDS with
-  // coalesced loads, then each thread folds whole rows / observables for all
-  // of them (one read of the row's column list serves every shot)
+  // spw <= 8 shots per workgroup: their corrections are staged in LDS
+  // transposed, bit q of es[c] holding column c of shot s0 + q (coalesced
+  // loads of four columns of each shot at a time), then each thread folds
+  // whole rows / observables for all of them with one LDS byte per column
+  // (one read of the row's column list serves every shot)
   extern __shared__ __align__(16) unsigned char es[];
-  const int nw = (cm.n_win + 15) & ~15;
   const int s0 = blockIdx.x * spw;
   const int ns = min(spw, n_shots - s0);
   if (ns <= 0) return;
   if ((cm.n_win & 3) == 0 && (((uintptr_t)ehat) & 3) == 0) {
     const int n4 = cm.n_win / 4;
-    for (int q = 0; q < ns; ++q) {
-      const uint32_t* e4 = (const uint32_t*)(ehat + (long long)(s0 + q) * cm.n_win);
-      for (int c = threadIdx.x; c < n4; c += blockDim.x) ((uint32_t*)(es + q * nw))[c] = e4[c];
+    for (int c = threadIdx.x; c < n4; c += blockDim.x) {
+      uint32_t x = 0u;
+      for (int q = 0; q < ns; ++q)
+        x |= (((const uint32_t*)(ehat + (long long)(s0 + q) * cm.n_win))[c] & 0x01010101u) << q;
+      ((uint32_t*)es)[c] = x;
     }
   } else {
-    for (int q = 0; q < ns; ++q) {
-      const uint8_t* e = ehat + (long long)(s0 + q) * cm.n_win;
-      for (int c = threadIdx.x; c < cm.n_win; c += blockDim.x) es[q * nw + c] = e[c];
+    for (int c = threadIdx.x; c < cm.n_win; c += blockDim.x) {
+      uint32_t x = 0u;
+      for (int q = 0; q < ns; ++q)
+        x |= (uint32_t)(ehat[(long long)(s0 + q) * cm.n_win + c] & 1u) << q;
+      es[c] = (uint8_t)x;
     }
   }
   __syncthreads();
@@ -2359,10 +2375,7 @@ __global__ __launch_bounds__(256) void gdg_commit_kernel(
     const int t1 = is_row ? cm.row_ptr[r + 1] : cm.obs_ptr[o + 1];
     const int* cols = is_row ? cm.row_col : cm.obs_col;
     uint32_t xm = 0u;   // bit q: the parity for shot s0 + q
-    for (int t = t0; t < t1; ++t) {
-      const int c = cols[t];
-      for (int q = 0; q < ns; ++q) xm ^= (uint32_t)(es[q * nw + c] & 1u) << q;
-    }
+    for (int t = t0; t < t1; ++t) xm ^= es[cols[t]];
     for (int q = 0; q < ns; ++q) {
       if (!((xm >> q) & 1u)) continue;
       const int shot = s0 + q;
@@ -2635,12 +2648,12 @@ hipError_t gdg_launch_commit(const gdg_commit_dev& cm, int n_shots, const uint8_
                              long long obs_stride, const long long* det_off,
                              const long long* obs_off, int row0, hipStream_t st) {
   if (n_shots <= 0 || cm.n_rows + cm.n_obs == 0) return hipSuccess;
-  // up to 8 shots per workgroup within 32 KiB of staged corrections (a
-  // window has at most 65535 columns: one shot then, within the default limit)
+  // 8 shots per workgroup, one staged byte per window column (a window has
+  // at most 65535 columns: within the default LDS limit)
   const size_t nw = ((size_t)cm.n_win + 15) & ~(size_t)15;
-  const int spw = (int)std::max<size_t>(1, std::min<size_t>(8, 32768 / nw));
+  const int spw = 8;
   const unsigned nb = (unsigned)((n_shots + spw - 1) / spw);
-  hipLaunchKernelGGL(gdg_commit_kernel, dim3(nb), dim3(256), (size_t)spw * nw, st, cm, n_shots,
+  hipLaunchKernelGGL(gdg_commit_kernel, dim3(nb), dim3(256), nw, st, cm, n_shots,
                      spw, ehat, det, det_stride, obs, obs_stride, det_off, obs_off, row0);
   return hipGetLastError();
 }

@@ -82,10 +82,12 @@ def test_device_sampler_bit_exact(model):
 
 
 @gpu
-@pytest.mark.parametrize("ns", [64, 61, 1])
-def test_commit_matches_integer_reference(ns):
+@pytest.mark.parametrize("ns,shift", [(64, 0), (61, 0), (1, 0), (61, 1)])
+def test_commit_matches_integer_reference(ns, shift):
     """Bit-exact against H and L over GF(2); shot counts that fill the
-    kernel's groups of shots exactly, leave a ragged last group, or are one."""
+    kernel's groups of shots exactly, leave a ragged last group, or are one;
+    corrections read four columns at a time, or byte by byte from a buffer
+    that starts off a four-byte boundary (shift)."""
     g = _g()
     dem = c2_dem("72", 6, 0.003)
     prm = g.params(**c2_params(0.003))
@@ -97,7 +99,10 @@ def test_commit_matches_integer_reference(ns):
         det = rng.integers(0, 2, (ns, dem.n_rows)).astype(np.uint8)
         obs = rng.integers(0, 2, (ns, dem.n_obs)).astype(np.uint8)
         dt, ot = torch.from_numpy(det).cuda(), torch.from_numpy(obs).cuda()
-        w.commit(torch.from_numpy(ehat).cuda(), dt, ot)
+        buf = torch.zeros(ns * w.n + shift, dtype=torch.uint8, device="cuda")
+        e_dev = buf[shift:].view(ns, w.n)
+        e_dev.copy_(torch.from_numpy(ehat))
+        w.commit(e_dev, dt, ot)
         torch.cuda.synchronize()
         H = dem.dense_h().astype(np.int64)
         L = dem.dense_l().astype(np.int64)
