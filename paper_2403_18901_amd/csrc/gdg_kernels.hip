@@ -489,16 +489,27 @@ __device__ __forceinline__ void set_status_uniform(PathCtx<VPL>& P, int v, int v
     }
 }
 
-// Whether the priors of the path's VNs fixed to 1 (decimated or peeled) sum
-// past the stopping threshold *thr (+infinity until a path has converged).
+// Whether a lower bound on the path's final Eq. 5 metric passes the stopping
+// threshold *thr (+infinity until a path has converged): the priors of its
+// VNs fixed to 1 (decimated or peeled; they stay 1 in its answer), plus, while
+// the residual syndrome has an unsatisfied row, the least prior of its active
+// VNs (an answer that meets a non-zero residual syndrome sets at least one of
+// them; +infinity when none is left, and such a path cannot converge).
 template <int VPL>
 __device__ __forceinline__ bool over_bound(const PathCtx<VPL>& P, int* thr) {
   const float t = __int_as_float(
       __builtin_amdgcn_readfirstlane(__hip_atomic_load(thr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)));
-  float lb = 0.0f;
+  float lb = 0.0f, mn = kInfF;
 #pragma unroll
-  for (int r = 0; r < VPL; ++r) lb += P.st(r) == 1 ? P.llr[r] : 0.0f;
-  return t < kInfF && wave_sum_f32(lb) > t;
+  for (int r = 0; r < VPL; ++r) {
+    lb += P.st(r) == 1 ? P.llr[r] : 0.0f;
+    const bool act = P.lane + kWave * r < P.n && P.st(r) < 0;
+    mn = act ? fminf(mn, P.llr[r]) : mn;
+  }
+  float lower = wave_sum_f32(lb);
+  if (wave_any(P.sres != 0u))
+    lower += __uint_as_float((uint32_t)wave_min_u64((unsigned long long)__float_as_uint(mn)));
+  return t < kInfF && lower > t;
 }
 
 // Peeling closure in synchronous rounds. Returns false on a contradiction
@@ -1345,8 +1356,9 @@ __device__ __attribute__((noinline)) void decode_shot(const gdg_win_dev& wref, c
       const bool share = !learned && ck != nullptr && n_tree > 1 && w.extra > 0;
       // Branch and bound over the paths: with positive priors a path's Eq. 5
       // metric is at least the sum of the priors of its VNs fixed to 1 (they
-      // stay 1 in its answer), so a path whose sum already exceeds a converged
-      // path's metric cannot be the answer and stops. The comparison is in
+      // stay 1 in its answer), plus the least active prior while its residual
+      // syndrome is non-zero (see over_bound), so a path whose bound already
+      // exceeds a converged path's metric cannot be the answer and stops. The comparison is in
       // FP32 against the metric widened by 2e-5, far above the rounding of
       // either side; the answer, its metric and the flags are unchanged (a
       // stop needs a converged path; a learned answer's fallback test reads

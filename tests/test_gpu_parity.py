@@ -576,8 +576,9 @@ def test_pipeline_c2_ler_parity(p, ns):
 @gpu
 @pytest.mark.parametrize("p,k", [(0.002, 0), (0.002, 5), (0.003, 5)])
 def test_path_bound_changes_no_answer(p, k):
-    """The bound that stops paths early (a path whose priors fixed to 1 already
-    sum past a converged path's Eq. 5 metric) is off when per-path traces are
+    """The bound that stops paths early (a path whose priors fixed to 1, plus
+    the least active prior while its residual syndrome is non-zero, already
+    pass a converged path's Eq. 5 metric) is off when per-path traces are
     asked for: the traced decode is the unbounded reference. Both decodes must
     give the same answer, metric and flags on every shot, the bounded one with
     no more BP work, and at this size it must have stopped some path."""

@@ -493,6 +493,93 @@ def test_decided_ones_bound_the_path_metric():
     assert checked > 0
 
 
+def test_path_bound_by_brute_force():
+    """The path bound's lower bound against exhaustive search on tiny random
+    instances: with VNs fixed to 1 (F1), fixed to 0, and the rest active (A),
+    the cheapest answer meeting the syndrome that keeps the fixed values costs
+    at least sum(F1) + [residual syndrome non-zero] * min(A); the bound is
+    attained on some instances of both kinds, so a larger added term (the
+    largest active prior, or the least one added while the residual syndrome
+    is already met) fails."""
+    rng = np.random.default_rng(17)
+    tight_res, tight_zero, n_cases = 0, 0, 0
+    for _ in range(400):
+        m, n = int(rng.integers(2, 5)), int(rng.integers(3, 8))
+        H = (rng.random((m, n)) < 0.5).astype(np.int64)
+        prior = rng.uniform(0.5, 9.0, n)
+        state = rng.integers(-1, 2, n)              # -1 active, 0 / 1 fixed
+        act = np.nonzero(state < 0)[0]
+        if act.size == 0:
+            continue
+        f1 = np.nonzero(state == 1)[0]
+        e_true = rng.integers(0, 2, n)
+        e_true[state >= 0] = state[state >= 0]        # consistent: an answer exists
+        syn = H @ e_true % 2
+        best = np.inf
+        for mask in range(1 << act.size):
+            e = (state == 1).astype(np.int64)
+            e[act[[(mask >> j) & 1 == 1 for j in range(act.size)]]] = 1
+            if ((H @ e) % 2 == syn).all():
+                best = min(best, prior[e == 1].sum())
+        res = (syn + H[:, f1].sum(axis=1)) % 2
+        lower = prior[f1].sum() + (prior[act].min() if res.any() else 0.0)
+        assert best >= lower - 1e-12
+        n_cases += 1
+        if abs(best - lower) <= 1e-12:
+            if res.any():
+                tight_res += 1
+            else:
+                tight_zero += 1
+    assert n_cases > 300 and tight_res > 0 and tight_zero > 0
+
+
+def test_unsatisfied_residual_adds_the_least_active_prior():
+    """The second term of the path bound: at a step where the VNs a path has
+    fixed to 1 (decimated or peeled) leave a non-zero residual syndrome, the
+    path's answer, if it converges, sets at least one more VN, and only VNs
+    still active can change; so its Eq. 5 metric is at least the fixed-to-1
+    priors plus the least prior of the active VNs. Checked at every step of
+    every converged path of the oracle's 16-path tree: the active VNs of a
+    step are those with an Alg. 1 key, the fixed ones keep their value in the
+    answer, and the residual syndrome is formed from the window matrix."""
+    dem = circuit_dem(get_code("72"), 6, 0.004)
+    prm = O.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=1, dmax_main=25,
+                   extra_steps=10)
+    e = sample_errors(dem.thresholds(), 80, seed=5)
+    det, _ = syndromes(dem, e)
+    w = O.OracleWindow(dem, 0, 3)
+    ex = w.export()
+    H, llr = ex["H"].astype(np.int64), ex["llr"]
+    syn = np.ascontiguousarray(det[:, w.row0:w.row0 + w.m])
+    out = w.decode(prm, syn, logs=True)
+    checked = tight = 0
+    for s in range(syn.shape[0]):
+        if out["ends"][s, :, 1].max() == 0:
+            continue
+        sel = out["sel"][s]
+        for p in range(out["dec"].shape[1]):
+            d = out["dec"][s, p]
+            steps = int((d[:, 0] >= 0).sum())
+            r = w.replay(prm, syn[s], sel, p, d[:steps, 0], d[:steps, 1])
+            if r["end"] != 1:
+                continue
+            cols = sel[sel >= 0]
+            for D in range(r["steps"]):
+                keys = r["step_lsum"][D][:cols.size]
+                if np.isnan(keys).all():
+                    continue          # the step converged: no key recorded
+                active = ~np.isnan(keys)
+                fixed1 = cols[~active][r["e"][cols[~active]] == 1]
+                res = (syn[s].astype(np.int64) + H[:, fixed1].sum(axis=1)) % 2
+                lower = llr[fixed1].sum()
+                if res.any():
+                    lower += llr[cols[active]].min()
+                    tight += 1
+                assert r["pm"] >= lower * (1 - 1e-12), (s, p, D)
+                checked += 1
+    assert checked > 0 and tight > 0
+
+
 @pytest.mark.parametrize("W,F", [(3, 1), (4, 1), (5, 2), (4, 3)])
 def test_wf_windows_commit_every_column_once(W, F):
     """(W,F) sliding windows (Sec. III; App. E): window k holds rounds
