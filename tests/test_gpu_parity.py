@@ -688,6 +688,43 @@ def test_one_round_models(model, key):
 
 
 @gpu
+def test_zero_sized_calls_are_noops():
+    """Calls with no shots, items or rows return success without a launch and
+    leave every buffer as it was: the commits, the row copy, the comparator,
+    the warm-start decode and the chained launch; negative counts are refused."""
+    g = _g()
+    dem = c2_dem("72", 6, 0.003)
+    prm = g.params(**c2_params(0.003))
+    K = g.SlidingWindowDecoder(dem, prm, W=3).n_windows
+    first, mid, last = (g.Window(dem, k, 3, prm) for k in (0, 1, K - 1))
+    L = g.lib()
+    det = torch.randint(0, 2, (4, dem.n_rows), dtype=torch.uint8, device="cuda")
+    obs = torch.randint(0, 2, (4, dem.n_obs), dtype=torch.uint8, device="cuda")
+    d0, o0 = det.clone(), obs.clone()
+    eh = torch.zeros((4, first.n), dtype=torch.uint8, device="cuda")
+    off = torch.zeros(4, dtype=torch.int64, device="cuda")
+    pm = torch.zeros((4, K), dtype=torch.float64, device="cuda")
+    fl = torch.zeros((4, K), dtype=torch.int32, device="cuda")
+    kk = torch.zeros(4, dtype=torch.int32, device="cuda")
+    st = g._stream()
+    P = g._ptr
+    assert L.gdg_commit(first.h, 0, P(eh), P(det), det.shape[1], P(obs), obs.shape[1], st) == 0
+    assert L.gdg_commit_indexed(first.h, 0, P(eh), P(det), P(off), P(obs), P(off), st) == 0
+    assert L.gdg_copy_rows(0, dem.n_rows, P(det), P(off), P(det), P(off), st) == 0
+    assert L.gdg_decode_osd(first.h, 0, P(det), det.shape[1], 10, 1, 10, 0, P(eh), P(pm), P(fl),
+                            None, None, st) == 0
+    assert L.gdg_decode_batch_warm(first.h, 0, P(det), det.shape[1], None, 0, None, 0, P(eh),
+                                   P(pm), P(fl), None, 0, None, st) == 0
+    assert L.gdg_decode_chain(first.h, mid.h, last.h, K, 0, P(kk), P(kk), P(det), P(off), P(obs),
+                              P(off), P(eh), eh.shape[1], P(pm), P(fl), st) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(det, d0) and torch.equal(obs, o0)
+    assert L.gdg_commit(first.h, -1, P(eh), P(det), det.shape[1], P(obs), obs.shape[1], st) == -22
+    assert L.gdg_decode_chain(first.h, mid.h, last.h, K, -1, P(kk), P(kk), P(det), P(off), P(obs),
+                              P(off), P(eh), eh.shape[1], P(pm), P(fl), st) == -22
+
+
+@gpu
 def test_decode_edge_cases():
     """Empty and degenerate inputs of gdg_decode_batch: no shots is a no-op; an
     all-zero syndrome gives the empty answer with metric 0 (the preprocessing
