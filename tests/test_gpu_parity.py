@@ -615,6 +615,25 @@ def test_path_bound_changes_no_answer(p, k):
 # ------------------------------------------------------------ other window shapes and models
 
 @gpu
+def test_window_build_refuses_unsupported_shapes():
+    """gdg_build_window refuses, with an error and nothing built: a window of
+    more than 512 rows ((4,1) on [[288,12,18]]: 576, GDG_ESHAPE), F above W,
+    F below 1, and a first round past the DEM's last round, the final readout
+    included (GDG_EINVAL)."""
+    g = _g()
+    prm = g.params(**c2_params(0.002))
+    big = c2_dem("288", 6, 0.002)
+    with pytest.raises(RuntimeError, match="error -34"):
+        g.Window(big, 0, 4, prm, F=1)
+    dem = c2_dem("72", 6, 0.002)
+    for k, W, F in ((0, 3, 4), (0, 3, 0), (dem.n_rounds, 3, 1)):
+        with pytest.raises(RuntimeError, match="error -22"):
+            g.Window(dem, k, W, prm, F=F)
+    w = g.Window(dem, 0, 3, prm)   # the library is still usable afterwards
+    assert w.m == 3 * 36
+
+
+@gpu
 @pytest.mark.parametrize("W,F,k", [(4, 1, 0), (4, 1, 4), (5, 2, 0), (5, 2, 2), (5, 2, 4)])
 def test_window_decode_wf(W, F, k):
     """(4,1) and (5,2) sliding windows (App. E) of [[144,12,12]] at p = 0.003
