@@ -2552,7 +2552,9 @@ hipError_t gdg_launch_jobs(const gdg_jobs_dev& J, int bucket, bool low, int wave
   int b = 0;
 #define GDG_LAUNCH(V)                                                                      \
   if (b++ == bucket) {                                                                     \
-    if (learn)                                                                             \
+    if (learn && low)                                                                      \
+      hipLaunchKernelGGL((gdg_decode_kernel<V, true, true>), g, block, lds, st, J, tr);    \
+    else if (learn)                                                                        \
       hipLaunchKernelGGL((gdg_decode_kernel<V, true, false>), g, block, lds, st, J, tr);   \
     else if (low)                                                                          \
       hipLaunchKernelGGL((gdg_decode_kernel<V, false, true>), g, block, lds, st, J, tr);   \
