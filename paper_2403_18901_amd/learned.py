@@ -12,9 +12,10 @@ the learned paths cannot satisfy, so every committed correction still meets
 its window syndrome when plain GDG's would.
 
 Training data comes from the project's own sampler: shots at noise levels p
-drawn from a range, decoded with plain GDG in record mode on their first
-window; each recorded candidate is labelled with the sampled error bit of
-its DEM column. The network is trained on the GPU with the library's FP32
+drawn from a range, decoded with plain GDG in record mode on one of their
+windows (the earlier ones decoded and committed first); each recorded
+candidate is labelled with the sampled error bit of its DEM column, or for a
+unit column with the parity of the merged columns' errors on its row. The network is trained on the GPU with the library's FP32
 forward/backward kernels and Adam.
 """
 from __future__ import annotations
@@ -41,20 +42,57 @@ def init_params(seed: int) -> torch.Tensor:
     return torch.from_numpy(p.astype(np.float32)).cuda()
 
 
+def unit_column_sources(dem, src: np.ndarray, row0: int) -> dict:
+    """For each unit column of a window (the columns reaching past its last
+    round, merged per last-round row they touch; Sec. III), the DEM columns
+    merged into it: those touching that row that start inside the window and
+    are not window columns themselves. src: the window's column table (DEM
+    column, or -1 - local row for a unit column); row0: its first DEM row.
+    Keyed by the unit column's local row."""
+    src = np.asarray(src)
+    own = np.zeros(dem.n_cols, bool)
+    own[src[src >= 0]] = True
+    first = dem.first_round()
+    k_round = row0 // dem.w
+    edge_col = np.repeat(np.arange(dem.n_cols), np.diff(np.asarray(dem.h_ptr)))
+    edge_row = np.asarray(dem.h_idx)
+    keep = ~own[edge_col] & (first[edge_col] >= k_round)
+    out = {}
+    for r in (-1 - src[src < 0]).tolist():
+        out[r] = np.unique(edge_col[keep & (edge_row == row0 + r)]).astype(np.int64)
+    return out
+
+
 def record(dem, prm: G.Params, n_shots: int, seed: int, stream: int = 0, rec_steps: int = 8,
-           chunk: int = 20000):
+           chunk: int = 20000, window: int = 0):
     """Features x [N, 17] and labels y [N] (float 0/1) of the candidates met on
-    the plain main path of window 0 of n_shots sampled shots."""
+    the plain main path of window `window` of n_shots sampled shots (the
+    earlier windows decoded with plain GDG and committed first). A candidate's
+    label is the sampled error bit of its DEM column; for a unit column, the
+    parity of the errors of the columns merged into it on its row (Alg. 1
+    offers only VNs of degree 3 or more and unit columns have degree 1, so
+    this case arises only if candidates are ever drawn more widely)."""
     dev = torch.device("cuda")
-    win = G.Window(dem, 0, 3, prm)
-    src = torch.from_numpy(win.columns()[0].astype(np.int64)).to(dev)
+    wins = [G.Window(dem, k, 3, prm) for k in range(window + 1)]
+    win = wins[window]
+    src_np = win.columns()[0].astype(np.int64)
+    src = torch.from_numpy(src_np).to(dev)
+    units = unit_column_sources(dem, src_np, win.row0) if (src_np < 0).any() else {}
     ddem = G.DeviceDem(dem)
     work = G.learned_work(win)
     xs, ys = [], []
     for s0 in range(0, n_shots, chunk):
         n = min(chunk, n_shots - s0)
-        det, _ = ddem.sample(n, seed=seed, stream=stream, shot0=s0, device=dev)
+        det, obs = ddem.sample(n, seed=seed, stream=stream, shot0=s0, device=dev)
         err = G.sample_errors(ddem, n, seed=seed, stream=stream, shot0=s0, device=dev)
+        for w in wins[:window]:
+            eh, _, _ = w.decode(det, syn_offset=w.row0)
+            w.commit(eh, det, obs)
+        # unit-column truth per local row: parity of the merged columns' errors
+        unit_truth = torch.zeros((n, win.m), dtype=torch.int32, device=dev)
+        for r, cols in units.items():
+            if cols.size:
+                unit_truth[:, r] = err[:, torch.from_numpy(cols).to(dev)].int().sum(1) % 2
         rx = torch.zeros((n, rec_steps, N_CAND, G.MLP_IN), dtype=torch.float32, device=dev)
         rc = torch.full((n, rec_steps, N_CAND), -1, dtype=torch.int32, device=dev)
         rf = torch.zeros((n, rec_steps, N_CAND), dtype=torch.int32, device=dev)
@@ -63,9 +101,10 @@ def record(dem, prm: G.Params, n_shots: int, seed: int, stream: int = 0, rec_ste
         G.decode_learned(win, det, win.row0, cfg, work=work)
         ok = rc >= 0
         shot = torch.arange(n, device=dev).view(n, 1, 1).expand_as(rc)[ok]
-        col = rc[ok].long()
-        dcol = src[col]
-        truth = err[shot, dcol].int()
+        dcol = src[rc[ok].long()]
+        col_truth = err[shot, dcol.clamp(min=0)].int()
+        row_truth = unit_truth[shot, (-1 - dcol).clamp(min=0)]
+        truth = torch.where(dcol >= 0, col_truth, row_truth)
         xs.append(rx[ok])
         ys.append(truth.float())
     return torch.cat(xs), torch.cat(ys)

@@ -5,8 +5,10 @@ windows on the GPU and writes its FP32 parameters (numpy .npy, no pickle).
       --out paper_2403_18901_amd/proposer_144.npy
 
 Shots are spread evenly over noise levels p in [pmin, pmax]; each is decoded
-with plain GDG in record mode on its first window (12 noisy rounds, W = 3,
-g = 4, 8 preprocessing iterations; Alg. 3 on above p = 0.002).
+with plain GDG in record mode on its first window, or with --windows all on
+one of the windows, spread evenly over them, after the earlier windows are
+decoded and committed (12 noisy rounds, W = 3, g = 4, 8 preprocessing
+iterations; Alg. 3 on above p = 0.002).
 """
 import argparse
 import json
@@ -32,6 +34,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--windows", choices=["first", "all"], default="first")
     ap.add_argument("--out", default=LRN.default_model_path("144"))
     a = ap.parse_args()
     t0 = time.time()
@@ -41,10 +44,13 @@ def main():
     for i, p in enumerate(ps):
         dem = circuit_dem(get_code("144"), 12, float(p))
         prm = G.params(alpha=1.0, g=4, pre_iters=8, trunc_factor=2, low_error=int(p <= 0.002))
-        x, y = LRN.record(dem, prm, per, seed=a.seed + i, stream=0)
-        xs.append(x)
-        ys.append(y)
-        print(f"p={p:.4f}: {x.shape[0]} candidates, in error {float(y.mean()):.3f}", flush=True)
+        n_win = G.n_windows(dem.n_rounds, 3) if a.windows == "all" else 1
+        for k in range(n_win):
+            x, y = LRN.record(dem, prm, per // n_win, seed=a.seed + i, stream=k, window=k)
+            xs.append(x)
+            ys.append(y)
+            print(f"p={p:.4f} window {k}: {x.shape[0]} candidates, in error "
+                  f"{float(y.mean()):.3f}", flush=True)
     x, y = torch.cat(xs), torch.cat(ys)
     n = x.shape[0]
     gen = torch.Generator(device="cuda")
