@@ -8,7 +8,10 @@ shapes on a sample of the real jobs and keeps the fastest:
 * wavefronts per workgroup (each wavefront runs whole decision paths),
 * persistent grid size (workgroups per CU x CU count, or one per shot),
 * schedule: all jobs in one launch, or one launch per kernel register tiling
-  (so small codes do not run in the largest code's tiling).
+  (so small codes do not run in the largest code's tiling), each tiling's
+  launch then with a shape of its own: the tilings' launches run one after
+  another, so the tuner times each tiling's jobs alone, composes the fastest
+  shape per tiling and times the composed plan as well.
 """
 from __future__ import annotations
 
@@ -32,30 +35,35 @@ def _bucket(w) -> int:
 
 
 class LaunchPlan:
-    """How a set of jobs is launched: waves, grid, and grouping into launches."""
+    """How a set of jobs is launched: waves, grid, and grouping into launches.
+    per_bucket ({tiling: (waves, wg_per_cu)}, split plans only) overrides the
+    shape of that tiling's launch."""
 
-    def __init__(self, waves=4, wg_per_cu=0, split=False):
+    def __init__(self, waves=4, wg_per_cu=0, split=False, per_bucket=None):
         self.waves = waves
         self.wg_per_cu = wg_per_cu      # 0: one workgroup per shot
         self.split = split              # one launch per register tiling
+        self.per_bucket = dict(per_bucket or {}) if split else {}
 
     def __repr__(self):
-        return f"LaunchPlan(waves={self.waves}, wg_per_cu={self.wg_per_cu}, split={self.split})"
+        extra = f", per_bucket={self.per_bucket}" if self.per_bucket else ""
+        return (f"LaunchPlan(waves={self.waves}, wg_per_cu={self.wg_per_cu}, "
+                f"split={self.split}{extra})")
 
     def key(self):
-        return (self.waves, self.wg_per_cu, self.split)
+        return (self.waves, self.wg_per_cu, self.split, tuple(sorted(self.per_bucket.items())))
 
     def run(self, jobs):
         """jobs: list of (Window, syn, offset, outs), costliest first."""
-        groups = [jobs]
+        groups = [(None, jobs)]
         if self.split:
             by = {}
             for j in jobs:
                 by.setdefault(_bucket(j[0]), []).append(j)
-            groups = [by[b] for b in sorted(by, reverse=True)]
-        for grp in groups:
-            wg = self.wg_per_cu * N_CU if self.wg_per_cu else 0
-            G.decode_jobs(grp, waves=self.waves, workgroups=wg)
+            groups = [(b, by[b]) for b in sorted(by, reverse=True)]
+        for b, grp in groups:
+            waves, wpc = self.per_bucket.get(b, (self.waves, self.wg_per_cu))
+            G.decode_jobs(grp, waves=waves, workgroups=wpc * N_CU if wpc else 0)
 
 
 def candidate_plans(windows):
@@ -82,23 +90,45 @@ def autotune(jobs, reps: int = 2, plans=None, verbose: bool = False):
     key = tuple((w.m, w.n, w.n_act, w.n_paths, j[1].shape[0]) for w, j in zip(windows, jobs))
     if key in _cache and plans is None:
         return _cache[key]
+    composed = plans is None
     plans = plans or candidate_plans(windows)
     timings = {}
-    for p in plans:
-        p.run(jobs)                       # warm-up (LDS attribute, code load)
+
+    def time_plan(p, js):
+        p.run(js)                         # warm-up (LDS attribute, code load)
         torch.cuda.synchronize()
         best = float("inf")
         for _ in range(reps):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            p.run(jobs)
+            p.run(js)
             e1.record()
             e1.synchronize()
             best = min(best, e0.elapsed_time(e1))
-        timings[p.key()] = best
+        return best
+
+    for p in plans:
+        timings[p.key()] = time_plan(p, jobs)
         if verbose:
-            print(f"  {p}: {best:.2f} ms", flush=True)
+            print(f"  {p}: {timings[p.key()]:.2f} ms", flush=True)
+    by = {}
+    for j in jobs:
+        by.setdefault(_bucket(j[0]), []).append(j)
+    if composed and len(by) > 1:
+        # each tiling's launch on its own, then the composition of the fastest
+        per = {}
+        for b, grp in by.items():
+            sub = {}
+            for p in candidate_plans([j[0] for j in grp]):
+                if not p.split:
+                    sub[(p.waves, p.wg_per_cu)] = time_plan(p, grp)
+            per[b] = min(sub, key=sub.get)
+        comp = LaunchPlan(split=True, per_bucket=per)
+        plans = list(plans) + [comp]
+        timings[comp.key()] = time_plan(comp, jobs)
+        if verbose:
+            print(f"  {comp}: {timings[comp.key()]:.2f} ms", flush=True)
     best_key = min(timings, key=timings.get)
     best = next(p for p in plans if p.key() == best_key)
     _cache[key] = (best, timings)

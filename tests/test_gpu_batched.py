@@ -54,6 +54,11 @@ def test_jobs_match_single_window_for_every_plan():
     windows = [w for w, _ in jobs_in]
     plans = B.candidate_plans(windows)
     assert len(plans) >= 6
+    # per-tiling shapes, as the autotuner composes them
+    buckets = sorted({B._bucket(w) for w in windows})
+    shapes = [(8, 0), (4, 0), (2, 1), (4, 2)]
+    plans.append(B.LaunchPlan(split=True, per_bucket={b: shapes[i % len(shapes)]
+                                                      for i, b in enumerate(buckets)}))
     for plan in plans:
         outs = [(torch.full_like(r[0], 7), torch.full_like(r[1], -1.0), torch.full_like(r[2], -1))
                 for r in ref]
