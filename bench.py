@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--stream-waves", default="4,8",
                     help="wavefronts per workgroup of the streaming launches: one count, "
                          "or one per code ([[144]],[[288]]), e.g. 4,8")
+    ap.add_argument("--stream-wpc", default="0",
+                    help="persistent workgroups per CU of the streaming launches (0: one "
+                         "workgroup per shot): one count, or one per code")
     ap.add_argument("--stream-mem-mib", type=float, default=0.0,
                     help="device memory budget of the streaming service's experiment "
                          "slots in MiB (0: a quarter of the free memory, at most 1 GiB)")
@@ -460,8 +463,14 @@ def bench_stream(args):
         waves = waves * len(dems)
     if len(waves) != len(dems) or any(w not in (2, 4, 8) for w in waves):
         raise SystemExit("--stream-waves: 2, 4 or 8, once or once per code")
+    wpcs = [int(x) for x in str(args.stream_wpc).split(",")]
+    if len(wpcs) == 1:
+        wpcs = wpcs * len(dems)
+    if len(wpcs) != len(dems) or any(not 0 <= x <= 8 for x in wpcs):
+        raise SystemExit("--stream-wpc: 0..8, once or once per code")
     chain = dict(chain=args.stream_chain >= 0, chain_max=max(args.stream_chain, 0),
-                 plan=[BT.LaunchPlan(waves=w, wg_per_cu=0, split=True) for w in waves],
+                 plan=[BT.LaunchPlan(waves=w, wg_per_cu=x, split=True)
+                       for w, x in zip(waves, wpcs)],
                  decouple=bool(args.stream_decouple))
     sat = S.StreamingService(dems, prm, rate=1e6, n_slots=None, seed=args.seed,
                              mem_budget=budget, **chain)
@@ -487,7 +496,7 @@ def bench_stream(args):
         "config": {"workload": f"256 x [[144,12,12]] (12 rounds) + 32 x [[288,12,18]] (18 rounds), "
                                f"circuit-level p={args.p}, g={args.g}, Poisson round arrivals, "
                                "virtual time advanced by measured device time",
-                   "blocks": 288, "chain": args.stream_chain, "waves": waves,
+                   "blocks": 288, "chain": args.stream_chain, "waves": waves, "wg_per_cu": wpcs,
                    "decouple": bool(args.stream_decouple)},
         "saturated_1_round_per_us": dict(rep_sat, wall_s=wall_sat),
         "load_80pct": rep80,
